@@ -1,0 +1,262 @@
+#!/usr/bin/env python3
+"""Throughput of one LEEA generation on one MI355X.
+
+A step is one whole generation of the paper's Algorithm 1 on the device:
+draw the minibatch, rank + plan, crossover/mutation into the other
+population buffer, and the fused forward + fitness evaluation of all P
+networks on that batch.  Workload: the paper-scale configuration (MLP
+784-112-32-10, 91,866 parameters; population 1000; batch 512; section-4
+default hyperparameters), synthetic prototype data resident in HBM.
+
+Prints ONE JSON line: value = network-sample evaluations per second
+(P * b * generations / s), plus the roofline of the dominant kernel
+(measured with HIP events on the launch stream over the timed region) and
+the CPU oracle timed on a bounded sample of the same workload.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+if HERE not in sys.path:
+    sys.path.insert(0, HERE)
+
+METRIC = "network-sample evals/s (pop×batch fwd+fitness), gens/s vs plain FP32, same acc"
+HBM_PEAK = 8.0e12          # bytes/s, MI355X HBM3E
+MFMA_F32_PEAK = 157.3e12   # FLOP/s, MI355X dense FP32 matrix
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(batch):
+    from paper_1806_09819_amd import presets
+    p = dict(presets.PAPER)
+    p["batch"] = batch
+    return p
+
+
+def algorithmic(params, genes, b):
+    """Per-launch algorithmic FLOPs and HBM bytes of the evaluation kernel:
+    2 * sum n_{l-1} n_l FLOPs per network-sample; every weight read once
+    plus the shared batch."""
+    w = params["widths"]
+    per_sample = 2 * sum(w[i] * w[i + 1] for i in range(len(w) - 1))
+    P = params["pop"]
+    flops = float(per_sample) * P * b
+    nbytes = 4.0 * P * genes + 4.0 * b * (w[0] + 1) + 8.0 * P
+    return flops, nbytes
+
+
+def vary_bytes(params, genes):
+    """Algorithmic bytes of one variation launch: every child written once;
+    elites and mutants read one parent, crossover children two."""
+    from paper_1806_09819_amd import leea as B
+    n_e, n_c, n_m, _ = B.counts(params["pop"], params["p_elite"], params["p_cross"],
+                                params["p_mut"], params["rho"])
+    return 4.0 * genes * (2 * n_e + 3 * n_c + 2 * n_m)
+
+
+def run_gpu(params, steps, warmup, x_train, y_train, timed_events=True):
+    import torch
+    from paper_1806_09819_amd import leea as B
+
+    run = B.Leea(B.make_config(**dict(params, max_batch=params["batch"])))
+    lib = B.library()
+    ctx = run._ctx
+    b = params["batch"]
+    xb = torch.empty((b, params["widths"][0]), dtype=torch.float32, device="cuda")
+    yb = torch.empty((b,), dtype=torch.int32, device="cuda")
+    P = B._ptr
+
+    def call(st):
+        if st != 0:
+            raise B.LeeaError(st, lib.leea_last_error(ctx).decode())
+
+    run.draw_batch(0, x_train, y_train, b, xb, yb)
+    run.evaluate(xb, yb)
+    gen = [0]
+
+    def one_step(ev=None):
+        g = gen[0] + 1
+        if ev is not None:
+            ev[0].record()
+        call(lib.leea_draw_batch(ctx, g, P(x_train), P(y_train), x_train.shape[0], b, P(xb),
+                                 P(yb)))
+        if ev is not None:
+            ev[1].record()
+        call(lib.leea_select(ctx, None, None, None))
+        if ev is not None:
+            ev[2].record()
+        call(lib.leea_crossover_mutate(ctx))
+        if ev is not None:
+            ev[3].record()
+        call(lib.leea_evaluate(ctx, P(xb), P(yb), b, None, None, None))
+        if ev is not None:
+            ev[4].record()
+        gen[0] = g
+
+    for _ in range(warmup):
+        one_step()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        one_step(events[k] if timed_events else None)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phases = np.zeros(4)
+    if timed_events:
+        for ev in events:
+            for i in range(4):
+                phases[i] += ev[i].elapsed_time(ev[i + 1])
+        phases /= steps
+    _, f_adj = run.population()
+    best = float(torch.max(torch.nan_to_num(f_adj, nan=-np.inf)).item())
+    out = dict(seconds=t1 - t0, phases_ms=dict(batch=phases[0], select=phases[1],
+                                                vary=phases[2], evaluate=phases[3]),
+               genes=run.genes, best_f_adj=best)
+    run.close()
+    return out
+
+
+def cpu_baseline(params, b, min_seconds=10.0, max_gens=3):
+    """The oracle (numpy: float64 forward and fitness, float32 genetic
+    operators) running whole generations of the same workload -- rank, plan,
+    vary and evaluate every slot -- until at least min_seconds have passed
+    (at most max_gens generations)."""
+    from oracle import leea as O
+    from paper_1806_09819_amd import datagen
+    import threadpoolctl
+
+    cfg = O.Config(**{k: v for k, v in params.items() if k in O.Config.__dataclass_fields__})
+    widths = tuple(params["widths"])
+    c = O.param_count(widths)
+    rng = np.random.Generator(np.random.PCG64(0))
+    pop = (rng.standard_normal((cfg.pop, c), dtype=np.float32) * np.float32(0.05))
+    f = rng.standard_normal(cfg.pop).astype(np.float32)
+    info = threadpoolctl.threadpool_info()
+    blas_threads = max([i.get("num_threads", 1) for i in info] or [1])
+    gens = 0
+    t0 = time.perf_counter()
+    while gens < max_gens:
+        g = gens + 1
+        x, y = datagen.prototype_data(b, seed=0, sample_seed=5 + g)
+        order = O.rank(f)
+        ops, p1, p2, fi = O.plan(order, f, cfg, g)
+        pop = O.vary(pop, ops, p1, p2, cfg, g)
+        f_raw, _ = O.evaluate(pop, widths, x, y)
+        f = O.inherit(f_raw, fi, cfg.alpha).astype(np.float32)
+        gens += 1
+        if time.perf_counter() - t0 >= min_seconds:
+            break
+    t1 = time.perf_counter()
+    return dict(value=gens * cfg.pop * b / (t1 - t0), unit="network-sample evals/s",
+                cores=int(blas_threads), kind="oracle",
+                sample="%d whole generation(s) of the same workload (pop %d, batch %d, "
+                       "91,866-parameter nets): rank, plan, vary and evaluate every slot, "
+                       "%.1f s on the host; value = generations*pop*batch/s"
+                       % (gens, cfg.pop, b, t1 - t0),
+                host_cpus=len(os.sched_getaffinity(0)))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--batch", type=int, default=512)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--sweep-steps", type=int, default=50)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the LEEA hot path here runs on a single MI355X "
+              "(multi-GPU sharding by individual is a design note, not a build target); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1806_09819_amd import datagen
+
+    torch.cuda.init()
+    data = datagen.splits("prototypes", sizes=(45000, 0, 0))
+    x_train = torch.from_numpy(data["x_train"]).cuda()
+    y_train = torch.from_numpy(data["y_train"]).cuda()
+
+    params = workload(args.batch)
+    log("bench: timed run, batch", args.batch)
+    r = run_gpu(params, args.steps, args.warmup, x_train, y_train)
+    P, b, K = params["pop"], args.batch, args.steps
+    value = P * b * K / r["seconds"]
+    flops, nbytes = algorithmic(params, r["genes"], b)
+    eval_s = r["phases_ms"]["evaluate"] * 1e-3
+    ridge = MFMA_F32_PEAK / HBM_PEAK
+    if flops / nbytes > ridge:
+        achieved = flops / eval_s / 1e12
+        roof = dict(bound="mfma", achieved=achieved, peak=MFMA_F32_PEAK / 1e12,
+                    unit="TFLOP/s", frac=achieved / (MFMA_F32_PEAK / 1e12))
+    else:
+        achieved = nbytes / eval_s / 1e9
+        roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK / 1e9, unit="GB/s",
+                    frac=achieved / (HBM_PEAK / 1e9))
+    roof["traffic"] = None
+    roof["kernel"] = "evaluate (fused forward + fitness, one launch per generation)"
+    roof["per_launch"] = dict(flops=flops, bytes=nbytes, avg_ms=r["phases_ms"]["evaluate"])
+    vb = vary_bytes(params, r["genes"])
+    phases = {k: round(v, 4) for k, v in r["phases_ms"].items()}
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "network-sample evals/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": r["seconds"] / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "paper-scale LEEA generation: MLP 784-112-32-10 (91,866 params), "
+                        "population 1000, batch %d, uniform crossover, p_E/p_C/p_M "
+                        "0.05/0.50/0.45, sigma 0.001, rho 0.5, alpha 1; synthetic 10-prototype "
+                        "Gaussian inputs (45k train set in HBM)" % b,
+            "widths": list(params["widths"]), "pop": P, "batch": b,
+            "gens_per_s": K / r["seconds"],
+        },
+        "phases_ms": phases,
+        "vary_hbm_GBps": vb / (r["phases_ms"]["vary"] * 1e-3) / 1e9,
+        "roofline": roof,
+    }
+    if not args.no_sweep:
+        sweep = []
+        for bb in (1, 8, 64, 512):
+            if bb == b:
+                continue
+            log("bench: sweep batch", bb)
+            pb = workload(bb)
+            rs = run_gpu(pb, args.sweep_steps, 3, x_train, y_train)
+            fl, nb = algorithmic(pb, rs["genes"], bb)
+            es = rs["phases_ms"]["evaluate"] * 1e-3
+            sweep.append(dict(batch=bb, value=P * bb * args.sweep_steps / rs["seconds"],
+                              ms_per_step=rs["seconds"] / args.sweep_steps * 1e3,
+                              phases_ms={k: round(v, 4) for k, v in rs["phases_ms"].items()},
+                              eval_hbm_frac=nb / es / HBM_PEAK, eval_mfma_frac=fl / es / MFMA_F32_PEAK,
+                              vary_hbm_frac=vb / (rs["phases_ms"]["vary"] * 1e-3) / HBM_PEAK))
+        line["batch_sweep"] = sweep
+    if not args.no_cpu_baseline:
+        log("bench: cpu baseline (oracle)")
+        line["cpu_baseline"] = cpu_baseline(params, b)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * leea.h -- C ABI of the MI355X (gfx950) limited-evaluation evolutionary
+ * algorithm library, libleea.so.
+ *
+ * The library runs one generation of the EA of Prellberg & Kramer,
+ * "Limited Evaluation Evolutionary Optimization of Large Neural Networks"
+ * (arXiv 1806.09819), Algorithm 1 of section 3.1, entirely on one GPU:
+ * population-batched forward pass of P directly encoded MLPs on a shared
+ * minibatch (section 3.3), softmax-cross-entropy fitness (Eq. 1) and accuracy,
+ * fitness inheritance (section 3.1), rank + truncation or tournament
+ * selection, uniform or arithmetic crossover and Gaussian mutation
+ * (section 3.2).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Memory.  Every pointer named "device" is caller-owned device memory (for
+ *   example a torch tensor's data_ptr()).  The workspace given to
+ *   leea_init_population holds the population and all per-individual state
+ *   and must stay allocated until leea_destroy.  The ctx is a host object
+ *   owned by the library.
+ * Streams.  Every call enqueues work on the HIP stream given at init (a
+ *   hipStream_t cast to void*, e.g. torch.cuda.current_stream().cuda_stream;
+ *   NULL is the legacy default stream) and returns without synchronising,
+ *   except leea_save / leea_load which synchronise that stream.
+ * Errors.  Every call returns a leea_status and never aborts.  Argument and
+ *   call-order checks happen on the host before anything is enqueued; a
+ *   failed check leaves the state unchanged.  A launch failure or sticky
+ *   device error returns LEEA_EDEVICE.  leea_last_error(ctx) gives a
+ *   human-readable message of the last failure on that ctx;
+ *   leea_last_error(NULL) that of the last failure of a call without a ctx.
+ * Threads.  A ctx must not be used by two host threads at once; different
+ *   ctxs are independent.
+ * Call order.  init -> evaluate (generation 0) -> { select ->
+ *   crossover_mutate -> evaluate }*, or step in place of the braces.
+ *   Out-of-order calls return LEEA_ESTATE.
+ * Genome layout.  Logical gene i of a network with widths n0..nL runs layer
+ *   by layer: W_l as [n_l][n_{l-1}] row-major, then b_l.  The device stores
+ *   individual j's genome at genomes + j*stride (floats), stride = the gene
+ *   count rounded up to a multiple of 64; padding genes are zero.
+ * Random numbers.  Philox4x32-10 (Salmon et al., SC'11) with key = seed and
+ *   counter = (block, slot, generation, run << 8 | purpose); every draw of
+ *   the method is a pure function of that counter, so results do not depend
+ *   on launch shapes.
+ */
+#ifndef LEEA_H
+#define LEEA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LEEA_MAX_LAYERS 8       /* weight layers */
+#define LEEA_MAX_WIDTH 256      /* widest hidden or output layer */
+#define LEEA_MAX_POP 8192       /* lambda; the rank kernel sorts in one workgroup */
+#define LEEA_MAX_BATCH 65536
+
+typedef struct leea_ctx leea_ctx;
+
+typedef enum {
+  LEEA_OK = 0,
+  LEEA_EINVAL = 1,   /* bad argument or configuration */
+  LEEA_ENOMEM = 2,   /* workspace too small, or host allocation failed */
+  LEEA_EDEVICE = 3,  /* HIP launch or runtime error */
+  LEEA_ESTATE = 4    /* call out of order */
+} leea_status;
+
+enum { LEEA_SEL_TRUNCATION = 0, LEEA_SEL_TOURNAMENT = 1 };
+enum { LEEA_XO_UNIFORM = 0, LEEA_XO_ARITHMETIC = 1 };
+enum { LEEA_OP_ELITE = 0, LEEA_OP_CROSSOVER = 1, LEEA_OP_MUTATION = 2 };
+
+/* Hyperparameters of one EA run.  Counts are integers: the caller rounds
+ * the paper's fractions p_E*lambda, p_C*lambda, p_M*lambda and rho*lambda
+ * (Algorithm 1); n_elite + n_cross + n_mut must equal pop. */
+typedef struct {
+  int32_t n_layers;                       /* L >= 1 weight layers */
+  int32_t widths[LEEA_MAX_LAYERS + 1];    /* widths[0] = input dim (multiple of 4),
+                                             widths[L] = classes d; widths[1..L] <= 256 */
+  int32_t pop;                            /* lambda, 1..LEEA_MAX_POP */
+  int32_t n_elite, n_cross, n_mut;        /* offspring made by each operator */
+  int32_t n_trunc;                        /* rho*lambda, 1..pop (truncation selection) */
+  int32_t selection;                      /* LEEA_SEL_* */
+  int32_t tournament_k;                   /* contestants, 1..16 (tournament only) */
+  int32_t crossover;                      /* LEEA_XO_* */
+  float sigma;                            /* mutation strength (section 3.2), >= 0 */
+  float alpha;                            /* inheritance weight in [0,1]; 1 = off */
+  uint64_t mut_threshold;                 /* gene mutated iff its 32-bit draw < this;
+                                             4294967296 = every gene (the paper) */
+  float glorot_a[LEEA_MAX_LAYERS];        /* Glorot-uniform bound of each layer (section 4.1) */
+  uint64_t seed;                          /* Philox key */
+  uint32_t run;                           /* run index in the Philox counter */
+  int32_t max_batch;                      /* largest b passed to evaluate/step, 1..LEEA_MAX_BATCH */
+} leea_config;
+
+/* Genes per network (c) and the padded per-individual stride in floats. */
+leea_status leea_param_count(const leea_config* cfg, int64_t* genes, int64_t* stride);
+
+/* Bytes of device workspace leea_init_population needs for cfg. */
+leea_status leea_workspace_bytes(const leea_config* cfg, size_t* bytes);
+
+/* Validate cfg, carve the workspace (device, >= leea_workspace_bytes, 256-byte
+ * aligned) and write the initial population (Algorithm 1, first line):
+ * Glorot-uniform weights, zero biases.  On success *out is a new ctx at
+ * generation 0 that still needs its first evaluate. */
+leea_status leea_init_population(const leea_config* cfg, void* workspace, size_t bytes,
+                                 void* hip_stream, leea_ctx** out);
+
+/* Draw generation gen's minibatch (Algorithm 1, "select random batch"): b
+ * examples with replacement from x_train [n_train][widths[0]] / y_train
+ * [n_train] (device) into x_out [b][widths[0]] / y_out [b] (device).
+ * Example k is index floor(w * n_train / 2^32), w = word k&3 of Philox block
+ * (BATCH, gen, slot 0, k>>2).  Valid in any state. */
+leea_status leea_draw_batch(leea_ctx* ctx, uint32_t gen, const float* x_train,
+                            const int32_t* y_train, int64_t n_train, int32_t b,
+                            float* x_out, int32_t* y_out);
+
+/* Evaluate the current population on the batch x [b][widths[0]], y [b]
+ * (device; labels in [0, d)) (Algorithm 1, last line): logits through every
+ * layer (ReLU on all but the last, section 4.1), fitness = mean log-softmax
+ * of the true class (Eq. 1, left side), accuracy = share of argmax == y
+ * (lowest class wins ties), then f_adj = (1-alpha) f_inh + alpha fitness
+ * (section 3.1) once a selection has produced inherited values.  The three
+ * outputs (device, [pop] floats each) may be NULL.  Labels outside [0, d)
+ * give a NaN fitness for that network.  1 <= b <= max_batch. */
+leea_status leea_evaluate(leea_ctx* ctx, const float* x, const int32_t* y, int32_t b,
+                          float* f_adj, float* f_raw, float* acc);
+
+/* Fitness and accuracy of the current population on n examples without
+ * touching the EA state (validation / test scoring).  1 <= n <= max_batch. */
+leea_status leea_score(leea_ctx* ctx, const float* x, const int32_t* y, int32_t n,
+                       float* f_raw, float* acc);
+
+/* Sort by adjusted fitness (descending; ties by slot, -0 == +0, NaN last)
+ * and plan the next generation (Algorithm 1, sort / elites / parent pairs /
+ * mutation parents): slot j < n_elite copies rank j; the next n_cross slots
+ * are crossover children and the rest mutants, with parents drawn from the
+ * top n_trunc (truncation) or by k-tournament.  Optional outputs (device):
+ * plan_out [pop][4] int32 {op, parent1, parent2, 0}, f_inh_out [pop] float,
+ * order_out [pop] int32 (slot of each rank).  Requires a preceding evaluate. */
+leea_status leea_select(leea_ctx* ctx, int32_t* plan_out, float* f_inh_out,
+                        int32_t* order_out);
+
+/* Build the next population from the plan (Algorithm 1, crossover / mutation
+ * / union): elites copied, crossover children not mutated, mutants get
+ * theta + sigma*N(0,1) on each gene selected by mut_threshold.  Advances the
+ * generation counter.  Requires a preceding select. */
+leea_status leea_crossover_mutate(leea_ctx* ctx);
+
+/* select -> crossover_mutate -> evaluate, one generation. */
+leea_status leea_step(leea_ctx* ctx, const float* x, const int32_t* y, int32_t b,
+                      float* f_adj, float* f_raw, float* acc);
+
+/* Mutation strength for the following crossover_mutate calls (for sigma
+ * schedules such as the exponential decay of section 3.2). */
+leea_status leea_set_sigma(leea_ctx* ctx, float sigma);
+
+/* Current generation index (0 after init). */
+leea_status leea_generation(const leea_ctx* ctx, uint32_t* gen);
+
+/* Borrowed device pointers, valid until the next crossover_mutate/step:
+ * the current population ([pop][stride] floats) and its f_adj [pop]. */
+leea_status leea_population(leea_ctx* ctx, float** genomes, int64_t* stride,
+                            float** f_adj);
+
+/* Replace the current population with src (device, [pop][stride] floats,
+ * padding genes zero) and, if f_adj is not NULL, its adjusted fitness
+ * (device [pop]), which makes the ctx ready for select.  f_inh (device, may be
+ * NULL) gives inherited values for the next evaluate (else none).  Used for
+ * checkpoint restore and for feeding identical inputs to tests. */
+leea_status leea_set_state(leea_ctx* ctx, const float* src, const float* f_adj,
+                           const float* f_inh);
+
+/* Host checkpoint: bytes needed, save (synchronises the stream) and load. */
+leea_status leea_state_bytes(const leea_ctx* ctx, size_t* bytes);
+leea_status leea_save(leea_ctx* ctx, void* host_buf, size_t bytes);
+leea_status leea_load(leea_ctx* ctx, const void* host_buf, size_t bytes);
+
+const char* leea_last_error(const leea_ctx* ctx);
+void leea_destroy(leea_ctx* ctx);
+
+/* ---- generator entry points (bit-exactness checks of the random streams) ----
+ * Each enqueues on hip_stream and returns without synchronising. */
+
+/* out[i][0..3] = Philox4x32-10(ctr[i][0..3], key) for i < n (device arrays). */
+leea_status leea_rng_philox(const uint32_t* ctr, uint64_t key, uint32_t* out, int64_t n,
+                            void* hip_stream);
+/* out[i] = float32 natural log of u[i] in (0, 1] (the mutation sampler's ln). */
+leea_status leea_rng_ln32(const float* u, float* out, int64_t n, void* hip_stream);
+/* Box-Muller: z[i][0..1] from words ab[i][0..1] (device). */
+leea_status leea_rng_normal_pairs(const uint32_t* ab, float* z, int64_t n, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LEEA_H */

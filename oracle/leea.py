@@ -131,18 +131,20 @@ def glorot_bound(n_in, n_out):
 
 # ------------------------------------------------------------------ init ---
 
-def init_population(cfg):
+def init_population(cfg, slots=None):
     """lambda networks with independent Glorot-uniform weights, zero biases.
 
     Gene i of slot j draws word (i & 3) of Philox block (INIT, gen 0, slot j,
     block i >> 2); u = (word >> 8) * 2**-24 in [0, 1) and the weight is
-    (2u - 1) * a_l in float32.
+    (2u - 1) * a_l in float32.  ``slots`` restricts the output to those
+    slots (rows in the given order).
     """
     widths = tuple(cfg.widths)
     c = param_count(widths)
-    pop = np.zeros((cfg.pop, c), dtype=F32)
+    slots = range(cfg.pop) if slots is None else list(slots)
+    pop = np.zeros((len(slots), c), dtype=F32)
     genes = np.arange(c, dtype=np.int64)
-    for j in range(cfg.pop):
+    for row, j in enumerate(slots):
         words = philox.draw(cfg.seed, philox.INIT, 0, j, genes >> 2, cfg.run)
         w = words[genes, genes & 3]
         u = (w >> np.uint32(8)).astype(F32) * F32(2.0 ** -24)
@@ -150,7 +152,7 @@ def init_population(cfg):
         t = t - F32(1.0)
         for l, ((w0, w1), _b) in enumerate(layer_slices(widths), start=1):
             a = glorot_bound(widths[l - 1], widths[l])
-            pop[j, w0:w1] = t[w0:w1] * a
+            pop[row, w0:w1] = t[w0:w1] * a
     return pop
 
 
@@ -349,35 +351,40 @@ def mutation_parts(seed, gen, slot, c, threshold, run=0):
     return mutated, z
 
 
-def vary(pop, ops, p1, p2, cfg, gen, sigma=None):
+def vary(pop, ops, p1, p2, cfg, gen, sigma=None, slots=None):
     """New population from the plan (Algorithm 1: E, C', M' and their union).
 
     Elites are copied unchanged.  Crossover children are not mutated.
     Uniform crossover takes each gene from one parent by a fair coin;
     arithmetic crossover is fl(fl(t1 + t2) * 0.5); mutation adds
-    fl(sigma * z) to each mutated gene (section 3.2).
+    fl(sigma * z) to each mutated gene (section 3.2).  ``slots`` restricts
+    the output to those offspring slots (rows in the given order).
     """
     sigma = F32(cfg.sigma if sigma is None else sigma)
     threshold = mutation_threshold(cfg.p_gene)
     P, c = pop.shape
-    out = np.empty_like(pop)
-    for j in range(P):
-        a = pop[p1[j]]
-        if ops[j] == ELITE:
-            out[j] = a
-        elif ops[j] == CROSS:
-            b = pop[p2[j]]
-            if cfg.crossover == "uniform":
-                out[j] = np.where(uniform_mask(cfg.seed, gen, j, c, cfg.run), b, a)
-            elif cfg.crossover == "arithmetic":
-                out[j] = (a + b) * F32(0.5)
-            else:
-                raise ValueError(cfg.crossover)
-        else:
-            mutated, z = mutation_parts(cfg.seed, gen, j, c, threshold, cfg.run)
-            noise = sigma * z
-            out[j] = np.where(mutated, a + noise, a)
+    slots = range(len(ops)) if slots is None else list(slots)
+    out = np.empty((len(slots), c), dtype=pop.dtype)
+    for row, j in enumerate(slots):
+        out[row] = _child(pop, ops, p1, p2, cfg, gen, sigma, threshold, j, c)
     return out
+
+
+def _child(pop, ops, p1, p2, cfg, gen, sigma, threshold, j, c):
+    """Offspring of slot j (one row of ``vary``)."""
+    a = pop[p1[j]]
+    if ops[j] == ELITE:
+        return a.copy()
+    if ops[j] == CROSS:
+        b = pop[p2[j]]
+        if cfg.crossover == "uniform":
+            return np.where(uniform_mask(cfg.seed, gen, j, c, cfg.run), b, a)
+        if cfg.crossover == "arithmetic":
+            return (a + b) * F32(0.5)
+        raise ValueError(cfg.crossover)
+    mutated, z = mutation_parts(cfg.seed, gen, j, c, threshold, cfg.run)
+    noise = sigma * z
+    return np.where(mutated, a + noise, a)
 
 
 # ----------------------------------------------------------------- batch ---

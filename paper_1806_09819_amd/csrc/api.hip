@@ -1,0 +1,490 @@
+// C ABI of libleea.so: argument validation, workspace carving, the call-order
+// state machine of Algorithm 1 and kernel sequencing.  Declarations and the
+// contract of every entry point are in include/leea.h.
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "../../include/leea.h"
+#include "internal.hpp"
+
+using namespace leea;
+
+namespace {
+
+enum State { kNeedEval = 0, kEvaluated = 1, kSelected = 2 };
+
+thread_local std::string g_err;
+
+constexpr uint32_t kStateMagic = 0x4C454541u;  // checkpoint tag
+constexpr uint32_t kStateVersion = 1u;
+
+}  // namespace
+
+struct leea_ctx {
+  leea_config cfg;
+  NetDesc nd;
+  hipStream_t stream;
+  float* genomes[2];
+  int cur;
+  float* f_adj;
+  float* f_raw;
+  float* acc;
+  float* f_inh;
+  float* f_inh_next;
+  int4* plan;
+  int32_t* order;
+  float2* partial;
+  int n_mt_max;
+  uint32_t gen;
+  int state;
+  int has_inh;
+  float sigma;
+  std::string err;
+};
+
+namespace {
+
+leea_status fail(leea_ctx* c, leea_status st, const char* fmt, const char* extra = nullptr) {
+  char buf[512];
+  snprintf(buf, sizeof buf, fmt, extra ? extra : "");
+  if (c)
+    c->err = buf;
+  else
+    g_err = buf;
+  return st;
+}
+
+leea_status dev(leea_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return LEEA_OK;
+  char buf[512];
+  snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+  if (c)
+    c->err = buf;
+  else
+    g_err = buf;
+  return LEEA_EDEVICE;
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+leea_status validate(const leea_config* cfg, NetDesc* nd) {
+  if (!cfg) return fail(nullptr, LEEA_EINVAL, "config is NULL");
+  const int L = cfg->n_layers;
+  if (L < 1 || L > LEEA_MAX_LAYERS) return fail(nullptr, LEEA_EINVAL, "n_layers must be 1..8");
+  if (cfg->widths[0] < 4 || cfg->widths[0] % 4 != 0 || cfg->widths[0] > 1 << 20)
+    return fail(nullptr, LEEA_EINVAL, "widths[0] must be a positive multiple of 4");
+  for (int l = 1; l <= L; ++l)
+    if (cfg->widths[l] < 1 || cfg->widths[l] > LEEA_MAX_WIDTH)
+      return fail(nullptr, LEEA_EINVAL, "widths[1..L] must be in 1..256");
+  if (cfg->widths[L] < 2) return fail(nullptr, LEEA_EINVAL, "need at least 2 classes");
+  if (cfg->pop < 1 || cfg->pop > LEEA_MAX_POP)
+    return fail(nullptr, LEEA_EINVAL, "pop must be in 1..8192");
+  if (cfg->n_elite < 0 || cfg->n_cross < 0 || cfg->n_mut < 0 ||
+      (int64_t)cfg->n_elite + cfg->n_cross + cfg->n_mut != cfg->pop)
+    return fail(nullptr, LEEA_EINVAL, "n_elite + n_cross + n_mut must equal pop");
+  if (cfg->n_trunc < 1 || cfg->n_trunc > cfg->pop)
+    return fail(nullptr, LEEA_EINVAL, "n_trunc must be in 1..pop");
+  if (cfg->selection != LEEA_SEL_TRUNCATION && cfg->selection != LEEA_SEL_TOURNAMENT)
+    return fail(nullptr, LEEA_EINVAL, "unknown selection");
+  if (cfg->selection == LEEA_SEL_TOURNAMENT && (cfg->tournament_k < 1 || cfg->tournament_k > 16))
+    return fail(nullptr, LEEA_EINVAL, "tournament_k must be in 1..16");
+  if (cfg->crossover != LEEA_XO_UNIFORM && cfg->crossover != LEEA_XO_ARITHMETIC)
+    return fail(nullptr, LEEA_EINVAL, "unknown crossover");
+  if (!(cfg->sigma >= 0.0f) || cfg->sigma == __builtin_inff())
+    return fail(nullptr, LEEA_EINVAL, "sigma must be finite and >= 0");
+  if (!(cfg->alpha >= 0.0f && cfg->alpha <= 1.0f))
+    return fail(nullptr, LEEA_EINVAL, "alpha must be in [0, 1]");
+  if (cfg->mut_threshold > (1ull << 32))
+    return fail(nullptr, LEEA_EINVAL, "mut_threshold must be <= 2^32");
+  if (cfg->max_batch < 1 || cfg->max_batch > LEEA_MAX_BATCH)
+    return fail(nullptr, LEEA_EINVAL, "max_batch must be in 1..65536");
+  for (int l = 0; l < L; ++l)
+    if (!(cfg->glorot_a[l] >= 0.0f) || cfg->glorot_a[l] == __builtin_inff())
+      return fail(nullptr, LEEA_EINVAL, "glorot_a must be finite and >= 0");
+  NetDesc d;
+  memset(&d, 0, sizeof d);
+  d.L = L;
+  int64_t off = 0;
+  for (int l = 0; l <= L; ++l) d.w[l] = cfg->widths[l];
+  for (int l = 0; l < L; ++l) {
+    d.woff[l] = off;
+    off += (int64_t)d.w[l + 1] * d.w[l];
+    d.boff[l] = off;
+    off += d.w[l + 1];
+  }
+  d.genes = off;
+  d.stride = (off + 63) & ~(int64_t)63;
+  if ((int64_t)cfg->pop * d.stride > (1ll << 40))
+    return fail(nullptr, LEEA_EINVAL, "population too large");
+  if (d.stride > 0xFFFFFFFFll * 4)
+    return fail(nullptr, LEEA_EINVAL, "network too large for 32-bit gene blocks");
+  if (nd) *nd = d;
+  return LEEA_OK;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Carve {
+  size_t genomes, scalars, plan, order, partial, total;
+};
+
+Carve carve(const leea_config* cfg, const NetDesc& nd) {
+  Carve c;
+  const size_t P = (size_t)cfg->pop;
+  const int n_mt = (cfg->max_batch + 63) / 64;
+  c.genomes = align256(P * (size_t)nd.stride * 4);
+  c.scalars = align256(P * 4);
+  c.plan = align256(P * 16);
+  c.order = align256(P * 4);
+  c.partial = align256(P * (size_t)n_mt * 8);
+  c.total = 2 * c.genomes + 5 * c.scalars + c.plan + c.order + c.partial;
+  return c;
+}
+
+Key key_of(const leea_ctx* c) {
+  Key k;
+  k.k0 = (uint32_t)c->cfg.seed;
+  k.k1 = (uint32_t)(c->cfg.seed >> 32);
+  k.run = c->cfg.run;
+  return k;
+}
+
+leea_status check_batch(leea_ctx* c, const float* x, const int32_t* y, int32_t b) {
+  if (!x || !y) return fail(c, LEEA_EINVAL, "x and y must be device pointers");
+  if (!aligned16(x)) return fail(c, LEEA_EINVAL, "x must be 16-byte aligned");
+  if (b < 1 || b > c->cfg.max_batch) return fail(c, LEEA_EINVAL, "b must be in 1..max_batch");
+  return LEEA_OK;
+}
+
+leea_status run_eval(leea_ctx* c, const float* x, const int32_t* y, int32_t b, bool update,
+                     float* f_adj, float* f_raw, float* acc) {
+  leea_status st = dev(c, launch_evaluate(c->genomes[c->cur], c->nd, c->cfg.pop, x, y, b,
+                                          c->partial, c->stream),
+                       "evaluate launch");
+  if (st) return st;
+  const int n_mt = eval_mtiles(c->nd, b);
+  const int use_inh = update && c->has_inh && c->cfg.alpha != 1.0f;
+  st = dev(c, launch_finalize(c->partial, c->cfg.pop, n_mt, b, c->f_inh, use_inh, c->cfg.alpha,
+                              update ? c->f_adj : nullptr, update ? c->f_raw : nullptr,
+                              update ? c->acc : nullptr, f_adj, f_raw, acc, c->stream),
+           "finalize launch");
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+leea_status leea_param_count(const leea_config* cfg, int64_t* genes, int64_t* stride) {
+  NetDesc nd;
+  leea_status st = validate(cfg, &nd);
+  if (st) return st;
+  if (genes) *genes = nd.genes;
+  if (stride) *stride = nd.stride;
+  return LEEA_OK;
+}
+
+leea_status leea_workspace_bytes(const leea_config* cfg, size_t* bytes) {
+  NetDesc nd;
+  leea_status st = validate(cfg, &nd);
+  if (st) return st;
+  if (!bytes) return fail(nullptr, LEEA_EINVAL, "bytes is NULL");
+  *bytes = carve(cfg, nd).total;
+  return LEEA_OK;
+}
+
+leea_status leea_init_population(const leea_config* cfg, void* workspace, size_t bytes,
+                                 void* hip_stream, leea_ctx** out) {
+  NetDesc nd;
+  leea_status st = validate(cfg, &nd);
+  if (st) return st;
+  if (!out) return fail(nullptr, LEEA_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!workspace) return fail(nullptr, LEEA_EINVAL, "workspace is NULL");
+  if ((uintptr_t)workspace & 255u) return fail(nullptr, LEEA_EINVAL, "workspace must be 256-byte aligned");
+  const Carve cv = carve(cfg, nd);
+  if (bytes < cv.total) return fail(nullptr, LEEA_ENOMEM, "workspace smaller than leea_workspace_bytes");
+  leea_ctx* c = new (std::nothrow) leea_ctx();
+  if (!c) return fail(nullptr, LEEA_ENOMEM, "host allocation failed");
+  c->cfg = *cfg;
+  c->nd = nd;
+  c->stream = (hipStream_t)hip_stream;
+  char* p = (char*)workspace;
+  c->genomes[0] = (float*)p;
+  p += cv.genomes;
+  c->genomes[1] = (float*)p;
+  p += cv.genomes;
+  c->f_adj = (float*)p;
+  p += cv.scalars;
+  c->f_raw = (float*)p;
+  p += cv.scalars;
+  c->acc = (float*)p;
+  p += cv.scalars;
+  c->f_inh = (float*)p;
+  p += cv.scalars;
+  c->f_inh_next = (float*)p;
+  p += cv.scalars;
+  c->plan = (int4*)p;
+  p += cv.plan;
+  c->order = (int32_t*)p;
+  p += cv.order;
+  c->partial = (float2*)p;
+  c->n_mt_max = (cfg->max_batch + 63) / 64;
+  c->cur = 0;
+  c->gen = 0;
+  c->state = kNeedEval;
+  c->has_inh = 0;
+  c->sigma = cfg->sigma;
+  Glorot ga;
+  for (int l = 0; l < LEEA_MAX_LAYERS; ++l) ga.a[l] = l < nd.L ? cfg->glorot_a[l] : 0.0f;
+  st = dev(nullptr, launch_init(c->genomes[0], nd, ga, cfg->pop, key_of(c), c->stream),
+           "init launch");
+  if (st) {
+    delete c;
+    return st;
+  }
+  *out = c;
+  return LEEA_OK;
+}
+
+leea_status leea_draw_batch(leea_ctx* c, uint32_t gen, const float* x_train,
+                            const int32_t* y_train, int64_t n_train, int32_t b, float* x_out,
+                            int32_t* y_out) {
+  if (!c) return fail(nullptr, LEEA_EINVAL, "ctx is NULL");
+  if (!x_train || !y_train || !x_out || !y_out)
+    return fail(c, LEEA_EINVAL, "training and output arrays must be device pointers");
+  if (!aligned16(x_train) || !aligned16(x_out))
+    return fail(c, LEEA_EINVAL, "x arrays must be 16-byte aligned");
+  if (n_train < 1 || n_train > 0xFFFFFFFFll) return fail(c, LEEA_EINVAL, "n_train out of range");
+  if (b < 1 || b > LEEA_MAX_BATCH) return fail(c, LEEA_EINVAL, "b out of range");
+  return dev(c, launch_draw_batch(x_train, y_train, n_train, c->nd.w[0], b, x_out, y_out,
+                                  key_of(c), gen, c->stream),
+             "draw_batch launch");
+}
+
+leea_status leea_evaluate(leea_ctx* c, const float* x, const int32_t* y, int32_t b,
+                          float* f_adj, float* f_raw, float* acc) {
+  if (!c) return fail(nullptr, LEEA_EINVAL, "ctx is NULL");
+  if (c->state == kSelected)
+    return fail(c, LEEA_ESTATE, "evaluate after select: call crossover_mutate first");
+  leea_status st = check_batch(c, x, y, b);
+  if (st) return st;
+  st = run_eval(c, x, y, b, true, f_adj, f_raw, acc);
+  if (st) return st;
+  c->state = kEvaluated;
+  return LEEA_OK;
+}
+
+leea_status leea_score(leea_ctx* c, const float* x, const int32_t* y, int32_t n, float* f_raw,
+                       float* acc) {
+  if (!c) return fail(nullptr, LEEA_EINVAL, "ctx is NULL");
+  leea_status st = check_batch(c, x, y, n);
+  if (st) return st;
+  return run_eval(c, x, y, n, false, nullptr, f_raw, acc);
+}
+
+leea_status leea_select(leea_ctx* c, int32_t* plan_out, float* f_inh_out, int32_t* order_out) {
+  if (!c) return fail(nullptr, LEEA_EINVAL, "ctx is NULL");
+  if (c->state != kEvaluated) return fail(c, LEEA_ESTATE, "select needs an evaluated population");
+  const leea_config& g = c->cfg;
+  leea_status st = dev(c,
+                       launch_select(c->f_adj, g.pop, g.n_elite, g.n_cross, g.n_trunc,
+                                     g.selection, g.tournament_k, key_of(c), c->gen + 1, c->plan,
+                                     c->f_inh_next, c->order, c->stream),
+                       "select launch");
+  if (st) return st;
+  if (plan_out)
+    st = dev(c, hipMemcpyAsync(plan_out, c->plan, (size_t)g.pop * 16, hipMemcpyDeviceToDevice,
+                               c->stream), "plan copy");
+  if (!st && f_inh_out)
+    st = dev(c, hipMemcpyAsync(f_inh_out, c->f_inh_next, (size_t)g.pop * 4,
+                               hipMemcpyDeviceToDevice, c->stream), "f_inh copy");
+  if (!st && order_out)
+    st = dev(c, hipMemcpyAsync(order_out, c->order, (size_t)g.pop * 4, hipMemcpyDeviceToDevice,
+                               c->stream), "order copy");
+  if (st) return st;
+  c->state = kSelected;
+  return LEEA_OK;
+}
+
+leea_status leea_crossover_mutate(leea_ctx* c) {
+  if (!c) return fail(nullptr, LEEA_EINVAL, "ctx is NULL");
+  if (c->state != kSelected) return fail(c, LEEA_ESTATE, "crossover_mutate needs a select first");
+  const int nxt = c->cur ^ 1;
+  leea_status st = dev(c,
+                       launch_vary(c->genomes[c->cur], c->genomes[nxt], c->plan, c->nd, c->cfg.pop,
+                                   c->cfg.crossover, c->sigma, c->cfg.mut_threshold, key_of(c),
+                                   c->gen + 1, c->stream),
+                       "vary launch");
+  if (st) return st;
+  c->cur = nxt;
+  float* t = c->f_inh;
+  c->f_inh = c->f_inh_next;
+  c->f_inh_next = t;
+  c->has_inh = 1;
+  c->gen += 1;
+  c->state = kNeedEval;
+  return LEEA_OK;
+}
+
+leea_status leea_step(leea_ctx* c, const float* x, const int32_t* y, int32_t b, float* f_adj,
+                      float* f_raw, float* acc) {
+  if (!c) return fail(nullptr, LEEA_EINVAL, "ctx is NULL");
+  if (c->state != kEvaluated) return fail(c, LEEA_ESTATE, "step needs an evaluated population");
+  leea_status st = check_batch(c, x, y, b);
+  if (st) return st;
+  st = leea_select(c, nullptr, nullptr, nullptr);
+  if (st) return st;
+  st = leea_crossover_mutate(c);
+  if (st) return st;
+  return leea_evaluate(c, x, y, b, f_adj, f_raw, acc);
+}
+
+leea_status leea_set_sigma(leea_ctx* c, float sigma) {
+  if (!c) return fail(nullptr, LEEA_EINVAL, "ctx is NULL");
+  if (!(sigma >= 0.0f) || sigma == __builtin_inff())
+    return fail(c, LEEA_EINVAL, "sigma must be finite and >= 0");
+  c->sigma = sigma;
+  return LEEA_OK;
+}
+
+leea_status leea_generation(const leea_ctx* c, uint32_t* gen) {
+  if (!c || !gen) return fail(nullptr, LEEA_EINVAL, "NULL argument");
+  *gen = c->gen;
+  return LEEA_OK;
+}
+
+leea_status leea_population(leea_ctx* c, float** genomes, int64_t* stride, float** f_adj) {
+  if (!c) return fail(nullptr, LEEA_EINVAL, "ctx is NULL");
+  if (genomes) *genomes = c->genomes[c->cur];
+  if (stride) *stride = c->nd.stride;
+  if (f_adj) *f_adj = c->f_adj;
+  return LEEA_OK;
+}
+
+leea_status leea_set_state(leea_ctx* c, const float* src, const float* f_adj,
+                           const float* f_inh) {
+  if (!c) return fail(nullptr, LEEA_EINVAL, "ctx is NULL");
+  const size_t gbytes = (size_t)c->cfg.pop * c->nd.stride * 4;
+  const size_t sbytes = (size_t)c->cfg.pop * 4;
+  leea_status st = LEEA_OK;
+  if (src)
+    st = dev(c, hipMemcpyAsync(c->genomes[c->cur], src, gbytes, hipMemcpyDeviceToDevice,
+                               c->stream), "population copy");
+  if (!st && f_adj)
+    st = dev(c, hipMemcpyAsync(c->f_adj, f_adj, sbytes, hipMemcpyDeviceToDevice, c->stream),
+             "f_adj copy");
+  if (!st && f_inh)
+    st = dev(c, hipMemcpyAsync(c->f_inh, f_inh, sbytes, hipMemcpyDeviceToDevice, c->stream),
+             "f_inh copy");
+  if (st) return st;
+  c->has_inh = f_inh ? 1 : 0;
+  c->state = f_adj ? kEvaluated : kNeedEval;
+  return LEEA_OK;
+}
+
+// Checkpoint: header {magic, version, gen, state, has_inh, cur=0, sigma,
+// pop, stride} then genomes, f_adj, f_raw, acc, f_inh.
+struct CkptHeader {
+  uint32_t magic, version, gen, state, has_inh;
+  float sigma;
+  int64_t pop, stride;
+  uint64_t seed;
+};
+
+leea_status leea_state_bytes(const leea_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return fail(nullptr, LEEA_EINVAL, "NULL argument");
+  *bytes = sizeof(CkptHeader) + (size_t)c->cfg.pop * c->nd.stride * 4 + 4 * (size_t)c->cfg.pop * 4;
+  return LEEA_OK;
+}
+
+leea_status leea_save(leea_ctx* c, void* host_buf, size_t bytes) {
+  if (!c || !host_buf) return fail(c, LEEA_EINVAL, "NULL argument");
+  size_t need;
+  leea_state_bytes(c, &need);
+  if (bytes < need) return fail(c, LEEA_ENOMEM, "checkpoint buffer too small");
+  CkptHeader h;
+  h.magic = kStateMagic;
+  h.version = kStateVersion;
+  h.gen = c->gen;
+  h.state = (uint32_t)c->state;
+  h.has_inh = (uint32_t)c->has_inh;
+  h.sigma = c->sigma;
+  h.pop = c->cfg.pop;
+  h.stride = c->nd.stride;
+  h.seed = c->cfg.seed;
+  char* p = (char*)host_buf;
+  memcpy(p, &h, sizeof h);
+  p += sizeof h;
+  const size_t gbytes = (size_t)c->cfg.pop * c->nd.stride * 4;
+  const size_t sbytes = (size_t)c->cfg.pop * 4;
+  leea_status st = dev(c, hipStreamSynchronize(c->stream), "sync before save");
+  if (!st) st = dev(c, hipMemcpy(p, c->genomes[c->cur], gbytes, hipMemcpyDeviceToHost), "save");
+  p += gbytes;
+  const float* arr[4] = {c->f_adj, c->f_raw, c->acc, c->f_inh};
+  for (int i = 0; i < 4 && !st; ++i) {
+    st = dev(c, hipMemcpy(p, arr[i], sbytes, hipMemcpyDeviceToHost), "save");
+    p += sbytes;
+  }
+  return st;
+}
+
+leea_status leea_load(leea_ctx* c, const void* host_buf, size_t bytes) {
+  if (!c || !host_buf) return fail(c, LEEA_EINVAL, "NULL argument");
+  size_t need;
+  leea_state_bytes(c, &need);
+  if (bytes < need) return fail(c, LEEA_EINVAL, "checkpoint buffer too small");
+  CkptHeader h;
+  memcpy(&h, host_buf, sizeof h);
+  if (h.magic != kStateMagic || h.version != kStateVersion)
+    return fail(c, LEEA_EINVAL, "not a LEEA checkpoint");
+  if (h.pop != c->cfg.pop || h.stride != c->nd.stride || h.seed != c->cfg.seed)
+    return fail(c, LEEA_EINVAL, "checkpoint does not match this configuration");
+  if (h.state > kSelected) return fail(c, LEEA_EINVAL, "corrupt checkpoint state");
+  const char* p = (const char*)host_buf + sizeof h;
+  const size_t gbytes = (size_t)c->cfg.pop * c->nd.stride * 4;
+  const size_t sbytes = (size_t)c->cfg.pop * 4;
+  leea_status st = dev(c, hipStreamSynchronize(c->stream), "sync before load");
+  if (!st) st = dev(c, hipMemcpy(c->genomes[c->cur], p, gbytes, hipMemcpyHostToDevice), "load");
+  p += gbytes;
+  float* arr[4] = {c->f_adj, c->f_raw, c->acc, c->f_inh};
+  for (int i = 0; i < 4 && !st; ++i) {
+    st = dev(c, hipMemcpy(arr[i], p, sbytes, hipMemcpyHostToDevice), "load");
+    p += sbytes;
+  }
+  if (st) return st;
+  c->gen = h.gen;
+  // a checkpoint taken between select and crossover_mutate resumes at select
+  c->state = h.state == kSelected ? kEvaluated : (int)h.state;
+  c->has_inh = (int)h.has_inh;
+  c->sigma = h.sigma;
+  return LEEA_OK;
+}
+
+const char* leea_last_error(const leea_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+void leea_destroy(leea_ctx* c) { delete c; }
+
+leea_status leea_rng_philox(const uint32_t* ctr, uint64_t key, uint32_t* out, int64_t n,
+                            void* hip_stream) {
+  if (!ctr || !out || n < 0) return fail(nullptr, LEEA_EINVAL, "bad arguments");
+  if (n == 0) return LEEA_OK;
+  return dev(nullptr, launch_rng_philox(ctr, key, out, n, (hipStream_t)hip_stream), "philox");
+}
+
+leea_status leea_rng_ln32(const float* u, float* out, int64_t n, void* hip_stream) {
+  if (!u || !out || n < 0) return fail(nullptr, LEEA_EINVAL, "bad arguments");
+  if (n == 0) return LEEA_OK;
+  return dev(nullptr, launch_rng_ln32(u, out, n, (hipStream_t)hip_stream), "ln32");
+}
+
+leea_status leea_rng_normal_pairs(const uint32_t* ab, float* z, int64_t n, void* hip_stream) {
+  if (!ab || !z || n < 0) return fail(nullptr, LEEA_EINVAL, "bad arguments");
+  if (n == 0) return LEEA_OK;
+  return dev(nullptr, launch_rng_normal_pairs(ab, z, n, (hipStream_t)hip_stream), "normal");
+}
+
+}  // extern "C"

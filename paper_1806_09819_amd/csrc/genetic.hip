@@ -1,0 +1,188 @@
+// Population initialisation, variation (elites / crossover / mutation) and
+// minibatch draw.  All three are HBM-streaming kernels: float4 accesses,
+// whole 1 KiB wave-wide segments, and one Philox call per lane per
+// 4 (mutation) or 128 (uniform crossover) genes.
+#include "internal.hpp"
+
+namespace leea {
+
+// Glorot-uniform weights, zero biases and padding (Algorithm 1, first line;
+// section 4.1).  Thread = 4 consecutive genes = one Philox block.
+__global__ __launch_bounds__(256) void init_kernel(float* __restrict__ genomes, NetDesc nd,
+                                                   Glorot ga, Key key) {
+#pragma clang fp contract(off)
+  const int j = blockIdx.y;
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n4 = nd.stride >> 2;
+  if (q >= n4) return;
+  const uint4 w = draw(key, kInit, 0, (uint32_t)j, (uint32_t)q);
+  float v[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t i = 4 * q + e;
+    v[e] = 0.0f;
+    for (int l = 0; l < nd.L; ++l) {
+      const int64_t w0 = nd.woff[l];
+      const int64_t w1 = w0 + (int64_t)nd.w[l + 1] * nd.w[l];
+      if (i >= w0 && i < w1) {
+        const float u = (float)(word_of(w, e) >> 8) * 5.9604644775390625e-8f;
+        float t = 2.0f * u;
+        t = t - 1.0f;
+        v[e] = t * ga.a[l];
+      }
+    }
+  }
+  reinterpret_cast<float4*>(genomes + (int64_t)j * nd.stride)[q] =
+      make_float4(v[0], v[1], v[2], v[3]);
+}
+
+hipError_t launch_init(float* genomes, const NetDesc& nd, const Glorot& ga, int pop,
+                       const Key& key, hipStream_t s) {
+  const int64_t n4 = nd.stride >> 2;
+  dim3 grid((unsigned)((n4 + 255) / 256), (unsigned)pop);
+  hipLaunchKernelGGL(init_kernel, grid, dim3(256), 0, s, genomes, nd, ga, key);
+  return hipGetLastError();
+}
+
+// One wave handles an 8192-gene group G: lane q, step t (0..31) touches the
+// float4 at gene 8192 G + 256 t + 4 q, so every step is one contiguous
+// 1 KiB access per parent.  Uniform crossover: the lane's 32 steps x 4
+// genes use the 128 bits of Philox block (XO, gen, slot, 64 G + q): word
+// t/8, bit 4 (t mod 8) + element.  Mutation: the float4 at gene 4f uses
+// block f of MUTNORM (four normals) and, when not every gene mutates, block
+// f of MUTMASK (four decisions).  Padding genes stay zero.
+template <int kXoKind>
+__global__ __launch_bounds__(256) void vary_kernel(const float* __restrict__ cur,
+                                                   float* __restrict__ nxt,
+                                                   const int4* __restrict__ plan,
+                                                   int64_t stride, int64_t genes, float sigma,
+                                                   uint64_t thr, Key key, uint32_t gen) {
+#pragma clang fp contract(off)
+  const int j = blockIdx.y;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t G = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t n4 = stride >> 2;
+  const int64_t base4 = G * 2048 + lane;
+  if (G * 2048 >= n4) return;
+  const int4 pl = plan[j];
+  const float4* __restrict__ a4 = reinterpret_cast<const float4*>(cur + (int64_t)pl.y * stride);
+  const float4* __restrict__ b4 = reinterpret_cast<const float4*>(cur + (int64_t)pl.z * stride);
+  float4* __restrict__ d4 = reinterpret_cast<float4*>(nxt + (int64_t)j * stride);
+
+  if (pl.x == kOpElite) {
+#pragma unroll 8
+    for (int t = 0; t < 32; ++t) {
+      const int64_t f = base4 + 64 * t;
+      if (f < n4) d4[f] = a4[f];
+    }
+  } else if (pl.x == kOpCross) {
+    if (kXoKind == 0) {
+      const uint4 m = draw(key, kXo, gen, (uint32_t)j, (uint32_t)(G * 64 + lane));
+#pragma unroll 8
+      for (int t = 0; t < 32; ++t) {
+        const int64_t f = base4 + 64 * t;
+        if (f < n4) {
+          const float4 a = a4[f];
+          const float4 b = b4[f];
+          const uint32_t bits = word_of(m, t >> 3) >> (4 * (t & 7));
+          float4 o;
+          o.x = (bits & 1u) ? b.x : a.x;
+          o.y = (bits & 2u) ? b.y : a.y;
+          o.z = (bits & 4u) ? b.z : a.z;
+          o.w = (bits & 8u) ? b.w : a.w;
+          d4[f] = o;
+        }
+      }
+    } else {
+#pragma unroll 8
+      for (int t = 0; t < 32; ++t) {
+        const int64_t f = base4 + 64 * t;
+        if (f < n4) {
+          const float4 a = a4[f];
+          const float4 b = b4[f];
+          float4 o;
+          o.x = (a.x + b.x) * 0.5f;
+          o.y = (a.y + b.y) * 0.5f;
+          o.z = (a.z + b.z) * 0.5f;
+          o.w = (a.w + b.w) * 0.5f;
+          d4[f] = o;
+        }
+      }
+    }
+  } else {
+    const bool all = thr >= (1ull << 32);
+    const uint32_t t32 = (uint32_t)thr;
+#pragma unroll 4
+    for (int t = 0; t < 32; ++t) {
+      const int64_t f = base4 + 64 * t;
+      if (f < n4) {
+        const float4 a = a4[f];
+        const int64_t i0 = 4 * f;
+        if (i0 >= genes) {
+          d4[f] = a;
+          continue;
+        }
+        const float4 z = normals4(draw(key, kMutNorm, gen, (uint32_t)j, (uint32_t)f));
+        uint4 mw = make_uint4(0u, 0u, 0u, 0u);
+        if (!all) mw = draw(key, kMutMask, gen, (uint32_t)j, (uint32_t)f);
+        const bool m0 = (all || mw.x < t32) && i0 + 0 < genes;
+        const bool m1 = (all || mw.y < t32) && i0 + 1 < genes;
+        const bool m2 = (all || mw.z < t32) && i0 + 2 < genes;
+        const bool m3 = (all || mw.w < t32) && i0 + 3 < genes;
+        float4 o;
+        const float n0 = sigma * z.x;
+        const float n1 = sigma * z.y;
+        const float n2 = sigma * z.z;
+        const float n3 = sigma * z.w;
+        o.x = m0 ? a.x + n0 : a.x;
+        o.y = m1 ? a.y + n1 : a.y;
+        o.z = m2 ? a.z + n2 : a.z;
+        o.w = m3 ? a.w + n3 : a.w;
+        d4[f] = o;
+      }
+    }
+  }
+}
+
+hipError_t launch_vary(const float* cur, float* nxt, const int4* plan, const NetDesc& nd,
+                       int pop, int crossover, float sigma, uint64_t mut_threshold,
+                       const Key& key, uint32_t gen, hipStream_t s) {
+  const int64_t groups = (nd.stride + 8191) / 8192;
+  dim3 grid((unsigned)((groups + 3) / 4), (unsigned)pop);
+  if (crossover == 0)
+    hipLaunchKernelGGL(vary_kernel<0>, grid, dim3(256), 0, s, cur, nxt, plan, nd.stride,
+                       nd.genes, sigma, mut_threshold, key, gen);
+  else
+    hipLaunchKernelGGL(vary_kernel<1>, grid, dim3(256), 0, s, cur, nxt, plan, nd.stride,
+                       nd.genes, sigma, mut_threshold, key, gen);
+  return hipGetLastError();
+}
+
+// Example k of the batch is row floor(w * n_train / 2^32) of the training
+// set, w = word k&3 of block (BATCH, gen, slot 0, k>>2).  One workgroup
+// copies one row (float4 granularity; n_in is a multiple of 4).
+__global__ __launch_bounds__(256) void draw_batch_kernel(const float* __restrict__ x_train,
+                                                         const int32_t* __restrict__ y_train,
+                                                         int64_t n_train, int n_in,
+                                                         float* __restrict__ x_out,
+                                                         int32_t* __restrict__ y_out, Key key,
+                                                         uint32_t gen) {
+  const int k = blockIdx.x;
+  const uint4 w = draw(key, kBatch, gen, 0u, (uint32_t)(k >> 2));
+  const uint64_t idx = ((uint64_t)word_of(w, k & 3) * (uint64_t)n_train) >> 32;
+  const float4* src = reinterpret_cast<const float4*>(x_train + (int64_t)idx * n_in);
+  float4* dst = reinterpret_cast<float4*>(x_out + (int64_t)k * n_in);
+  for (int c = threadIdx.x; c < (n_in >> 2); c += 256) dst[c] = src[c];
+  if (threadIdx.x == 0) y_out[k] = y_train[idx];
+}
+
+hipError_t launch_draw_batch(const float* x_train, const int32_t* y_train, int64_t n_train,
+                             int n_in, int b, float* x_out, int32_t* y_out, const Key& key,
+                             uint32_t gen, hipStream_t s) {
+  hipLaunchKernelGGL(draw_batch_kernel, dim3((unsigned)b), dim3(256), 0, s, x_train, y_train,
+                     n_train, n_in, x_out, y_out, key, gen);
+  return hipGetLastError();
+}
+
+}  // namespace leea

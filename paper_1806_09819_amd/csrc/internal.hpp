@@ -1,0 +1,45 @@
+// Host-side launchers of the LEEA kernels (one translation unit per kernel
+// family); used only by the C-ABI implementation in api.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.hpp"
+
+namespace leea {
+
+struct Glorot {
+  float a[kMaxLayers];
+};
+
+// init.hip / vary.hip / batch.hip
+hipError_t launch_init(float* genomes, const NetDesc& nd, const Glorot& ga, int pop,
+                       const Key& key, hipStream_t s);
+hipError_t launch_vary(const float* cur, float* nxt, const int4* plan, const NetDesc& nd,
+                       int pop, int crossover, float sigma, uint64_t mut_threshold,
+                       const Key& key, uint32_t gen, hipStream_t s);
+hipError_t launch_draw_batch(const float* x_train, const int32_t* y_train, int64_t n_train,
+                             int n_in, int b, float* x_out, int32_t* y_out, const Key& key,
+                             uint32_t gen, hipStream_t s);
+
+// select.hip
+hipError_t launch_select(const float* f_adj, int pop, int n_elite, int n_cross, int n_trunc,
+                         int selection, int tk, const Key& key, uint32_t gen, int4* plan,
+                         float* f_inh_next, int32_t* order, hipStream_t s);
+
+// evaluate.hip
+int eval_mtiles(const NetDesc& nd, int b);
+hipError_t launch_evaluate(const float* genomes, const NetDesc& nd, int pop, const float* x,
+                           const int32_t* y, int b, float2* partial, hipStream_t s);
+hipError_t launch_finalize(const float2* partial, int pop, int n_mt, int b, const float* f_inh,
+                           int use_inh, float alpha, float* f_adj, float* f_raw, float* acc,
+                           float* f_adj_out, float* f_raw_out, float* acc_out, hipStream_t s);
+
+// rng.hip (generator entry points)
+hipError_t launch_rng_philox(const uint32_t* ctr, uint64_t key, uint32_t* out, int64_t n,
+                             hipStream_t s);
+hipError_t launch_rng_ln32(const float* u, float* out, int64_t n, hipStream_t s);
+hipError_t launch_rng_normal_pairs(const uint32_t* ab, float* z, int64_t n, hipStream_t s);
+
+}  // namespace leea

@@ -1,0 +1,122 @@
+// Rank + selection plan in one single-workgroup kernel (Algorithm 1: sort
+// by fitness, elites, parent pairs, mutation parents).
+//
+// Each slot's fitness becomes a unique 64-bit key: the high word is an
+// order-reversing map of the float (larger fitness -> smaller key, -0 -> +0,
+// every NaN -> 0xFFFFFFFF), the low word the slot index.  Unique keys make
+// the result independent of the sorting algorithm; an LDS bitonic sort over
+// the next power of two (padding keys all-ones) then gives the order.
+#include "internal.hpp"
+
+namespace leea {
+
+__device__ __forceinline__ uint64_t rank_key(float f, uint32_t slot) {
+  uint32_t hi;
+  if (f != f) {
+    hi = 0xFFFFFFFFu;
+  } else {
+    uint32_t b = __float_as_uint(f);
+    if ((b << 1) == 0u) b = 0u;  // -0 -> +0
+    hi = (b & 0x80000000u) ? b : (~b & 0x7FFFFFFFu);
+  }
+  return ((uint64_t)hi << 32) | slot;
+}
+
+// Rank of one parent: truncation = floor(w * n_trunc / 2^32) from word p;
+// tournament = best of k ranks floor(w * pop / 2^32) from words p*k + c.
+__device__ __forceinline__ uint32_t parent_rank(const Key& key, uint32_t gen, uint32_t slot,
+                                                int p, int selection, int tk, uint32_t n_trunc,
+                                                uint32_t pop) {
+  if (selection == 0) {
+    const uint4 w = draw(key, kSel, gen, slot, 0u);
+    return (uint32_t)(((uint64_t)word_of(w, p) * n_trunc) >> 32);
+  }
+  uint32_t best = 0xFFFFFFFFu;
+  int blk = -1;
+  uint4 w = make_uint4(0u, 0u, 0u, 0u);
+  for (int c = 0; c < tk; ++c) {
+    const int idx = p * tk + c;
+    if ((idx >> 2) != blk) {
+      blk = idx >> 2;
+      w = draw(key, kSel, gen, slot, (uint32_t)blk);
+    }
+    const uint32_t r = (uint32_t)(((uint64_t)word_of(w, idx & 3) * pop) >> 32);
+    best = r < best ? r : best;
+  }
+  return best;
+}
+
+__global__ __launch_bounds__(1024) void select_kernel(const float* __restrict__ f_adj, int pop,
+                                                      int n2, int n_elite, int n_cross,
+                                                      int n_trunc, int selection, int tk,
+                                                      Key key, uint32_t gen,
+                                                      int4* __restrict__ plan,
+                                                      float* __restrict__ f_inh_next,
+                                                      int32_t* __restrict__ order_out) {
+#pragma clang fp contract(off)
+  extern __shared__ uint64_t keys[];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n2; i += 1024)
+    keys[i] = i < pop ? rank_key(f_adj[i], (uint32_t)i) : ~0ull;
+  __syncthreads();
+  for (int size = 2; size <= n2; size <<= 1) {
+    for (int half = size >> 1; half > 0; half >>= 1) {
+      for (int i = tid; i < (n2 >> 1); i += 1024) {
+        const int lo = 2 * i - (i & (half - 1));
+        const int hi = lo + half;
+        const bool up = (lo & size) == 0;
+        const uint64_t a = keys[lo];
+        const uint64_t b = keys[hi];
+        if ((a > b) == up) {
+          keys[lo] = b;
+          keys[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int r = tid; r < pop; r += 1024) {
+    const int32_t slot = (int32_t)(uint32_t)keys[r];
+    if (order_out) order_out[r] = slot;
+  }
+  // plan: slot j < n_elite copies rank j; then n_cross crossover children;
+  // the rest are mutants
+  for (int j = tid; j < pop; j += 1024) {
+    int op, p1, p2;
+    float fi;
+    if (j < n_elite) {
+      op = kOpElite;
+      p1 = p2 = (int)(uint32_t)keys[j];
+      fi = f_adj[p1];
+    } else if (j < n_elite + n_cross) {
+      op = kOpCross;
+      const uint32_t r1 = parent_rank(key, gen, (uint32_t)j, 0, selection, tk, n_trunc, pop);
+      const uint32_t r2 = parent_rank(key, gen, (uint32_t)j, 1, selection, tk, n_trunc, pop);
+      p1 = (int)(uint32_t)keys[r1];
+      p2 = (int)(uint32_t)keys[r2];
+      const float sum = f_adj[p1] + f_adj[p2];
+      fi = sum * 0.5f;
+    } else {
+      op = kOpMut;
+      const uint32_t r1 = parent_rank(key, gen, (uint32_t)j, 0, selection, tk, n_trunc, pop);
+      p1 = p2 = (int)(uint32_t)keys[r1];
+      fi = f_adj[p1];
+    }
+    plan[j] = make_int4(op, p1, p2, 0);
+    f_inh_next[j] = fi;
+  }
+}
+
+hipError_t launch_select(const float* f_adj, int pop, int n_elite, int n_cross, int n_trunc,
+                         int selection, int tk, const Key& key, uint32_t gen, int4* plan,
+                         float* f_inh_next, int32_t* order, hipStream_t s) {
+  int n2 = 1;
+  while (n2 < pop) n2 <<= 1;
+  if (n2 < 2) n2 = 2;
+  const size_t lds = (size_t)n2 * sizeof(uint64_t);
+  hipLaunchKernelGGL(select_kernel, dim3(1), dim3(1024), lds, s, f_adj, pop, n2, n_elite,
+                     n_cross, n_trunc, selection, tk, key, gen, plan, f_inh_next, order);
+  return hipGetLastError();
+}
+
+}  // namespace leea

@@ -1,0 +1,306 @@
+"""Thin Python binding of libleea.so (argument marshalling only).
+
+Every step of the EA runs in the library's HIP kernels; PyTorch supplies the
+device memory (workspace, batches, outputs) and the stream.  The library
+must be built (``python -m paper_1806_09819_amd.build``); importing this
+module does not fall back to anything if it is missing.
+"""
+
+import ctypes
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libleea.so")
+
+MAX_LAYERS = 8
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, 1, 2, 3, 4
+SEL = {"truncation": 0, "tournament": 1}
+XO = {"uniform": 0, "arithmetic": 1}
+OP_ELITE, OP_CROSS, OP_MUT = 0, 1, 2
+
+
+class LeeaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("leea status %d: %s" % (status, msg))
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("n_layers", ctypes.c_int32),
+        ("widths", ctypes.c_int32 * (MAX_LAYERS + 1)),
+        ("pop", ctypes.c_int32),
+        ("n_elite", ctypes.c_int32),
+        ("n_cross", ctypes.c_int32),
+        ("n_mut", ctypes.c_int32),
+        ("n_trunc", ctypes.c_int32),
+        ("selection", ctypes.c_int32),
+        ("tournament_k", ctypes.c_int32),
+        ("crossover", ctypes.c_int32),
+        ("sigma", ctypes.c_float),
+        ("alpha", ctypes.c_float),
+        ("mut_threshold", ctypes.c_uint64),
+        ("glorot_a", ctypes.c_float * MAX_LAYERS),
+        ("seed", ctypes.c_uint64),
+        ("run", ctypes.c_uint32),
+        ("max_batch", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def library():
+    """Load libleea.so (after torch, so both share torch's HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libleea.so is not built: run python -m paper_1806_09819_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I32, I64, U32, U64, F = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_float
+    CP = ctypes.POINTER(Config)
+    sig = {
+        "leea_param_count": [CP, ctypes.POINTER(I64), ctypes.POINTER(I64)],
+        "leea_workspace_bytes": [CP, ctypes.POINTER(ctypes.c_size_t)],
+        "leea_init_population": [CP, P, ctypes.c_size_t, P, ctypes.POINTER(P)],
+        "leea_draw_batch": [P, U32, P, P, I64, I32, P, P],
+        "leea_evaluate": [P, P, P, I32, P, P, P],
+        "leea_score": [P, P, P, I32, P, P],
+        "leea_select": [P, P, P, P],
+        "leea_crossover_mutate": [P],
+        "leea_step": [P, P, P, I32, P, P, P],
+        "leea_set_sigma": [P, F],
+        "leea_generation": [P, ctypes.POINTER(U32)],
+        "leea_population": [P, ctypes.POINTER(P), ctypes.POINTER(I64), ctypes.POINTER(P)],
+        "leea_set_state": [P, P, P, P],
+        "leea_state_bytes": [P, ctypes.POINTER(ctypes.c_size_t)],
+        "leea_save": [P, P, ctypes.c_size_t],
+        "leea_load": [P, P, ctypes.c_size_t],
+        "leea_rng_philox": [P, U64, P, I64, P],
+        "leea_rng_ln32": [P, P, I64, P],
+        "leea_rng_normal_pairs": [P, P, I64, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.leea_last_error.argtypes = [P]
+    lib.leea_last_error.restype = ctypes.c_char_p
+    lib.leea_destroy.argtypes = [P]
+    lib.leea_destroy.restype = None
+    _lib = lib
+    return lib
+
+
+def _check(st, ctx=None):
+    if st != OK:
+        msg = library().leea_last_error(ctx)
+        raise LeeaError(st, msg.decode() if msg else "")
+
+
+# ------------------------------------------------------------ host helpers --
+
+def counts(pop, p_elite, p_cross, p_mut, rho):
+    """Integer offspring counts from the paper's fractions (Algorithm 1):
+    round half up; mutants take the remainder; n_rho clamped to [1, pop]."""
+    if abs(p_elite + p_cross + p_mut - 1.0) > 1e-9:
+        raise ValueError("p_E + p_C + p_M must equal 1")
+    n_e = int(math.floor(p_elite * pop + 0.5))
+    n_c = int(math.floor(p_cross * pop + 0.5))
+    n_m = pop - n_e - n_c
+    if min(n_e, n_c, n_m) < 0:
+        raise ValueError("counts do not fit the population")
+    n_r = min(max(int(math.floor(rho * pop + 0.5)), 1), pop)
+    return n_e, n_c, n_m, n_r
+
+
+def threshold(p_gene):
+    """32-bit mutation threshold floor(p * 2^32) (2^32 = every gene)."""
+    if not 0.0 <= p_gene <= 1.0:
+        raise ValueError("p_gene must be in [0, 1]")
+    return min(1 << 32, int(math.floor(Fraction(p_gene) * (1 << 32))))
+
+
+def make_config(widths, pop, p_elite=0.05, p_cross=0.50, p_mut=0.45, rho=0.5,
+                selection="truncation", tournament_k=2, crossover="uniform", sigma=0.001,
+                p_gene=1.0, alpha=1.0, seed=0, run=0, max_batch=512, **_ignored):
+    """leea_config from the paper's hyperparameters (fractions)."""
+    widths = tuple(int(w) for w in widths)
+    L = len(widths) - 1
+    if not 1 <= L <= MAX_LAYERS:
+        raise ValueError("1..8 weight layers")
+    n_e, n_c, n_m, n_r = counts(pop, p_elite, p_cross, p_mut, rho)
+    c = Config()
+    c.n_layers = L
+    for i, w in enumerate(widths):
+        c.widths[i] = w
+    c.pop, c.n_elite, c.n_cross, c.n_mut, c.n_trunc = pop, n_e, n_c, n_m, n_r
+    c.selection = SEL[selection]
+    c.tournament_k = tournament_k
+    c.crossover = XO[crossover]
+    c.sigma = sigma
+    c.alpha = alpha
+    c.mut_threshold = threshold(p_gene)
+    for l in range(L):
+        # Glorot-uniform limit sqrt(6 / (fan_in + fan_out)), float64 -> float32
+        c.glorot_a[l] = float(np.float32(math.sqrt(6.0 / (widths[l] + widths[l + 1]))))
+    c.seed = seed
+    c.run = run
+    c.max_batch = max_batch
+    return c
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ------------------------------------------------------------------- ctx --
+
+class Leea:
+    """One EA run on the current CUDA (HIP) device and stream."""
+
+    def __init__(self, cfg, device="cuda"):
+        lib = library()
+        self.cfg = cfg
+        self.device = torch.device(device)
+        nbytes = ctypes.c_size_t()
+        _check(lib.leea_workspace_bytes(ctypes.byref(cfg), ctypes.byref(nbytes)))
+        genes, stride = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.leea_param_count(ctypes.byref(cfg), ctypes.byref(genes), ctypes.byref(stride)))
+        self.genes, self.stride = genes.value, stride.value
+        self.pop = cfg.pop
+        self.d = cfg.widths[cfg.n_layers]
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        ctx = ctypes.c_void_p()
+        _check(lib.leea_init_population(ctypes.byref(cfg), _ptr(self.workspace), nbytes.value,
+                                        _stream(), ctypes.byref(ctx)))
+        self._ctx = ctx
+
+    @classmethod
+    def from_params(cls, device="cuda", **kw):
+        return cls(make_config(**kw), device=device)
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            library().leea_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _out(self, dtype=torch.float32, shape=None):
+        return torch.empty(shape if shape is not None else (self.pop,), dtype=dtype,
+                           device=self.device)
+
+    def evaluate(self, x, y):
+        f_adj, f_raw, acc = self._out(), self._out(), self._out()
+        _check(library().leea_evaluate(self._ctx, _ptr(x), _ptr(y), x.shape[0], _ptr(f_adj),
+                                       _ptr(f_raw), _ptr(acc)), self._ctx)
+        return f_adj, f_raw, acc
+
+    def score(self, x, y):
+        f_raw, acc = self._out(), self._out()
+        _check(library().leea_score(self._ctx, _ptr(x), _ptr(y), x.shape[0], _ptr(f_raw),
+                                    _ptr(acc)), self._ctx)
+        return f_raw, acc
+
+    def select(self):
+        plan = self._out(torch.int32, (self.pop, 4))
+        f_inh = self._out()
+        order = self._out(torch.int32)
+        _check(library().leea_select(self._ctx, _ptr(plan), _ptr(f_inh), _ptr(order)), self._ctx)
+        return plan, f_inh, order
+
+    def crossover_mutate(self):
+        _check(library().leea_crossover_mutate(self._ctx), self._ctx)
+
+    def step(self, x, y, outputs=True):
+        if outputs:
+            f_adj, f_raw, acc = self._out(), self._out(), self._out()
+        else:
+            f_adj = f_raw = acc = None
+        _check(library().leea_step(self._ctx, _ptr(x), _ptr(y), x.shape[0], _ptr(f_adj),
+                                   _ptr(f_raw), _ptr(acc)), self._ctx)
+        return f_adj, f_raw, acc
+
+    def draw_batch(self, gen, x_train, y_train, b, x_out=None, y_out=None):
+        if x_out is None:
+            x_out = torch.empty((b, x_train.shape[1]), dtype=torch.float32, device=self.device)
+            y_out = torch.empty((b,), dtype=torch.int32, device=self.device)
+        _check(library().leea_draw_batch(self._ctx, gen, _ptr(x_train), _ptr(y_train),
+                                         x_train.shape[0], b, _ptr(x_out), _ptr(y_out)), self._ctx)
+        return x_out, y_out
+
+    def set_sigma(self, sigma):
+        _check(library().leea_set_sigma(self._ctx, sigma), self._ctx)
+
+    @property
+    def generation(self):
+        g = ctypes.c_uint32()
+        _check(library().leea_generation(self._ctx, ctypes.byref(g)), self._ctx)
+        return g.value
+
+    def _view(self, ptr, nbytes):
+        off = ptr - self.workspace.data_ptr()
+        assert 0 <= off and off + nbytes <= self.workspace.numel()
+        return self.workspace[off:off + nbytes]
+
+    def population(self):
+        """(genomes [pop, stride] float32 view, f_adj [pop] view) -- borrowed."""
+        g, f = ctypes.c_void_p(), ctypes.c_void_p()
+        stride = ctypes.c_int64()
+        _check(library().leea_population(self._ctx, ctypes.byref(g), ctypes.byref(stride),
+                                         ctypes.byref(f)), self._ctx)
+        genomes = self._view(g.value, self.pop * self.stride * 4).view(torch.float32)
+        f_adj = self._view(f.value, self.pop * 4).view(torch.float32)
+        return genomes.view(self.pop, self.stride), f_adj
+
+    def set_state(self, genomes=None, f_adj=None, f_inh=None):
+        _check(library().leea_set_state(self._ctx, _ptr(genomes), _ptr(f_adj), _ptr(f_inh)),
+               self._ctx)
+
+    def save(self):
+        n = ctypes.c_size_t()
+        _check(library().leea_state_bytes(self._ctx, ctypes.byref(n)), self._ctx)
+        buf = np.empty(n.value, dtype=np.uint8)
+        _check(library().leea_save(self._ctx, buf.ctypes.data, n.value), self._ctx)
+        return buf
+
+    def load(self, buf):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        _check(library().leea_load(self._ctx, buf.ctypes.data, buf.size), self._ctx)
+
+
+# ------------------------------------------------------ generator checks --
+
+def rng_philox(ctr, key):
+    """Philox4x32-10 of device uint32 counters [n, 4] under a 64-bit key."""
+    out = torch.empty_like(ctr)
+    _check(library().leea_rng_philox(_ptr(ctr), key, _ptr(out), ctr.shape[0], _stream()))
+    return out
+
+
+def rng_ln32(u):
+    out = torch.empty_like(u)
+    _check(library().leea_rng_ln32(_ptr(u), _ptr(out), u.numel(), _stream()))
+    return out
+
+
+def rng_normal_pairs(ab):
+    z = torch.empty(ab.shape, dtype=torch.float32, device=ab.device)
+    _check(library().leea_rng_normal_pairs(_ptr(ab), _ptr(z), ab.shape[0], _stream()))
+    return z

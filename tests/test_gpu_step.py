@@ -1,0 +1,142 @@
+"""End-to-end generations on the GPU, teacher-forced against the oracle:
+every generation's plan and population must match bit for bit and the
+fitness within tolerance; plus step() equivalence, checkpoint/resume,
+determinism and call-order errors."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import (F32, check_fitness, genomes_np, make_run, oracle_eval, say, to_dev,
+                         to_np)
+from oracle import leea as O
+from paper_1806_09819_amd import datagen
+from paper_1806_09819_amd import leea as B
+from paper_1806_09819_amd import presets
+
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def data():
+    x, y = datagen.teacher_data(4000)
+    return x, y, to_dev(x), to_dev(y)
+
+
+VARIANTS = [
+    ("small", {}),
+    ("small_alpha_half_tournament_arith", dict(alpha=0.5, selection="tournament",
+                                               crossover="arithmetic")),
+    ("paper_like_small_pop", dict(widths=(784, 112, 32, 10), pop=48, sigma=0.001, p_gene=1.0,
+                                  rho=0.5, batch=8)),
+]
+
+
+@pytest.mark.parametrize("name,over", VARIANTS, ids=[v[0] for v in VARIANTS])
+def test_teacher_forced_generations(data, name, over):
+    x, y, xd, yd = data
+    params = dict(presets.SMALL)
+    params.update(over)
+    b = params["batch"]
+    gens = params["generations"]
+    run, ocfg = make_run(params, max_batch=b)
+    widths = tuple(params["widths"])
+    pop_o = O.init_population(ocfg)
+    assert np.array_equal(genomes_np(run), pop_o)
+    xb, yb = run.draw_batch(0, xd, yd, b)
+    f_adj, f_raw, acc = run.evaluate(xb, yb)
+    idx = O.batch_indices(ocfg.seed, 0, b, x.shape[0], ocfg.run)
+    f_o, acc_o, amb = oracle_eval(pop_o, widths, x[idx], y[idx])
+    check_fitness(to_np(f_raw), to_np(acc), f_o, acc_o, amb, b, "gen0")
+    for g in range(1, gens + 1):
+        say(name, "generation", g)
+        f_prev = to_np(f_adj).copy()
+        xb, yb = run.draw_batch(g, xd, yd, b)
+        plan, f_inh, order = run.select()
+        run.crossover_mutate()
+        f_adj, f_raw, acc = run.evaluate(xb, yb)
+        order_o = O.rank(f_prev)
+        ops, p1, p2, fi = O.plan(order_o, f_prev, ocfg, g)
+        pl = to_np(plan)
+        assert np.array_equal(to_np(order), order_o)
+        assert np.array_equal(pl[:, 0], ops) and np.array_equal(pl[:, 1], p1)
+        assert np.array_equal(pl[:, 2], p2)
+        assert np.array_equal(to_np(f_inh).view(np.uint32), fi.view(np.uint32))
+        pop_o = O.vary(pop_o, ops, p1, p2, ocfg, g)
+        assert np.array_equal(genomes_np(run).view(np.uint32), pop_o.view(np.uint32)), g
+        idx = O.batch_indices(ocfg.seed, g, b, x.shape[0], ocfg.run)
+        f_o, acc_o, amb = oracle_eval(pop_o, widths, x[idx], y[idx])
+        check_fitness(to_np(f_raw), to_np(acc), f_o, acc_o, amb, b, "gen%d" % g)
+        fa_o = O.inherit(f_o, fi.astype(np.float64), ocfg.alpha)
+        fa = to_np(f_adj).astype(np.float64)
+        assert np.all(np.abs(fa - fa_o) <= 1e-5 * np.abs(fa_o) + 1e-6)
+
+
+def _run_steps(run, xd, yd, b, g0, n):
+    f = None
+    for g in range(g0, g0 + n):
+        xb, yb = run.draw_batch(g, xd, yd, b)
+        f = run.step(xb, yb)[0]
+    return f
+
+
+def test_step_equals_three_calls_and_is_deterministic(data):
+    _, _, xd, yd = data
+    say("step vs select+crossover_mutate+evaluate")
+    outs = []
+    for use_step in (True, False, True):
+        run, _ = make_run(presets.SMALL, max_batch=32)
+        xb, yb = run.draw_batch(0, xd, yd, 32)
+        f = run.evaluate(xb, yb)[0]
+        for g in range(1, 6):
+            xb, yb = run.draw_batch(g, xd, yd, 32)
+            if use_step:
+                f = run.step(xb, yb)[0]
+            else:
+                run.select()
+                run.crossover_mutate()
+                f = run.evaluate(xb, yb)[0]
+        outs.append((to_np(f), genomes_np(run)))
+    for f, g in outs[1:]:
+        assert np.array_equal(f, outs[0][0]) and np.array_equal(g, outs[0][1])
+
+
+def test_checkpoint_resume_bitwise(data):
+    _, _, xd, yd = data
+    say("checkpoint")
+    params = dict(presets.SMALL, alpha=0.5)
+    a, _ = make_run(params, max_batch=32)
+    xb, yb = a.draw_batch(0, xd, yd, 32)
+    a.evaluate(xb, yb)
+    _run_steps(a, xd, yd, 32, 1, 5)
+    ck = a.save()
+    fa = _run_steps(a, xd, yd, 32, 6, 5)
+    b, _ = make_run(params, max_batch=32)
+    b.load(ck)
+    assert b.generation == 5
+    fb = _run_steps(b, xd, yd, 32, 6, 5)
+    assert torch.equal(fa, fb) and np.array_equal(genomes_np(a), genomes_np(b))
+
+
+def test_call_order_errors(data):
+    _, _, xd, yd = data
+    run, _ = make_run(presets.SMALL, max_batch=32)
+    with pytest.raises(B.LeeaError) as e:
+        run.select()
+    assert e.value.status == B.ESTATE
+    with pytest.raises(B.LeeaError) as e:
+        run.crossover_mutate()
+    assert e.value.status == B.ESTATE
+    xb, yb = run.draw_batch(0, xd, yd, 32)
+    run.evaluate(xb, yb)
+    run.select()
+    with pytest.raises(B.LeeaError) as e:
+        run.evaluate(xb, yb)
+    assert e.value.status == B.ESTATE
+    with pytest.raises(B.LeeaError) as e:
+        run.step(xb, yb)
+    assert e.value.status == B.ESTATE
+    run.crossover_mutate()
+    with pytest.raises(B.LeeaError) as e:
+        run.evaluate(xd[:33], yd[:33])
+    assert e.value.status == B.EINVAL
