@@ -3,32 +3,41 @@
 //
 // Layer 1 of every network reads the same minibatch X [b][n0], so for the
 // whole population it is one dense product X * [W1_1 .. W1_P]^T (M = b,
-// N = P * n1, K = n0).  One workgroup owns one individual's n1 columns
-// (all of its layer-1 neurons) for up to 64 batch rows and accumulates them
-// on the matrix cores with v_mfma_f32_16x16x4_f32 (FP32 in, FP32
-// accumulate).  Keeping all n1 columns of an individual in one workgroup
-// lets the rest of the network and the fitness run in the same kernel on
-// the layer-1 tile held in LDS: nothing but two floats per (individual,
-// row tile) ever goes back to HBM.
+// N = P * n1, K = n0).  A workgroup owns one individual's n1 columns (all of
+// its layer-1 neurons) for a tile of batch rows and accumulates them on the
+// matrix cores with v_mfma_f32_16x16x4_f32 (FP32 in, FP32 accumulate).
+// Keeping all n1 columns of an individual in one workgroup lets the rest of
+// the network and the fitness run in the same kernel on the layer-1 tile
+// held in LDS: only two floats per (individual, row tile) go back to HBM.
 //
 // MFMA 16x16x4 f32 operand layout (wave64): lane l supplies A[l%16][l/16]
 // and B[l/16][l%16]; the 4 accumulator values of lane l are
-// D[4*(l/16)+i][l%16].  A float4 load of 4 consecutive k per lane feeds 4
-// MFMAs: in the e-th one lane (m, kq) contributes k = k0 + 4*kq + e, so the
-// four MFMAs together cover k0 .. k0+15 (one "super-step").
+// D[4*(l/16)+i][l%16].  A float4 of 4 consecutive k per lane feeds 4 MFMAs:
+// in the e-th one lane (m, kq) contributes k = k0 + 4*kq + e, so the four
+// MFMAs together cover k0 .. k0+15 (one "super-step").
 //
 // Two layer-1 schemes:
-// * small batch (b <= 16): one workgroup per individual, 4 waves split the
-//   K range; weights stream straight from HBM into registers (each weight
-//   is read exactly once; the kernel is bandwidth-bound), X sits in LDS.
-// * large batch: workgroup = (row tile of 64, individual); 4 waves split the
-//   rows; 16-wide K chunks of W and X are staged through double-buffered
-//   LDS so each weight fragment read from HBM serves all 4 waves.
+// * small batch (b <= 16, bandwidth-bound): one workgroup per individual;
+//   its 4 waves split the K range, weight fragments stream straight from
+//   HBM into registers (every weight is read exactly once), batch fragments
+//   come from L2; the four K-partial tiles are summed through LDS.
+// * large batch (compute-bound): workgroup = (tile of 64*MW rows,
+//   individual), each wave owns 16*MW rows x all n1 columns; 32-wide K
+//   chunks of W and X are staged through double-buffered, XOR-swizzled LDS
+//   so each weight fragment fetched serves every wave.  Workgroup ids are
+//   remapped so all row tiles of one individual run on the same XCD and
+//   share its weights in that XCD's L2.
+// Layers 2..L run on the matrix cores too (weight fragments as float4 loads
+// from L2) whenever the hidden widths are multiples of 4, else on VALU.
 #include "internal.hpp"
 
 namespace leea {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ floatx4 mfma(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
 
 // One super-step for NT column tiles; consecutive MFMAs go to different
 // accumulators so none waits on the previous one's result.
@@ -36,106 +45,155 @@ template <int NT>
 __device__ __forceinline__ void mfma_superstep(const float4& a, const float4 (&b)[NT],
                                                floatx4 (&acc)[NT]) {
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
-    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b[t].x, acc[t], 0, 0, 0);
+  for (int t = 0; t < NT; ++t) acc[t] = mfma(a.x, b[t].x, acc[t]);
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
-    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b[t].y, acc[t], 0, 0, 0);
+  for (int t = 0; t < NT; ++t) acc[t] = mfma(a.y, b[t].y, acc[t]);
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
-    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b[t].z, acc[t], 0, 0, 0);
+  for (int t = 0; t < NT; ++t) acc[t] = mfma(a.z, b[t].z, acc[t]);
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
-    acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b[t].w, acc[t], 0, 0, 0);
+  for (int t = 0; t < NT; ++t) acc[t] = mfma(a.w, b[t].w, acc[t]);
 }
 
 __device__ __forceinline__ float relu_keep_nan(float v) { return v < 0.0f ? 0.0f : v; }
 
-// LDS carve-up shared by both kernels (offsets in floats, set on the host).
+__device__ __forceinline__ float4 zero4() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+
+// LDS carve-up shared by both kernels (offsets and strides in floats).
 struct EvalLds {
-  int h1;      // [rows][ld1] layer-1 activations
+  int h1;     // layer-1 activations [rows][ld1]; later reused as a tail buffer
   int ld1;
-  int buf_a;   // [16][ldt] tail activations (ping)
-  int buf_b;   // [16][ldt] (pong)
+  int ta;     // tail activations [rows][ldt]
   int ldt;
-  int ll;      // [rows] per-sample log-likelihood
-  int cor;     // [rows] per-sample correctness (int)
-  int total;   // floats of dynamic LDS
+  int ll;     // [rows] per-sample log-likelihood
+  int cor;    // [rows] per-sample correctness (int)
+  int total;  // floats of dynamic LDS
 };
 
-// Layers 2..L and the fitness of `rows` samples whose layer-1 activations
-// are in LDS; writes ll[m] and cor[m] for m < rows.  Per-sample
-// log-likelihood: (z_y - max z) - log sum_k exp(z_k - max z) (Eq. 1, left
-// side); correct iff the first maximal logit is the label.
-__device__ void tail_fitness(const float* __restrict__ genome, const NetDesc& nd,
-                             float* lds, const EvalLds& lo, int rows, int m0,
-                             const int32_t* __restrict__ y) {
-  const int tid = threadIdx.x;
-  const int d = nd.w[nd.L];
-  float* ll = lds + lo.ll;
-  int* cor = reinterpret_cast<int*>(lds + lo.cor);
-  for (int r0 = 0; r0 < rows; r0 += 16) {
-    const int rc = rows - r0 < 16 ? rows - r0 : 16;
-    const float* in = lds + lo.h1 + r0 * lo.ld1;
-    int ldin = lo.ld1;
-    float* out = lds + lo.buf_a;
-    for (int l = 1; l < nd.L; ++l) {
-      const int n_in = nd.w[l];
-      const int n_out = nd.w[l + 1];
-      const float* __restrict__ W = genome + nd.woff[l];
-      const float* __restrict__ bias = genome + nd.boff[l];
-      const bool last = (l == nd.L - 1);
-      for (int idx = tid; idx < rc * n_out; idx += blockDim.x) {
-        const int m = idx / n_out;
-        const int n = idx - m * n_out;
-        const float* a = in + m * ldin;
-        const float* w = W + (int64_t)n * n_in;
-        float acc = 0.0f;
-        for (int k = 0; k < n_in; ++k) acc += a[k] * w[k];
-        acc += bias[n];
-        out[m * lo.ldt + n] = last ? acc : relu_keep_nan(acc);
+// One fully connected layer on the matrix cores for rows [0, 16*mtiles):
+// out = act(in * W^T + bias).  `in` (LDS, row stride ldi) must hold zeros in
+// columns [n_in, round16(n_in)); `out` gets zeros in [n_out, round16(n_out)).
+// W is [n_out][n_in] row-major in global memory with n_in and the matrix
+// offset multiples of 4; all fragments of a tile are loaded before its MFMAs.
+__device__ void mfma_layer(const float* in, int ldi, int n_in, float* out, int ldo, int n_out,
+                           const float* __restrict__ W, const float* __restrict__ bias,
+                           bool relu, int mtiles) {
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int mn = lane & 15;
+  const int kq = lane >> 4;
+  const int ntiles = (n_out + 15) >> 4;
+  const int kss = (n_in + 15) >> 4;  // <= 16: widths are at most 256
+  for (int item = wave; item < mtiles * ntiles; item += 4) {
+    const int mt = item / ntiles;
+    const int nt = item - mt * ntiles;
+    const int n = nt * 16 + mn;
+    const bool nv = n < n_out;
+    const float* __restrict__ wr = W + (int64_t)(nv ? n : 0) * n_in;
+    float4 bf[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int k = 16 * s + 4 * kq;
+      bf[s] = (s < kss && nv && k < n_in) ? *reinterpret_cast<const float4*>(wr + k) : zero4();
+    }
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    const float* arow = in + (mt * 16 + mn) * ldi + 4 * kq;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      if (s < kss) {
+        const float4 a = *reinterpret_cast<const float4*>(arow + 16 * s);
+        acc = mfma(a.x, bf[s].x, acc);
+        acc = mfma(a.y, bf[s].y, acc);
+        acc = mfma(a.z, bf[s].z, acc);
+        acc = mfma(a.w, bf[s].w, acc);
       }
-      __syncthreads();
-      in = out;
-      ldin = lo.ldt;
-      out = (out == lds + lo.buf_a) ? lds + lo.buf_b : lds + lo.buf_a;
     }
-    for (int m = tid; m < rc; m += blockDim.x) {
-      const float* z = in + m * ldin;
-      const int yy = y[m0 + r0 + m];
-      float mx = z[0];
-      int best = 0;
-      for (int k = 1; k < d; ++k)
-        if (z[k] > mx) {
-          mx = z[k];
-          best = k;
-        }
-      float s = 0.0f;
-      for (int k = 0; k < d; ++k) s += expf(z[k] - mx);
-      float v;
-      if (yy >= 0 && yy < d)
-        v = (z[yy] - mx) - logf(s);
-      else
-        v = __builtin_nanf("");
-      ll[r0 + m] = v;
-      cor[r0 + m] = (best == yy) ? 1 : 0;
+    const float bb = nv ? bias[n] : 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float v = acc[i] + bb;
+      if (relu) v = relu_keep_nan(v);
+      out[(mt * 16 + 4 * kq + i) * ldo + n] = nv ? v : 0.0f;
     }
-    __syncthreads();
   }
 }
 
-__device__ __forceinline__ void write_partial(float* lds, const EvalLds& lo, int rows,
-                                              float2* __restrict__ out) {
-  if (threadIdx.x == 0) {
-    const float* ll = lds + lo.ll;
-    const int* cor = reinterpret_cast<const int*>(lds + lo.cor);
+// The same layer on VALU, for hidden widths that are not multiples of 4.
+__device__ void scalar_layer(const float* in, int ldi, int n_in, float* out, int ldo, int n_out,
+                             const float* __restrict__ W, const float* __restrict__ bias,
+                             bool relu, int rows) {
+  const int n16 = (n_out + 15) & ~15;
+  for (int idx = threadIdx.x; idx < rows * n16; idx += blockDim.x) {
+    const int m = idx / n16;
+    const int n = idx - m * n16;
+    float v = 0.0f;
+    if (n < n_out) {
+      const float* a = in + m * ldi;
+      const float* w = W + (int64_t)n * n_in;
+      for (int k = 0; k < n_in; ++k) v += a[k] * w[k];
+      v += bias[n];
+      if (relu) v = relu_keep_nan(v);
+    }
+    out[m * ldo + n] = v;
+  }
+}
+
+// Layers 2..L on the LDS tile of layer-1 activations, then the per-sample
+// fitness of the first `rows` rows: log-likelihood (z_y - max z) -
+// log sum_k exp(z_k - max z) (Eq. 1, left side) and correctness (first
+// maximal logit equals the label); a label outside [0, d) gives NaN.  The
+// row sums go to *out in a fixed order (deterministic).
+__device__ void tail_and_fitness(float* lds, const EvalLds& lo, const NetDesc& nd,
+                                 const float* __restrict__ genome, int mtiles, int rows,
+                                 int m0, const int32_t* __restrict__ y, bool tail_vec,
+                                 float2* __restrict__ out) {
+  const float* in = lds + lo.h1;
+  int ldi = lo.ld1;
+  float* dst = lds + lo.ta;
+  for (int l = 1; l < nd.L; ++l) {
+    const float* W = genome + nd.woff[l];
+    const float* bias = genome + nd.boff[l];
+    const bool relu = l < nd.L - 1;
+    if (tail_vec)
+      mfma_layer(in, ldi, nd.w[l], dst, lo.ldt, nd.w[l + 1], W, bias, relu, mtiles);
+    else
+      scalar_layer(in, ldi, nd.w[l], dst, lo.ldt, nd.w[l + 1], W, bias, relu, 16 * mtiles);
+    __syncthreads();
+    in = dst;
+    ldi = lo.ldt;
+    dst = (dst == lds + lo.ta) ? lds + lo.h1 : lds + lo.ta;
+  }
+  const int d = nd.w[nd.L];
+  float* ll = lds + lo.ll;
+  int* cor = reinterpret_cast<int*>(lds + lo.cor);
+  for (int m = threadIdx.x; m < rows; m += blockDim.x) {
+    const float* z = in + m * ldi;
+    const int yy = y[m0 + m];
+    float mx = z[0];
+    int best = 0;
+    for (int k = 1; k < d; ++k)
+      if (z[k] > mx) {
+        mx = z[k];
+        best = k;
+      }
+    float s = 0.0f;
+    for (int k = 0; k < d; ++k) s += expf(z[k] - mx);
+    ll[m] = (yy >= 0 && yy < d) ? (z[yy] - mx) - logf(s) : __builtin_nanf("");
+    cor[m] = (best == yy) ? 1 : 0;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
     float s = 0.0f;
     int c = 0;
-    for (int m = 0; m < rows; ++m) {
+    for (int m = threadIdx.x; m < rows; m += 64) {
       s += ll[m];
       c += cor[m];
     }
-    *out = make_float2(s, (float)c);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      s += __shfl_xor(s, off);
+      c += __shfl_xor(c, off);
+    }
+    if (threadIdx.x == 0) *out = make_float2(s, (float)c);
   }
 }
 
@@ -145,35 +203,19 @@ __global__ __launch_bounds__(256) void eval_small_kernel(const float* __restrict
                                                          NetDesc nd, const float* __restrict__ x,
                                                          const int32_t* __restrict__ y, int b,
                                                          float2* __restrict__ partial,
-                                                         EvalLds lo, int ldx, int part_off,
-                                                         int ldp) {
+                                                         EvalLds lo, int tail_vec) {
   extern __shared__ float lds[];
   const int tid = threadIdx.x;
   const int j = blockIdx.x;
   const float* __restrict__ genome = genomes + (int64_t)j * nd.stride;
   const int n0 = nd.w[0];
   const int n1 = nd.w[1];
-  const int n0p = (n0 + 15) & ~15;
-  const int c4 = n0p >> 2;
-
-  // X rows into LDS, zero beyond b and beyond n0
-  for (int idx = tid; idx < 16 * c4; idx += 256) {
-    const int m = idx / c4;
-    const int c = idx - m * c4;
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (m < b && 4 * c < n0) v = reinterpret_cast<const float4*>(x + (int64_t)m * n0)[c];
-    *reinterpret_cast<float4*>(lds + m * ldx + 4 * c) = v;
-  }
-  __syncthreads();
-
   const int wave = tid >> 6;
   const int lane = tid & 63;
   const int mn = lane & 15;
   const int kq = lane >> 4;
-  floatx4 acc[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-
+  const bool xv = mn < b;
+  const float* __restrict__ xrow = x + (int64_t)(xv ? mn : 0) * n0;
   const float* wrow[NT];
   bool rvalid[NT];
 #pragma unroll
@@ -182,16 +224,19 @@ __global__ __launch_bounds__(256) void eval_small_kernel(const float* __restrict
     rvalid[t] = r < n1;
     wrow[t] = genome + nd.woff[0] + (int64_t)(rvalid[t] ? r : 0) * n0;
   }
-  const int nss = n0p >> 4;
+  floatx4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  const int nss = (n0 + 15) >> 4;
   float4 xa, wb[NT];
   auto load = [&](int s, float4& xo, float4* wo) {
     const int k = 16 * s + 4 * kq;
-    xo = *reinterpret_cast<const float4*>(lds + mn * ldx + k);
     const bool kv = k < n0;
+    xo = (xv && kv) ? *reinterpret_cast<const float4*>(xrow + k) : zero4();
 #pragma unroll
     for (int t = 0; t < NT; ++t)
-      wo[t] = (rvalid[t] && kv) ? *reinterpret_cast<const float4*>(wrow[t] + k)
-                                : make_float4(0.f, 0.f, 0.f, 0.f);
+      wo[t] = (rvalid[t] && kv) ? *reinterpret_cast<const float4*>(wrow[t] + k) : zero4();
   };
   int s = wave;
   if (s < nss) load(s, xa, wb);
@@ -205,213 +250,314 @@ __global__ __launch_bounds__(256) void eval_small_kernel(const float* __restrict
       for (int t = 0; t < NT; ++t) wb[t] = wn[t];
     }
   }
-  __syncthreads();  // every wave is done with X in LDS
 
-  // cross-wave reduction of the 4 K-partial tiles, fixed order
-  float* part = lds + part_off;
+  // the 4 K-partial tiles -> LDS [wave][16][ld1], summed in a fixed order
+  // into tile 0, which becomes the layer-1 activations (bias, ReLU, zero
+  // padding columns)
+  const int ld1 = lo.ld1;
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      part[(wave * 16 + 4 * kq + i) * ldp + t * 16 + mn] = acc[t][i];
+    for (int i = 0; i < 4; ++i) lds[(wave * 16 + 4 * kq + i) * ld1 + t * 16 + mn] = acc[t][i];
   __syncthreads();
   const float* __restrict__ b1 = genome + nd.boff[0];
   const bool hidden = nd.L > 1;
-  for (int idx = tid; idx < b * n1; idx += 256) {
-    const int m = idx / n1;
-    const int n = idx - m * n1;
-    float v = part[(0 * 16 + m) * ldp + n] + part[(1 * 16 + m) * ldp + n];
-    v += part[(2 * 16 + m) * ldp + n];
-    v += part[(3 * 16 + m) * ldp + n];
-    v += b1[n];
-    lds[lo.h1 + m * lo.ld1 + n] = hidden ? relu_keep_nan(v) : v;
+  for (int idx = tid; idx < 16 * NT * 16; idx += 256) {
+    const int m = idx / (NT * 16);
+    const int n = idx - m * (NT * 16);
+    float v = 0.0f;
+    if (n < n1) {
+      v = lds[m * ld1 + n] + lds[(16 + m) * ld1 + n];
+      v += lds[(32 + m) * ld1 + n];
+      v += lds[(48 + m) * ld1 + n];
+      v += b1[n];
+      if (hidden) v = relu_keep_nan(v);
+    }
+    lds[m * ld1 + n] = v;
   }
   __syncthreads();
-  tail_fitness(genome, nd, lds, lo, b, 0, y);
-  write_partial(lds, lo, b, partial + j);
+  tail_and_fitness(lds, lo, nd, genome, 1, b, 0, y, tail_vec != 0, partial + j);
 }
 
 // ---------------------------------------------------------------- large b --
-template <int NT>
+template <int NT, int MW>
 __global__ __launch_bounds__(256) void eval_large_kernel(const float* __restrict__ genomes,
                                                          NetDesc nd, const float* __restrict__ x,
                                                          const int32_t* __restrict__ y, int b,
                                                          float2* __restrict__ partial,
-                                                         EvalLds lo, int n_mt) {
+                                                         EvalLds lo, int n_mt, int pop,
+                                                         int tail_vec) {
   extern __shared__ float lds[];
-  constexpr int NR = NT * 16;             // staged weight rows
-  constexpr int WBUF = 4 * NR * 4;        // floats per W staging buffer
-  constexpr int XBUF = 4 * 64 * 4;        // floats per X staging buffer
-  constexpr int WITEMS = NR * 4;          // float4 items of one W chunk
+  constexpr int MT = 64 * MW;              // rows per workgroup
+  constexpr int NR = NT * 16;              // staged weight rows
+  constexpr int WBUF = 8 * NR * 4;         // floats of one W chunk [8][NR][4]
+  constexpr int XBUF = 8 * MT * 4;         // floats of one X chunk [8][MT][4]
+  constexpr int BUF = WBUF + XBUF;
+  constexpr int WITEMS = NR * 8;           // float4 items of a W chunk
   constexpr int WPT = (WITEMS + 255) / 256;
+  constexpr int XPT = MT * 8 / 256;
+
+  // XCD-aware remap: hardware workgroup i runs on XCD i % 8; give each XCD a
+  // contiguous range of (individual, row tile) pairs so one individual's row
+  // tiles share that XCD's L2.
+  const int T = n_mt * pop;
+  const int i = blockIdx.x;
+  const int q = T >> 3;
+  const int r = T & 7;
+  const int xcd = i & 7;
+  const int kk = i >> 3;
+  const int L = xcd < r ? xcd * (q + 1) + kk : r * (q + 1) + (xcd - r) * q + kk;
+  const int j = L / n_mt;
+  const int mt = L - j * n_mt;
+
   const int tid = threadIdx.x;
-  const int mt = blockIdx.x;
-  const int j = blockIdx.y;
-  const int m0 = mt * 64;
-  const int rows = b - m0 < 64 ? b - m0 : 64;
+  const int m0 = mt * MT;
+  const int rows = b - m0 < MT ? b - m0 : MT;
   const float* __restrict__ genome = genomes + (int64_t)j * nd.stride;
   const float* __restrict__ W1 = genome + nd.woff[0];
   const int n0 = nd.w[0];
   const int n1 = nd.w[1];
-  const int nss = (n0 + 15) >> 4;
-  float* wst = lds;                // [2][4][NR][4]
-  float* xst = lds + 2 * WBUF;     // [2][4][64][4]
+  const int nch = (n0 + 31) >> 5;
 
-  float4 wr[WPT];
-  float4 xr;
-  auto gload = [&](int s) {
+  // global -> register prefetch of one 32-wide K chunk; item it covers row
+  // it/8, k = k0 + 4*(it%8); LDS slot [c][row ^ 2c] with c = it%8 keeps both
+  // the stores and the fragment reads free of bank conflicts
+  float4 wr[WPT], xr[XPT];
+  auto gload = [&](int ch) {
+    const int k0 = ch * 32;
 #pragma unroll
-    for (int q = 0; q < WPT; ++q) {
-      const int it = tid + 256 * q;
-      const int r = it >> 2;
-      const int k = 16 * s + 4 * (it & 3);
-      wr[q] = (it < WITEMS && r < n1 && k < n0)
-                  ? *reinterpret_cast<const float4*>(W1 + (int64_t)r * n0 + k)
-                  : make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int qq = 0; qq < WPT; ++qq) {
+      const int it = tid + 256 * qq;
+      const int row = it >> 3;
+      const int k = k0 + 4 * (it & 7);
+      wr[qq] = (it < WITEMS && row < n1 && k < n0)
+                   ? *reinterpret_cast<const float4*>(W1 + (int64_t)row * n0 + k)
+                   : zero4();
     }
-    const int m = tid >> 2;
-    const int k = 16 * s + 4 * (tid & 3);
-    xr = (m < rows && k < n0)
-             ? *reinterpret_cast<const float4*>(x + (int64_t)(m0 + m) * n0 + k)
-             : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int qq = 0; qq < XPT; ++qq) {
+      const int it = tid + 256 * qq;
+      const int m = it >> 3;
+      const int k = k0 + 4 * (it & 7);
+      xr[qq] = (m < rows && k < n0)
+                   ? *reinterpret_cast<const float4*>(x + (int64_t)(m0 + m) * n0 + k)
+                   : zero4();
+    }
   };
   auto sstore = [&](int buf) {
+    float* wst = lds + buf * BUF;
+    float* xst = wst + WBUF;
 #pragma unroll
-    for (int q = 0; q < WPT; ++q) {
-      const int it = tid + 256 * q;
+    for (int qq = 0; qq < WPT; ++qq) {
+      const int it = tid + 256 * qq;
+      const int c = it & 7;
       if (it < WITEMS)
-        *reinterpret_cast<float4*>(wst + buf * WBUF + ((it & 3) * NR + (it >> 2)) * 4) = wr[q];
+        *reinterpret_cast<float4*>(wst + (c * NR + ((it >> 3) ^ (2 * c))) * 4) = wr[qq];
     }
-    *reinterpret_cast<float4*>(xst + buf * XBUF + ((tid & 3) * 64 + (tid >> 2)) * 4) = xr;
+#pragma unroll
+    for (int qq = 0; qq < XPT; ++qq) {
+      const int it = tid + 256 * qq;
+      const int c = it & 7;
+      *reinterpret_cast<float4*>(xst + (c * MT + ((it >> 3) ^ (2 * c))) * 4) = xr[qq];
+    }
   };
 
   const int wave = tid >> 6;
   const int lane = tid & 63;
   const int mn = lane & 15;
   const int kq = lane >> 4;
-  floatx4 acc[NT];
+  floatx4 acc[MW][NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int mi = 0; mi < MW; ++mi)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[mi][t] = floatx4{0.f, 0.f, 0.f, 0.f};
 
   gload(0);
   sstore(0);
   __syncthreads();
-  for (int s = 0; s < nss; ++s) {
-    const int buf = s & 1;
-    if (s + 1 < nss) gload(s + 1);
-    const float4 xa =
-        *reinterpret_cast<const float4*>(xst + buf * XBUF + (kq * 64 + wave * 16 + mn) * 4);
-    float4 wb[NT];
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nch) gload(ch + 1);
+    const float* wst = lds + buf * BUF;
+    const float* xst = wst + WBUF;
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
-      wb[t] = *reinterpret_cast<const float4*>(wst + buf * WBUF + (kq * NR + t * 16 + mn) * 4);
-    mfma_superstep<NT>(xa, wb, acc);
-    if (s + 1 < nss) sstore(buf ^ 1);
+    for (int ss = 0; ss < 2; ++ss) {
+      if (ch * 32 + ss * 16 < n0) {
+        const int c = ss * 4 + kq;
+        float4 xa[MW], wb[NT];
+#pragma unroll
+        for (int mi = 0; mi < MW; ++mi)
+          xa[mi] = *reinterpret_cast<const float4*>(
+              xst + (c * MT + ((wave * MW * 16 + mi * 16 + mn) ^ (2 * c))) * 4);
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          wb[t] = *reinterpret_cast<const float4*>(wst + (c * NR + ((t * 16 + mn) ^ (2 * c))) * 4);
+#pragma unroll
+        for (int mi = 0; mi < MW; ++mi) mfma_superstep<NT>(xa[mi], wb, acc[mi]);
+      }
+    }
+    if (ch + 1 < nch) sstore(buf ^ 1);
     __syncthreads();
   }
 
-  // epilogue: bias + ReLU into the LDS layer-1 tile (staging is dead now)
+  // epilogue: bias + ReLU into the LDS layer-1 tile (staging is dead now);
+  // columns n1 .. NT*16-1 are written as zeros for the next layer's K loop
   const float* __restrict__ b1 = genome + nd.boff[0];
   const bool hidden = nd.L > 1;
+  float* h1 = lds + lo.h1;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int n = t * 16 + mn;
-    if (n < n1) {
-      const float bb = b1[n];
+    const bool nv = n < n1;
+    const float bb = nv ? b1[n] : 0.0f;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int m = wave * 16 + 4 * kq + i;
-        const float v = acc[t][i] + bb;
-        lds[lo.h1 + m * lo.ld1 + n] = hidden ? relu_keep_nan(v) : v;
+    for (int mi = 0; mi < MW; ++mi)
+#pragma unroll
+      for (int i2 = 0; i2 < 4; ++i2) {
+        const int m = wave * MW * 16 + mi * 16 + 4 * kq + i2;
+        float v = acc[mi][t][i2] + bb;
+        if (hidden) v = relu_keep_nan(v);
+        h1[m * lo.ld1 + n] = nv ? v : 0.0f;
       }
-    }
   }
   __syncthreads();
-  tail_fitness(genome, nd, lds, lo, rows, m0, y);
-  write_partial(lds, lo, rows, partial + (int64_t)j * n_mt + mt);
+  tail_and_fitness(lds, lo, nd, genome, MT / 16, rows, m0, y, tail_vec != 0,
+                   partial + (int64_t)j * n_mt + mt);
 }
 
 // -------------------------------------------------------------- dispatch --
 
-static EvalLds tail_layout(const NetDesc& nd, int rows, int base) {
+static int round16(int v) { return (v + 15) & ~15; }
+
+static int tail_width(const NetDesc& nd) {
+  int w = 4;
+  for (int l = 2; l <= nd.L; ++l) w = nd.w[l] > w ? nd.w[l] : w;
+  return round16(w) + 4;
+}
+
+static bool tail_vectorizable(const NetDesc& nd) {
+  for (int l = 1; l < nd.L; ++l)
+    if (nd.w[l] % 4 != 0) return false;
+  return true;
+}
+
+// Tail regions for a tile of `rows` (padded) rows: the layer-1 tile (also
+// the second tail ping-pong buffer), the first tail buffer, per-row results.
+static EvalLds tail_layout(const NetDesc& nd, int rows) {
   EvalLds lo;
-  int ldt = 4;
-  for (int l = 2; l <= nd.L; ++l) ldt = nd.w[l] > ldt ? nd.w[l] : ldt;
-  ldt = ((ldt + 3) & ~3) + 4;
-  const int n1p = ((nd.w[1] + 15) & ~15);
-  lo.ld1 = n1p + 4;
-  lo.h1 = base;
-  lo.buf_a = lo.h1 + rows * lo.ld1;
-  lo.buf_b = lo.buf_a + 16 * ldt;
-  lo.ldt = ldt;
-  lo.ll = lo.buf_b + 16 * ldt;
+  lo.ld1 = round16(nd.w[1]) + 4;
+  lo.ldt = tail_width(nd);
+  const int ldmax = lo.ld1 > lo.ldt ? lo.ld1 : lo.ldt;
+  lo.h1 = 0;
+  lo.ta = rows * ldmax;
+  lo.ll = lo.ta + rows * lo.ldt;
   lo.cor = lo.ll + rows;
   lo.total = lo.cor + rows;
   return lo;
 }
 
-static bool small_fits(const NetDesc& nd, int b) {
-  if (b > 16) return false;
-  const int n0p = (nd.w[0] + 15) & ~15;
-  return 16 * (n0p + 4) * 4 <= 64 * 1024;
+static size_t small_lds_bytes(const NetDesc& nd, EvalLds* out) {
+  EvalLds lo = tail_layout(nd, 16);
+  const int part = 4 * 16 * lo.ld1;  // the four K-partial tiles
+  lo.total = lo.total > part ? lo.total : part;
+  if (out) *out = lo;
+  return (size_t)lo.total * 4;
 }
 
-int eval_mtiles(const NetDesc& nd, int b) { return small_fits(nd, b) ? 1 : (b + 63) / 64; }
+template <int NT, int MW>
+static size_t large_lds_bytes(const NetDesc& nd, EvalLds* out) {
+  EvalLds lo = tail_layout(nd, 64 * MW);
+  const int staging = 2 * (8 * NT * 16 * 4 + 8 * 64 * MW * 4);
+  lo.total = lo.total > staging ? lo.total : staging;
+  if (out) *out = lo;
+  return (size_t)lo.total * 4;
+}
+
+static constexpr size_t kMaxLds = 160 * 1024;
+static constexpr size_t kTwoPerCu = 80 * 1024;
+
+static bool use_small(int b) { return b <= 16; }
+
+template <int NT>
+static int large_mw(const NetDesc& nd, int b) {
+  if (b > 64 && large_lds_bytes<NT, 2>(nd, nullptr) <= kTwoPerCu) return 2;
+  return 1;
+}
+
+template <typename K>
+static hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 64 * 1024) return hipSuccess;
+  if (bytes > kMaxLds) return hipErrorInvalidValue;
+  return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
+template <int NT>
+static int mtiles_nt(const NetDesc& nd, int b) {
+  if (use_small(b)) return 1;
+  const int mt = 64 * large_mw<NT>(nd, b);
+  return (b + mt - 1) / mt;
+}
 
 template <int NT>
 static hipError_t launch_nt(const float* genomes, const NetDesc& nd, int pop, const float* x,
                             const int32_t* y, int b, float2* partial, hipStream_t s) {
-  if (small_fits(nd, b)) {
-    const int n0p = (nd.w[0] + 15) & ~15;
-    const int ldx = n0p + 4;
-    const int ldp = NT * 16 + 4;
-    const int part_off = 0;
-    EvalLds lo = tail_layout(nd, 16, part_off + 4 * 16 * ldp);
-    int total = lo.total > 16 * ldx ? lo.total : 16 * ldx;
-    lo.total = total;
-    const size_t bytes = (size_t)total * 4;
-    if (bytes > 64 * 1024) {
-      const hipError_t e = hipFuncSetAttribute((const void*)eval_small_kernel<NT>,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)bytes);
-      if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(eval_small_kernel<NT>, dim3((unsigned)pop), dim3(256), bytes, s, genomes,
-                       nd, x, y, b, partial, lo, ldx, part_off, ldp);
+  const int tv = tail_vectorizable(nd) ? 1 : 0;
+  EvalLds lo;
+  if (use_small(b)) {
+    const size_t bytes = small_lds_bytes(nd, &lo);
+    hipError_t e = allow_lds(eval_small_kernel<NT>, bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(eval_small_kernel<NT>, dim3((unsigned)pop), dim3(256), bytes, s,
+                       genomes, nd, x, y, b, partial, lo, tv);
+    return hipGetLastError();
+  }
+  const int n_mt = mtiles_nt<NT>(nd, b);
+  if (large_mw<NT>(nd, b) == 2) {
+    const size_t bytes = large_lds_bytes<NT, 2>(nd, &lo);
+    hipError_t e = allow_lds(eval_large_kernel<NT, 2>, bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((eval_large_kernel<NT, 2>), dim3((unsigned)(n_mt * pop)), dim3(256),
+                       bytes, s, genomes, nd, x, y, b, partial, lo, n_mt, pop, tv);
   } else {
-    const int n_mt = (b + 63) / 64;
-    const int staging = 2 * (4 * NT * 16 * 4) + 2 * (4 * 64 * 4);
-    EvalLds lo = tail_layout(nd, 64, 0);
-    lo.total = lo.total > staging ? lo.total : staging;
-    const size_t bytes = (size_t)lo.total * 4;
-    if (bytes > 64 * 1024) {
-      const hipError_t e = hipFuncSetAttribute((const void*)eval_large_kernel<NT>,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)bytes);
-      if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(eval_large_kernel<NT>, dim3((unsigned)n_mt, (unsigned)pop), dim3(256),
-                       bytes, s, genomes, nd, x, y, b, partial, lo, n_mt);
+    const size_t bytes = large_lds_bytes<NT, 1>(nd, &lo);
+    hipError_t e = allow_lds(eval_large_kernel<NT, 1>, bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((eval_large_kernel<NT, 1>), dim3((unsigned)(n_mt * pop)), dim3(256),
+                       bytes, s, genomes, nd, x, y, b, partial, lo, n_mt, pop, tv);
   }
   return hipGetLastError();
 }
 
+#define LEEA_NT_SWITCH(EXPR, DEFAULT)                                               \
+  switch ((nd.w[1] + 15) / 16) {                                                     \
+    case 1: { constexpr int N = 1; return EXPR; }                                   \
+    case 2: { constexpr int N = 2; return EXPR; }                                   \
+    case 3: { constexpr int N = 3; return EXPR; }                                   \
+    case 4: { constexpr int N = 4; return EXPR; }                                   \
+    case 5: { constexpr int N = 5; return EXPR; }                                   \
+    case 6: { constexpr int N = 6; return EXPR; }                                   \
+    case 7: { constexpr int N = 7; return EXPR; }                                   \
+    case 8: { constexpr int N = 8; return EXPR; }                                   \
+    case 9: { constexpr int N = 9; return EXPR; }                                   \
+    case 10: { constexpr int N = 10; return EXPR; }                                 \
+    case 11: { constexpr int N = 11; return EXPR; }                                 \
+    case 12: { constexpr int N = 12; return EXPR; }                                 \
+    case 13: { constexpr int N = 13; return EXPR; }                                 \
+    case 14: { constexpr int N = 14; return EXPR; }                                 \
+    case 15: { constexpr int N = 15; return EXPR; }                                 \
+    case 16: { constexpr int N = 16; return EXPR; }                                 \
+    default: return DEFAULT;                                                        \
+  }
+
+int eval_mtiles(const NetDesc& nd, int b) { LEEA_NT_SWITCH((mtiles_nt<N>(nd, b)), 1) }
+
 hipError_t launch_evaluate(const float* genomes, const NetDesc& nd, int pop, const float* x,
                            const int32_t* y, int b, float2* partial, hipStream_t s) {
-  const int nt = (nd.w[1] + 15) / 16;
-  switch (nt) {
-#define LEEA_NT_CASE(N) \
-  case N:               \
-    return launch_nt<N>(genomes, nd, pop, x, y, b, partial, s);
-    LEEA_NT_CASE(1) LEEA_NT_CASE(2) LEEA_NT_CASE(3) LEEA_NT_CASE(4)
-    LEEA_NT_CASE(5) LEEA_NT_CASE(6) LEEA_NT_CASE(7) LEEA_NT_CASE(8)
-    LEEA_NT_CASE(9) LEEA_NT_CASE(10) LEEA_NT_CASE(11) LEEA_NT_CASE(12)
-    LEEA_NT_CASE(13) LEEA_NT_CASE(14) LEEA_NT_CASE(15) LEEA_NT_CASE(16)
-#undef LEEA_NT_CASE
-    default:
-      return hipErrorInvalidValue;
-  }
+  LEEA_NT_SWITCH((launch_nt<N>(genomes, nd, pop, x, y, b, partial, s)), hipErrorInvalidValue)
 }
+
+#undef LEEA_NT_SWITCH
 
 // Fitness = (sum of per-sample log-likelihoods) / b, accuracy = correct / b,
 // summed over row tiles in order; then the inheritance weighting
