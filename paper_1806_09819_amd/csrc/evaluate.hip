@@ -199,7 +199,7 @@ __device__ void tail_and_fitness(float* lds, const EvalLds& lo, const NetDesc& n
 
 // ---------------------------------------------------------------- small b --
 template <int NT>
-__global__ __launch_bounds__(256) void eval_small_kernel(const float* __restrict__ genomes,
+__global__ __launch_bounds__(256, 4) void eval_small_kernel(const float* __restrict__ genomes,
                                                          NetDesc nd, const float* __restrict__ x,
                                                          const int32_t* __restrict__ y, int b,
                                                          float2* __restrict__ partial,

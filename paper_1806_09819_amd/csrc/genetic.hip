@@ -6,6 +6,17 @@
 
 namespace leea {
 
+typedef float floatv4 __attribute__((ext_vector_type(4)));
+
+// Children are written with non-temporal stores: the next kernel (the
+// evaluation) streams them back once, and dirty lines left in L2 / the
+// memory-side cache would otherwise be written back while it reads,
+// halving its read bandwidth.
+__device__ __forceinline__ void store_stream(float4* p, const float4& v) {
+  floatv4 w = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(w, reinterpret_cast<floatv4*>(p));
+}
+
 // Glorot-uniform weights, zero biases and padding (Algorithm 1, first line;
 // section 4.1).  Thread = 4 consecutive genes = one Philox block.
 __global__ __launch_bounds__(256) void init_kernel(float* __restrict__ genomes, NetDesc nd,
@@ -51,14 +62,19 @@ hipError_t launch_init(float* genomes, const NetDesc& nd, const Glorot& ga, int 
 // t/8, bit 4 (t mod 8) + element.  Mutation: the float4 at gene 4f uses
 // block f of MUTNORM (four normals) and, when not every gene mutates, block
 // f of MUTMASK (four decisions).  Padding genes stay zero.
+// Workgroups are dispatched in blockIdx order; slot j = (y * mul) mod pop
+// (mul coprime to pop) interleaves the compute-heavy mutation children with
+// the bandwidth-bound elites and crossover children instead of running them
+// all at the end.
 template <int kXoKind>
 __global__ __launch_bounds__(256) void vary_kernel(const float* __restrict__ cur,
                                                    float* __restrict__ nxt,
                                                    const int4* __restrict__ plan,
                                                    int64_t stride, int64_t genes, float sigma,
-                                                   uint64_t thr, Key key, uint32_t gen) {
+                                                   uint64_t thr, Key key, uint32_t gen, int pop,
+                                                   uint32_t mul) {
 #pragma clang fp contract(off)
-  const int j = blockIdx.y;
+  const int j = (int)(((uint64_t)blockIdx.y * mul) % (uint32_t)pop);
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int64_t G = (int64_t)blockIdx.x * 4 + wave;
@@ -74,7 +90,7 @@ __global__ __launch_bounds__(256) void vary_kernel(const float* __restrict__ cur
 #pragma unroll 8
     for (int t = 0; t < 32; ++t) {
       const int64_t f = base4 + 64 * t;
-      if (f < n4) d4[f] = a4[f];
+      if (f < n4) store_stream(d4 + f, a4[f]);
     }
   } else if (pl.x == kOpCross) {
     if (kXoKind == 0) {
@@ -91,7 +107,7 @@ __global__ __launch_bounds__(256) void vary_kernel(const float* __restrict__ cur
           o.y = (bits & 2u) ? b.y : a.y;
           o.z = (bits & 4u) ? b.z : a.z;
           o.w = (bits & 8u) ? b.w : a.w;
-          d4[f] = o;
+          store_stream(d4 + f, o);
         }
       }
     } else {
@@ -106,7 +122,7 @@ __global__ __launch_bounds__(256) void vary_kernel(const float* __restrict__ cur
           o.y = (a.y + b.y) * 0.5f;
           o.z = (a.z + b.z) * 0.5f;
           o.w = (a.w + b.w) * 0.5f;
-          d4[f] = o;
+          store_stream(d4 + f, o);
         }
       }
     }
@@ -120,7 +136,7 @@ __global__ __launch_bounds__(256) void vary_kernel(const float* __restrict__ cur
         const float4 a = a4[f];
         const int64_t i0 = 4 * f;
         if (i0 >= genes) {
-          d4[f] = a;
+          store_stream(d4 + f, a);
           continue;
         }
         const float4 z = normals4(draw(key, kMutNorm, gen, (uint32_t)j, (uint32_t)f));
@@ -139,7 +155,7 @@ __global__ __launch_bounds__(256) void vary_kernel(const float* __restrict__ cur
         o.y = m1 ? a.y + n1 : a.y;
         o.z = m2 ? a.z + n2 : a.z;
         o.w = m3 ? a.w + n3 : a.w;
-        d4[f] = o;
+        store_stream(d4 + f, o);
       }
     }
   }
@@ -150,12 +166,24 @@ hipError_t launch_vary(const float* cur, float* nxt, const int4* plan, const Net
                        const Key& key, uint32_t gen, hipStream_t s) {
   const int64_t groups = (nd.stride + 8191) / 8192;
   dim3 grid((unsigned)((groups + 3) / 4), (unsigned)pop);
+  // a multiplier near pop * 0.618 that is coprime to pop
+  uint32_t mul = (uint32_t)(pop * 0.6180339887) | 1u;
+  auto gcd = [](uint32_t a, uint32_t b) {
+    while (b) {
+      const uint32_t t = a % b;
+      a = b;
+      b = t;
+    }
+    return a;
+  };
+  while (pop > 1 && gcd(mul, (uint32_t)pop) != 1u) ++mul;
+  if (pop == 1) mul = 1;
   if (crossover == 0)
     hipLaunchKernelGGL(vary_kernel<0>, grid, dim3(256), 0, s, cur, nxt, plan, nd.stride,
-                       nd.genes, sigma, mut_threshold, key, gen);
+                       nd.genes, sigma, mut_threshold, key, gen, pop, mul);
   else
     hipLaunchKernelGGL(vary_kernel<1>, grid, dim3(256), 0, s, cur, nxt, plan, nd.stride,
-                       nd.genes, sigma, mut_threshold, key, gen);
+                       nd.genes, sigma, mut_threshold, key, gen, pop, mul);
   return hipGetLastError();
 }
 
