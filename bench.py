@@ -63,6 +63,26 @@ def vary_bytes(params, genes):
     return 4.0 * genes * (2 * n_e + 3 * n_c + 2 * n_m)
 
 
+def measured_traffic(workload_tag):
+    """HBM bytes per launch of the evaluate kernel from the committed
+    rocprofv3 counter summary, or None when the kernel source has changed
+    since the counters were taken (or no record exists)."""
+    import hashlib
+    path = os.path.join(HERE, "profiles", "pmc_traffic_evaluate.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if not line.startswith("{"):
+            continue
+        rec = json.loads(line)
+        if rec.get("workload") != workload_tag:
+            continue
+        src = os.path.join(HERE, rec["source"])
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        return float(rec["hbm_bytes_per_launch"]) if sha == rec["source_sha256"] else None
+    return None
+
+
 def run_gpu(params, steps, warmup, x_train, y_train, timed_events=True):
     import torch
     from paper_1806_09819_amd import leea as B
@@ -219,7 +239,7 @@ def main():
         achieved = nbytes / eval_s / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK / 1e9, unit="GB/s",
                     frac=achieved / (HBM_PEAK / 1e9))
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic("paper_b%d" % b)
     roof["kernel"] = "evaluate (fused forward + fitness, one launch per generation)"
     roof["per_launch"] = dict(flops=flops, bytes=nbytes, avg_ms=r["phases_ms"]["evaluate"])
     vb = vary_bytes(params, r["genes"])
