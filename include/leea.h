@@ -70,6 +70,12 @@ typedef enum {
 enum { LEEA_SEL_TRUNCATION = 0, LEEA_SEL_TOURNAMENT = 1 };
 enum { LEEA_XO_UNIFORM = 0, LEEA_XO_ARITHMETIC = 1 };
 enum { LEEA_OP_ELITE = 0, LEEA_OP_CROSSOVER = 1, LEEA_OP_MUTATION = 2 };
+/* Mutation-strength control (section 3.2): constant; exponential decay
+ * sigma_i = sigma * 0.99^(i/k) for the mutation that creates generation i
+ * (computed on the host in double precision, rounded once to float); or
+ * self-adaptive, where every individual carries a sigma gene (see
+ * leea_crossover_mutate). */
+enum { LEEA_SIGMA_CONSTANT = 0, LEEA_SIGMA_DECAY = 1, LEEA_SIGMA_SELF_ADAPTIVE = 2 };
 
 /* Hyperparameters of one EA run.  Counts are integers: the caller rounds
  * the paper's fractions p_E*lambda, p_C*lambda, p_M*lambda and rho*lambda
@@ -92,6 +98,11 @@ typedef struct {
   uint64_t seed;                          /* Philox key */
   uint32_t run;                           /* run index in the Philox counter */
   int32_t max_batch;                      /* largest b passed to evaluate/step, 1..LEEA_MAX_BATCH */
+  int32_t sigma_mode;                     /* LEEA_SIGMA_* */
+  float sigma_decay_k;                    /* k > 0 of the decay schedule */
+  float tau;                              /* self-adaptation rate in [0, 10]; 0 = 1/sqrt(genes) */
+  int32_t input_pool;                     /* 0, or 2: draw_batch max-pools 2x2 from square images
+                                             of 4*widths[0] pixels (section 4.1) */
 } leea_config;
 
 /* Genes per network (c) and the padded per-individual stride in floats. */
@@ -108,8 +119,10 @@ leea_status leea_init_population(const leea_config* cfg, void* workspace, size_t
                                  void* hip_stream, leea_ctx** out);
 
 /* Draw generation gen's minibatch (Algorithm 1, "select random batch"): b
- * examples with replacement from x_train [n_train][widths[0]] / y_train
- * [n_train] (device) into x_out [b][widths[0]] / y_out [b] (device).
+ * examples with replacement from x_train [n_train][row] / y_train
+ * [n_train] (device) into x_out [b][widths[0]] / y_out [b] (device), where
+ * row = widths[0], or 4*widths[0] pixels of a square image that is 2x2
+ * max-pooled on the way when input_pool = 2 (NaN if any pooled pixel is NaN).
  * Example k is index floor(w * n_train / 2^32), w = word k&3 of Philox block
  * (BATCH, gen, slot 0, k>>2).  Valid in any state. */
 leea_status leea_draw_batch(leea_ctx* ctx, uint32_t gen, const float* x_train,
@@ -144,17 +157,28 @@ leea_status leea_select(leea_ctx* ctx, int32_t* plan_out, float* f_inh_out,
 
 /* Build the next population from the plan (Algorithm 1, crossover / mutation
  * / union): elites copied, crossover children not mutated, mutants get
- * theta + sigma*N(0,1) on each gene selected by mut_threshold.  Advances the
- * generation counter.  Requires a preceding select. */
+ * theta + sigma*N(0,1) on each gene selected by mut_threshold.  With
+ * self-adaptive sigma (section 3.2) elites keep their sigma gene, crossover
+ * children take the parents' mean fl(fl(s1+s2)*0.5), and mutants take
+ * fl(s * exp(fl(tau*z))) (z = first normal of Philox block (SIGMA, gen,
+ * slot, 0), exp the library's float32 exp) and are mutated with that new
+ * sigma.  Advances the generation counter.  Requires a preceding select. */
 leea_status leea_crossover_mutate(leea_ctx* ctx);
 
 /* select -> crossover_mutate -> evaluate, one generation. */
 leea_status leea_step(leea_ctx* ctx, const float* x, const int32_t* y, int32_t b,
                       float* f_adj, float* f_raw, float* acc);
 
-/* Mutation strength for the following crossover_mutate calls (for sigma
- * schedules such as the exponential decay of section 3.2). */
+/* Base mutation strength for the following crossover_mutate calls; with
+ * self-adaptive sigma it resets every individual's sigma gene to sigma. */
 leea_status leea_set_sigma(leea_ctx* ctx, float sigma);
+
+/* Self-adaptive sigma genes of the current population (device [pop],
+ * borrowed, valid until the next crossover_mutate); NULL in other modes. */
+leea_status leea_sigmas(leea_ctx* ctx, float** sigmas);
+
+/* Replace the sigma genes (device [pop]); LEEA_ESTATE unless self-adaptive. */
+leea_status leea_set_sigmas(leea_ctx* ctx, const float* sigmas);
 
 /* Current generation index (0 after init). */
 leea_status leea_generation(const leea_ctx* ctx, uint32_t* gen);
@@ -179,6 +203,11 @@ leea_status leea_load(leea_ctx* ctx, const void* host_buf, size_t bytes);
 
 const char* leea_last_error(const leea_ctx* ctx);
 void leea_destroy(leea_ctx* ctx);
+
+/* 2x2 max-pooling (section 4.1) of n square side x side images x [n][side*side]
+ * (device) into out [n][(side/2)^2] (device); side even.  NaN if any pooled
+ * pixel is NaN.  Enqueues on hip_stream. */
+leea_status leea_pool2x2(const float* x, int64_t n, int32_t side, float* out, void* hip_stream);
 
 /* ---- generator entry points (bit-exactness checks of the random streams) ----
  * Each enqueues on hip_stream and returns without synchronising. */

@@ -34,7 +34,7 @@ import math
 import numpy as np
 
 from . import philox
-from .normal32 import normals4
+from .normal32 import exp32, normal_pair, normals4
 
 F32 = np.float32
 
@@ -58,6 +58,10 @@ class Config:
     sigma: float = 0.001
     p_gene: float = 1.0           # per-gene mutation probability (1 = paper)
     alpha: float = 1.0            # fitness-inheritance weight (1 = off)
+    sigma_mode: str = "constant"  # "constant", "decay" or "self_adaptive" (section 3.2)
+    sigma_decay_k: float = 1.0    # k of sigma_i = sigma * 0.99**(i/k)
+    tau: float = 0.0              # self-adaptation rate (0 -> 1/sqrt(c))
+    pool: int = 0                 # 2: 2x2 max-pool of square image inputs (section 4.1)
     seed: int = 0
     run: int = 0
     extra: dict = field(default_factory=dict)
@@ -385,6 +389,62 @@ def _child(pop, ops, p1, p2, cfg, gen, sigma, threshold, j, c):
     mutated, z = mutation_parts(cfg.seed, gen, j, c, threshold, cfg.run)
     noise = sigma * z
     return np.where(mutated, a + noise, a)
+
+
+# ------------------------------------------------------------ sigma ---
+
+def sigma_decay(sigma, gen, k):
+    """Exponentially decaying mutation strength sigma_i = sigma * 0.99**(i/k)
+    (section 3.2) for the mutation that creates generation ``gen``; float64
+    power, rounded once to float32."""
+    return F32(float(sigma) * math.pow(0.99, gen / float(k)))
+
+
+def default_tau(widths):
+    """Self-adaptation rate when none is given: 1/sqrt(c), c = genes."""
+    return 1.0 / math.sqrt(param_count(widths))
+
+
+def child_sigmas(sig, ops, p1, p2, cfg, gen):
+    """Per-individual sigma genes of the next population (section 3.2,
+    self-adaptive control): elites keep theirs; crossover children take the
+    mean fl(fl(s1 + s2) * 0.5); mutants take fl(s * exp32(fl(tau * z))) with z
+    the first normal of the pair from block (SIGMA, gen, slot, 0)."""
+    tau = F32(cfg.tau if cfg.tau > 0 else default_tau(cfg.widths))
+    sig = np.asarray(sig, dtype=F32)
+    out = np.empty(len(ops), dtype=F32)
+    for j in range(len(ops)):
+        if ops[j] == ELITE:
+            out[j] = sig[p1[j]]
+        elif ops[j] == CROSS:
+            out[j] = (sig[p1[j]] + sig[p2[j]]) * F32(0.5)
+        else:
+            w = philox.draw(cfg.seed, philox.SIGMA, gen, j, 0, cfg.run)
+            z, _ = normal_pair(w[0], w[1])
+            out[j] = sig[p1[j]] * exp32(tau * F32(z))
+    return out
+
+
+def vary_adaptive(pop, sig_new, ops, p1, p2, cfg, gen, slots=None):
+    """vary() where each mutant uses its own (already adapted) sigma gene."""
+    threshold = mutation_threshold(cfg.p_gene)
+    P, c = pop.shape
+    slots = range(len(ops)) if slots is None else list(slots)
+    out = np.empty((len(slots), c), dtype=pop.dtype)
+    for row, j in enumerate(slots):
+        out[row] = _child(pop, ops, p1, p2, cfg, gen, F32(sig_new[j]), threshold, j, c)
+    return out
+
+
+# ----------------------------------------------------------- pooling ---
+
+def pool2x2(x, side):
+    """2x2 max-pooling of square images x [n][side*side] -> [n][(side/2)**2]
+    (section 4.1: the network max-pools its 28x28 inputs first)."""
+    x = np.asarray(x)
+    n = x.shape[0]
+    h = side // 2
+    return x.reshape(n, h, 2, h, 2).max(axis=(2, 4)).reshape(n, h * h)
 
 
 # ----------------------------------------------------------------- batch ---

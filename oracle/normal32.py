@@ -76,6 +76,9 @@ SIN_C = {2 * n + 1: f32_nearest(Fraction((-1) ** n, factorial(2 * n + 1)))
 COS_C = {2 * n: f32_nearest(Fraction((-1) ** n, factorial(2 * n)))
          for n in range(1, 7)}                     # x^2 .. x^12
 TWO_M24 = F32(2.0 ** -24)
+INV_LN2 = f32_nearest(1 / _LN2)
+# Taylor coefficients 1/n! for exp, n = 2..7
+EXP_C = {n: f32_nearest(Fraction(1, factorial(n))) for n in range(2, 8)}
 
 
 def ln32(u):
@@ -161,3 +164,31 @@ def normals4(words):
     z0, z1 = normal_pair(words[..., 0], words[..., 1])
     z2, z3 = normal_pair(words[..., 2], words[..., 3])
     return np.stack([z0, z1, z2, z3], axis=-1)
+
+
+def exp32(x):
+    """e**x for float32 ``x`` with |x| <= 80, float32 ops (self-adaptive sigma).
+
+    n = rint(x / ln 2) (ties to even), r = (x - n*LN2_HI) - n*LN2_LO (the same
+    two-part ln 2 as ln32, n*LN2_HI exact), e**r by its Taylor series to r^7
+    (|r| <= 0.35), then an exact scaling by 2**n built from the exponent bits.
+    """
+    x = np.asarray(x, dtype=F32)
+    if np.any(np.abs(x) > F32(80.0)):
+        raise ValueError("exp32 domain is |x| <= 80")
+    t = x * INV_LN2
+    n = np.rint(t).astype(F32)
+    hi = n * LN2_HI
+    r = x - hi
+    lo = n * LN2_LO
+    r = r - lo
+    p = EXP_C[7]
+    for k in (6, 5, 4, 3, 2):
+        p = p * r
+        p = p + EXP_C[k]
+    p = p * r
+    p = p + F32(1.0)
+    p = p * r
+    p = p + F32(1.0)
+    scale = ((n.astype(np.int32) + np.int32(127)).astype(np.uint32) << np.uint32(23)).view(F32)
+    return (p * scale).astype(F32)

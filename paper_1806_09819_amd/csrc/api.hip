@@ -1,6 +1,7 @@
 // C ABI of libleea.so: argument validation, workspace carving, the call-order
 // state machine of Algorithm 1 and kernel sequencing.  Declarations and the
 // contract of every entry point are in include/leea.h.
+#include <math.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -19,7 +20,7 @@ enum State { kNeedEval = 0, kEvaluated = 1, kSelected = 2 };
 thread_local std::string g_err;
 
 constexpr uint32_t kStateMagic = 0x4C454541u;  // checkpoint tag
-constexpr uint32_t kStateVersion = 1u;
+constexpr uint32_t kStateVersion = 2u;
 
 }  // namespace
 
@@ -37,7 +38,10 @@ struct leea_ctx {
   int4* plan;
   int32_t* order;
   float2* partial;
+  float* sig[2];   // self-adaptive sigma genes (ping-pong with the genomes)
   int n_mt_max;
+  int side;        // input image side when draw_batch pools 2x2, else 0
+  float tau;       // effective self-adaptation rate
   uint32_t gen;
   int state;
   int has_inh;
@@ -104,6 +108,22 @@ leea_status validate(const leea_config* cfg, NetDesc* nd) {
   for (int l = 0; l < L; ++l)
     if (!(cfg->glorot_a[l] >= 0.0f) || cfg->glorot_a[l] == __builtin_inff())
       return fail(nullptr, LEEA_EINVAL, "glorot_a must be finite and >= 0");
+  if (cfg->sigma_mode < LEEA_SIGMA_CONSTANT || cfg->sigma_mode > LEEA_SIGMA_SELF_ADAPTIVE)
+    return fail(nullptr, LEEA_EINVAL, "unknown sigma_mode");
+  if (cfg->sigma_mode == LEEA_SIGMA_DECAY &&
+      !(cfg->sigma_decay_k > 0.0f && cfg->sigma_decay_k < __builtin_inff()))
+    return fail(nullptr, LEEA_EINVAL, "sigma_decay_k must be positive and finite");
+  if (!(cfg->tau >= 0.0f && cfg->tau <= 10.0f))
+    return fail(nullptr, LEEA_EINVAL, "tau must be in [0, 10]");
+  if (cfg->input_pool != 0 && cfg->input_pool != 2)
+    return fail(nullptr, LEEA_EINVAL, "input_pool must be 0 or 2");
+  if (cfg->input_pool == 2) {
+    const int64_t raw = 4ll * cfg->widths[0];
+    int64_t side = (int64_t)sqrt((double)raw);
+    while (side * side < raw) ++side;
+    if (side * side != raw || side % 2 != 0)
+      return fail(nullptr, LEEA_EINVAL, "input_pool needs 4*widths[0] to be an even square");
+  }
   NetDesc d;
   memset(&d, 0, sizeof d);
   d.L = L;
@@ -140,7 +160,7 @@ Carve carve(const leea_config* cfg, const NetDesc& nd) {
   c.plan = align256(P * 16);
   c.order = align256(P * 4);
   c.partial = align256(P * (size_t)n_mt * 8);
-  c.total = 2 * c.genomes + 5 * c.scalars + c.plan + c.order + c.partial;
+  c.total = 2 * c.genomes + 7 * c.scalars + c.plan + c.order + c.partial;
   return c;
 }
 
@@ -232,7 +252,18 @@ leea_status leea_init_population(const leea_config* cfg, void* workspace, size_t
   c->order = (int32_t*)p;
   p += cv.order;
   c->partial = (float2*)p;
+  p += cv.partial;
+  c->sig[0] = (float*)p;
+  p += cv.scalars;
+  c->sig[1] = (float*)p;
   c->n_mt_max = (cfg->max_batch + 63) / 64;
+  c->side = 0;
+  if (cfg->input_pool == 2) {
+    int side = 2;
+    while ((int64_t)side * side < 4ll * cfg->widths[0]) side += 2;
+    c->side = side;
+  }
+  c->tau = cfg->tau > 0.0f ? cfg->tau : (float)(1.0 / sqrt((double)nd.genes));
   c->cur = 0;
   c->gen = 0;
   c->state = kNeedEval;
@@ -242,6 +273,8 @@ leea_status leea_init_population(const leea_config* cfg, void* workspace, size_t
   for (int l = 0; l < LEEA_MAX_LAYERS; ++l) ga.a[l] = l < nd.L ? cfg->glorot_a[l] : 0.0f;
   st = dev(nullptr, launch_init(c->genomes[0], nd, ga, cfg->pop, key_of(c), c->stream),
            "init launch");
+  if (!st && cfg->sigma_mode == LEEA_SIGMA_SELF_ADAPTIVE)
+    st = dev(nullptr, launch_fill(c->sig[0], cfg->pop, cfg->sigma, c->stream), "sigma fill");
   if (st) {
     delete c;
     return st;
@@ -260,8 +293,8 @@ leea_status leea_draw_batch(leea_ctx* c, uint32_t gen, const float* x_train,
     return fail(c, LEEA_EINVAL, "x arrays must be 16-byte aligned");
   if (n_train < 1 || n_train > 0xFFFFFFFFll) return fail(c, LEEA_EINVAL, "n_train out of range");
   if (b < 1 || b > LEEA_MAX_BATCH) return fail(c, LEEA_EINVAL, "b out of range");
-  return dev(c, launch_draw_batch(x_train, y_train, n_train, c->nd.w[0], b, x_out, y_out,
-                                  key_of(c), gen, c->stream),
+  return dev(c, launch_draw_batch(x_train, y_train, n_train, c->nd.w[0], c->side, b, x_out,
+                                  y_out, key_of(c), gen, c->stream),
              "draw_batch launch");
 }
 
@@ -314,10 +347,16 @@ leea_status leea_crossover_mutate(leea_ctx* c) {
   if (!c) return fail(nullptr, LEEA_EINVAL, "ctx is NULL");
   if (c->state != kSelected) return fail(c, LEEA_ESTATE, "crossover_mutate needs a select first");
   const int nxt = c->cur ^ 1;
+  const uint32_t g = c->gen + 1;
+  float sigma = c->sigma;
+  const bool adaptive = c->cfg.sigma_mode == LEEA_SIGMA_SELF_ADAPTIVE;
+  if (c->cfg.sigma_mode == LEEA_SIGMA_DECAY)
+    sigma = (float)((double)c->sigma * pow(0.99, (double)g / (double)c->cfg.sigma_decay_k));
   leea_status st = dev(c,
                        launch_vary(c->genomes[c->cur], c->genomes[nxt], c->plan, c->nd, c->cfg.pop,
-                                   c->cfg.crossover, c->sigma, c->cfg.mut_threshold, key_of(c),
-                                   c->gen + 1, c->stream),
+                                   c->cfg.crossover, sigma, c->cfg.mut_threshold, key_of(c), g,
+                                   adaptive ? c->sig[c->cur] : nullptr,
+                                   adaptive ? c->sig[nxt] : nullptr, c->tau, c->stream),
                        "vary launch");
   if (st) return st;
   c->cur = nxt;
@@ -348,7 +387,23 @@ leea_status leea_set_sigma(leea_ctx* c, float sigma) {
   if (!(sigma >= 0.0f) || sigma == __builtin_inff())
     return fail(c, LEEA_EINVAL, "sigma must be finite and >= 0");
   c->sigma = sigma;
+  if (c->cfg.sigma_mode == LEEA_SIGMA_SELF_ADAPTIVE)
+    return dev(c, launch_fill(c->sig[c->cur], c->cfg.pop, sigma, c->stream), "sigma fill");
   return LEEA_OK;
+}
+
+leea_status leea_sigmas(leea_ctx* c, float** sigmas) {
+  if (!c || !sigmas) return fail(nullptr, LEEA_EINVAL, "NULL argument");
+  *sigmas = c->cfg.sigma_mode == LEEA_SIGMA_SELF_ADAPTIVE ? c->sig[c->cur] : nullptr;
+  return LEEA_OK;
+}
+
+leea_status leea_set_sigmas(leea_ctx* c, const float* sigmas) {
+  if (!c || !sigmas) return fail(nullptr, LEEA_EINVAL, "NULL argument");
+  if (c->cfg.sigma_mode != LEEA_SIGMA_SELF_ADAPTIVE)
+    return fail(c, LEEA_ESTATE, "sigma genes exist only with self-adaptive sigma");
+  return dev(c, hipMemcpyAsync(c->sig[c->cur], sigmas, (size_t)c->cfg.pop * 4,
+                               hipMemcpyDeviceToDevice, c->stream), "sigma copy");
 }
 
 leea_status leea_generation(const leea_ctx* c, uint32_t* gen) {
@@ -397,7 +452,7 @@ struct CkptHeader {
 
 leea_status leea_state_bytes(const leea_ctx* c, size_t* bytes) {
   if (!c || !bytes) return fail(nullptr, LEEA_EINVAL, "NULL argument");
-  *bytes = sizeof(CkptHeader) + (size_t)c->cfg.pop * c->nd.stride * 4 + 4 * (size_t)c->cfg.pop * 4;
+  *bytes = sizeof(CkptHeader) + (size_t)c->cfg.pop * c->nd.stride * 4 + 5 * (size_t)c->cfg.pop * 4;
   return LEEA_OK;
 }
 
@@ -424,8 +479,8 @@ leea_status leea_save(leea_ctx* c, void* host_buf, size_t bytes) {
   leea_status st = dev(c, hipStreamSynchronize(c->stream), "sync before save");
   if (!st) st = dev(c, hipMemcpy(p, c->genomes[c->cur], gbytes, hipMemcpyDeviceToHost), "save");
   p += gbytes;
-  const float* arr[4] = {c->f_adj, c->f_raw, c->acc, c->f_inh};
-  for (int i = 0; i < 4 && !st; ++i) {
+  const float* arr[5] = {c->f_adj, c->f_raw, c->acc, c->f_inh, c->sig[c->cur]};
+  for (int i = 0; i < 5 && !st; ++i) {
     st = dev(c, hipMemcpy(p, arr[i], sbytes, hipMemcpyDeviceToHost), "save");
     p += sbytes;
   }
@@ -450,8 +505,8 @@ leea_status leea_load(leea_ctx* c, const void* host_buf, size_t bytes) {
   leea_status st = dev(c, hipStreamSynchronize(c->stream), "sync before load");
   if (!st) st = dev(c, hipMemcpy(c->genomes[c->cur], p, gbytes, hipMemcpyHostToDevice), "load");
   p += gbytes;
-  float* arr[4] = {c->f_adj, c->f_raw, c->acc, c->f_inh};
-  for (int i = 0; i < 4 && !st; ++i) {
+  float* arr[5] = {c->f_adj, c->f_raw, c->acc, c->f_inh, c->sig[c->cur]};
+  for (int i = 0; i < 5 && !st; ++i) {
     st = dev(c, hipMemcpy(arr[i], p, sbytes, hipMemcpyHostToDevice), "load");
     p += sbytes;
   }
@@ -467,6 +522,13 @@ leea_status leea_load(leea_ctx* c, const void* host_buf, size_t bytes) {
 const char* leea_last_error(const leea_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
 
 void leea_destroy(leea_ctx* c) { delete c; }
+
+leea_status leea_pool2x2(const float* x, int64_t n, int32_t side, float* out, void* hip_stream) {
+  if (!x || !out || n < 0 || side < 2 || side % 2 != 0 || side > 4096)
+    return fail(nullptr, LEEA_EINVAL, "bad arguments");
+  if (n == 0) return LEEA_OK;
+  return dev(nullptr, launch_pool2x2(x, n, side, out, (hipStream_t)hip_stream), "pool2x2");
+}
 
 leea_status leea_rng_philox(const uint32_t* ctr, uint64_t key, uint32_t* out, int64_t n,
                             void* hip_stream) {

@@ -183,6 +183,35 @@ __device__ __forceinline__ float4 normals4(uint4 w) {
   return z;
 }
 
+// e^x for |x| <= 80: n = rint(x / ln 2), r = (x - n*ln2_hi) - n*ln2_lo,
+// Taylor series of e^r to r^7, exact scaling by 2^n from the exponent bits.
+__device__ __forceinline__ float exp32(float x) {
+#pragma clang fp contract(off)
+  const float t = x * 1.44269504088896340736f;  // nearest float32 to 1/ln 2
+  const float n = __builtin_rintf(t);
+  const float hi = n * (45426.0f / 65536.0f);
+  float r = x - hi;
+  const float lo = n * 1.42860682030941723212e-6f;
+  r = r - lo;
+  float p = 1.0f / 5040.0f;
+  p = p * r;
+  p = p + 1.0f / 720.0f;
+  p = p * r;
+  p = p + 1.0f / 120.0f;
+  p = p * r;
+  p = p + 1.0f / 24.0f;
+  p = p * r;
+  p = p + 1.0f / 6.0f;
+  p = p * r;
+  p = p + 0.5f;
+  p = p * r;
+  p = p + 1.0f;
+  p = p * r;
+  p = p + 1.0f;
+  const float scale = __uint_as_float((uint32_t)((int)n + 127) << 23);
+  return p * scale;
+}
+
 __device__ __forceinline__ float f4get(const float4& v, int i) {
   return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
 }

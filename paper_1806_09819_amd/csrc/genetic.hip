@@ -66,13 +66,19 @@ hipError_t launch_init(float* genomes, const NetDesc& nd, const Glorot& ga, int 
 // (mul coprime to pop) interleaves the compute-heavy mutation children with
 // the bandwidth-bound elites and crossover children instead of running them
 // all at the end.
+// Self-adaptive mutation strength (sig_cur != NULL): every individual
+// carries a sigma gene.  Elites keep theirs, crossover children take the
+// parents' mean, mutants take sigma * exp(tau * z) with z the first normal
+// of block (SIGMA, gen, slot, 0), and are then mutated with that new sigma.
+// Every workgroup of a slot computes the same value; the first writes it.
 template <int kXoKind>
 __global__ __launch_bounds__(256) void vary_kernel(const float* __restrict__ cur,
                                                    float* __restrict__ nxt,
                                                    const int4* __restrict__ plan,
                                                    int64_t stride, int64_t genes, float sigma,
                                                    uint64_t thr, Key key, uint32_t gen, int pop,
-                                                   uint32_t mul) {
+                                                   uint32_t mul, const float* __restrict__ sig_cur,
+                                                   float* __restrict__ sig_next, float tau) {
 #pragma clang fp contract(off)
   const int j = (int)(((uint64_t)blockIdx.y * mul) % (uint32_t)pop);
   const int wave = threadIdx.x >> 6;
@@ -80,8 +86,25 @@ __global__ __launch_bounds__(256) void vary_kernel(const float* __restrict__ cur
   const int64_t G = (int64_t)blockIdx.x * 4 + wave;
   const int64_t n4 = stride >> 2;
   const int64_t base4 = G * 2048 + lane;
-  if (G * 2048 >= n4) return;
   const int4 pl = plan[j];
+  if (sig_cur) {
+    float sc;
+    if (pl.x == kOpElite) {
+      sc = sig_cur[pl.y];
+    } else if (pl.x == kOpCross) {
+      const float sum = sig_cur[pl.y] + sig_cur[pl.z];
+      sc = sum * 0.5f;
+    } else {
+      const uint4 w = draw(key, kSigma, gen, (uint32_t)j, 0u);
+      float z0, z1;
+      normal_pair(w.x, w.y, z0, z1);
+      const float t = tau * z0;
+      sc = sig_cur[pl.y] * exp32(t);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) sig_next[j] = sc;
+    sigma = sc;
+  }
+  if (G * 2048 >= n4) return;
   const float4* __restrict__ a4 = reinterpret_cast<const float4*>(cur + (int64_t)pl.y * stride);
   const float4* __restrict__ b4 = reinterpret_cast<const float4*>(cur + (int64_t)pl.z * stride);
   float4* __restrict__ d4 = reinterpret_cast<float4*>(nxt + (int64_t)j * stride);
@@ -163,7 +186,8 @@ __global__ __launch_bounds__(256) void vary_kernel(const float* __restrict__ cur
 
 hipError_t launch_vary(const float* cur, float* nxt, const int4* plan, const NetDesc& nd,
                        int pop, int crossover, float sigma, uint64_t mut_threshold,
-                       const Key& key, uint32_t gen, hipStream_t s) {
+                       const Key& key, uint32_t gen, const float* sig_cur, float* sig_next,
+                       float tau, hipStream_t s) {
   const int64_t groups = (nd.stride + 8191) / 8192;
   dim3 grid((unsigned)((groups + 3) / 4), (unsigned)pop);
   // a multiplier near pop * 0.618 that is coprime to pop
@@ -180,36 +204,91 @@ hipError_t launch_vary(const float* cur, float* nxt, const int4* plan, const Net
   if (pop == 1) mul = 1;
   if (crossover == 0)
     hipLaunchKernelGGL(vary_kernel<0>, grid, dim3(256), 0, s, cur, nxt, plan, nd.stride,
-                       nd.genes, sigma, mut_threshold, key, gen, pop, mul);
+                       nd.genes, sigma, mut_threshold, key, gen, pop, mul, sig_cur, sig_next, tau);
   else
     hipLaunchKernelGGL(vary_kernel<1>, grid, dim3(256), 0, s, cur, nxt, plan, nd.stride,
-                       nd.genes, sigma, mut_threshold, key, gen, pop, mul);
+                       nd.genes, sigma, mut_threshold, key, gen, pop, mul, sig_cur, sig_next, tau);
   return hipGetLastError();
+}
+
+// Max of a 2x2 block; NaN if any of the four is NaN.
+__device__ __forceinline__ float max4_nan(float a, float b, float c, float d) {
+  float m = a > b ? a : b;
+  m = m > c ? m : c;
+  m = m > d ? m : d;
+  if (a != a || b != b || c != c || d != d) m = __builtin_nanf("");
+  return m;
 }
 
 // Example k of the batch is row floor(w * n_train / 2^32) of the training
 // set, w = word k&3 of block (BATCH, gen, slot 0, k>>2).  One workgroup
-// copies one row (float4 granularity; n_in is a multiple of 4).
+// copies one row (float4 granularity; n_in is a multiple of 4).  With
+// side > 0 the rows are side x side images that are 2x2 max-pooled on the
+// way (section 4.1: the network pools its 28x28 inputs first).
 __global__ __launch_bounds__(256) void draw_batch_kernel(const float* __restrict__ x_train,
                                                          const int32_t* __restrict__ y_train,
-                                                         int64_t n_train, int n_in,
+                                                         int64_t n_train, int n_in, int side,
                                                          float* __restrict__ x_out,
                                                          int32_t* __restrict__ y_out, Key key,
                                                          uint32_t gen) {
   const int k = blockIdx.x;
   const uint4 w = draw(key, kBatch, gen, 0u, (uint32_t)(k >> 2));
   const uint64_t idx = ((uint64_t)word_of(w, k & 3) * (uint64_t)n_train) >> 32;
-  const float4* src = reinterpret_cast<const float4*>(x_train + (int64_t)idx * n_in);
-  float4* dst = reinterpret_cast<float4*>(x_out + (int64_t)k * n_in);
-  for (int c = threadIdx.x; c < (n_in >> 2); c += 256) dst[c] = src[c];
+  if (side == 0) {
+    const float4* src = reinterpret_cast<const float4*>(x_train + (int64_t)idx * n_in);
+    float4* dst = reinterpret_cast<float4*>(x_out + (int64_t)k * n_in);
+    for (int c = threadIdx.x; c < (n_in >> 2); c += 256) dst[c] = src[c];
+  } else {
+    const float* src = x_train + (int64_t)idx * side * side;
+    const int h = side >> 1;
+    for (int p = threadIdx.x; p < h * h; p += 256) {
+      const int r = p / h;
+      const int c = p - r * h;
+      const float* q = src + 2 * r * side + 2 * c;
+      x_out[(int64_t)k * n_in + p] = max4_nan(q[0], q[1], q[side], q[side + 1]);
+    }
+  }
   if (threadIdx.x == 0) y_out[k] = y_train[idx];
 }
 
 hipError_t launch_draw_batch(const float* x_train, const int32_t* y_train, int64_t n_train,
-                             int n_in, int b, float* x_out, int32_t* y_out, const Key& key,
-                             uint32_t gen, hipStream_t s) {
+                             int n_in, int side, int b, float* x_out, int32_t* y_out,
+                             const Key& key, uint32_t gen, hipStream_t s) {
   hipLaunchKernelGGL(draw_batch_kernel, dim3((unsigned)b), dim3(256), 0, s, x_train, y_train,
-                     n_train, n_in, x_out, y_out, key, gen);
+                     n_train, n_in, side, x_out, y_out, key, gen);
+  return hipGetLastError();
+}
+
+__global__ void pool2x2_kernel(const float* __restrict__ x, int64_t n, int side,
+                               float* __restrict__ out) {
+  const int h = side >> 1;
+  const int64_t total = n * h * h;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * 256) {
+    const int64_t e = i / (h * h);
+    const int p = (int)(i - e * h * h);
+    const int r = p / h;
+    const int c = p - r * h;
+    const float* q = x + e * side * side + 2 * r * side + 2 * c;
+    out[i] = max4_nan(q[0], q[1], q[side], q[side + 1]);
+  }
+}
+
+hipError_t launch_pool2x2(const float* x, int64_t n, int side, float* out, hipStream_t s) {
+  const int64_t total = n * (side / 2) * (side / 2);
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(pool2x2_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, n, side, out);
+  return hipGetLastError();
+}
+
+__global__ void fill_kernel(float* __restrict__ p, int n, float v) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill(float* p, int n, float v, hipStream_t s) {
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 

@@ -18,10 +18,13 @@ hipError_t launch_init(float* genomes, const NetDesc& nd, const Glorot& ga, int 
                        const Key& key, hipStream_t s);
 hipError_t launch_vary(const float* cur, float* nxt, const int4* plan, const NetDesc& nd,
                        int pop, int crossover, float sigma, uint64_t mut_threshold,
-                       const Key& key, uint32_t gen, hipStream_t s);
+                       const Key& key, uint32_t gen, const float* sig_cur, float* sig_next,
+                       float tau, hipStream_t s);
 hipError_t launch_draw_batch(const float* x_train, const int32_t* y_train, int64_t n_train,
-                             int n_in, int b, float* x_out, int32_t* y_out, const Key& key,
-                             uint32_t gen, hipStream_t s);
+                             int n_in, int side, int b, float* x_out, int32_t* y_out,
+                             const Key& key, uint32_t gen, hipStream_t s);
+hipError_t launch_pool2x2(const float* x, int64_t n, int side, float* out, hipStream_t s);
+hipError_t launch_fill(float* p, int n, float v, hipStream_t s);
 
 // select.hip
 hipError_t launch_select(const float* f_adj, int pop, int n_elite, int n_cross, int n_trunc,

@@ -21,6 +21,7 @@ MAX_LAYERS = 8
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, 1, 2, 3, 4
 SEL = {"truncation": 0, "tournament": 1}
 XO = {"uniform": 0, "arithmetic": 1}
+SIGMA_MODES = {"constant": 0, "decay": 1, "self_adaptive": 2}
 OP_ELITE, OP_CROSS, OP_MUT = 0, 1, 2
 
 
@@ -49,6 +50,10 @@ class Config(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("run", ctypes.c_uint32),
         ("max_batch", ctypes.c_int32),
+        ("sigma_mode", ctypes.c_int32),
+        ("sigma_decay_k", ctypes.c_float),
+        ("tau", ctypes.c_float),
+        ("input_pool", ctypes.c_int32),
     ]
 
 
@@ -83,6 +88,9 @@ def library():
         "leea_state_bytes": [P, ctypes.POINTER(ctypes.c_size_t)],
         "leea_save": [P, P, ctypes.c_size_t],
         "leea_load": [P, P, ctypes.c_size_t],
+        "leea_sigmas": [P, ctypes.POINTER(P)],
+        "leea_set_sigmas": [P, P],
+        "leea_pool2x2": [P, I64, I32, P, P],
         "leea_rng_philox": [P, U64, P, I64, P],
         "leea_rng_ln32": [P, P, I64, P],
         "leea_rng_normal_pairs": [P, P, I64, P],
@@ -130,7 +138,8 @@ def threshold(p_gene):
 
 def make_config(widths, pop, p_elite=0.05, p_cross=0.50, p_mut=0.45, rho=0.5,
                 selection="truncation", tournament_k=2, crossover="uniform", sigma=0.001,
-                p_gene=1.0, alpha=1.0, seed=0, run=0, max_batch=512, **_ignored):
+                p_gene=1.0, alpha=1.0, seed=0, run=0, max_batch=512, sigma_mode="constant",
+                sigma_decay_k=1.0, tau=0.0, pool=0, **_ignored):
     """leea_config from the paper's hyperparameters (fractions)."""
     widths = tuple(int(w) for w in widths)
     L = len(widths) - 1
@@ -154,6 +163,10 @@ def make_config(widths, pop, p_elite=0.05, p_cross=0.50, p_mut=0.45, rho=0.5,
     c.seed = seed
     c.run = run
     c.max_batch = max_batch
+    c.sigma_mode = SIGMA_MODES[sigma_mode]
+    c.sigma_decay_k = sigma_decay_k
+    c.tau = tau
+    c.input_pool = pool
     return c
 
 
@@ -269,6 +282,17 @@ class Leea:
         f_adj = self._view(f.value, self.pop * 4).view(torch.float32)
         return genomes.view(self.pop, self.stride), f_adj
 
+    def sigmas(self):
+        """Self-adaptive sigma genes [pop] (borrowed view), or None."""
+        ptr = ctypes.c_void_p()
+        _check(library().leea_sigmas(self._ctx, ctypes.byref(ptr)), self._ctx)
+        if not ptr.value:
+            return None
+        return self._view(ptr.value, self.pop * 4).view(torch.float32)
+
+    def set_sigmas(self, sig):
+        _check(library().leea_set_sigmas(self._ctx, _ptr(sig)), self._ctx)
+
     def set_state(self, genomes=None, f_adj=None, f_inh=None):
         _check(library().leea_set_state(self._ctx, _ptr(genomes), _ptr(f_adj), _ptr(f_inh)),
                self._ctx)
@@ -291,6 +315,14 @@ def rng_philox(ctr, key):
     """Philox4x32-10 of device uint32 counters [n, 4] under a 64-bit key."""
     out = torch.empty_like(ctr)
     _check(library().leea_rng_philox(_ptr(ctr), key, _ptr(out), ctr.shape[0], _stream()))
+    return out
+
+
+def pool2x2(x, side):
+    """2x2 max-pooling of square images x [n, side*side] on the device."""
+    h = side // 2
+    out = torch.empty((x.shape[0], h * h), dtype=torch.float32, device=x.device)
+    _check(library().leea_pool2x2(_ptr(x), x.shape[0], side, _ptr(out), _stream()))
     return out
 
 

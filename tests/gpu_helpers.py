@@ -83,3 +83,55 @@ def check_fitness(f_gpu, acc_gpu, f_ref, acc_ref, amb, b, label=""):
     dc = np.abs(np.rint(np.asarray(acc_gpu, dtype=np.float64) * b) - np.rint(acc_ref * b))
     assert np.all(dc[ok] <= amb[ok]), (label, dc.max())
     return float(np.max(err / np.maximum(np.abs(f_ref[ok]), 1e-30))) if ok.any() else 0.0
+
+
+def teacher_forced(params, gens, x, y, check_every=1, label=""):
+    """Run `gens` generations on the device and, teacher-forced with the
+    device's float32 adjusted fitness, in the oracle; assert plans, sigma
+    genes and genomes bit-exact and fitness within tolerance each generation.
+    x is the raw training set (pooled on the way when params['pool'] == 2)."""
+    from oracle import leea as O
+    b = params["batch"]
+    run, ocfg = make_run(params, max_batch=b)
+    widths = tuple(params["widths"])
+    mode = params.get("sigma_mode", "constant")
+    side = int(round(np.sqrt(x.shape[1]))) if params.get("pool", 0) else 0
+    xd, yd = to_dev(x), to_dev(y)
+
+    def obatch(g):
+        idx = O.batch_indices(ocfg.seed, g, b, x.shape[0], ocfg.run)
+        xb = x[idx]
+        return (O.pool2x2(xb, side) if side else xb), y[idx]
+
+    pop_o = O.init_population(ocfg)
+    assert np.array_equal(genomes_np(run), pop_o)
+    sig_o = np.full(run.pop, F32(params["sigma"]), dtype=F32)
+    xb, yb = run.draw_batch(0, xd, yd, b)
+    xo, yo = obatch(0)
+    assert np.array_equal(to_np(xb), xo)
+    f_adj, f_raw, acc = run.evaluate(xb, yb)
+    f_o, acc_o, amb = oracle_eval(pop_o, widths, xo, yo)
+    check_fitness(to_np(f_raw), to_np(acc), f_o, acc_o, amb, b, label + " gen0")
+    for g in range(1, gens + 1):
+        say(label, "generation", g)
+        f_prev = to_np(f_adj).copy()
+        xb, yb = run.draw_batch(g, xd, yd, b)
+        plan, f_inh, order = run.select()
+        run.crossover_mutate()
+        f_adj, f_raw, acc = run.evaluate(xb, yb)
+        ops, p1, p2, fi = O.plan(O.rank(f_prev), f_prev, ocfg, g)
+        pl = to_np(plan)
+        assert np.array_equal(pl[:, 1], p1) and np.array_equal(pl[:, 2], p2), g
+        if mode == "self_adaptive":
+            sig_o = O.child_sigmas(sig_o, ops, p1, p2, ocfg, g)
+            assert np.array_equal(to_np(run.sigmas()).view(np.uint32), sig_o.view(np.uint32)), g
+            pop_o = O.vary_adaptive(pop_o, sig_o, ops, p1, p2, ocfg, g)
+        else:
+            sigma = O.sigma_decay(ocfg.sigma, g, ocfg.sigma_decay_k) if mode == "decay" else None
+            pop_o = O.vary(pop_o, ops, p1, p2, ocfg, g, sigma=sigma)
+        assert np.array_equal(genomes_np(run).view(np.uint32), pop_o.view(np.uint32)), g
+        if g % check_every == 0 or g == gens:
+            xo, yo = obatch(g)
+            f_o, acc_o, amb = oracle_eval(pop_o, widths, xo, yo)
+            check_fitness(to_np(f_raw), to_np(acc), f_o, acc_o, amb, b, "%s gen%d" % (label, g))
+    return run
