@@ -395,9 +395,10 @@ def _child(pop, ops, p1, p2, cfg, gen, sigma, threshold, j, c):
 
 def sigma_decay(sigma, gen, k):
     """Exponentially decaying mutation strength sigma_i = sigma * 0.99**(i/k)
-    (section 3.2) for the mutation that creates generation ``gen``; float64
-    power, rounded once to float32."""
-    return F32(float(sigma) * math.pow(0.99, gen / float(k)))
+    (section 3.2) for the mutation that creates generation ``gen``.  sigma and
+    k are float32 hyperparameters; the product is formed in float64 and
+    rounded once to float32."""
+    return F32(float(F32(sigma)) * math.pow(0.99, gen / float(F32(k))))
 
 
 def default_tau(widths):

@@ -252,7 +252,7 @@ class Leea:
 
     def draw_batch(self, gen, x_train, y_train, b, x_out=None, y_out=None):
         if x_out is None:
-            x_out = torch.empty((b, x_train.shape[1]), dtype=torch.float32, device=self.device)
+            x_out = torch.empty((b, self.cfg.widths[0]), dtype=torch.float32, device=self.device)
             y_out = torch.empty((b,), dtype=torch.int32, device=self.device)
         _check(library().leea_draw_batch(self._ctx, gen, _ptr(x_train), _ptr(y_train),
                                          x_train.shape[0], b, _ptr(x_out), _ptr(y_out)), self._ctx)
