@@ -83,7 +83,10 @@ def measured_traffic(workload_tag):
     return None
 
 
-def run_gpu(params, steps, warmup, x_train, y_train, timed_events=True):
+def run_gpu(params, steps, warmup, x_train, y_train, timed_events=True, fused=False):
+    """Time `steps` generations.  Variation and evaluation are timed as
+    separate calls; with fused=True (b <= 16 only) the second half of the step
+    is the single fused variation + evaluation call instead."""
     import torch
     from paper_1806_09819_amd import leea as B
 
@@ -91,6 +94,7 @@ def run_gpu(params, steps, warmup, x_train, y_train, timed_events=True):
     lib = B.library()
     ctx = run._ctx
     b = params["batch"]
+    fused = fused and b <= 16
     xb = torch.empty((b, params["widths"][0]), dtype=torch.float32, device="cuda")
     yb = torch.empty((b,), dtype=torch.int32, device="cuda")
     P = B._ptr
@@ -99,9 +103,12 @@ def run_gpu(params, steps, warmup, x_train, y_train, timed_events=True):
         if st != 0:
             raise B.LeeaError(st, lib.leea_last_error(ctx).decode())
 
+    run.set_fused_step(fused)
     run.draw_batch(0, x_train, y_train, b, xb, yb)
     run.evaluate(xb, yb)
     gen = [0]
+    names = ["batch", "select", "vary+evaluate"] if fused else ["batch", "select", "vary",
+                                                                 "evaluate"]
 
     def one_step(ev=None):
         g = gen[0] + 1
@@ -114,36 +121,76 @@ def run_gpu(params, steps, warmup, x_train, y_train, timed_events=True):
         call(lib.leea_select(ctx, None, None, None))
         if ev is not None:
             ev[2].record()
-        call(lib.leea_crossover_mutate(ctx))
+        if fused:
+            call(lib.leea_crossover_mutate_evaluate(ctx, P(xb), P(yb), b, None, None, None))
+        else:
+            call(lib.leea_crossover_mutate(ctx))
+            if ev is not None:
+                ev[3].record()
+            call(lib.leea_evaluate(ctx, P(xb), P(yb), b, None, None, None))
         if ev is not None:
-            ev[3].record()
-        call(lib.leea_evaluate(ctx, P(xb), P(yb), b, None, None, None))
-        if ev is not None:
-            ev[4].record()
+            ev[len(names)].record()
         gen[0] = g
 
     for _ in range(warmup):
         one_step()
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+              for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
         one_step(events[k] if timed_events else None)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    phases = np.zeros(4)
+    phases = np.zeros(len(names))
     if timed_events:
         for ev in events:
-            for i in range(4):
+            for i in range(len(names)):
                 phases[i] += ev[i].elapsed_time(ev[i + 1])
         phases /= steps
     _, f_adj = run.population()
     best = float(torch.max(torch.nan_to_num(f_adj, nan=-np.inf)).item())
-    out = dict(seconds=t1 - t0, phases_ms=dict(batch=phases[0], select=phases[1],
-                                                vary=phases[2], evaluate=phases[3]),
-               genes=run.genes, best_f_adj=best)
+    out = dict(seconds=t1 - t0, phases_ms=dict(zip(names, phases.tolist())), genes=run.genes,
+               stride=run.stride, best_f_adj=best, fused=fused)
     run.close()
     return out
+
+
+def fused_bytes(params, stride, b):
+    """Algorithmic bytes of one fused variation + evaluation launch: every
+    child written once, one parent read per elite and mutant, two per
+    crossover child, and the shared batch."""
+    from paper_1806_09819_amd import leea as B
+    n_e, n_c, n_m, _ = B.counts(params["pop"], params["p_elite"], params["p_cross"],
+                                params["p_mut"], params["rho"])
+    return 4.0 * stride * (2 * n_e + 3 * n_c + 2 * n_m) + 4.0 * b * (params["widths"][0] + 1)
+
+
+def roofline_of(params, r, b):
+    """Roofline object of the dominant kernel of a measured run."""
+    if r["fused"]:
+        nbytes = fused_bytes(params, r["stride"], b)
+        sec = r["phases_ms"]["vary+evaluate"] * 1e-3
+        achieved = nbytes / sec / 1e9
+        return dict(bound="hbm", achieved=achieved, peak=HBM_PEAK / 1e9, unit="GB/s",
+                    frac=achieved / (HBM_PEAK / 1e9), traffic=None,
+                    kernel="fused variation + evaluation (crossover_mutate_evaluate call)",
+                    per_launch=dict(bytes=nbytes, avg_ms=r["phases_ms"]["vary+evaluate"]))
+    flops, nbytes = algorithmic(params, r["genes"], b)
+    sec = r["phases_ms"]["evaluate"] * 1e-3
+    if flops / nbytes > MFMA_F32_PEAK / HBM_PEAK:
+        achieved = flops / sec / 1e12
+        roof = dict(bound="mfma", achieved=achieved, peak=MFMA_F32_PEAK / 1e12,
+                    unit="TFLOP/s", frac=achieved / (MFMA_F32_PEAK / 1e12))
+    else:
+        achieved = nbytes / sec / 1e9
+        roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK / 1e9, unit="GB/s",
+                    frac=achieved / (HBM_PEAK / 1e9))
+    roof["traffic"] = measured_traffic("paper_b%d" % b)
+    roof["vary_hbm_frac"] = vary_bytes(params, r["stride"]) / (r["phases_ms"]["vary"] * 1e-3) / HBM_PEAK
+    roof["kernel"] = "evaluate (fused forward + fitness, one launch per generation)"
+    roof["per_launch"] = dict(flops=flops, bytes=nbytes, avg_ms=r["phases_ms"]["evaluate"])
+    return roof
 
 
 def cpu_baseline(params, b, min_seconds=10.0, max_gens=3):
@@ -195,6 +242,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--sweep-steps", type=int, default=50)
+    ap.add_argument("--fused", action="store_true",
+                    help="time the fused variation + evaluation call at batch <= 16")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 5 times (scales the "
                          "FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
@@ -225,24 +274,10 @@ def main():
 
     params = workload(args.batch)
     log("bench: timed run, batch", args.batch)
-    r = run_gpu(params, args.steps, args.warmup, x_train, y_train)
+    r = run_gpu(params, args.steps, args.warmup, x_train, y_train, fused=args.fused)
     P, b, K = params["pop"], args.batch, args.steps
     value = P * b * K / r["seconds"]
-    flops, nbytes = algorithmic(params, r["genes"], b)
-    eval_s = r["phases_ms"]["evaluate"] * 1e-3
-    ridge = MFMA_F32_PEAK / HBM_PEAK
-    if flops / nbytes > ridge:
-        achieved = flops / eval_s / 1e12
-        roof = dict(bound="mfma", achieved=achieved, peak=MFMA_F32_PEAK / 1e12,
-                    unit="TFLOP/s", frac=achieved / (MFMA_F32_PEAK / 1e12))
-    else:
-        achieved = nbytes / eval_s / 1e9
-        roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK / 1e9, unit="GB/s",
-                    frac=achieved / (HBM_PEAK / 1e9))
-    roof["traffic"] = measured_traffic("paper_b%d" % b)
-    roof["kernel"] = "evaluate (fused forward + fitness, one launch per generation)"
-    roof["per_launch"] = dict(flops=flops, bytes=nbytes, avg_ms=r["phases_ms"]["evaluate"])
-    vb = vary_bytes(params, r["genes"])
+    roof = roofline_of(params, r, b)
     phases = {k: round(v, 4) for k, v in r["phases_ms"].items()}
     line = {
         "metric": METRIC,
@@ -266,7 +301,6 @@ def main():
             "gens_per_s": K / r["seconds"],
         },
         "phases_ms": phases,
-        "vary_hbm_GBps": vb / (r["phases_ms"]["vary"] * 1e-3) / 1e9,
         "roofline": roof,
     }
     if not args.no_sweep:
@@ -276,14 +310,13 @@ def main():
                 continue
             log("bench: sweep batch", bb)
             pb = workload(bb)
-            rs = run_gpu(pb, args.sweep_steps, 3, x_train, y_train)
-            fl, nb = algorithmic(pb, rs["genes"], bb)
-            es = rs["phases_ms"]["evaluate"] * 1e-3
+            rs = run_gpu(pb, args.sweep_steps, 3, x_train, y_train, fused=args.fused)
+            rf = roofline_of(pb, rs, bb)
             sweep.append(dict(batch=bb, value=P * bb * args.sweep_steps / rs["seconds"],
                               ms_per_step=rs["seconds"] / args.sweep_steps * 1e3,
                               phases_ms={k: round(v, 4) for k, v in rs["phases_ms"].items()},
-                              eval_hbm_frac=nb / es / HBM_PEAK, eval_mfma_frac=fl / es / MFMA_F32_PEAK,
-                              vary_hbm_frac=vb / (rs["phases_ms"]["vary"] * 1e-3) / HBM_PEAK))
+                              dominant=rf["kernel"], bound=rf["bound"],
+                              frac=round(rf["frac"], 4)))
         line["batch_sweep"] = sweep
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")

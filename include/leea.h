@@ -165,9 +165,27 @@ leea_status leea_select(leea_ctx* ctx, int32_t* plan_out, float* f_inh_out,
  * sigma.  Advances the generation counter.  Requires a preceding select. */
 leea_status leea_crossover_mutate(leea_ctx* ctx);
 
-/* select -> crossover_mutate -> evaluate, one generation. */
+/* select -> crossover_mutate -> evaluate, one generation.  For b <= 16 (and
+ * hidden widths that are multiples of 4, with the genes after layer 1's
+ * weights small enough for LDS) the variation and the evaluation run as one
+ * kernel that builds each child from its parents in registers and evaluates
+ * it as it is written (the children are not streamed back from HBM); the
+ * results are bitwise identical to the three separate calls. */
 leea_status leea_step(leea_ctx* ctx, const float* x, const int32_t* y, int32_t b,
                       float* f_adj, float* f_raw, float* acc);
+
+/* crossover_mutate followed by evaluate (the second half of leea_step, with
+ * the same fused small-batch path).  Requires a preceding select. */
+leea_status leea_crossover_mutate_evaluate(leea_ctx* ctx, const float* x, const int32_t* y,
+                                          int32_t b, float* f_adj, float* f_raw, float* acc);
+
+/* Allow (enable != 0) or forbid (the default) the fused small-batch path of
+ * leea_step and leea_crossover_mutate_evaluate: one kernel that builds each
+ * child from its parents and evaluates it without writing and re-reading it
+ * (batches of at most 16, hidden widths multiples of 4).  Results are
+ * bit-identical either way; it is off by default because the separate
+ * variation and evaluation kernels measured faster. */
+leea_status leea_set_fused_step(leea_ctx* ctx, int32_t enable);
 
 /* Base mutation strength for the following crossover_mutate calls; with
  * self-adaptive sigma it resets every individual's sigma gene to sigma. */

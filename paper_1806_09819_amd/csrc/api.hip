@@ -46,6 +46,7 @@ struct leea_ctx {
   int state;
   int has_inh;
   float sigma;
+  int fused;       // leea_step may fuse variation and small-batch evaluation
   std::string err;
 };
 
@@ -269,6 +270,7 @@ leea_status leea_init_population(const leea_config* cfg, void* workspace, size_t
   c->state = kNeedEval;
   c->has_inh = 0;
   c->sigma = cfg->sigma;
+  c->fused = 0;
   Glorot ga;
   for (int l = 0; l < LEEA_MAX_LAYERS; ++l) ga.a[l] = l < nd.L ? cfg->glorot_a[l] : 0.0f;
   st = dev(nullptr, launch_init(c->genomes[0], nd, ga, cfg->pop, key_of(c), c->stream),
@@ -343,29 +345,87 @@ leea_status leea_select(leea_ctx* c, int32_t* plan_out, float* f_inh_out, int32_
   return LEEA_OK;
 }
 
-leea_status leea_crossover_mutate(leea_ctx* c) {
-  if (!c) return fail(nullptr, LEEA_EINVAL, "ctx is NULL");
-  if (c->state != kSelected) return fail(c, LEEA_ESTATE, "crossover_mutate needs a select first");
-  const int nxt = c->cur ^ 1;
-  const uint32_t g = c->gen + 1;
-  float sigma = c->sigma;
-  const bool adaptive = c->cfg.sigma_mode == LEEA_SIGMA_SELF_ADAPTIVE;
+}  // extern "C"
+
+namespace {
+
+// Mutation strength of the variation that creates generation g (constant,
+// decayed, or NULL sigma arrays unless self-adaptive).
+void vary_sigma(const leea_ctx* c, uint32_t g, float* sigma, const float** sig_cur,
+                float** sig_next) {
+  *sigma = c->sigma;
   if (c->cfg.sigma_mode == LEEA_SIGMA_DECAY)
-    sigma = (float)((double)c->sigma * pow(0.99, (double)g / (double)c->cfg.sigma_decay_k));
-  leea_status st = dev(c,
-                       launch_vary(c->genomes[c->cur], c->genomes[nxt], c->plan, c->nd, c->cfg.pop,
-                                   c->cfg.crossover, sigma, c->cfg.mut_threshold, key_of(c), g,
-                                   adaptive ? c->sig[c->cur] : nullptr,
-                                   adaptive ? c->sig[nxt] : nullptr, c->tau, c->stream),
-                       "vary launch");
-  if (st) return st;
-  c->cur = nxt;
+    *sigma = (float)((double)c->sigma * pow(0.99, (double)g / (double)c->cfg.sigma_decay_k));
+  const bool adaptive = c->cfg.sigma_mode == LEEA_SIGMA_SELF_ADAPTIVE;
+  *sig_cur = adaptive ? c->sig[c->cur] : nullptr;
+  *sig_next = adaptive ? c->sig[c->cur ^ 1] : nullptr;
+}
+
+// The new population becomes current: buffers swap, inherited fitness of
+// the plan takes effect, the generation advances.
+void advance(leea_ctx* c) {
+  c->cur ^= 1;
   float* t = c->f_inh;
   c->f_inh = c->f_inh_next;
   c->f_inh_next = t;
   c->has_inh = 1;
   c->gen += 1;
   c->state = kNeedEval;
+}
+
+}  // namespace
+
+extern "C" {
+
+leea_status leea_crossover_mutate(leea_ctx* c) {
+  if (!c) return fail(nullptr, LEEA_EINVAL, "ctx is NULL");
+  if (c->state != kSelected) return fail(c, LEEA_ESTATE, "crossover_mutate needs a select first");
+  const uint32_t g = c->gen + 1;
+  float sigma;
+  const float* sig_cur;
+  float* sig_next;
+  vary_sigma(c, g, &sigma, &sig_cur, &sig_next);
+  leea_status st = dev(c,
+                       launch_vary(c->genomes[c->cur], c->genomes[c->cur ^ 1], c->plan, c->nd,
+                                   c->cfg.pop, c->cfg.crossover, sigma, c->cfg.mut_threshold,
+                                   key_of(c), g, sig_cur, sig_next, c->tau, c->stream),
+                       "vary launch");
+  if (st) return st;
+  advance(c);
+  return LEEA_OK;
+}
+
+leea_status leea_crossover_mutate_evaluate(leea_ctx* c, const float* x, const int32_t* y,
+                                          int32_t b, float* f_adj, float* f_raw, float* acc) {
+  if (!c) return fail(nullptr, LEEA_EINVAL, "ctx is NULL");
+  if (c->state != kSelected)
+    return fail(c, LEEA_ESTATE, "crossover_mutate_evaluate needs a select first");
+  leea_status st = check_batch(c, x, y, b);
+  if (st) return st;
+  if (!(c->fused && fused_supported(c->nd, b))) {
+    st = leea_crossover_mutate(c);
+    if (st) return st;
+    return leea_evaluate(c, x, y, b, f_adj, f_raw, acc);
+  }
+  // small batch: variation and evaluation in one pass over the parents
+  const uint32_t g = c->gen + 1;
+  float sigma;
+  const float* sig_cur;
+  float* sig_next;
+  vary_sigma(c, g, &sigma, &sig_cur, &sig_next);
+  st = dev(c,
+           launch_vary_eval(c->genomes[c->cur], c->genomes[c->cur ^ 1], c->plan, c->nd,
+                            c->cfg.pop, c->cfg.crossover, sigma, c->cfg.mut_threshold, key_of(c),
+                            g, sig_cur, sig_next, c->tau, x, y, b, c->partial, c->stream),
+           "fused vary+evaluate launch");
+  if (st) return st;
+  advance(c);
+  const int use_inh = c->cfg.alpha != 1.0f;
+  st = dev(c, launch_finalize(c->partial, c->cfg.pop, 1, b, c->f_inh, use_inh, c->cfg.alpha,
+                              c->f_adj, c->f_raw, c->acc, f_adj, f_raw, acc, c->stream),
+           "finalize launch");
+  if (st) return st;
+  c->state = kEvaluated;
   return LEEA_OK;
 }
 
@@ -377,9 +437,13 @@ leea_status leea_step(leea_ctx* c, const float* x, const int32_t* y, int32_t b, 
   if (st) return st;
   st = leea_select(c, nullptr, nullptr, nullptr);
   if (st) return st;
-  st = leea_crossover_mutate(c);
-  if (st) return st;
-  return leea_evaluate(c, x, y, b, f_adj, f_raw, acc);
+  return leea_crossover_mutate_evaluate(c, x, y, b, f_adj, f_raw, acc);
+}
+
+leea_status leea_set_fused_step(leea_ctx* c, int32_t enable) {
+  if (!c) return fail(nullptr, LEEA_EINVAL, "ctx is NULL");
+  c->fused = enable ? 1 : 0;
+  return LEEA_OK;
 }
 
 leea_status leea_set_sigma(leea_ctx* c, float sigma) {

@@ -1,0 +1,175 @@
+// Device pieces shared by the evaluation kernels (evaluate.hip) and the
+// fused variation + evaluation kernel (fused.hip): MFMA super-steps, the
+// LDS carve-up, layers 2..L and the fused fitness.
+#pragma once
+
+#include "internal.hpp"
+
+namespace leea {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ floatx4 mfma(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// One super-step for NT column tiles; consecutive MFMAs go to different
+// accumulators so none waits on the previous one's result.
+template <int NT>
+__device__ __forceinline__ void mfma_superstep(const float4& a, const float4 (&b)[NT],
+                                               floatx4 (&acc)[NT]) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = mfma(a.x, b[t].x, acc[t]);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = mfma(a.y, b[t].y, acc[t]);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = mfma(a.z, b[t].z, acc[t]);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = mfma(a.w, b[t].w, acc[t]);
+}
+
+__device__ __forceinline__ float relu_keep_nan(float v) { return v < 0.0f ? 0.0f : v; }
+
+__device__ __forceinline__ float4 zero4() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+
+// LDS carve-up shared by both kernels (offsets and strides in floats).
+struct EvalLds {
+  int h1;     // layer-1 activations [rows][ld1]; later reused as a tail buffer
+  int ld1;
+  int ta;     // tail activations [rows][ldt]
+  int ldt;
+  int ll;     // [rows] per-sample log-likelihood
+  int cor;    // [rows] per-sample correctness (int)
+  int total;  // floats of dynamic LDS
+};
+
+// One fully connected layer on the matrix cores for rows [0, 16*mtiles):
+// out = act(in * W^T + bias).  `in` (LDS, row stride ldi) must hold zeros in
+// columns [n_in, round16(n_in)); `out` gets zeros in [n_out, round16(n_out)).
+// W is [n_out][n_in] row-major in global memory with n_in and the matrix
+// offset multiples of 4; all fragments of a tile are loaded before its MFMAs.
+static __device__ void mfma_layer(const float* in, int ldi, int n_in, float* out, int ldo, int n_out,
+                           const float* W, const float* bias, bool relu, int mtiles) {
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int mn = lane & 15;
+  const int kq = lane >> 4;
+  const int ntiles = (n_out + 15) >> 4;
+  const int kss = (n_in + 15) >> 4;  // <= 16: widths are at most 256
+  for (int item = wave; item < mtiles * ntiles; item += 4) {
+    const int mt = item / ntiles;
+    const int nt = item - mt * ntiles;
+    const int n = nt * 16 + mn;
+    const bool nv = n < n_out;
+    const float* wr = W + (int64_t)(nv ? n : 0) * n_in;
+    float4 bf[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int k = 16 * s + 4 * kq;
+      bf[s] = (s < kss && nv && k < n_in) ? *reinterpret_cast<const float4*>(wr + k) : zero4();
+    }
+    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+    const float* arow = in + (mt * 16 + mn) * ldi + 4 * kq;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      if (s < kss) {
+        const float4 a = *reinterpret_cast<const float4*>(arow + 16 * s);
+        acc = mfma(a.x, bf[s].x, acc);
+        acc = mfma(a.y, bf[s].y, acc);
+        acc = mfma(a.z, bf[s].z, acc);
+        acc = mfma(a.w, bf[s].w, acc);
+      }
+    }
+    const float bb = nv ? bias[n] : 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float v = acc[i] + bb;
+      if (relu) v = relu_keep_nan(v);
+      out[(mt * 16 + 4 * kq + i) * ldo + n] = nv ? v : 0.0f;
+    }
+  }
+}
+
+// The same layer on VALU, for hidden widths that are not multiples of 4.
+static __device__ void scalar_layer(const float* in, int ldi, int n_in, float* out, int ldo, int n_out,
+                             const float* W, const float* bias, bool relu, int rows) {
+  const int n16 = (n_out + 15) & ~15;
+  for (int idx = threadIdx.x; idx < rows * n16; idx += blockDim.x) {
+    const int m = idx / n16;
+    const int n = idx - m * n16;
+    float v = 0.0f;
+    if (n < n_out) {
+      const float* a = in + m * ldi;
+      const float* w = W + (int64_t)n * n_in;
+      for (int k = 0; k < n_in; ++k) v += a[k] * w[k];
+      v += bias[n];
+      if (relu) v = relu_keep_nan(v);
+    }
+    out[m * ldo + n] = v;
+  }
+}
+
+// Layers 2..L on the LDS tile of layer-1 activations, then the per-sample
+// fitness of the first `rows` rows: log-likelihood (z_y - max z) -
+// log sum_k exp(z_k - max z) (Eq. 1, left side) and correctness (first
+// maximal logit equals the label); a label outside [0, d) gives NaN.  The
+// row sums go to *out in a fixed order (deterministic).
+// Layer weights come from tw: W_l at tw + (woff[l] - toff) (the genome in
+// global memory with toff = 0, or a copy of the genome's tail in LDS).
+static __device__ void tail_and_fitness(float* lds, const EvalLds& lo, const NetDesc& nd,
+                                 const float* tw, int64_t toff, int mtiles, int rows,
+                                 int m0, const int32_t* __restrict__ y, bool tail_vec,
+                                 float2* __restrict__ out) {
+  const float* in = lds + lo.h1;
+  int ldi = lo.ld1;
+  float* dst = lds + lo.ta;
+  for (int l = 1; l < nd.L; ++l) {
+    const float* W = tw + (nd.woff[l] - toff);
+    const float* bias = tw + (nd.boff[l] - toff);
+    const bool relu = l < nd.L - 1;
+    if (tail_vec)
+      mfma_layer(in, ldi, nd.w[l], dst, lo.ldt, nd.w[l + 1], W, bias, relu, mtiles);
+    else
+      scalar_layer(in, ldi, nd.w[l], dst, lo.ldt, nd.w[l + 1], W, bias, relu, 16 * mtiles);
+    __syncthreads();
+    in = dst;
+    ldi = lo.ldt;
+    dst = (dst == lds + lo.ta) ? lds + lo.h1 : lds + lo.ta;
+  }
+  const int d = nd.w[nd.L];
+  float* ll = lds + lo.ll;
+  int* cor = reinterpret_cast<int*>(lds + lo.cor);
+  for (int m = threadIdx.x; m < rows; m += blockDim.x) {
+    const float* z = in + m * ldi;
+    const int yy = y[m0 + m];
+    float mx = z[0];
+    int best = 0;
+    for (int k = 1; k < d; ++k)
+      if (z[k] > mx) {
+        mx = z[k];
+        best = k;
+      }
+    float s = 0.0f;
+    for (int k = 0; k < d; ++k) s += expf(z[k] - mx);
+    ll[m] = (yy >= 0 && yy < d) ? (z[yy] - mx) - logf(s) : __builtin_nanf("");
+    cor[m] = (best == yy) ? 1 : 0;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    float s = 0.0f;
+    int c = 0;
+    for (int m = threadIdx.x; m < rows; m += 64) {
+      s += ll[m];
+      c += cor[m];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      s += __shfl_xor(s, off);
+      c += __shfl_xor(c, off);
+    }
+    if (threadIdx.x == 0) *out = make_float2(s, (float)c);
+  }
+}
+
+
+}  // namespace leea

@@ -3,19 +3,9 @@
 // whole 1 KiB wave-wide segments, and one Philox call per lane per
 // 4 (mutation) or 128 (uniform crossover) genes.
 #include "internal.hpp"
+#include "vary_common.hpp"
 
 namespace leea {
-
-typedef float floatv4 __attribute__((ext_vector_type(4)));
-
-// Children are written with non-temporal stores: the next kernel (the
-// evaluation) streams them back once, and dirty lines left in L2 / the
-// memory-side cache would otherwise be written back while it reads,
-// halving its read bandwidth.
-__device__ __forceinline__ void store_stream(float4* p, const float4& v) {
-  floatv4 w = {v.x, v.y, v.z, v.w};
-  __builtin_nontemporal_store(w, reinterpret_cast<floatv4*>(p));
-}
 
 // Glorot-uniform weights, zero biases and padding (Algorithm 1, first line;
 // section 4.1).  Thread = 4 consecutive genes = one Philox block.
@@ -88,21 +78,8 @@ __global__ __launch_bounds__(256) void vary_kernel(const float* __restrict__ cur
   const int64_t base4 = G * 2048 + lane;
   const int4 pl = plan[j];
   if (sig_cur) {
-    float sc;
-    if (pl.x == kOpElite) {
-      sc = sig_cur[pl.y];
-    } else if (pl.x == kOpCross) {
-      const float sum = sig_cur[pl.y] + sig_cur[pl.z];
-      sc = sum * 0.5f;
-    } else {
-      const uint4 w = draw(key, kSigma, gen, (uint32_t)j, 0u);
-      float z0, z1;
-      normal_pair(w.x, w.y, z0, z1);
-      const float t = tau * z0;
-      sc = sig_cur[pl.y] * exp32(t);
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) sig_next[j] = sc;
-    sigma = sc;
+    sigma = child_sigma(pl, sig_cur, key, gen, (uint32_t)j, tau);
+    if (blockIdx.x == 0 && threadIdx.x == 0) sig_next[j] = sigma;
   }
   if (G * 2048 >= n4) return;
   const float4* __restrict__ a4 = reinterpret_cast<const float4*>(cur + (int64_t)pl.y * stride);
@@ -140,57 +117,39 @@ __global__ __launch_bounds__(256) void vary_kernel(const float* __restrict__ cur
         if (f < n4) {
           const float4 a = a4[f];
           const float4 b = b4[f];
-          float4 o;
-          o.x = (a.x + b.x) * 0.5f;
-          o.y = (a.y + b.y) * 0.5f;
-          o.z = (a.z + b.z) * 0.5f;
-          o.w = (a.w + b.w) * 0.5f;
+          const float4 o = xo_arith4(a, b);
           store_stream(d4 + f, o);
         }
       }
     }
   } else {
-    const bool all = thr >= (1ull << 32);
-    const uint32_t t32 = (uint32_t)thr;
+    VaryParams vp;
+    vp.sigma = sigma;
+    vp.all = thr >= (1ull << 32);
+    vp.t32 = (uint32_t)thr;
+    vp.key = key;
+    vp.gen = gen;
+    vp.slot = (uint32_t)j;
+    vp.genes = genes;
 #pragma unroll 4
     for (int t = 0; t < 32; ++t) {
       const int64_t f = base4 + 64 * t;
       if (f < n4) {
         const float4 a = a4[f];
-        const int64_t i0 = 4 * f;
-        if (i0 >= genes) {
+        if (4 * f >= genes) {  // padding only: skip the draws
           store_stream(d4 + f, a);
           continue;
         }
-        const float4 z = normals4(draw(key, kMutNorm, gen, (uint32_t)j, (uint32_t)f));
-        uint4 mw = make_uint4(0u, 0u, 0u, 0u);
-        if (!all) mw = draw(key, kMutMask, gen, (uint32_t)j, (uint32_t)f);
-        const bool m0 = (all || mw.x < t32) && i0 + 0 < genes;
-        const bool m1 = (all || mw.y < t32) && i0 + 1 < genes;
-        const bool m2 = (all || mw.z < t32) && i0 + 2 < genes;
-        const bool m3 = (all || mw.w < t32) && i0 + 3 < genes;
-        float4 o;
-        const float n0 = sigma * z.x;
-        const float n1 = sigma * z.y;
-        const float n2 = sigma * z.z;
-        const float n3 = sigma * z.w;
-        o.x = m0 ? a.x + n0 : a.x;
-        o.y = m1 ? a.y + n1 : a.y;
-        o.z = m2 ? a.z + n2 : a.z;
-        o.w = m3 ? a.w + n3 : a.w;
-        store_stream(d4 + f, o);
+        store_stream(d4 + f, mutate4(vp, f, a));
       }
     }
   }
 }
 
-hipError_t launch_vary(const float* cur, float* nxt, const int4* plan, const NetDesc& nd,
-                       int pop, int crossover, float sigma, uint64_t mut_threshold,
-                       const Key& key, uint32_t gen, const float* sig_cur, float* sig_next,
-                       float tau, hipStream_t s) {
-  const int64_t groups = (nd.stride + 8191) / 8192;
-  dim3 grid((unsigned)((groups + 3) / 4), (unsigned)pop);
-  // a multiplier near pop * 0.618 that is coprime to pop
+// A multiplier near pop * 0.618 that is coprime to pop: slot = (y * mul) mod
+// pop visits every slot once and spreads the operators over the dispatch.
+uint32_t slot_multiplier(int pop) {
+  if (pop <= 1) return 1u;
   uint32_t mul = (uint32_t)(pop * 0.6180339887) | 1u;
   auto gcd = [](uint32_t a, uint32_t b) {
     while (b) {
@@ -200,8 +159,17 @@ hipError_t launch_vary(const float* cur, float* nxt, const int4* plan, const Net
     }
     return a;
   };
-  while (pop > 1 && gcd(mul, (uint32_t)pop) != 1u) ++mul;
-  if (pop == 1) mul = 1;
+  while (gcd(mul, (uint32_t)pop) != 1u) ++mul;
+  return mul;
+}
+
+hipError_t launch_vary(const float* cur, float* nxt, const int4* plan, const NetDesc& nd,
+                       int pop, int crossover, float sigma, uint64_t mut_threshold,
+                       const Key& key, uint32_t gen, const float* sig_cur, float* sig_next,
+                       float tau, hipStream_t s) {
+  const int64_t groups = (nd.stride + 8191) / 8192;
+  dim3 grid((unsigned)((groups + 3) / 4), (unsigned)pop);
+  const uint32_t mul = slot_multiplier(pop);
   if (crossover == 0)
     hipLaunchKernelGGL(vary_kernel<0>, grid, dim3(256), 0, s, cur, nxt, plan, nd.stride,
                        nd.genes, sigma, mut_threshold, key, gen, pop, mul, sig_cur, sig_next, tau);

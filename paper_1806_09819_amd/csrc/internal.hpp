@@ -25,6 +25,15 @@ hipError_t launch_draw_batch(const float* x_train, const int32_t* y_train, int64
                              const Key& key, uint32_t gen, hipStream_t s);
 hipError_t launch_pool2x2(const float* x, int64_t n, int side, float* out, hipStream_t s);
 hipError_t launch_fill(float* p, int n, float v, hipStream_t s);
+uint32_t slot_multiplier(int pop);
+
+// fused.hip: variation + small-batch evaluation in one kernel
+bool fused_supported(const NetDesc& nd, int b);
+hipError_t launch_vary_eval(const float* cur, float* nxt, const int4* plan, const NetDesc& nd,
+                            int pop, int crossover, float sigma, uint64_t thr, const Key& key,
+                            uint32_t gen, const float* sig_cur, float* sig_next, float tau,
+                            const float* x, const int32_t* y, int b, float2* partial,
+                            hipStream_t s);
 
 // select.hip
 hipError_t launch_select(const float* f_adj, int pop, int n_elite, int n_cross, int n_trunc,

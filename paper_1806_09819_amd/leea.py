@@ -88,6 +88,8 @@ def library():
         "leea_state_bytes": [P, ctypes.POINTER(ctypes.c_size_t)],
         "leea_save": [P, P, ctypes.c_size_t],
         "leea_load": [P, P, ctypes.c_size_t],
+        "leea_set_fused_step": [P, I32],
+        "leea_crossover_mutate_evaluate": [P, P, P, I32, P, P, P],
         "leea_sigmas": [P, ctypes.POINTER(P)],
         "leea_set_sigmas": [P, P],
         "leea_pool2x2": [P, I64, I32, P, P],
@@ -241,6 +243,13 @@ class Leea:
     def crossover_mutate(self):
         _check(library().leea_crossover_mutate(self._ctx), self._ctx)
 
+    def crossover_mutate_evaluate(self, x, y):
+        f_adj, f_raw, acc = self._out(), self._out(), self._out()
+        _check(library().leea_crossover_mutate_evaluate(self._ctx, _ptr(x), _ptr(y), x.shape[0],
+                                                        _ptr(f_adj), _ptr(f_raw), _ptr(acc)),
+               self._ctx)
+        return f_adj, f_raw, acc
+
     def step(self, x, y, outputs=True):
         if outputs:
             f_adj, f_raw, acc = self._out(), self._out(), self._out()
@@ -257,6 +266,9 @@ class Leea:
         _check(library().leea_draw_batch(self._ctx, gen, _ptr(x_train), _ptr(y_train),
                                          x_train.shape[0], b, _ptr(x_out), _ptr(y_out)), self._ctx)
         return x_out, y_out
+
+    def set_fused_step(self, enable):
+        _check(library().leea_set_fused_step(self._ctx, 1 if enable else 0), self._ctx)
 
     def set_sigma(self, sigma):
         _check(library().leea_set_sigma(self._ctx, sigma), self._ctx)

@@ -85,14 +85,18 @@ def check_fitness(f_gpu, acc_gpu, f_ref, acc_ref, amb, b, label=""):
     return float(np.max(err / np.maximum(np.abs(f_ref[ok]), 1e-30))) if ok.any() else 0.0
 
 
-def teacher_forced(params, gens, x, y, check_every=1, label=""):
+def teacher_forced(params, gens, x, y, check_every=1, label="", use_step=False):
     """Run `gens` generations on the device and, teacher-forced with the
     device's float32 adjusted fitness, in the oracle; assert plans, sigma
     genes and genomes bit-exact and fitness within tolerance each generation.
+    use_step: the second half of each generation is one
+    crossover_mutate_evaluate call with the fused small-batch path allowed.
     x is the raw training set (pooled on the way when params['pool'] == 2)."""
     from oracle import leea as O
     b = params["batch"]
     run, ocfg = make_run(params, max_batch=b)
+    if use_step:
+        run.set_fused_step(True)
     widths = tuple(params["widths"])
     mode = params.get("sigma_mode", "constant")
     side = int(round(np.sqrt(x.shape[1]))) if params.get("pool", 0) else 0
@@ -117,8 +121,11 @@ def teacher_forced(params, gens, x, y, check_every=1, label=""):
         f_prev = to_np(f_adj).copy()
         xb, yb = run.draw_batch(g, xd, yd, b)
         plan, f_inh, order = run.select()
-        run.crossover_mutate()
-        f_adj, f_raw, acc = run.evaluate(xb, yb)
+        if use_step:
+            f_adj, f_raw, acc = run.crossover_mutate_evaluate(xb, yb)
+        else:
+            run.crossover_mutate()
+            f_adj, f_raw, acc = run.evaluate(xb, yb)
         ops, p1, p2, fi = O.plan(O.rank(f_prev), f_prev, ocfg, g)
         pl = to_np(plan)
         assert np.array_equal(pl[:, 1], p1) and np.array_equal(pl[:, 2], p2), g
