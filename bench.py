@@ -63,11 +63,24 @@ def vary_bytes(params, genes):
     return 4.0 * genes * (2 * n_e + 3 * n_c + 2 * n_m)
 
 
+TRAFFIC_SOURCES = ("paper_1806_09819_amd/csrc/evaluate.hip",
+                   "paper_1806_09819_amd/csrc/eval_common.hpp",
+                   "paper_1806_09819_amd/csrc/device.hpp")
+
+
+def sources_sha256(paths):
+    """sha256 over the concatenated bytes of the given repository files."""
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(os.path.join(HERE, p), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(workload_tag):
     """HBM bytes per launch of the evaluate kernel from the committed
-    rocprofv3 counter summary, or None when the kernel source has changed
+    rocprofv3 counter summary, or None when the kernel sources have changed
     since the counters were taken (or no record exists)."""
-    import hashlib
     path = os.path.join(HERE, "profiles", "pmc_traffic_evaluate.txt")
     if not os.path.exists(path):
         return None
@@ -77,9 +90,9 @@ def measured_traffic(workload_tag):
         rec = json.loads(line)
         if rec.get("workload") != workload_tag:
             continue
-        src = os.path.join(HERE, rec["source"])
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        return float(rec["hbm_bytes_per_launch"]) if sha == rec["source_sha256"] else None
+        if rec.get("sources_sha256") != sources_sha256(rec.get("sources", ())):
+            return None
+        return float(rec["hbm_bytes_per_launch"])
     return None
 
 
@@ -193,7 +206,7 @@ def roofline_of(params, r, b):
     return roof
 
 
-def cpu_baseline(params, b, min_seconds=10.0, max_gens=3):
+def cpu_baseline(params, b, min_seconds=12.0, max_gens=8):
     """The oracle (numpy: float64 forward and fitness, float32 genetic
     operators) running whole generations of the same workload -- rank, plan,
     vary and evaluate every slot -- until at least min_seconds have passed

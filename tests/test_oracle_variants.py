@@ -52,6 +52,11 @@ def test_pool2x2_hand_example_and_brute_force():
             for c in range(14):
                 assert out[n, r * 14 + c] == max(im[2 * r, 2 * c], im[2 * r, 2 * c + 1],
                                                  im[2 * r + 1, 2 * c], im[2 * r + 1, 2 * c + 1])
+    nan_img = np.zeros((1, 16), dtype=F32)
+    nan_img[0, 5] = np.nan          # window (0, 0)
+    nan_img[0, 15] = np.nan         # window (1, 1)
+    got = L.pool2x2(nan_img, 4)[0]
+    assert np.isnan(got[0]) and np.isnan(got[3]) and got[1] == 0 and got[2] == 0
 
 
 def test_paper_network_on_pooled_inputs_has_92k_params():
