@@ -1,0 +1,180 @@
+"""Reduced-precision evaluation of the population (oracle side; test
+infrastructure only).
+
+The paper evaluates in float32.  The reduced-precision variants change only
+the first layer, the product of the shared batch with every network's
+first weight matrix (section 3.3), which holds most of the weights and
+FLOPs; the per-network rest of the forward pass and the fitness (Eq. 1)
+stay as in ``leea.forward``:
+
+* ``bf16``: the batch X and the weights W_1 are rounded to bfloat16
+  (8 significant bits, float32's exponent range; round to nearest, ties to
+  even).  Products of two such values are exact in float32, so the layer is
+  a sum of exact products: the device accumulates it in float32, the
+  oracle in float64.
+* ``fp8``: OCP FP8 E4M3 (1 sign, 4 exponent bits with bias 7, 3 mantissa
+  bits; largest finite value 448, no infinities, subnormals down to 2^-9)
+  with power-of-two scales: W_1 of each network is divided by 2^e_w and X
+  by 2^e_x, rounded to E4M3 (nearest, ties to even), and the product is
+  multiplied back by 2^(e_w + e_x).  e is the smallest integer with
+  amax <= 448 * 2^e, amax the largest magnitude of the operand (per network
+  for W_1, per batch for X), so no scaled value exceeds 448.  An operand
+  holding NaN or an infinity makes the fitness of the affected networks NaN.
+
+Scaling by powers of two and products of these short significands are
+exact in float64; beyond the quantisation itself the oracle rounds only in
+its float64 sums.
+"""
+
+import math
+
+import numpy as np
+
+from . import leea as L
+
+BF16 = "bf16"
+FP8 = "fp8"
+F32 = "f32"
+E4M3_MAX = 448.0
+
+
+def round_bf16(x):
+    """Nearest bfloat16 value of each float32 element, ties to even; NaN and
+    infinities are kept.  Dropping the low 16 bits of the float32 encoding
+    with a round-half-even carry is exactly that rounding (the encoding is
+    monotone in the magnitude and the carry may overflow into the exponent,
+    which is the correct next binade or infinity)."""
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    u = a.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    r = ((u + 0x7FFF + lsb) & 0xFFFF0000).astype(np.uint32)
+    out = r.view(np.float32).copy()
+    nan = np.isnan(a)
+    out[nan] = np.nan
+    return out
+
+
+def e4m3_table():
+    """The 127 non-negative finite E4M3 values, indexed by their 7-bit code
+    (exponent field e, mantissa field m): m * 2^-9 for e = 0 (subnormal),
+    (1 + m/8) * 2^(e-7) otherwise; code 127 (e = 15, m = 7) is NaN."""
+    vals = []
+    for code in range(127):
+        e, m = code >> 3, code & 7
+        vals.append(m * 2.0**-9 if e == 0 else (1.0 + m / 8.0) * 2.0**(e - 7))
+    return np.array(vals, dtype=np.float64)
+
+
+_E4M3 = e4m3_table()
+
+
+def round_e4m3_codes(v):
+    """E4M3 code (sign bit 7, magnitude code in bits 0..6) of the nearest
+    value to each float64 element with |v| <= 448, ties to the even code
+    (the one with an even mantissa).  NaN gives code 0x7F."""
+    v = np.asarray(v, dtype=np.float64)
+    a = np.abs(v)
+    nan = np.isnan(v)
+    if np.any(a[~nan] > E4M3_MAX):
+        raise ValueError("value beyond the E4M3 range after scaling")
+    a = np.where(nan, 0.0, a)
+    hi = np.searchsorted(_E4M3, a, side="left")          # first table value >= a
+    hi = np.minimum(hi, len(_E4M3) - 1)
+    lo = np.maximum(hi - 1, 0)
+    dlo = a - _E4M3[lo]
+    dhi = _E4M3[hi] - a
+    pick_hi = (dhi < dlo) | ((dhi == dlo) & (hi % 2 == 0))
+    code = np.where(pick_hi, hi, lo)
+    code = np.where(a == _E4M3[hi], hi, code)
+    sign = (np.signbit(v) & ~nan).astype(np.int64) << 7
+    return np.where(nan, 0x7F, code | sign).astype(np.uint8)
+
+
+def e4m3_value(codes):
+    """float64 value of E4M3 codes (0x7F / 0xFF are NaN)."""
+    c = np.asarray(codes, dtype=np.int64)
+    mag = c & 0x7F
+    val = np.where(mag == 0x7F, np.nan, _E4M3[np.minimum(mag, 126)])
+    return np.where(c & 0x80, -val, val)
+
+
+def round_e4m3(v):
+    """Nearest E4M3 value (float64) of each element with |v| <= 448."""
+    return e4m3_value(round_e4m3_codes(v))
+
+
+def fp8_exponent(amax):
+    """Smallest integer e with amax <= 448 * 2^e (0 for amax = 0).  amax is
+    a non-negative finite number; every comparison is exact."""
+    amax = float(amax)
+    if not math.isfinite(amax) or amax < 0:
+        raise ValueError("amax must be finite and non-negative")
+    if amax == 0.0:
+        return 0
+    _, k = math.frexp(amax)                  # amax in [2^(k-1), 2^k)
+    e = k - 9                                # 448 * 2^(k-9) < 2^k
+    while amax > E4M3_MAX * 2.0**e:
+        e += 1
+    while amax <= E4M3_MAX * 2.0**(e - 1):
+        e -= 1
+    return e
+
+
+def quantize_fp8(a):
+    """(values, e): a (float32) divided by 2^e, rounded to E4M3, as float64
+    values still scaled by 2^-e; e from the operand's largest magnitude.
+    Returns (None, None) if a holds NaN or an infinity."""
+    a = np.asarray(a, dtype=np.float64)
+    if not np.all(np.isfinite(a)):
+        return None, None
+    e = fp8_exponent(np.max(np.abs(a)) if a.size else 0.0)
+    return round_e4m3(a * 2.0**-e), e
+
+
+def layer1_operands(genome, widths, x, dtype):
+    """(Xq, Wq, factor) such that the first layer's product is
+    factor * Xq Wq^T exactly; Xq / Wq are None when an fp8 operand is not
+    finite (the network's fitness is NaN)."""
+    W1 = L.unpack(np.asarray(genome), widths)[0][0]
+    if dtype == BF16:
+        return (round_bf16(x).astype(np.float64), round_bf16(W1).astype(np.float64), 1.0)
+    if dtype == FP8:
+        xq, ex = quantize_fp8(x)
+        wq, ew = quantize_fp8(W1)
+        if xq is None or wq is None:
+            return None, None, None
+        return xq, wq, 2.0**(ex + ew)
+    if dtype == F32:
+        return (np.asarray(x, dtype=np.float64), W1.astype(np.float64), 1.0)
+    raise ValueError("unknown dtype %r" % (dtype,))
+
+
+def forward_lowp(genome, widths, x, dtype):
+    """Logits (float64) of one network with the first layer in `dtype`."""
+    layers = L.unpack(np.asarray(genome), widths)
+    xq, wq, factor = layer1_operands(genome, widths, x, dtype)
+    n = np.asarray(x).shape[0]
+    if xq is None:
+        return np.full((n, widths[-1]), np.nan)
+    h = factor * (xq @ wq.T) + layers[0][1].astype(np.float64)
+    for l, (W, b) in enumerate(layers):
+        if l > 0:
+            h = h @ W.astype(np.float64).T + b.astype(np.float64)
+        if l < len(layers) - 1:
+            h = np.maximum(h, 0.0)
+    return h
+
+
+def evaluate_lowp(pop, widths, x, y, dtype):
+    """Raw fitness and accuracy of every network with the first layer in
+    `dtype` (float64 everywhere else)."""
+    P = pop.shape[0]
+    f = np.empty(P, dtype=np.float64)
+    acc = np.empty(P, dtype=np.float64)
+    for j in range(P):
+        z = forward_lowp(pop[j], widths, x, dtype)
+        if np.isnan(z).any():
+            f[j], acc[j] = np.nan, np.nan
+        else:
+            f[j], acc[j] = L.fitness_from_logits(z, y)
+    return f, acc

@@ -1,0 +1,169 @@
+"""Pins for the reduced-precision oracle (first layer in bfloat16 or OCP
+FP8 E4M3 with power-of-two scales): the roundings against torch's own
+casts and against brute force over the formats' value grids, the scale
+rule in closed form, and the forward pass against the float64 forward on
+inputs that every format represents exactly."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import leea as L
+from oracle import precision as Q
+
+F32 = np.float32
+
+
+def _grid_values(n, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mant = rng.random(n) + 1.0
+    expo = rng.integers(-40, 40, n)
+    sign = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    return (sign * mant * 2.0**expo).astype(F32)
+
+
+def test_round_bf16_matches_torch_cast():
+    x = _grid_values(400000, 0)
+    # exact ties: low 16 bits 0x8000, both parities of the kept part
+    u = _grid_values(2000, 1).view(np.uint32)
+    ties = ((u & 0xFFFF0000) | 0x8000).view(F32)
+    special = np.array([0.0, -0.0, np.inf, -np.inf, np.finfo(F32).max, np.finfo(F32).tiny,
+                        1e-45, 1.0, 1.0 + 2**-8, 1.0 + 3 * 2**-8], dtype=F32)
+    for arr in (x, ties, special):
+        ref = torch.from_numpy(arr).to(torch.bfloat16).float().numpy()
+        got = Q.round_bf16(arr)
+        assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+    assert np.isnan(Q.round_bf16(np.array([np.nan], dtype=F32))[0])
+
+
+def test_round_bf16_brute_force_nearest():
+    x = _grid_values(300, 2)
+    for v in x:
+        u = int(np.array([v], dtype=F32).view(np.uint32)[0])
+        lo = np.array([u & 0xFFFF0000], dtype=np.uint32).view(F32)[0]
+        hi = np.array([(u & 0xFFFF0000) + 0x10000], dtype=np.uint32).view(F32)[0]
+        fv, flo, fhi = Fraction(float(v)), Fraction(float(lo)), Fraction(float(hi))
+        dlo, dhi = abs(fv - flo), abs(fhi - fv)
+        if dlo < dhi:
+            want = lo
+        elif dhi < dlo:
+            want = hi
+        else:
+            want = lo if ((u >> 16) & 1) == 0 else hi
+        assert Q.round_bf16(np.array([v], dtype=F32))[0] == want
+
+
+def test_e4m3_table_known_values():
+    t = Q.e4m3_table()
+    assert len(t) == 127
+    assert t[0] == 0.0 and t[1] == 2.0**-9 and t[7] == 7 * 2.0**-9
+    assert t[8] == 2.0**-6                    # smallest normal
+    assert t[0x38] == 1.0
+    assert t[126] == 448.0 == Q.E4M3_MAX
+    assert np.all(np.diff(t) > 0)
+    assert np.isnan(Q.e4m3_value(0x7F)) and np.isnan(Q.e4m3_value(0xFF))
+    assert Q.e4m3_value(0x80 | 0x38) == -1.0
+
+
+def test_round_e4m3_matches_torch_cast():
+    t = Q.e4m3_table()
+    mids = (t[1:] + t[:-1]) / 2                               # every tie
+    rng = np.random.Generator(np.random.PCG64(3))
+    dense = rng.uniform(-448, 448, 200000)
+    small = rng.uniform(-2.0**-5, 2.0**-5, 50000)             # subnormal range
+    for arr in (mids, -mids, dense, small, t, -t):
+        arr32 = arr.astype(F32)
+        ref = torch.from_numpy(arr32).to(torch.float8_e4m3fn).float().numpy().astype(np.float64)
+        got = Q.round_e4m3(arr32.astype(np.float64))
+        assert np.array_equal(got, ref)
+    with pytest.raises(ValueError):
+        Q.round_e4m3(np.array([449.0]))
+
+
+def test_round_e4m3_brute_force_nearest_even():
+    t = Q.e4m3_table()
+    rng = np.random.Generator(np.random.PCG64(4))
+    vals = np.concatenate([rng.uniform(0, 448, 500), (t[1:] + t[:-1]) / 2])
+    for v in vals:
+        d = np.abs(t - v)
+        best = np.flatnonzero(d == d.min())
+        want = best[0] if len(best) == 1 else [c for c in best if c % 2 == 0][0]
+        assert Q.round_e4m3_codes(np.array([v]))[0] == want
+
+
+def test_fp8_exponent_closed_form():
+    assert Q.fp8_exponent(0.0) == 0
+    assert Q.fp8_exponent(448.0) == 0
+    assert Q.fp8_exponent(np.nextafter(448.0, 1e9)) == 1
+    assert Q.fp8_exponent(224.0) == -1
+    assert Q.fp8_exponent(1.0) == -8          # 448 / 256 = 1.75 >= 1 > 0.875
+    rng = np.random.Generator(np.random.PCG64(5))
+    for a in np.exp(rng.uniform(-60, 60, 2000)):
+        e = Q.fp8_exponent(a)
+        assert a <= 448.0 * 2.0**e and a > 448.0 * 2.0**(e - 1)
+
+
+def test_quantize_fp8_scale_equivariance():
+    rng = np.random.Generator(np.random.PCG64(6))
+    a = (rng.standard_normal(5000) * 0.05).astype(F32)
+    q, e = Q.quantize_fp8(a)
+    assert np.max(np.abs(q)) <= 448.0 and np.max(np.abs(q)) > 224.0 - 16.0
+    for k in (-5, 3, 20):
+        q2, e2 = Q.quantize_fp8((a.astype(np.float64) * 2.0**k).astype(F32))
+        assert e2 == e + k and np.array_equal(q2, q)
+    assert Q.quantize_fp8(np.array([1.0, np.nan], dtype=F32)) == (None, None)
+
+
+def _tiny_net(widths, rng, scale):
+    c = L.param_count(widths)
+    g = np.zeros(c, dtype=F32)
+    # dyadic weights with 3 significant bits: exact in bf16 and (scaled) E4M3
+    g[:] = (rng.integers(-7, 8, c) * 2.0**-scale).astype(F32)
+    return g
+
+
+def test_forward_lowp_reduces_to_forward_on_representable_values():
+    rng = np.random.Generator(np.random.PCG64(7))
+    widths = (12, 8, 5, 3)
+    g = _tiny_net(widths, rng, 6)
+    x = (rng.integers(0, 8, (9, 12)) * 2.0**-3).astype(F32)
+    ref = L.forward(g, widths, x)
+    for dt in (Q.F32, Q.BF16, Q.FP8):
+        assert np.array_equal(Q.forward_lowp(g, widths, x, dt), ref), dt
+
+
+def test_forward_lowp_error_within_quantisation_bound():
+    rng = np.random.Generator(np.random.PCG64(8))
+    widths = (64, 16, 4)
+    g = (rng.standard_normal(L.param_count(widths)) * 0.1).astype(F32)
+    x = rng.random((20, 64)).astype(F32)
+    W1 = L.unpack(g, widths)[0][0].astype(np.float64)
+    mag = np.abs(x.astype(np.float64)) @ np.abs(W1).T      # sum |x||w| per unit
+    exact = x.astype(np.float64) @ W1.T
+    for dt, u in ((Q.BF16, 2.0**-8), (Q.FP8, 2.0**-4)):
+        xq, wq, fac = Q.layer1_operands(g, widths, x, dt)
+        got = fac * (xq @ wq.T)
+        # each operand carries relative error <= u (normals); fp8 subnormals
+        # add an absolute 2^-10 * 2^e per operand
+        bound = mag * (2 * u + u * u)
+        if dt == Q.FP8:
+            ex = Q.fp8_exponent(np.abs(x).max())
+            ew = Q.fp8_exponent(np.abs(W1).max())
+            sub = 2.0**-10
+            bound += (np.abs(x).sum(1)[:, None] * sub * 2.0**ew
+                      + (np.abs(W1).sum(1)[None, :] * sub * 2.0**ex) + 64 * sub * sub * 2.0**(ex + ew)) * 1.01
+        assert np.all(np.abs(got - exact) <= bound + 1e-15), dt
+        assert np.any(got != exact), dt
+
+
+def test_lowp_nan_operands_give_nan_fitness():
+    rng = np.random.Generator(np.random.PCG64(9))
+    widths = (8, 4, 3)
+    pop = (rng.standard_normal((3, L.param_count(widths))) * 0.3).astype(F32)
+    pop[1, 5] = np.nan
+    x = rng.random((6, 8)).astype(F32)
+    y = rng.integers(0, 3, 6)
+    for dt in (Q.BF16, Q.FP8):
+        f, _ = Q.evaluate_lowp(pop, widths, x, y, dt)
+        assert np.isnan(f[1]) and np.isfinite(f[0]) and np.isfinite(f[2])
