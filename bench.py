@@ -29,16 +29,18 @@ if HERE not in sys.path:
 METRIC = "network-sample evals/s (pop×batch fwd+fitness), gens/s vs plain FP32, same acc"
 HBM_PEAK = 8.0e12          # bytes/s, MI355X HBM3E
 MFMA_F32_PEAK = 157.3e12   # FLOP/s, MI355X dense FP32 matrix
+MFMA_PEAK = {"f32": MFMA_F32_PEAK, "bf16": 2.5e15, "fp8": 5.0e15}   # dense, per operand type
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def workload(batch):
+def workload(batch, eval_dtype="f32"):
     from paper_1806_09819_amd import presets
     p = dict(presets.PAPER)
     p["batch"] = batch
+    p["eval_dtype"] = eval_dtype
     return p
 
 
@@ -191,15 +193,17 @@ def roofline_of(params, r, b):
                     per_launch=dict(bytes=nbytes, avg_ms=r["phases_ms"]["vary+evaluate"]))
     flops, nbytes = algorithmic(params, r["genes"], b)
     sec = r["phases_ms"]["evaluate"] * 1e-3
-    if flops / nbytes > MFMA_F32_PEAK / HBM_PEAK:
+    peak = MFMA_PEAK[params.get("eval_dtype", "f32")]
+    if flops / nbytes > peak / HBM_PEAK:
         achieved = flops / sec / 1e12
-        roof = dict(bound="mfma", achieved=achieved, peak=MFMA_F32_PEAK / 1e12,
-                    unit="TFLOP/s", frac=achieved / (MFMA_F32_PEAK / 1e12))
+        roof = dict(bound="mfma", achieved=achieved, peak=peak / 1e12,
+                    unit="TFLOP/s", frac=achieved / (peak / 1e12))
     else:
         achieved = nbytes / sec / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK / 1e9, unit="GB/s",
                     frac=achieved / (HBM_PEAK / 1e9))
-    roof["traffic"] = measured_traffic("paper_b%d" % b)
+    roof["traffic"] = (measured_traffic("paper_b%d" % b)
+                       if params.get("eval_dtype", "f32") == "f32" else None)
     roof["vary_hbm_frac"] = vary_bytes(params, r["stride"]) / (r["phases_ms"]["vary"] * 1e-3) / HBM_PEAK
     roof["kernel"] = "evaluate (fused forward + fitness, one launch per generation)"
     roof["per_launch"] = dict(flops=flops, bytes=nbytes, avg_ms=r["phases_ms"]["evaluate"])
@@ -255,6 +259,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--sweep-steps", type=int, default=50)
+    ap.add_argument("--eval-dtype", default="f32", choices=("f32", "bf16", "fp8"),
+                    help="arithmetic of the first layer (bf16 / fp8: reduced-precision variants)")
     ap.add_argument("--fused", action="store_true",
                     help="time the fused variation + evaluation call at batch <= 16")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="BYTES",
@@ -285,7 +291,7 @@ def main():
     x_train = torch.from_numpy(data["x_train"]).cuda()
     y_train = torch.from_numpy(data["y_train"]).cuda()
 
-    params = workload(args.batch)
+    params = workload(args.batch, args.eval_dtype)
     log("bench: timed run, batch", args.batch)
     r = run_gpu(params, args.steps, args.warmup, x_train, y_train, fused=args.fused)
     P, b, K = params["pop"], args.batch, args.steps
@@ -303,7 +309,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": args.eval_dtype,
         "data": "synthetic",
         "config": {
             "workload": "paper-scale LEEA generation: MLP 784-112-32-10 (91,866 params), "
@@ -311,6 +317,7 @@ def main():
                         "0.05/0.50/0.45, sigma 0.001, rho 0.5, alpha 1; synthetic 10-prototype "
                         "Gaussian inputs (45k train set in HBM)" % b,
             "widths": list(params["widths"]), "pop": P, "batch": b,
+            "first_layer": args.eval_dtype,
             "gens_per_s": K / r["seconds"],
         },
         "phases_ms": phases,
@@ -322,7 +329,7 @@ def main():
             if bb == b:
                 continue
             log("bench: sweep batch", bb)
-            pb = workload(bb)
+            pb = workload(bb, args.eval_dtype)
             rs = run_gpu(pb, args.sweep_steps, 3, x_train, y_train, fused=args.fused)
             rf = roofline_of(pb, rs, bb)
             sweep.append(dict(batch=bb, value=P * bb * args.sweep_steps / rs["seconds"],

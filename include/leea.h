@@ -76,6 +76,19 @@ enum { LEEA_OP_ELITE = 0, LEEA_OP_CROSSOVER = 1, LEEA_OP_MUTATION = 2 };
  * self-adaptive, where every individual carries a sigma gene (see
  * leea_crossover_mutate). */
 enum { LEEA_SIGMA_CONSTANT = 0, LEEA_SIGMA_DECAY = 1, LEEA_SIGMA_SELF_ADAPTIVE = 2 };
+/* Arithmetic of the first layer, the shared-batch product X W_1^T of the
+ * whole population (section 3.3); every other layer, the fitness (Eq. 1)
+ * and the genomes stay float32.
+ * F32:  float32 operands (the paper's arithmetic).
+ * BF16: X and W_1 rounded to bfloat16 (nearest, ties to even), products
+ *       summed in float32 on the bf16 matrix cores.
+ * FP8:  OCP FP8 E4M3 with power-of-two scales: X / 2^e_x and W_1 / 2^e_w
+ *       rounded to E4M3 (nearest, ties to even), e the smallest integer with
+ *       amax <= 448 * 2^e (amax = largest |value| of the batch, resp. of each
+ *       network's W_1), products summed in float32 and multiplied by
+ *       2^(e_x + e_w).  A batch holding NaN or an infinity gives every
+ *       network a NaN fitness; such a W_1 gives its network a NaN fitness. */
+enum { LEEA_DT_F32 = 0, LEEA_DT_BF16 = 1, LEEA_DT_FP8 = 2 };
 
 /* Hyperparameters of one EA run.  Counts are integers: the caller rounds
  * the paper's fractions p_E*lambda, p_C*lambda, p_M*lambda and rho*lambda
@@ -103,6 +116,7 @@ typedef struct {
   float tau;                              /* self-adaptation rate in [0, 10]; 0 = 1/sqrt(genes) */
   int32_t input_pool;                     /* 0, or 2: draw_batch max-pools 2x2 from square images
                                              of 4*widths[0] pixels (section 4.1) */
+  int32_t eval_dtype;                     /* LEEA_DT_*: arithmetic of the first layer */
 } leea_config;
 
 /* Genes per network (c) and the padded per-individual stride in floats. */

@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libleea.so")
-SOURCES = ("api.hip", "genetic.hip", "rng.hip", "select.hip", "evaluate.hip", "fused.hip")
+SOURCES = ("api.hip", "genetic.hip", "rng.hip", "select.hip", "evaluate.hip", "fused.hip",
+           "evaluate_lp.hip", "quant.hip")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -47,6 +47,11 @@ struct leea_ctx {
   int has_inh;
   float sigma;
   int fused;       // leea_step may fuse variation and small-batch evaluation
+  int dt;          // arithmetic of the first layer (LEEA_DT_*)
+  int kp;          // n0 rounded up to 32 (packed quantised batch row)
+  uint32_t* w_amax[2];  // FP8: largest |W_1| of each network (ping-pong with the genomes)
+  uint32_t* x_amax;     // FP8: largest |x| of the batch being evaluated
+  void* xq;             // quantised batch (values [b][n0] or packed [b][kp])
   std::string err;
 };
 
@@ -118,6 +123,8 @@ leea_status validate(const leea_config* cfg, NetDesc* nd) {
     return fail(nullptr, LEEA_EINVAL, "tau must be in [0, 10]");
   if (cfg->input_pool != 0 && cfg->input_pool != 2)
     return fail(nullptr, LEEA_EINVAL, "input_pool must be 0 or 2");
+  if (cfg->eval_dtype < LEEA_DT_F32 || cfg->eval_dtype > LEEA_DT_FP8)
+    return fail(nullptr, LEEA_EINVAL, "unknown eval_dtype");
   if (cfg->input_pool == 2) {
     const int64_t raw = 4ll * cfg->widths[0];
     int64_t side = (int64_t)sqrt((double)raw);
@@ -142,6 +149,9 @@ leea_status validate(const leea_config* cfg, NetDesc* nd) {
     return fail(nullptr, LEEA_EINVAL, "population too large");
   if (d.stride > 0xFFFFFFFFll * 4)
     return fail(nullptr, LEEA_EINVAL, "network too large for 32-bit gene blocks");
+  if (cfg->eval_dtype != LEEA_DT_F32 && cfg->max_batch > 16 &&
+      !eval_lp_supported(d, cfg->max_batch, cfg->eval_dtype))
+    return fail(nullptr, LEEA_EINVAL, "reduced-precision evaluation does not fit these widths");
   if (nd) *nd = d;
   return LEEA_OK;
 }
@@ -149,8 +159,10 @@ leea_status validate(const leea_config* cfg, NetDesc* nd) {
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Carve {
-  size_t genomes, scalars, plan, order, partial, total;
+  size_t genomes, scalars, plan, order, partial, xq, total;
 };
+
+int padded_k(int n0) { return (n0 + 31) & ~31; }
 
 Carve carve(const leea_config* cfg, const NetDesc& nd) {
   Carve c;
@@ -161,7 +173,14 @@ Carve carve(const leea_config* cfg, const NetDesc& nd) {
   c.plan = align256(P * 16);
   c.order = align256(P * 4);
   c.partial = align256(P * (size_t)n_mt * 8);
-  c.total = 2 * c.genomes + 7 * c.scalars + c.plan + c.order + c.partial;
+  c.xq = 0;
+  if (cfg->eval_dtype != LEEA_DT_F32) {
+    const size_t row = (size_t)nd.w[0] * 4 > (size_t)padded_k(nd.w[0]) * 2
+                           ? (size_t)nd.w[0] * 4
+                           : (size_t)padded_k(nd.w[0]) * 2;
+    c.xq = align256((size_t)cfg->max_batch * row) + 256;  // + the batch amax
+  }
+  c.total = 2 * c.genomes + 9 * c.scalars + c.plan + c.order + c.partial + c.xq;
   return c;
 }
 
@@ -180,13 +199,50 @@ leea_status check_batch(leea_ctx* c, const float* x, const int32_t* y, int32_t b
   return LEEA_OK;
 }
 
+// Reduced-precision first layer: batch amax (FP8), the quantised batch, then
+// the small-batch kernel on quantised values (b <= 16) or the bf16 / FP8
+// matrix-core kernel.  Returns the number of partial row tiles.
+leea_status run_eval_lp(leea_ctx* c, const float* x, const int32_t* y, int32_t b, int* n_mt) {
+  const int n0 = c->nd.w[0];
+  leea_status st = LEEA_OK;
+  if (c->dt == LEEA_DT_FP8) {
+    st = dev(c, launch_fill((float*)c->x_amax, 1, 0.0f, c->stream), "amax clear");
+    if (!st)
+      st = dev(c, launch_amax(x, (int64_t)b * n0, c->x_amax, c->stream), "amax launch");
+    if (st) return st;
+  }
+  const bool small = b <= 16;
+  if (!small && !eval_lp_supported(c->nd, b, c->dt))
+    return fail(c, LEEA_EINVAL, "reduced-precision evaluation does not fit this batch");
+  st = dev(c, launch_quantize_x(c->dt, !small, x, b, n0, c->kp, c->x_amax, c->xq, c->stream),
+           "quantize launch");
+  if (st) return st;
+  if (small) {
+    *n_mt = 1;
+    return dev(c, launch_evaluate_small_lp(c->dt, c->genomes[c->cur], c->nd, c->cfg.pop,
+                                           (const float*)c->xq, y, b, c->partial,
+                                           c->w_amax[c->cur], c->x_amax, c->stream),
+               "evaluate launch");
+  }
+  *n_mt = eval_lp_ptiles(c->nd, b, c->dt);
+  return dev(c, launch_evaluate_lp(c->dt, c->genomes[c->cur], c->nd, c->cfg.pop, c->xq, c->kp,
+                                   c->w_amax[c->cur], c->x_amax, y, b, c->partial, c->stream),
+             "evaluate launch");
+}
+
 leea_status run_eval(leea_ctx* c, const float* x, const int32_t* y, int32_t b, bool update,
                      float* f_adj, float* f_raw, float* acc) {
-  leea_status st = dev(c, launch_evaluate(c->genomes[c->cur], c->nd, c->cfg.pop, x, y, b,
-                                          c->partial, c->stream),
-                       "evaluate launch");
+  int n_mt = 1;
+  leea_status st;
+  if (c->dt == LEEA_DT_F32) {
+    st = dev(c, launch_evaluate(c->genomes[c->cur], c->nd, c->cfg.pop, x, y, b, c->partial,
+                                c->stream),
+             "evaluate launch");
+    n_mt = eval_mtiles(c->nd, b);
+  } else {
+    st = run_eval_lp(c, x, y, b, &n_mt);
+  }
   if (st) return st;
-  const int n_mt = eval_mtiles(c->nd, b);
   const int use_inh = update && c->has_inh && c->cfg.alpha != 1.0f;
   st = dev(c, launch_finalize(c->partial, c->cfg.pop, n_mt, b, c->f_inh, use_inh, c->cfg.alpha,
                               update ? c->f_adj : nullptr, update ? c->f_raw : nullptr,
@@ -257,6 +313,15 @@ leea_status leea_init_population(const leea_config* cfg, void* workspace, size_t
   c->sig[0] = (float*)p;
   p += cv.scalars;
   c->sig[1] = (float*)p;
+  p += cv.scalars;
+  c->w_amax[0] = (uint32_t*)p;
+  p += cv.scalars;
+  c->w_amax[1] = (uint32_t*)p;
+  p += cv.scalars;
+  c->x_amax = cv.xq ? (uint32_t*)p : nullptr;
+  c->xq = cv.xq ? (void*)(p + 256) : nullptr;
+  c->dt = cfg->eval_dtype;
+  c->kp = padded_k(nd.w[0]);
   c->n_mt_max = (cfg->max_batch + 63) / 64;
   c->side = 0;
   if (cfg->input_pool == 2) {
@@ -277,6 +342,9 @@ leea_status leea_init_population(const leea_config* cfg, void* workspace, size_t
            "init launch");
   if (!st && cfg->sigma_mode == LEEA_SIGMA_SELF_ADAPTIVE)
     st = dev(nullptr, launch_fill(c->sig[0], cfg->pop, cfg->sigma, c->stream), "sigma fill");
+  if (!st && c->dt == LEEA_DT_FP8)
+    st = dev(nullptr, launch_amax_w1(c->genomes[0], nd, cfg->pop, c->w_amax[0], c->stream),
+             "amax launch");
   if (st) {
     delete c;
     return st;
@@ -385,11 +453,15 @@ leea_status leea_crossover_mutate(leea_ctx* c) {
   const float* sig_cur;
   float* sig_next;
   vary_sigma(c, g, &sigma, &sig_cur, &sig_next);
-  leea_status st = dev(c,
-                       launch_vary(c->genomes[c->cur], c->genomes[c->cur ^ 1], c->plan, c->nd,
-                                   c->cfg.pop, c->cfg.crossover, sigma, c->cfg.mut_threshold,
-                                   key_of(c), g, sig_cur, sig_next, c->tau, c->stream),
-                       "vary launch");
+  uint32_t* amax = c->dt == LEEA_DT_FP8 ? c->w_amax[c->cur ^ 1] : nullptr;
+  leea_status st = LEEA_OK;
+  if (amax) st = dev(c, launch_fill((float*)amax, c->cfg.pop, 0.0f, c->stream), "amax clear");
+  if (st) return st;
+  st = dev(c,
+           launch_vary(c->genomes[c->cur], c->genomes[c->cur ^ 1], c->plan, c->nd, c->cfg.pop,
+                       c->cfg.crossover, sigma, c->cfg.mut_threshold, key_of(c), g, sig_cur,
+                       sig_next, c->tau, amax, c->stream),
+           "vary launch");
   if (st) return st;
   advance(c);
   return LEEA_OK;
@@ -402,7 +474,7 @@ leea_status leea_crossover_mutate_evaluate(leea_ctx* c, const float* x, const in
     return fail(c, LEEA_ESTATE, "crossover_mutate_evaluate needs a select first");
   leea_status st = check_batch(c, x, y, b);
   if (st) return st;
-  if (!(c->fused && fused_supported(c->nd, b))) {
+  if (!(c->fused && c->dt == LEEA_DT_F32 && fused_supported(c->nd, b))) {
     st = leea_crossover_mutate(c);
     if (st) return st;
     return leea_evaluate(c, x, y, b, f_adj, f_raw, acc);
@@ -499,6 +571,9 @@ leea_status leea_set_state(leea_ctx* c, const float* src, const float* f_adj,
   if (!st && f_inh)
     st = dev(c, hipMemcpyAsync(c->f_inh, f_inh, sbytes, hipMemcpyDeviceToDevice, c->stream),
              "f_inh copy");
+  if (!st && src && c->dt == LEEA_DT_FP8)
+    st = dev(c, launch_amax_w1(c->genomes[c->cur], c->nd, c->cfg.pop, c->w_amax[c->cur],
+                               c->stream), "amax launch");
   if (st) return st;
   c->has_inh = f_inh ? 1 : 0;
   c->state = f_adj ? kEvaluated : kNeedEval;
@@ -574,6 +649,9 @@ leea_status leea_load(leea_ctx* c, const void* host_buf, size_t bytes) {
     st = dev(c, hipMemcpy(arr[i], p, sbytes, hipMemcpyHostToDevice), "load");
     p += sbytes;
   }
+  if (!st && c->dt == LEEA_DT_FP8)
+    st = dev(c, launch_amax_w1(c->genomes[c->cur], c->nd, c->cfg.pop, c->w_amax[c->cur],
+                               c->stream), "amax launch");
   if (st) return st;
   c->gen = h.gen;
   // a checkpoint taken between select and crossover_mutate resumes at select

@@ -47,7 +47,12 @@ struct EvalLds {
 // out = act(in * W^T + bias).  `in` (LDS, row stride ldi) must hold zeros in
 // columns [n_in, round16(n_in)); `out` gets zeros in [n_out, round16(n_out)).
 // W is [n_out][n_in] row-major in global memory with n_in and the matrix
-// offset multiples of 4; all fragments of a tile are loaded before its MFMAs.
+// offset multiples of 4.  A wave loads the weight fragments of one column
+// tile once and runs G row tiles at a time on independent accumulators, so
+// the matrix-core chains overlap (G = 1 for register-tight kernels); every
+// output tile accumulates its K range in the same order (s = 0, 1, ... and
+// e = 0..3 inside a super-step) whatever G is.
+template <int G>
 static __device__ void mfma_layer(const float* in, int ldi, int n_in, float* out, int ldo, int n_out,
                            const float* W, const float* bias, bool relu, int mtiles) {
   const int wave = threadIdx.x >> 6;
@@ -56,9 +61,17 @@ static __device__ void mfma_layer(const float* in, int ldi, int n_in, float* out
   const int kq = lane >> 4;
   const int ntiles = (n_out + 15) >> 4;
   const int kss = (n_in + 15) >> 4;  // <= 16: widths are at most 256
-  for (int item = wave; item < mtiles * ntiles; item += 4) {
-    const int mt = item / ntiles;
-    const int nt = item - mt * ntiles;
+  // (nt, mt) work of this wave: column tiles nt0, nt0 + nstep, ...; for each
+  // of them row tiles mt0, mt0 + mstep, ...
+  int nt0, nstep, mt0, mstep;
+  if (ntiles >= 4) {
+    nt0 = wave, nstep = 4, mt0 = 0, mstep = 1;
+  } else {
+    const int per = 4 / ntiles;           // waves sharing a column tile
+    nt0 = wave % ntiles, nstep = 4, mt0 = wave / ntiles, mstep = per;
+    if (wave >= per * ntiles) nt0 = ntiles;  // idle wave (ntiles == 3)
+  }
+  for (int nt = nt0; nt < ntiles; nt += nstep) {
     const int n = nt * 16 + mn;
     const bool nv = n < n_out;
     const float* wr = W + (int64_t)(nv ? n : 0) * n_in;
@@ -68,24 +81,46 @@ static __device__ void mfma_layer(const float* in, int ldi, int n_in, float* out
       const int k = 16 * s + 4 * kq;
       bf[s] = (s < kss && nv && k < n_in) ? *reinterpret_cast<const float4*>(wr + k) : zero4();
     }
-    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-    const float* arow = in + (mt * 16 + mn) * ldi + 4 * kq;
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      if (s < kss) {
-        const float4 a = *reinterpret_cast<const float4*>(arow + 16 * s);
-        acc = mfma(a.x, bf[s].x, acc);
-        acc = mfma(a.y, bf[s].y, acc);
-        acc = mfma(a.z, bf[s].z, acc);
-        acc = mfma(a.w, bf[s].w, acc);
-      }
-    }
     const float bb = nv ? bias[n] : 0.0f;
+    for (int mt = mt0; mt < mtiles; mt += G * mstep) {
+      floatx4 acc[G];
+      const float* arow[G];
+      bool mv[G];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      float v = acc[i] + bb;
-      if (relu) v = relu_keep_nan(v);
-      out[(mt * 16 + 4 * kq + i) * ldo + n] = nv ? v : 0.0f;
+      for (int g = 0; g < G; ++g) {
+        acc[g] = floatx4{0.f, 0.f, 0.f, 0.f};
+        const int m = mt + g * mstep;
+        mv[g] = m < mtiles;
+        arow[g] = in + ((mv[g] ? m : mt) * 16 + mn) * ldi + 4 * kq;
+      }
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        if (s < kss) {
+          float4 a[G];
+#pragma unroll
+          for (int g = 0; g < G; ++g) a[g] = *reinterpret_cast<const float4*>(arow[g] + 16 * s);
+#pragma unroll
+          for (int g = 0; g < G; ++g) acc[g] = mfma(a[g].x, bf[s].x, acc[g]);
+#pragma unroll
+          for (int g = 0; g < G; ++g) acc[g] = mfma(a[g].y, bf[s].y, acc[g]);
+#pragma unroll
+          for (int g = 0; g < G; ++g) acc[g] = mfma(a[g].z, bf[s].z, acc[g]);
+#pragma unroll
+          for (int g = 0; g < G; ++g) acc[g] = mfma(a[g].w, bf[s].w, acc[g]);
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        if (mv[g]) {
+          const int m = mt + g * mstep;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            float v = acc[g][i] + bb;
+            if (relu) v = relu_keep_nan(v);
+            out[(m * 16 + 4 * kq + i) * ldo + n] = nv ? v : 0.0f;
+          }
+        }
+      }
     }
   }
 }
@@ -116,6 +151,8 @@ static __device__ void scalar_layer(const float* in, int ldi, int n_in, float* o
 // row sums go to *out in a fixed order (deterministic).
 // Layer weights come from tw: W_l at tw + (woff[l] - toff) (the genome in
 // global memory with toff = 0, or a copy of the genome's tail in LDS).
+// G: row tiles per matrix-core group in the hidden layers (see mfma_layer).
+template <int G>
 static __device__ void tail_and_fitness(float* lds, const EvalLds& lo, const NetDesc& nd,
                                  const float* tw, int64_t toff, int mtiles, int rows,
                                  int m0, const int32_t* __restrict__ y, bool tail_vec,
@@ -128,7 +165,7 @@ static __device__ void tail_and_fitness(float* lds, const EvalLds& lo, const Net
     const float* bias = tw + (nd.boff[l] - toff);
     const bool relu = l < nd.L - 1;
     if (tail_vec)
-      mfma_layer(in, ldi, nd.w[l], dst, lo.ldt, nd.w[l + 1], W, bias, relu, mtiles);
+      mfma_layer<G>(in, ldi, nd.w[l], dst, lo.ldt, nd.w[l + 1], W, bias, relu, mtiles);
     else
       scalar_layer(in, ldi, nd.w[l], dst, lo.ldt, nd.w[l + 1], W, bias, relu, 16 * mtiles);
     __syncthreads();

@@ -30,19 +30,27 @@
 // Layers 2..L run on the matrix cores too (weight fragments as float4 loads
 // from L2) whenever the hidden widths are multiples of 4, else on VALU.
 #include "eval_common.hpp"
+#include "lowp.hpp"
 
 namespace leea {
 
 // ---------------------------------------------------------------- small b --
-template <int NT>
+// DT selects the first layer's arithmetic (0 float32; 1 bfloat16, 2 FP8
+// E4M3: x holds the batch already quantised, the weight fragments are
+// quantised in registers; products of such values are exact in float32, so
+// the FP32 matrix cores sum exactly the reduced-precision products).
+template <int NT, int DT>
 __global__ __launch_bounds__(256, 4) void eval_small_kernel(const float* __restrict__ genomes,
                                                          NetDesc nd, const float* __restrict__ x,
                                                          const int32_t* __restrict__ y, int b,
                                                          float2* __restrict__ partial,
-                                                         EvalLds lo, int tail_vec) {
+                                                         EvalLds lo, int tail_vec,
+                                                         const uint32_t* __restrict__ w_amax,
+                                                         const uint32_t* __restrict__ x_amax) {
   extern __shared__ float lds[];
   const int tid = threadIdx.x;
   const int j = blockIdx.x;
+  const int neg_ew = DT == 2 ? -fp8_exponent(w_amax[j]) : 0;
   const float* __restrict__ genome = genomes + (int64_t)j * nd.stride;
   const int n0 = nd.w[0];
   const int n1 = nd.w[1];
@@ -73,6 +81,15 @@ __global__ __launch_bounds__(256, 4) void eval_small_kernel(const float* __restr
 #pragma unroll
     for (int t = 0; t < NT; ++t)
       wo[t] = (rvalid[t] && kv) ? *reinterpret_cast<const float4*>(wrow[t] + k) : zero4();
+    if constexpr (DT != 0) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        wo[t].x = quantize<DT>(wo[t].x, neg_ew);
+        wo[t].y = quantize<DT>(wo[t].y, neg_ew);
+        wo[t].z = quantize<DT>(wo[t].z, neg_ew);
+        wo[t].w = quantize<DT>(wo[t].w, neg_ew);
+      }
+    }
   };
   int s = wave;
   if (s < nss) load(s, xa, wb);
@@ -98,6 +115,7 @@ __global__ __launch_bounds__(256, 4) void eval_small_kernel(const float* __restr
   __syncthreads();
   const float* __restrict__ b1 = genome + nd.boff[0];
   const bool hidden = nd.L > 1;
+  const float fac = DT == 2 ? fp8_factor(*x_amax, w_amax[j]) : 1.0f;
   for (int idx = tid; idx < 16 * NT * 16; idx += 256) {
     const int m = idx / (NT * 16);
     const int n = idx - m * (NT * 16);
@@ -106,13 +124,14 @@ __global__ __launch_bounds__(256, 4) void eval_small_kernel(const float* __restr
       v = lds[m * ld1 + n] + lds[(16 + m) * ld1 + n];
       v += lds[(32 + m) * ld1 + n];
       v += lds[(48 + m) * ld1 + n];
+      if (DT == 2) v = v * fac;
       v += b1[n];
       if (hidden) v = relu_keep_nan(v);
     }
     lds[m * ld1 + n] = v;
   }
   __syncthreads();
-  tail_and_fitness(lds, lo, nd, genome, 0, 1, b, 0, y, tail_vec != 0, partial + j);
+  tail_and_fitness<1>(lds, lo, nd, genome, 0, 1, b, 0, y, tail_vec != 0, partial + j);
 }
 
 // ---------------------------------------------------------------- large b --
@@ -257,7 +276,7 @@ __global__ __launch_bounds__(256) void eval_large_kernel(const float* __restrict
       }
   }
   __syncthreads();
-  tail_and_fitness(lds, lo, nd, genome, 0, MT / 16, rows, m0, y, tail_vec != 0,
+  tail_and_fitness<4>(lds, lo, nd, genome, 0, MT / 16, rows, m0, y, tail_vec != 0,
                    partial + (int64_t)j * n_mt + mt);
 }
 
@@ -335,19 +354,27 @@ static int mtiles_nt(const NetDesc& nd, int b) {
   return (b + mt - 1) / mt;
 }
 
+template <int NT, int DT>
+static hipError_t launch_small(const float* genomes, const NetDesc& nd, int pop, const float* x,
+                               const int32_t* y, int b, float2* partial, const uint32_t* w_amax,
+                               const uint32_t* x_amax, hipStream_t s) {
+  const int tv = tail_vectorizable(nd) ? 1 : 0;
+  EvalLds lo;
+  const size_t bytes = small_lds_bytes(nd, &lo);
+  hipError_t e = allow_lds(eval_small_kernel<NT, DT>, bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((eval_small_kernel<NT, DT>), dim3((unsigned)pop), dim3(256), bytes, s,
+                     genomes, nd, x, y, b, partial, lo, tv, w_amax, x_amax);
+  return hipGetLastError();
+}
+
 template <int NT>
 static hipError_t launch_nt(const float* genomes, const NetDesc& nd, int pop, const float* x,
                             const int32_t* y, int b, float2* partial, hipStream_t s) {
   const int tv = tail_vectorizable(nd) ? 1 : 0;
   EvalLds lo;
-  if (use_small(b)) {
-    const size_t bytes = small_lds_bytes(nd, &lo);
-    hipError_t e = allow_lds(eval_small_kernel<NT>, bytes);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(eval_small_kernel<NT>, dim3((unsigned)pop), dim3(256), bytes, s,
-                       genomes, nd, x, y, b, partial, lo, tv);
-    return hipGetLastError();
-  }
+  if (use_small(b))
+    return launch_small<NT, 0>(genomes, nd, pop, x, y, b, partial, nullptr, nullptr, s);
   const int n_mt = mtiles_nt<NT>(nd, b);
   if (large_mw<NT>(nd, b) == 2) {
     const size_t bytes = large_lds_bytes<NT, 2>(nd, &lo);
@@ -391,6 +418,17 @@ int eval_mtiles(const NetDesc& nd, int b) { LEEA_NT_SWITCH((mtiles_nt<N>(nd, b))
 hipError_t launch_evaluate(const float* genomes, const NetDesc& nd, int pop, const float* x,
                            const int32_t* y, int b, float2* partial, hipStream_t s) {
   LEEA_NT_SWITCH((launch_nt<N>(genomes, nd, pop, x, y, b, partial, s)), hipErrorInvalidValue)
+}
+
+hipError_t launch_evaluate_small_lp(int dt, const float* genomes, const NetDesc& nd, int pop,
+                                    const float* xq, const int32_t* y, int b, float2* partial,
+                                    const uint32_t* w_amax, const uint32_t* x_amax,
+                                    hipStream_t s) {
+  if (dt == 1)
+    LEEA_NT_SWITCH((launch_small<N, 1>(genomes, nd, pop, xq, y, b, partial, w_amax, x_amax, s)),
+                   hipErrorInvalidValue)
+  LEEA_NT_SWITCH((launch_small<N, 2>(genomes, nd, pop, xq, y, b, partial, w_amax, x_amax, s)),
+                 hipErrorInvalidValue)
 }
 
 #undef LEEA_NT_SWITCH

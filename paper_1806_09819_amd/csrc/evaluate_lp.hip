@@ -1,0 +1,405 @@
+// Population forward pass with the first layer on the bfloat16 / FP8 matrix
+// cores (batches above 16 rows; smaller batches use the FP32 small-batch
+// kernel on quantised values, which is bandwidth-bound either way).
+//
+// Same decomposition as the FP32 large-batch kernel (section 3.3: one
+// shared-input product X * [W1_1 .. W1_P]^T, then each network's tail and
+// fitness on its LDS tile), with these differences:
+// * v_mfma_f32_16x16x32_{bf16,fp8_fp8}: lane l supplies A[l%16][8(l/16)+e]
+//   and B[8(l/16)+e][l%16] for e = 0..7 (16 bytes of bf16, 8 bytes of fp8)
+//   and receives D[4(l/16)+i][l%16]; one instruction covers a 32-wide K
+//   chunk, so each staged chunk costs one MFMA per (row tile, column tile).
+// * W_1 is read as float32 from the genome and converted while it is
+//   staged (bfloat16, or E4M3 of w * 2^-e_w); the batch arrives already
+//   quantised and packed [b][kp] (kp = n0 rounded up to 32).
+// * A workgroup owns 64*MW rows (MW 1 or 2); the tail layers and the
+//   fitness run in passes of 64 or 128 rows over the LDS tile, each pass
+//   writing its own partial sums.  (Four row tiles per wave measured slower:
+//   their accumulators push the kernel to one wave per SIMD and into
+//   accumulator-register shuffling.)
+// * FP8 products are rescaled by 2^(e_x + e_w) (exact) before the bias.
+// LDS rows hold 32 elements (64 or 32 bytes) in four 8-element slots; slot s
+// of row r is stored at slot s ^ ((r >> SH) & 3), which spreads the 16 lanes
+// reading one slot column of 16 rows over distinct banks.
+#include "eval_common.hpp"
+#include "lowp.hpp"
+
+namespace leea {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <int DT>
+struct Lp;
+
+template <>
+struct Lp<1> {  // bfloat16
+  static constexpr int ES = 2;  // bytes per element
+  static constexpr int SH = 1;  // swizzle shift
+  typedef uint4 Frag;
+  static __device__ __forceinline__ floatx4 mma(const Frag& a, const Frag& b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                  __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+  }
+  // 8 floats -> one slot
+  static __device__ __forceinline__ Frag pack(const float4& a, const float4& b, int) {
+    Frag f;
+    f.x = pack_bf16x2(a.x, a.y);
+    f.y = pack_bf16x2(a.z, a.w);
+    f.z = pack_bf16x2(b.x, b.y);
+    f.w = pack_bf16x2(b.z, b.w);
+    return f;
+  }
+};
+
+template <>
+struct Lp<2> {  // OCP FP8 E4M3
+  static constexpr int ES = 1;
+  static constexpr int SH = 2;
+  typedef uint2 Frag;
+  static __device__ __forceinline__ floatx4 mma(const Frag& a, const Frag& b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(
+        (long)__builtin_bit_cast(unsigned long long, a),
+        (long)__builtin_bit_cast(unsigned long long, b), c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ Frag pack(const float4& a, const float4& b, int neg_e) {
+    Frag f;
+    f.x = pack_fp8x4(ldexpf(a.x, neg_e), ldexpf(a.y, neg_e), ldexpf(a.z, neg_e),
+                     ldexpf(a.w, neg_e));
+    f.y = pack_fp8x4(ldexpf(b.x, neg_e), ldexpf(b.y, neg_e), ldexpf(b.z, neg_e),
+                     ldexpf(b.w, neg_e));
+    return f;
+  }
+};
+
+template <int NT, int MW, int DT, int D>
+__global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lp_kernel(const float* __restrict__ genomes,
+                                                      NetDesc nd, const void* __restrict__ xq,
+                                                      int kp, const uint32_t* __restrict__ w_amax,
+                                                      const uint32_t* __restrict__ x_amax,
+                                                      const int32_t* __restrict__ y, int b,
+                                                      float2* __restrict__ partial, EvalLds lo,
+                                                      int n_wt, int n_pt, int pass_rows, int pop,
+                                                      int tail_vec) {
+  typedef Lp<DT> T;
+  typedef typename T::Frag Frag;
+  extern __shared__ float lds[];
+  constexpr int ES = T::ES;
+  constexpr int FB = 8 * ES;        // bytes per slot (one lane fragment)
+  constexpr int RB = 4 * FB;        // bytes per staged row (32 elements)
+  constexpr int MT = 64 * MW;       // rows per workgroup
+  constexpr int NR = NT * 16;       // staged weight rows
+  constexpr int BUF = (NR + MT) * RB;
+  constexpr int WITEMS = NR * 4;    // slots of a W chunk
+  constexpr int WPT = (WITEMS + 255) / 256;
+  constexpr int XPT = MT * 4 / 256;  // = MW
+
+  // XCD-aware remap (hardware workgroup i runs on XCD i % 8): one network's
+  // row tiles get consecutive ids on the same XCD and share its L2.
+  const int Tn = n_wt * pop;
+  const int i = blockIdx.x;
+  const int q = Tn >> 3;
+  const int r8 = Tn & 7;
+  const int xcd = i & 7;
+  const int kk = i >> 3;
+  const int Lw = xcd < r8 ? xcd * (q + 1) + kk : r8 * (q + 1) + (xcd - r8) * q + kk;
+  const int j = Lw / n_wt;
+  const int wt = Lw - j * n_wt;
+
+  const int tid = threadIdx.x;
+  const int m0 = wt * MT;
+  const int rows = b - m0 < MT ? b - m0 : MT;
+  const float* __restrict__ genome = genomes + (int64_t)j * nd.stride;
+  const float* __restrict__ W1 = genome + nd.woff[0];
+  const int n0 = nd.w[0];
+  const int n1 = nd.w[1];
+  const int nch = kp >> 5;
+  const char* __restrict__ xb = reinterpret_cast<const char*>(xq);
+  const int neg_ew = DT == 2 ? -fp8_exponent(w_amax[j]) : 0;
+
+  // D register stages of global prefetch: chunk ch + D is requested while
+  // chunk ch is multiplied, which keeps D chunks of W_1 in flight per
+  // workgroup (the per-chunk matrix work alone is far shorter than the
+  // memory latency).
+  float4 wr[D][WPT][2];
+  Frag xr[D][XPT];
+  // Every load is issued unconditionally from a clamped (valid) address;
+  // out-of-range elements are zeroed only when the stage is stored to LDS.
+  // Branch-free loads whose results are untouched until then let the
+  // compiler wait for exactly the stage it consumes instead of draining
+  // every load in flight.
+  auto sel4 = [](bool keep, const float4& v) {
+    return make_float4(keep ? v.x : 0.0f, keep ? v.y : 0.0f, keep ? v.z : 0.0f,
+                       keep ? v.w : 0.0f);
+  };
+  auto gload = [&](int ch, float4 (&w)[WPT][2], Frag (&xx)[XPT]) {
+    const int k0 = (ch < nch ? ch : nch - 1) * 32;  // past the end: reload the last chunk
+#pragma unroll
+    for (int qq = 0; qq < WPT; ++qq) {
+      const int it = tid + 256 * qq;
+      const int row = it >> 2;
+      const int k = k0 + 8 * (it & 3);
+      const int rc = (it < WITEMS && row < n1) ? row : 0;
+      const int ka = k < n0 ? k : n0 - 4;
+      const int kb = k + 4 < n0 ? k + 4 : n0 - 4;
+      w[qq][0] = *reinterpret_cast<const float4*>(W1 + (int64_t)rc * n0 + ka);
+      w[qq][1] = *reinterpret_cast<const float4*>(W1 + (int64_t)rc * n0 + kb);
+    }
+#pragma unroll
+    for (int qq = 0; qq < XPT; ++qq) {
+      const int m = (tid + 256 * qq) >> 2;
+      const int s = (tid + 256 * qq) & 3;
+      const int mc = m < rows ? m : 0;
+      xx[qq] = *reinterpret_cast<const Frag*>(xb + ((int64_t)(m0 + mc) * kp + k0 + 8 * s) * ES);
+    }
+  };
+  auto sstore = [&](int ch, int buf, const float4 (&w)[WPT][2], const Frag (&xx)[XPT]) {
+    char* wst = reinterpret_cast<char*>(lds) + buf * BUF;
+    char* xst = wst + NR * RB;
+    const int k0 = ch * 32;
+#pragma unroll
+    for (int qq = 0; qq < WPT; ++qq) {
+      const int it = tid + 256 * qq;
+      const int row = it >> 2;
+      const int s = it & 3;
+      const int k = k0 + 8 * s;
+      const bool rv = row < n1;
+      if (it < WITEMS)
+        *reinterpret_cast<Frag*>(wst + row * RB + ((s ^ ((row >> T::SH) & 3)) * FB)) =
+            T::pack(sel4(rv && k < n0, w[qq][0]), sel4(rv && k + 4 < n0, w[qq][1]), neg_ew);
+    }
+#pragma unroll
+    for (int qq = 0; qq < XPT; ++qq) {
+      const int it = tid + 256 * qq;
+      const int m = it >> 2;
+      const int s = it & 3;
+      *reinterpret_cast<Frag*>(xst + m * RB + ((s ^ ((m >> T::SH) & 3)) * FB)) =
+          m < rows ? xx[qq] : Frag{};
+    }
+  };
+
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int mn = lane & 15;
+  const int kq = lane >> 4;
+  floatx4 acc[MW][NT];
+#pragma unroll
+  for (int mi = 0; mi < MW; ++mi)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[mi][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  auto compute = [&](int buf) {
+    const char* wst = reinterpret_cast<const char*>(lds) + buf * BUF;
+    const char* xst = wst + NR * RB;
+    Frag a[MW], bq[NT];
+#pragma unroll
+    for (int mi = 0; mi < MW; ++mi) {
+      const int m = wave * MW * 16 + mi * 16 + mn;
+      a[mi] = *reinterpret_cast<const Frag*>(xst + m * RB + ((kq ^ ((m >> T::SH) & 3)) * FB));
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int n = t * 16 + mn;
+      bq[t] = *reinterpret_cast<const Frag*>(wst + n * RB + ((kq ^ ((n >> T::SH) & 3)) * FB));
+    }
+#pragma unroll
+    for (int mi = 0; mi < MW; ++mi)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[mi][t] = T::mma(a[mi], bq[t], acc[mi][t]);
+  };
+
+  // double-buffered LDS: the store of chunk ch (buffer ch & 1) follows the
+  // barrier of chunk ch - 1, which every wave reaches only after finishing
+  // chunk ch - 2, the last reader of that buffer
+#pragma unroll
+  for (int s = 0; s < D; ++s) gload(s, wr[s], xr[s]);
+  for (int ch0 = 0; ch0 < nch; ch0 += D) {
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+      const int ch = ch0 + s;
+      if (ch < nch) {  // uniform across the workgroup
+        sstore(ch, ch & 1, wr[s], xr[s]);
+        __syncthreads();
+        gload(ch + D, wr[s], xr[s]);
+        compute(ch & 1);
+      }
+    }
+  }
+  __syncthreads();  // staging is dead from here on
+
+  // epilogue in passes of pass_rows rows: the waves owning those rows write
+  // scale * acc + bias (ReLU unless it is the output layer) into the LDS
+  // tile, then the tail layers and the fitness of the pass run
+  const float fac = DT == 2 ? fp8_factor(*x_amax, w_amax[j]) : 1.0f;
+  const float* __restrict__ b1 = genome + nd.boff[0];
+  const bool hidden = nd.L > 1;
+  float* h1 = lds + lo.h1;
+  const int passes = MT / pass_rows;
+  for (int p = 0; p < passes; ++p) {
+    const int pr0 = p * pass_rows;
+    const int prow = rows - pr0 < pass_rows ? rows - pr0 : pass_rows;
+    const int pidx = wt * passes + p;
+    if (prow <= 0 || pidx >= n_pt) break;  // uniform across the workgroup
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int n = t * 16 + mn;
+      const bool nv = n < n1;
+      const float bb = nv ? b1[n] : 0.0f;
+#pragma unroll
+      for (int mi = 0; mi < MW; ++mi)
+#pragma unroll
+        for (int i2 = 0; i2 < 4; ++i2) {
+          const int m = wave * MW * 16 + mi * 16 + 4 * kq + i2 - pr0;
+          if (m >= 0 && m < pass_rows) {
+            float v = acc[mi][t][i2];
+            if (DT == 2) v = v * fac;
+            v = v + bb;
+            if (hidden) v = relu_keep_nan(v);
+            h1[m * lo.ld1 + n] = nv ? v : 0.0f;
+          }
+        }
+    }
+    __syncthreads();
+    tail_and_fitness<4>(lds, lo, nd, genome, 0, pass_rows / 16, prow, m0 + pr0, y, tail_vec != 0,
+                     partial + (int64_t)j * n_pt + pidx);
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------- dispatch --
+
+static int round16i(int v) { return (v + 15) & ~15; }
+
+static EvalLds lp_tail_layout(const NetDesc& nd, int rows) {
+  EvalLds lo;
+  lo.ld1 = round16i(nd.w[1]) + 4;
+  int w = 4;
+  for (int l = 2; l <= nd.L; ++l) w = nd.w[l] > w ? nd.w[l] : w;
+  lo.ldt = round16i(w) + 4;
+  const int ldmax = lo.ld1 > lo.ldt ? lo.ld1 : lo.ldt;
+  lo.h1 = 0;
+  lo.ta = rows * ldmax;
+  lo.ll = lo.ta + rows * lo.ldt;
+  lo.cor = lo.ll + rows;
+  lo.total = lo.cor + rows;
+  return lo;
+}
+
+struct LpShape {
+  int mw, pass_rows;
+  size_t lds;
+  EvalLds lo;
+};
+
+static constexpr size_t kLdsMax = 160 * 1024;
+constexpr int kLpStages = 2;
+
+static size_t lp_bytes(const NetDesc& nd, int mw, int pass_rows, int es, EvalLds* lo) {
+  const int nt = (nd.w[1] + 15) / 16;
+  const size_t staging = 2 * (size_t)(nt * 16 + 64 * mw) * 32 * es;
+  *lo = lp_tail_layout(nd, pass_rows);
+  const size_t tail = (size_t)lo->total * 4;
+  const size_t bytes = staging > tail ? staging : tail;
+  lo->total = (int)((bytes + 3) / 4);
+  return bytes;
+}
+
+// Rows per workgroup grow with the batch (more rows share each weight
+// chunk) while the accumulators stay within 32 tiles per wave and LDS
+// within 160 KB.
+static bool lp_shape(const NetDesc& nd, int b, int dt, LpShape* out) {
+  const int nt = (nd.w[1] + 15) / 16;
+  const int es = dt == 1 ? 2 : 1;
+  int mw = b > 64 ? 2 : 1;
+  while (mw > 1 && mw * nt > 32) mw >>= 1;
+  for (; mw >= 1; mw >>= 1) {
+    for (int pr = 64 * mw < 128 ? 64 * mw : 128; pr >= 64; pr >>= 1) {
+      EvalLds lo;
+      const size_t bytes = lp_bytes(nd, mw, pr, es, &lo);
+      if (bytes <= kLdsMax) {
+        out->mw = mw;
+        out->pass_rows = pr;
+        out->lds = bytes;
+        out->lo = lo;
+        return true;
+      }
+    }
+  }
+  return false;
+}
+
+int eval_lp_ptiles(const NetDesc& nd, int b, int dt) {
+  LpShape sh;
+  if (!lp_shape(nd, b, dt, &sh)) return 1;
+  return (b + sh.pass_rows - 1) / sh.pass_rows;
+}
+
+bool eval_lp_supported(const NetDesc& nd, int b, int dt) {
+  LpShape sh;
+  return lp_shape(nd, b, dt, &sh);
+}
+
+template <int NT, int MW, int DT>
+static hipError_t launch_lp3(const float* genomes, const NetDesc& nd, int pop, const void* xq,
+                             int kp, const uint32_t* w_amax, const uint32_t* x_amax,
+                             const int32_t* y, int b, float2* partial, const LpShape& sh,
+                             int tv, hipStream_t s) {
+  auto kern = eval_lp_kernel<NT, MW, DT, kLpStages>;
+  if (sh.lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);
+    if (e != hipSuccess) return e;
+  }
+  const int n_wt = (b + 64 * MW - 1) / (64 * MW);
+  const int n_pt = (b + sh.pass_rows - 1) / sh.pass_rows;
+  hipLaunchKernelGGL(kern, dim3((unsigned)(n_wt * pop)), dim3(256), sh.lds, s, genomes, nd, xq,
+                     kp, w_amax, x_amax, y, b, partial, sh.lo, n_wt, n_pt, sh.pass_rows, pop, tv);
+  return hipGetLastError();
+}
+
+template <int NT, int DT>
+static hipError_t launch_lp2(const float* genomes, const NetDesc& nd, int pop, const void* xq,
+                             int kp, const uint32_t* w_amax, const uint32_t* x_amax,
+                             const int32_t* y, int b, float2* partial, const LpShape& sh,
+                             int tv, hipStream_t s) {
+  if (sh.mw == 2)
+    return launch_lp3<NT, 2, DT>(genomes, nd, pop, xq, kp, w_amax, x_amax, y, b, partial, sh, tv,
+                                 s);
+  if (sh.mw == 1)
+    return launch_lp3<NT, 1, DT>(genomes, nd, pop, xq, kp, w_amax, x_amax, y, b, partial, sh, tv,
+                                 s);
+  return hipErrorInvalidValue;
+}
+
+template <int NT>
+static hipError_t launch_lp_nt(int dt, const float* genomes, const NetDesc& nd, int pop,
+                               const void* xq, int kp, const uint32_t* w_amax,
+                               const uint32_t* x_amax, const int32_t* y, int b, float2* partial,
+                               hipStream_t s) {
+  LpShape sh;
+  if (!lp_shape(nd, b, dt, &sh)) return hipErrorInvalidValue;
+  int tv = 1;
+  for (int l = 1; l < nd.L; ++l)
+    if (nd.w[l] % 4 != 0) tv = 0;
+  if (dt == 1)
+    return launch_lp2<NT, 1>(genomes, nd, pop, xq, kp, w_amax, x_amax, y, b, partial, sh, tv, s);
+  return launch_lp2<NT, 2>(genomes, nd, pop, xq, kp, w_amax, x_amax, y, b, partial, sh, tv, s);
+}
+
+hipError_t launch_evaluate_lp(int dt, const float* genomes, const NetDesc& nd, int pop,
+                              const void* xq, int kp, const uint32_t* w_amax,
+                              const uint32_t* x_amax, const int32_t* y, int b, float2* partial,
+                              hipStream_t s) {
+  switch ((nd.w[1] + 15) / 16) {
+#define LEEA_LP_CASE(N) \
+  case N:               \
+    return launch_lp_nt<N>(dt, genomes, nd, pop, xq, kp, w_amax, x_amax, y, b, partial, s);
+    LEEA_LP_CASE(1) LEEA_LP_CASE(2) LEEA_LP_CASE(3) LEEA_LP_CASE(4) LEEA_LP_CASE(5)
+    LEEA_LP_CASE(6) LEEA_LP_CASE(7) LEEA_LP_CASE(8) LEEA_LP_CASE(9) LEEA_LP_CASE(10)
+    LEEA_LP_CASE(11) LEEA_LP_CASE(12) LEEA_LP_CASE(13) LEEA_LP_CASE(14) LEEA_LP_CASE(15)
+    LEEA_LP_CASE(16)
+#undef LEEA_LP_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace leea

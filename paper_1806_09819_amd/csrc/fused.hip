@@ -165,7 +165,7 @@ __global__ __launch_bounds__(256, 3) void vary_eval_small_kernel(
     }
   }
   __syncthreads();
-  tail_and_fitness(lds, lo, nd, tl, T0, 1, b, 0, y, tail_vec != 0, partial + j);
+  tail_and_fitness<1>(lds, lo, nd, tl, T0, 1, b, 0, y, tail_vec != 0, partial + j);
 }
 
 // Usable when the batch is small, the tail layers run on MFMA and the genes

@@ -3,6 +3,7 @@
 // whole 1 KiB wave-wide segments, and one Philox call per lane per
 // 4 (mutation) or 128 (uniform crossover) genes.
 #include "internal.hpp"
+#include "lowp.hpp"
 #include "vary_common.hpp"
 
 namespace leea {
@@ -61,14 +62,18 @@ hipError_t launch_init(float* genomes, const NetDesc& nd, const Glorot& ga, int 
 // parents' mean, mutants take sigma * exp(tau * z) with z the first normal
 // of block (SIGMA, gen, slot, 0), and are then mutated with that new sigma.
 // Every workgroup of a slot computes the same value; the first writes it.
-template <int kXoKind>
+// kAmax: also accumulate the largest magnitude of each child's W_1 (genes
+// [0, w1n), whole float4s since n0 % 4 == 0) into amax[j] (cleared
+// beforehand), the FP8 scale of the next evaluation.
+template <int kXoKind, bool kAmax>
 __global__ __launch_bounds__(256) void vary_kernel(const float* __restrict__ cur,
                                                    float* __restrict__ nxt,
                                                    const int4* __restrict__ plan,
                                                    int64_t stride, int64_t genes, float sigma,
                                                    uint64_t thr, Key key, uint32_t gen, int pop,
                                                    uint32_t mul, const float* __restrict__ sig_cur,
-                                                   float* __restrict__ sig_next, float tau) {
+                                                   float* __restrict__ sig_next, float tau,
+                                                   uint32_t* __restrict__ amax, int64_t w1n) {
 #pragma clang fp contract(off)
   const int j = (int)(((uint64_t)blockIdx.y * mul) % (uint32_t)pop);
   const int wave = threadIdx.x >> 6;
@@ -85,12 +90,27 @@ __global__ __launch_bounds__(256) void vary_kernel(const float* __restrict__ cur
   const float4* __restrict__ a4 = reinterpret_cast<const float4*>(cur + (int64_t)pl.y * stride);
   const float4* __restrict__ b4 = reinterpret_cast<const float4*>(cur + (int64_t)pl.z * stride);
   float4* __restrict__ d4 = reinterpret_cast<float4*>(nxt + (int64_t)j * stride);
+  const int64_t w1f = w1n >> 2;
+  uint32_t am = 0;
+  auto track = [&](int64_t f, const float4& o) {
+    if (kAmax && f < w1f) {
+      uint32_t a = mag_bits(o.x), b = mag_bits(o.y), c = mag_bits(o.z), d = mag_bits(o.w);
+      a = a > b ? a : b;
+      c = c > d ? c : d;
+      a = a > c ? a : c;
+      am = a > am ? a : am;
+    }
+  };
 
   if (pl.x == kOpElite) {
 #pragma unroll 8
     for (int t = 0; t < 32; ++t) {
       const int64_t f = base4 + 64 * t;
-      if (f < n4) store_stream(d4 + f, a4[f]);
+      if (f < n4) {
+        const float4 a = a4[f];
+        track(f, a);
+        store_stream(d4 + f, a);
+      }
     }
   } else if (pl.x == kOpCross) {
     if (kXoKind == 0) {
@@ -107,6 +127,7 @@ __global__ __launch_bounds__(256) void vary_kernel(const float* __restrict__ cur
           o.y = (bits & 2u) ? b.y : a.y;
           o.z = (bits & 4u) ? b.z : a.z;
           o.w = (bits & 8u) ? b.w : a.w;
+          track(f, o);
           store_stream(d4 + f, o);
         }
       }
@@ -118,6 +139,7 @@ __global__ __launch_bounds__(256) void vary_kernel(const float* __restrict__ cur
           const float4 a = a4[f];
           const float4 b = b4[f];
           const float4 o = xo_arith4(a, b);
+          track(f, o);
           store_stream(d4 + f, o);
         }
       }
@@ -140,9 +162,19 @@ __global__ __launch_bounds__(256) void vary_kernel(const float* __restrict__ cur
           store_stream(d4 + f, a);
           continue;
         }
-        store_stream(d4 + f, mutate4(vp, f, a));
+        const float4 o = mutate4(vp, f, a);
+        track(f, o);
+        store_stream(d4 + f, o);
       }
     }
+  }
+  if (kAmax && G * 2048 < w1f) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const uint32_t o = (uint32_t)__shfl_xor((int)am, off);
+      am = o > am ? o : am;
+    }
+    if (lane == 0 && am) atomicMax(amax + j, am);
   }
 }
 
@@ -166,16 +198,27 @@ uint32_t slot_multiplier(int pop) {
 hipError_t launch_vary(const float* cur, float* nxt, const int4* plan, const NetDesc& nd,
                        int pop, int crossover, float sigma, uint64_t mut_threshold,
                        const Key& key, uint32_t gen, const float* sig_cur, float* sig_next,
-                       float tau, hipStream_t s) {
+                       float tau, uint32_t* amax, hipStream_t s) {
   const int64_t groups = (nd.stride + 8191) / 8192;
   dim3 grid((unsigned)((groups + 3) / 4), (unsigned)pop);
   const uint32_t mul = slot_multiplier(pop);
-  if (crossover == 0)
-    hipLaunchKernelGGL(vary_kernel<0>, grid, dim3(256), 0, s, cur, nxt, plan, nd.stride,
-                       nd.genes, sigma, mut_threshold, key, gen, pop, mul, sig_cur, sig_next, tau);
-  else
-    hipLaunchKernelGGL(vary_kernel<1>, grid, dim3(256), 0, s, cur, nxt, plan, nd.stride,
-                       nd.genes, sigma, mut_threshold, key, gen, pop, mul, sig_cur, sig_next, tau);
+  const int64_t w1n = (int64_t)nd.w[0] * nd.w[1];
+#define LEEA_VARY(XO, AM)                                                                   \
+  hipLaunchKernelGGL((vary_kernel<XO, AM>), grid, dim3(256), 0, s, cur, nxt, plan, nd.stride, \
+                     nd.genes, sigma, mut_threshold, key, gen, pop, mul, sig_cur, sig_next, tau, \
+                     amax, w1n)
+  if (crossover == 0) {
+    if (amax)
+      LEEA_VARY(0, true);
+    else
+      LEEA_VARY(0, false);
+  } else {
+    if (amax)
+      LEEA_VARY(1, true);
+    else
+      LEEA_VARY(1, false);
+  }
+#undef LEEA_VARY
   return hipGetLastError();
 }
 

@@ -19,7 +19,7 @@ hipError_t launch_init(float* genomes, const NetDesc& nd, const Glorot& ga, int 
 hipError_t launch_vary(const float* cur, float* nxt, const int4* plan, const NetDesc& nd,
                        int pop, int crossover, float sigma, uint64_t mut_threshold,
                        const Key& key, uint32_t gen, const float* sig_cur, float* sig_next,
-                       float tau, hipStream_t s);
+                       float tau, uint32_t* amax, hipStream_t s);
 hipError_t launch_draw_batch(const float* x_train, const int32_t* y_train, int64_t n_train,
                              int n_in, int side, int b, float* x_out, int32_t* y_out,
                              const Key& key, uint32_t gen, hipStream_t s);
@@ -47,6 +47,24 @@ hipError_t launch_evaluate(const float* genomes, const NetDesc& nd, int pop, con
 hipError_t launch_finalize(const float2* partial, int pop, int n_mt, int b, const float* f_inh,
                            int use_inh, float alpha, float* f_adj, float* f_raw, float* acc,
                            float* f_adj_out, float* f_raw_out, float* acc_out, hipStream_t s);
+
+// evaluate.hip / evaluate_lp.hip / quant.hip: reduced-precision first layer
+// (dt 1 = bfloat16, 2 = FP8 E4M3 with power-of-two scales)
+hipError_t launch_evaluate_small_lp(int dt, const float* genomes, const NetDesc& nd, int pop,
+                                    const float* xq, const int32_t* y, int b, float2* partial,
+                                    const uint32_t* w_amax, const uint32_t* x_amax,
+                                    hipStream_t s);
+bool eval_lp_supported(const NetDesc& nd, int b, int dt);
+int eval_lp_ptiles(const NetDesc& nd, int b, int dt);
+hipError_t launch_evaluate_lp(int dt, const float* genomes, const NetDesc& nd, int pop,
+                              const void* xq, int kp, const uint32_t* w_amax,
+                              const uint32_t* x_amax, const int32_t* y, int b, float2* partial,
+                              hipStream_t s);
+hipError_t launch_amax(const float* x, int64_t n, uint32_t* out, hipStream_t s);
+hipError_t launch_amax_w1(const float* genomes, const NetDesc& nd, int pop, uint32_t* amax,
+                          hipStream_t s);
+hipError_t launch_quantize_x(int dt, bool packed, const float* x, int b, int n0, int kp,
+                             const uint32_t* x_amax, void* out, hipStream_t s);
 
 // rng.hip (generator entry points)
 hipError_t launch_rng_philox(const uint32_t* ctr, uint64_t key, uint32_t* out, int64_t n,

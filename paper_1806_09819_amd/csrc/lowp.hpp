@@ -1,0 +1,75 @@
+// Device helpers of the reduced-precision first layer: bfloat16 and OCP FP8
+// E4M3 rounding (round to nearest, ties to even, by the gfx950 conversion
+// instructions) and the power-of-two FP8 scales.  The scale exponent of an
+// operand with largest magnitude amax is the smallest integer e with
+// amax <= 448 * 2^e (448 = largest finite E4M3 value); a non-finite amax
+// marks the operand as unusable (the fitness it feeds becomes NaN).
+#pragma once
+
+#include "internal.hpp"
+
+namespace leea {
+
+constexpr uint32_t kNonFinite = 0x7F800000u;  // |x| bits at or above: inf or NaN
+
+// Magnitude bits of a float: ordered like the magnitudes for finite values,
+// above kNonFinite - 1 for infinities and NaNs, so an unsigned max over them
+// is the largest magnitude and flags any non-finite value.
+__device__ __forceinline__ uint32_t mag_bits(float v) { return __float_as_uint(v) & 0x7FFFFFFFu; }
+
+// e for a finite non-negative amax (0 for amax = 0): with amax = m * 2^k,
+// m in [0.5, 1), 448 * 2^(k-9) = 0.875 * 2^k covers amax iff m <= 0.875.
+__device__ __forceinline__ int fp8_exponent(uint32_t amax_bits) {
+  const float a = __uint_as_float(amax_bits);
+  if (a == 0.0f) return 0;
+  int k;
+  const float m = frexpf(a, &k);
+  return m <= 0.875f ? k - 9 : k - 8;
+}
+
+// 2^(e_x + e_w) for the product of two scaled operands, NaN if either
+// operand is not finite.
+__device__ __forceinline__ float fp8_factor(uint32_t ax_bits, uint32_t aw_bits) {
+  if (ax_bits >= kNonFinite || aw_bits >= kNonFinite) return __builtin_nanf("");
+  return ldexpf(1.0f, fp8_exponent(ax_bits) + fp8_exponent(aw_bits));
+}
+
+__device__ __forceinline__ float round_bf16(float v) {
+  const __bf16 h = (__bf16)v;
+  return (float)h;
+}
+
+typedef float float2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+
+// Two floats -> two bfloat16 in one dword (first in the low half); one
+// v_cvt_pk_bf16_f32 (round to nearest even, like the scalar conversion).
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+  const float2v v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2v));
+}
+
+// Four floats (already divided by their scale, |v| <= 448) -> four E4M3
+// codes in one dword (first in the low byte).
+__device__ __forceinline__ uint32_t pack_fp8x4(float a, float b, float c, float d) {
+  int p = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+  p = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, p, true);
+  return (uint32_t)p;
+}
+
+// The E4M3 value nearest to v (|v| <= 448), as a float.
+__device__ __forceinline__ float round_fp8(float v) {
+  const int p = __builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false);
+  return __builtin_amdgcn_cvt_f32_fp8(p, 0);
+}
+
+// Quantised value of a first-layer operand element in the given mode:
+// BF16 -> nearest bfloat16; FP8 -> nearest E4M3 of v * 2^-e (still scaled).
+template <int DT>
+__device__ __forceinline__ float quantize(float v, int neg_e) {
+  if constexpr (DT == 1) return round_bf16(v);
+  else if constexpr (DT == 2) return round_fp8(ldexpf(v, neg_e));
+  else return v;
+}
+
+}  // namespace leea

@@ -1,0 +1,143 @@
+// Operand preparation of the reduced-precision first layer: largest
+// magnitudes for the FP8 scales (of the batch, and of every network's W_1)
+// and the quantised copy of the batch that the evaluation kernels read.
+#include "lowp.hpp"
+
+namespace leea {
+
+__device__ __forceinline__ uint32_t wave_umax(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint32_t o = (uint32_t)__shfl_xor((int)v, off);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
+// *out = max over x of mag_bits (out cleared to 0 beforehand).
+__global__ __launch_bounds__(256) void amax_kernel(const float* __restrict__ x, int64_t n,
+                                                   uint32_t* __restrict__ out) {
+  uint32_t m = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const uint32_t v = mag_bits(x[i]);
+    m = v > m ? v : m;
+  }
+  m = wave_umax(m);
+  if ((threadIdx.x & 63) == 0 && m) atomicMax(out, m);
+}
+
+// amax[j] = max over network j's W_1 of mag_bits; one workgroup per network.
+__global__ __launch_bounds__(256) void amax_w1_kernel(const float* __restrict__ genomes,
+                                                      NetDesc nd, uint32_t* __restrict__ amax) {
+  __shared__ uint32_t red[4];
+  const int j = blockIdx.x;
+  const float* w = genomes + (int64_t)j * nd.stride + nd.woff[0];
+  const int64_t n = (int64_t)nd.w[0] * nd.w[1];  // w[0] % 4 == 0: whole float4s
+  const float4* w4 = reinterpret_cast<const float4*>(w);
+  uint32_t m = 0;
+  for (int64_t i = threadIdx.x; i < (n >> 2); i += 256) {
+    const float4 v = w4[i];
+    uint32_t a = mag_bits(v.x), b = mag_bits(v.y), c = mag_bits(v.z), d = mag_bits(v.w);
+    a = a > b ? a : b;
+    c = c > d ? c : d;
+    a = a > c ? a : c;
+    m = a > m ? a : m;
+  }
+  m = wave_umax(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t r = red[0];
+    for (int i = 1; i < 4; ++i) r = red[i] > r ? red[i] : r;
+    amax[j] = r;
+  }
+}
+
+// Quantised batch as float values [b][n0] (read by the small-batch kernel,
+// which multiplies exact products on the FP32 matrix cores).
+template <int DT>
+__global__ __launch_bounds__(256) void quantize_values_kernel(const float* __restrict__ x,
+                                                              int64_t n,
+                                                              const uint32_t* __restrict__ x_amax,
+                                                              float* __restrict__ out) {
+  const int neg_e = DT == 2 ? -fp8_exponent(*x_amax) : 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    out[i] = quantize<DT>(x[i], neg_e);
+}
+
+// Quantised batch packed for the low-precision matrix cores: [b][kp]
+// bfloat16 or E4M3 codes, kp = n0 rounded up to 32, zero padded.  One
+// thread per 8 consecutive elements.
+template <int DT>
+__global__ __launch_bounds__(256) void quantize_packed_kernel(const float* __restrict__ x, int b,
+                                                              int n0, int kp,
+                                                              const uint32_t* __restrict__ x_amax,
+                                                              void* __restrict__ out) {
+  const int neg_e = DT == 2 ? -fp8_exponent(*x_amax) : 0;
+  const int per_row = kp >> 3;
+  const int64_t items = (int64_t)b * per_row;
+  for (int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x; it < items;
+       it += (int64_t)gridDim.x * 256) {
+    const int m = (int)(it / per_row);
+    const int k = (int)(it - (int64_t)m * per_row) * 8;
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = k + e < n0 ? x[(int64_t)m * n0 + k + e] : 0.0f;
+    if constexpr (DT == 1) {
+      uint4 o;
+      o.x = pack_bf16x2(v[0], v[1]);
+      o.y = pack_bf16x2(v[2], v[3]);
+      o.z = pack_bf16x2(v[4], v[5]);
+      o.w = pack_bf16x2(v[6], v[7]);
+      reinterpret_cast<uint4*>(out)[it] = o;
+    } else {
+      uint2 o;
+      o.x = pack_fp8x4(ldexpf(v[0], neg_e), ldexpf(v[1], neg_e), ldexpf(v[2], neg_e),
+                       ldexpf(v[3], neg_e));
+      o.y = pack_fp8x4(ldexpf(v[4], neg_e), ldexpf(v[5], neg_e), ldexpf(v[6], neg_e),
+                       ldexpf(v[7], neg_e));
+      reinterpret_cast<uint2*>(out)[it] = o;
+    }
+  }
+}
+
+static unsigned grid_for(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+hipError_t launch_amax(const float* x, int64_t n, uint32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(amax_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_amax_w1(const float* genomes, const NetDesc& nd, int pop, uint32_t* amax,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(amax_w1_kernel, dim3((unsigned)pop), dim3(256), 0, s, genomes, nd, amax);
+  return hipGetLastError();
+}
+
+hipError_t launch_quantize_x(int dt, bool packed, const float* x, int b, int n0, int kp,
+                             const uint32_t* x_amax, void* out, hipStream_t s) {
+  if (packed) {
+    const int64_t items = (int64_t)b * (kp >> 3);
+    if (dt == 1)
+      hipLaunchKernelGGL(quantize_packed_kernel<1>, dim3(grid_for(items)), dim3(256), 0, s, x, b,
+                         n0, kp, x_amax, out);
+    else
+      hipLaunchKernelGGL(quantize_packed_kernel<2>, dim3(grid_for(items)), dim3(256), 0, s, x, b,
+                         n0, kp, x_amax, out);
+  } else {
+    const int64_t n = (int64_t)b * n0;
+    if (dt == 1)
+      hipLaunchKernelGGL(quantize_values_kernel<1>, dim3(grid_for(n)), dim3(256), 0, s, x, n,
+                         x_amax, (float*)out);
+    else
+      hipLaunchKernelGGL(quantize_values_kernel<2>, dim3(grid_for(n)), dim3(256), 0, s, x, n,
+                         x_amax, (float*)out);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace leea

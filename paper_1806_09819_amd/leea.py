@@ -22,6 +22,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, 1, 2, 3, 4
 SEL = {"truncation": 0, "tournament": 1}
 XO = {"uniform": 0, "arithmetic": 1}
 SIGMA_MODES = {"constant": 0, "decay": 1, "self_adaptive": 2}
+EVAL_DTYPES = {"f32": 0, "bf16": 1, "fp8": 2}
 OP_ELITE, OP_CROSS, OP_MUT = 0, 1, 2
 
 
@@ -54,6 +55,7 @@ class Config(ctypes.Structure):
         ("sigma_decay_k", ctypes.c_float),
         ("tau", ctypes.c_float),
         ("input_pool", ctypes.c_int32),
+        ("eval_dtype", ctypes.c_int32),
     ]
 
 
@@ -141,7 +143,7 @@ def threshold(p_gene):
 def make_config(widths, pop, p_elite=0.05, p_cross=0.50, p_mut=0.45, rho=0.5,
                 selection="truncation", tournament_k=2, crossover="uniform", sigma=0.001,
                 p_gene=1.0, alpha=1.0, seed=0, run=0, max_batch=512, sigma_mode="constant",
-                sigma_decay_k=1.0, tau=0.0, pool=0, **_ignored):
+                sigma_decay_k=1.0, tau=0.0, pool=0, eval_dtype="f32", **_ignored):
     """leea_config from the paper's hyperparameters (fractions)."""
     widths = tuple(int(w) for w in widths)
     L = len(widths) - 1
@@ -169,6 +171,7 @@ def make_config(widths, pop, p_elite=0.05, p_cross=0.50, p_mut=0.45, rho=0.5,
     c.sigma_decay_k = sigma_decay_k
     c.tau = tau
     c.input_pool = pool
+    c.eval_dtype = EVAL_DTYPES[eval_dtype]
     return c
 
 

@@ -1,0 +1,268 @@
+"""GPU parity of the reduced-precision first layer (bfloat16 and OCP FP8
+E4M3 with power-of-two scales) against the oracle's reduced-precision
+forward pass: the device multiplies exactly the quantised operands the
+oracle defines and sums in float32, so fitness must agree within the
+float32 tolerance.  Covers the small-batch kernel (b <= 16, quantised
+values on the FP32 matrix cores) and the bf16 / FP8 matrix-core kernel
+(b > 16), ragged shapes, special networks (zero, tiny, huge and NaN
+weights), a NaN batch, the FP8 scales that the variation kernel derives
+for each child, and state restores."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import (F32, FIT_ATOL, FIT_RTOL, genomes_np, make_run, oracle_cfg, say, to_dev,
+                         to_np)
+from oracle import leea as O
+from oracle import precision as Q
+from paper_1806_09819_amd import datagen
+from paper_1806_09819_amd import presets
+
+pytestmark = pytest.mark.gpu
+
+PAPER = dict(presets.PAPER)
+
+
+def lowp_oracle(rows, widths, x, y, dt):
+    f = np.empty(len(rows))
+    acc = np.empty(len(rows))
+    amb = np.zeros(len(rows), dtype=np.int64)
+    for i, g in enumerate(rows):
+        z = Q.forward_lowp(g, widths, x, dt)
+        if np.isnan(z).any():
+            f[i], acc[i] = np.nan, np.nan
+            continue
+        f[i], acc[i] = O.fitness_from_logits(z, y)
+        s = np.sort(z, axis=1)
+        amb[i] = np.count_nonzero(s[:, -1] - s[:, -2] < 1e-4 * (1.0 + np.abs(s[:, -1])))
+    return f, acc, amb
+
+
+def check(f_gpu, acc_gpu, f_ref, acc_ref, amb, b, label):
+    f_gpu = np.asarray(f_gpu, dtype=np.float64)
+    nan = np.isnan(f_ref)
+    assert np.array_equal(np.isnan(f_gpu), nan), (label, np.isnan(f_gpu), nan)
+    ok = ~nan
+    err = np.abs(f_gpu[ok] - f_ref[ok])
+    assert np.all(err <= FIT_RTOL * np.abs(f_ref[ok]) + FIT_ATOL), (label, err.max())
+    dc = np.abs(np.rint(np.asarray(acc_gpu, dtype=np.float64)[ok] * b) - np.rint(acc_ref[ok] * b))
+    assert np.all(dc <= amb[ok]), (label, dc.max())
+    return float(np.max(err / np.maximum(np.abs(f_ref[ok]), 1e-30))) if ok.any() else 0.0
+
+
+def special_population(run, widths, seed):
+    """Random genomes with a few special networks: all-zero first layer,
+    tiny and huge first-layer weights, and (slot 4) a NaN weight."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = O.param_count(widths)
+    pop = (rng.standard_normal((run.pop, c)) * 0.05).astype(F32)
+    w1 = widths[0] * widths[1]
+    pop[1, :w1] = 0.0
+    pop[2, :w1] *= F32(1e-30)
+    pop[3, :w1] *= F32(3e3)
+    pop[4, 7] = np.nan
+    full = np.zeros((run.pop, run.stride), dtype=F32)
+    full[:, :c] = pop
+    run.set_state(to_dev(full))
+    return pop
+
+
+CASES = [
+    ("paper", (784, 112, 32, 10), (1, 8, 16, 17, 64, 100, 300)),
+    ("ragged", (100, 20, 12, 3), (5, 33, 130)),
+    ("scalar_tail", (28, 7, 3), (9, 70)),
+    ("wide", (196, 256, 128, 64, 10), (12, 64, 200)),
+]
+
+
+@pytest.mark.parametrize("dt", ["bf16", "fp8"])
+@pytest.mark.parametrize("name,widths,batches", CASES, ids=[c[0] for c in CASES])
+def test_lowp_forward_matches_oracle(dt, name, widths, batches):
+    params = dict(PAPER, widths=widths, pop=12, eval_dtype=dt)
+    run, _ = make_run(params, max_batch=max(batches))
+    pop = special_population(run, widths, 11)
+    for b in batches:
+        say("lowp", dt, name, "b", b)
+        x = datagen.uniform_inputs((b, widths[0]), 100 + b)
+        y = datagen.labels(b, widths[-1], 200 + b)
+        f_raw, acc = run.score(to_dev(x), to_dev(y))
+        f_ref, acc_ref, amb = lowp_oracle(pop, widths, x, y, dt)
+        rel = check(to_np(f_raw), to_np(acc), f_ref, acc_ref, amb, b, "%s %s b%d" % (dt, name, b))
+        say("  worst relative fitness error", rel)
+
+
+@pytest.mark.parametrize("dt", ["bf16", "fp8"])
+def test_lowp_differs_from_f32_by_the_quantisation(dt):
+    """Sanity: the reduced-precision fitness is not the float32 one, and
+    sits within the quantisation's effect of the float64 forward."""
+    widths = (784, 112, 32, 10)
+    params = dict(PAPER, pop=16, eval_dtype=dt)
+    run, _ = make_run(params, max_batch=64)
+    x = datagen.uniform_inputs((64, 784), 5)
+    y = datagen.labels(64, 10, 6)
+    f_raw, _ = run.score(to_dev(x), to_dev(y))
+    pop = genomes_np(run)
+    f64, _ = O.evaluate(pop, widths, x, y)
+    d = np.abs(to_np(f_raw).astype(np.float64) - f64) / np.abs(f64)
+    say(dt, "relative difference to the float64 forward: max", d.max(), "median", np.median(d))
+    assert d.max() > 1e-6
+    assert d.max() < (2e-2 if dt == "bf16" else 2e-1)
+
+
+@pytest.mark.parametrize("dt", ["bf16", "fp8"])
+def test_lowp_nan_batch_gives_nan_fitness(dt):
+    widths = (100, 20, 12, 3)
+    params = dict(PAPER, widths=widths, pop=6, eval_dtype=dt)
+    run, _ = make_run(params, max_batch=40)
+    for b in (8, 40):
+        x = datagen.uniform_inputs((b, 100), 3)
+        x[b // 2, 17] = np.nan
+        y = datagen.labels(b, 3, 4)
+        f_raw, _ = run.score(to_dev(x), to_dev(y))
+        assert np.all(np.isnan(to_np(f_raw))), (dt, b)
+
+
+@pytest.mark.parametrize("b", [8, 64])
+def test_fp8_scales_from_the_variation_kernel(b):
+    """Generations in FP8 mode: each child's W_1 scale comes from the
+    variation kernel; the oracle recomputes it from the (bit-exact) child.
+    Teacher-forced with the device's adjusted fitness."""
+    x, y = datagen.prototype_data(2000, seed=0)
+    params = dict(PAPER, pop=24, batch=b, eval_dtype="fp8", p_gene=0.5, sigma=0.02,
+                  crossover="arithmetic")
+    widths = params["widths"]
+    run, ocfg = make_run(params, max_batch=b)
+    xd, yd = to_dev(x), to_dev(y)
+    pop_o = O.init_population(ocfg)
+    xb, yb = run.draw_batch(0, xd, yd, b)
+    f_adj, f_raw, acc = run.evaluate(xb, yb)
+    for g in range(1, 5):
+        say("fp8 generation", g, "b", b)
+        f_prev = to_np(f_adj).copy()
+        xb, yb = run.draw_batch(g, xd, yd, b)
+        run.select()
+        run.crossover_mutate()
+        f_adj, f_raw, acc = run.evaluate(xb, yb)
+        ops, p1, p2, _ = O.plan(O.rank(f_prev), f_prev, ocfg, g)
+        pop_o = O.vary(pop_o, ops, p1, p2, ocfg, g)
+        assert np.array_equal(genomes_np(run).view(np.uint32), pop_o.view(np.uint32))
+        idx = O.batch_indices(ocfg.seed, g, b, x.shape[0], ocfg.run)
+        f_ref, acc_ref, amb = lowp_oracle(pop_o, widths, x[idx], y[idx], "fp8")
+        check(to_np(f_raw), to_np(acc), f_ref, acc_ref, amb, b, "fp8 gen %d" % g)
+
+
+def test_fp8_scales_after_restore():
+    widths = (784, 112, 32, 10)
+    params = dict(PAPER, pop=10, eval_dtype="fp8")
+    run, _ = make_run(params, max_batch=32)
+    x = datagen.uniform_inputs((32, 784), 8)
+    y = datagen.labels(32, 10, 9)
+    xd, yd = to_dev(x), to_dev(y)
+    run.evaluate(xd, yd)
+    ck = run.save()
+    pop = special_population(run, widths, 12)         # set_state recomputes the scales
+    f1, _ = run.score(xd, yd)
+    f_ref, _, _ = lowp_oracle(pop, widths, x, y, "fp8")
+    f1 = to_np(f1).astype(np.float64)
+    ok = ~np.isnan(f_ref)
+    assert np.array_equal(np.isnan(f1), ~ok)
+    assert np.all(np.abs(f1[ok] - f_ref[ok]) <= FIT_RTOL * np.abs(f_ref[ok]) + FIT_ATOL)
+    run.load(ck)                                       # load recomputes them as well
+    f2, _ = run.score(xd, yd)
+    pop0 = genomes_np(run)
+    f_ref0, _, _ = lowp_oracle(pop0, widths, x, y, "fp8")
+    assert np.all(np.abs(to_np(f2) - f_ref0) <= FIT_RTOL * np.abs(f_ref0) + FIT_ATOL)
+
+
+@pytest.mark.parametrize("dt", ["bf16", "fp8"])
+def test_lowp_full_size_sampled(dt):
+    """The paper-scale population (P = 1000, b = 512) in the launch shape
+    the benchmark times, checked on a sample of networks."""
+    widths = (784, 112, 32, 10)
+    params = dict(PAPER, eval_dtype=dt)
+    run, _ = make_run(params, max_batch=512)
+    x, y = datagen.prototype_data(512, seed=0, sample_seed=3)
+    f_raw, acc = run.score(to_dev(x), to_dev(y))
+    pop = genomes_np(run)
+    sample = np.random.Generator(np.random.PCG64(4)).choice(run.pop, 12, replace=False)
+    f_ref, acc_ref, amb = lowp_oracle(pop[sample], widths, x, y, dt)
+    check(to_np(f_raw)[sample], to_np(acc)[sample], f_ref, acc_ref, amb, 512, dt + " full")
+
+
+def _kendall(a, b):
+    from scipy import stats
+    ok = np.isfinite(a) & np.isfinite(b)
+    return float(stats.kendalltau(a[ok], b[ok]).statistic)
+
+
+@pytest.mark.parametrize("dt", ["bf16", "fp8"])
+def test_precision_report_small_config(dt):
+    """The small configuration (784-32-10, P = 16, b = 32, 10 generations)
+    run in float32 and in reduced precision from the same seed: fitness
+    error and Kendall-tau rank agreement of the reduced-precision fitness
+    against the float64 forward, each generation, and the final validation
+    accuracy of the best network against the float32 run."""
+    data = datagen.splits("teacher", sizes=(4000, 1000, 0))
+    xt, yt = to_dev(data["x_train"]), to_dev(data["y_train"])
+    xv, yv = data["x_val"], data["y_val"]
+    params = dict(presets.SMALL)
+    b = params["batch"]
+    widths = params["widths"]
+    report = {}
+    for mode in ("f32", dt):
+        run, _ = make_run(dict(params, eval_dtype=mode), max_batch=max(b, len(yv)))
+        xb, yb = run.draw_batch(0, xt, yt, b)
+        run.evaluate(xb, yb)
+        errs, taus = [], []
+        for g in range(1, params["generations"] + 1):
+            xb, yb = run.draw_batch(g, xt, yt, b)
+            run.select()
+            run.crossover_mutate()
+            _, f_raw, _ = run.evaluate(xb, yb)
+            pop = genomes_np(run)
+            f64, _ = O.evaluate(pop, widths, to_np(xb), to_np(yb))
+            f = to_np(f_raw).astype(np.float64)
+            errs.append(float(np.max(np.abs(f - f64) / np.abs(f64))))
+            taus.append(_kendall(f, f64))
+        _, f_adj = run.population()
+        best = int(torch.argmax(f_adj).item())
+        zv = O.forward(genomes_np(run)[best], widths, xv)
+        acc = float(np.mean(np.argmax(zv, axis=1) == yv))
+        report[mode] = dict(max_rel_err=max(errs), min_tau=min(taus), mean_tau=float(np.mean(taus)),
+                            val_acc_best=acc)
+    say("precision report", dt, report)
+    assert report["f32"]["max_rel_err"] < 1e-5
+    assert report[dt]["max_rel_err"] < (1e-2 if dt == "bf16" else 1e-1)
+    assert report[dt]["mean_tau"] > (0.8 if dt == "bf16" else 0.5)
+
+
+@pytest.mark.parametrize("dt", ["bf16", "fp8"])
+def test_precision_rank_agreement_paper_scale(dt):
+    """P = 1000 paper-scale networks on one b = 512 batch: Kendall tau of the
+    reduced-precision fitness against the float32 fitness over the whole
+    population, and against the float64 forward on a sample of 64."""
+    widths = (784, 112, 32, 10)
+    params = dict(PAPER)
+    x, y = datagen.prototype_data(512, seed=0, sample_seed=7)
+    xd, yd = to_dev(x), to_dev(y)
+    r32, _ = make_run(params, max_batch=512)
+    rlp, _ = make_run(dict(params, eval_dtype=dt), max_batch=512)
+    # a spread of fitness: a few generations of the float32 run
+    r32.evaluate(xd, yd)
+    for g in range(1, 4):
+        r32.select()
+        r32.crossover_mutate()
+        r32.evaluate(xd, yd)
+    g32, _ = r32.population()
+    rlp.set_state(g32.clone())
+    f32, _ = r32.score(xd, yd)
+    flp, _ = rlp.score(xd, yd)
+    f32, flp = to_np(f32).astype(np.float64), to_np(flp).astype(np.float64)
+    tau_all = _kendall(flp, f32)
+    sample = np.random.Generator(np.random.PCG64(1)).choice(1000, 64, replace=False)
+    f64, _ = O.evaluate(genomes_np(r32)[sample], widths, x, y)
+    tau64 = _kendall(flp[sample], f64)
+    err = float(np.max(np.abs(flp[sample] - f64) / np.abs(f64)))
+    say("paper-scale rank agreement", dt, dict(tau_vs_f32=tau_all, tau_vs_f64_sample=tau64,
+                                               max_rel_err_sample=err))
+    assert tau_all > 0.5 and tau64 > 0.5
