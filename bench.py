@@ -210,6 +210,101 @@ def roofline_of(params, r, b):
     return roof
 
 
+def uneven_runs(n=64, seed=0):
+    """n uneven run configs: populations log-uniform in [32, 2048], MLP
+    784-h-10 with h in {16, 64, 112, 256}, batch in {8, 64, 256}, bfloat16
+    first layer, the paper's other defaults; run index r, seed r."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for r in range(n):
+        pop = int(round(float(np.exp(rng.uniform(np.log(32), np.log(2048))))))
+        h = int(rng.choice([16, 64, 112, 256]))
+        b = int(rng.choice([8, 64, 256]))
+        p = workload(b, "bf16")
+        p.update(widths=(784, h, 10), pop=pop, max_batch=b, seed=r, run=r)
+        out.append(p)
+    return out
+
+
+def multi_run_bench(x_train, y_train, steps=20, warmup=3, n=64):
+    """Generations of n uneven runs: grouped launches replayed from one
+    captured graph, the same launches eager, and the runs stepped one by
+    one through leea_step; then again after the autotuner."""
+    import torch
+    from paper_1806_09819_amd import leea as B
+
+    params = uneven_runs(n)
+    evals_per_gen = sum(p["pop"] * p["batch"] for p in params)
+
+    def time_runs(runs):
+        for _ in range(warmup):
+            runs.generation(x_train, y_train)
+        runs.sync()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(runs.stream)
+        for _ in range(steps):
+            runs.generation(x_train, y_train)
+        e1.record(runs.stream)
+        runs.sync()
+        wall = time.perf_counter() - t0
+        return wall / steps, e0.elapsed_time(e1) * 1e-3 / steps
+
+    runs = B.Runs([B.make_config(**p) for p in params])
+    runs.generation(x_train, y_train)
+    out = {}
+    for mode in ("graph", "eager"):
+        runs.set_graph(mode == "graph")
+        wall, dev = time_runs(runs)
+        out[mode] = dict(ms_per_gen=wall * 1e3, device_ms_per_gen=dev * 1e3,
+                         value=evals_per_gen / wall)
+    default = [runs.shape(r) for r in range(n)]
+    kind, mw, us = runs.autotune(x_train, y_train)
+    runs.set_graph(True)
+    wall, dev = time_runs(runs)
+    out["graph_tuned"] = dict(ms_per_gen=wall * 1e3, device_ms_per_gen=dev * 1e3,
+                              value=evals_per_gen / wall,
+                              shapes_changed=int(sum(1 for r in range(n)
+                                                     if (kind[r], mw[r]) != default[r])))
+    runs.close()
+    del runs
+    torch.cuda.empty_cache()
+    # one by one: n single-run contexts, each a leea_step per generation
+    singles = [B.Leea(B.make_config(**p)) for p in params]
+    xb = [torch.empty((p["batch"], 784), device="cuda") for p in params]
+    yb = [torch.empty((p["batch"],), dtype=torch.int32, device="cuda") for p in params]
+    for s_, p, xx, yy in zip(singles, params, xb, yb):
+        s_.draw_batch(0, x_train, y_train, p["batch"], xx, yy)
+        s_.evaluate(xx, yy)
+    lib = B.library()
+
+    def single_gen(g):
+        for s_, p, xx, yy in zip(singles, params, xb, yb):
+            s_.draw_batch(g, x_train, y_train, p["batch"], xx, yy)
+            st = lib.leea_step(s_._ctx, B._ptr(xx), B._ptr(yy), p["batch"], None, None, None)
+            if st != 0:
+                raise B.LeeaError(st, lib.leea_last_error(s_._ctx).decode())
+
+    for g in range(1, warmup + 1):
+        single_gen(g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in range(warmup + 1, warmup + 1 + steps):
+        single_gen(g)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    out["one_by_one"] = dict(ms_per_gen=wall * 1e3, value=evals_per_gen / wall)
+    for s_ in singles:
+        s_.close()
+    out["runs"] = n
+    out["network_samples_per_gen"] = evals_per_gen
+    out["pops"] = [p["pop"] for p in params]
+    out["hidden"] = [p["widths"][1] for p in params]
+    out["batches"] = [p["batch"] for p in params]
+    out["tuned_shapes"] = [[int(k), int(m)] for k, m in zip(kind, mw)]
+    return out
+
+
 def cpu_baseline(params, b, min_seconds=12.0, max_gens=8):
     """The oracle (numpy: float64 forward and fitness, float32 genetic
     operators) running whole generations of the same workload -- rank, plan,
@@ -259,6 +354,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--sweep-steps", type=int, default=50)
+    ap.add_argument("--no-multi-run", action="store_true",
+                    help="skip the 64 uneven runs measurement")
     ap.add_argument("--eval-dtype", default="f32", choices=("f32", "bf16", "fp8"),
                     help="arithmetic of the first layer (bf16 / fp8: reduced-precision variants)")
     ap.add_argument("--fused", action="store_true",
@@ -338,6 +435,9 @@ def main():
                               dominant=rf["kernel"], bound=rf["bound"],
                               frac=round(rf["frac"], 4)))
         line["batch_sweep"] = sweep
+    if not args.no_multi_run:
+        log("bench: 64 uneven runs")
+        line["multi_run"] = multi_run_bench(x_train, y_train)
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(params, b)

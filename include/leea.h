@@ -236,6 +236,71 @@ leea_status leea_load(leea_ctx* ctx, const void* host_buf, size_t bytes);
 const char* leea_last_error(const leea_ctx* ctx);
 void leea_destroy(leea_ctx* ctx);
 
+/* ---- Many independent runs driven together -----------------------------
+ * n EA runs, each with its own configuration (population, widths,
+ * selection, crossover, seed and run index; batch size = max_batch), share one
+ * training set and advance one generation per leea_runs_generation call.
+ * Every phase of a generation is a single grouped launch over all runs
+ * (evaluation: one launch per kernel class), and the generation is captured
+ * once into a HIP graph that later calls replay, so the host cost does not
+ * grow with the number of runs.  Each run computes exactly what it computes
+ * alone through leea_step with the same config and the same evaluation
+ * shape.  Restrictions: constant sigma, no input pooling, first layer in
+ * float32 or bfloat16.  The stream must not be the null stream (graph
+ * capture).  Calls on one leea_runs object must not overlap. */
+#define LEEA_MAX_RUNS 1024
+typedef struct leea_runs leea_runs;
+
+/* Device workspace bytes for these n configs (1 <= n <= LEEA_MAX_RUNS). */
+leea_status leea_runs_workspace_bytes(const leea_config* cfgs, int32_t n, size_t* bytes);
+
+/* Carve the workspace (device, 256-byte aligned, caller-owned) and write
+ * every run's initial population (Algorithm 1, first line).  *out is
+ * host memory owned by the library (leea_runs_destroy). */
+leea_status leea_runs_create(const leea_config* cfgs, int32_t n, void* workspace, size_t bytes,
+                             void* hip_stream, leea_runs** out);
+
+/* First call: draw generation 0's batch of every run and evaluate the
+ * initial populations.  Later calls: one whole generation of every run
+ * (draw, rank + plan, crossover / mutation, evaluate + inheritance).
+ * x_train [n_train][widths[0]] (16-byte aligned) and y_train [n_train] are
+ * device arrays shared by all runs (every run needs the same widths[0]). */
+leea_status leea_runs_generation(leea_runs* m, const float* x_train, const int32_t* y_train,
+                                 int64_t n_train);
+
+/* Replay captured graphs (enable != 0, the default) or launch eagerly. */
+leea_status leea_runs_set_graph(leea_runs* m, int32_t enable);
+
+/* Completed generations (the same for every run). */
+leea_status leea_runs_generation_count(const leea_runs* m, uint32_t* gen);
+
+/* Borrowed device views of run r: current genomes [pop][stride] and its
+ * adjusted / raw fitness and accuracy [pop] (any output may be NULL);
+ * valid until the next generation. */
+leea_status leea_runs_population(leea_runs* m, int32_t r, float** genomes, int64_t* stride,
+                                 float** f_adj, float** f_raw, float** acc);
+
+/* Evaluation shape of run r: kind 0 small-batch kernel (b <= 16), 1 float32
+ * large-batch, 2 bfloat16 large-batch; mw = row tiles of 16 rows per wave.
+ * set_shape fails with LEEA_EINVAL for a shape that does not exist there.
+ * A different shape may change the last bits of the fitness (the per-row
+ * sums are grouped differently). */
+leea_status leea_runs_shape(const leea_runs* m, int32_t r, int32_t* kind, int32_t* mw);
+leea_status leea_runs_set_shape(leea_runs* m, int32_t r, int32_t kind, int32_t mw);
+
+/* Autotuner: for each distinct (population, widths, batch, dtype) among the
+ * runs, time every evaluation shape that exists for it (HIP events, 5
+ * launches after 2 warm-ups, on a batch drawn from the training set) and
+ * give all runs with that key the fastest.  Optional outputs per run
+ * (host arrays of n): chosen kind, mw, and its time in microseconds. */
+leea_status leea_runs_autotune(leea_runs* m, const float* x_train, const int32_t* y_train,
+                               int64_t n_train, int32_t* kind_out, int32_t* mw_out,
+                               float* us_out);
+
+/* Text of the last error of m (of the last failed create if m is NULL). */
+const char* leea_runs_last_error(const leea_runs* m);
+void leea_runs_destroy(leea_runs* m);
+
 /* 2x2 max-pooling (section 4.1) of n square side x side images x [n][side*side]
  * (device) into out [n][(side/2)^2] (device); side even.  NaN if any pooled
  * pixel is NaN.  Enqueues on hip_stream. */

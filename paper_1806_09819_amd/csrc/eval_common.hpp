@@ -32,17 +32,6 @@ __device__ __forceinline__ float relu_keep_nan(float v) { return v < 0.0f ? 0.0f
 
 __device__ __forceinline__ float4 zero4() { return make_float4(0.f, 0.f, 0.f, 0.f); }
 
-// LDS carve-up shared by both kernels (offsets and strides in floats).
-struct EvalLds {
-  int h1;     // layer-1 activations [rows][ld1]; later reused as a tail buffer
-  int ld1;
-  int ta;     // tail activations [rows][ldt]
-  int ldt;
-  int ll;     // [rows] per-sample log-likelihood
-  int cor;    // [rows] per-sample correctness (int)
-  int total;  // floats of dynamic LDS
-};
-
 // One fully connected layer on the matrix cores for rows [0, 16*mtiles):
 // out = act(in * W^T + bias).  `in` (LDS, row stride ldi) must hold zeros in
 // columns [n_in, round16(n_in)); `out` gets zeros in [n_out, round16(n_out)).

@@ -29,8 +29,11 @@
 //   share its weights in that XCD's L2.
 // Layers 2..L run on the matrix cores too (weight fragments as float4 loads
 // from L2) whenever the hidden widths are multiples of 4, else on VALU.
+#include <string.h>
+
 #include "eval_common.hpp"
 #include "lowp.hpp"
+#include "runs.hpp"
 
 namespace leea {
 
@@ -40,16 +43,14 @@ namespace leea {
 // quantised in registers; products of such values are exact in float32, so
 // the FP32 matrix cores sum exactly the reduced-precision products).
 template <int NT, int DT>
-__global__ __launch_bounds__(256, 4) void eval_small_kernel(const float* __restrict__ genomes,
-                                                         NetDesc nd, const float* __restrict__ x,
-                                                         const int32_t* __restrict__ y, int b,
-                                                         float2* __restrict__ partial,
-                                                         EvalLds lo, int tail_vec,
-                                                         const uint32_t* __restrict__ w_amax,
-                                                         const uint32_t* __restrict__ x_amax) {
+__device__ __forceinline__ void eval_small_body(int j, const float* __restrict__ genomes,
+                                                const NetDesc& nd, const float* __restrict__ x,
+                                                const int32_t* __restrict__ y, int b,
+                                                float2* __restrict__ partial, const EvalLds& lo,
+                                                int tail_vec, const uint32_t* __restrict__ w_amax,
+                                                const uint32_t* __restrict__ x_amax) {
   extern __shared__ float lds[];
   const int tid = threadIdx.x;
-  const int j = blockIdx.x;
   const int neg_ew = DT == 2 ? -fp8_exponent(w_amax[j]) : 0;
   const float* __restrict__ genome = genomes + (int64_t)j * nd.stride;
   const int n0 = nd.w[0];
@@ -134,14 +135,26 @@ __global__ __launch_bounds__(256, 4) void eval_small_kernel(const float* __restr
   tail_and_fitness<1>(lds, lo, nd, genome, 0, 1, b, 0, y, tail_vec != 0, partial + j);
 }
 
-// ---------------------------------------------------------------- large b --
-template <int NT, int MW>
-__global__ __launch_bounds__(256) void eval_large_kernel(const float* __restrict__ genomes,
+template <int NT, int DT>
+__global__ __launch_bounds__(256, 4) void eval_small_kernel(const float* __restrict__ genomes,
                                                          NetDesc nd, const float* __restrict__ x,
                                                          const int32_t* __restrict__ y, int b,
                                                          float2* __restrict__ partial,
-                                                         EvalLds lo, int n_mt, int pop,
-                                                         int tail_vec) {
+                                                         EvalLds lo, int tail_vec,
+                                                         const uint32_t* __restrict__ w_amax,
+                                                         const uint32_t* __restrict__ x_amax) {
+  eval_small_body<NT, DT>(blockIdx.x, genomes, nd, x, y, b, partial, lo, tail_vec, w_amax,
+                          x_amax);
+}
+
+// ---------------------------------------------------------------- large b --
+// Body of one workgroup: network j, row tile mt (rows 64*MW*mt ...).
+template <int NT, int MW>
+__device__ __forceinline__ void eval_large_body(int j, int mt, const float* __restrict__ genomes,
+                                                const NetDesc& nd, const float* __restrict__ x,
+                                                const int32_t* __restrict__ y, int b,
+                                                float2* __restrict__ partial, const EvalLds& lo,
+                                                int n_mt, int tail_vec) {
   extern __shared__ float lds[];
   constexpr int MT = 64 * MW;              // rows per workgroup
   constexpr int NR = NT * 16;              // staged weight rows
@@ -151,19 +164,6 @@ __global__ __launch_bounds__(256) void eval_large_kernel(const float* __restrict
   constexpr int WITEMS = NR * 8;           // float4 items of a W chunk
   constexpr int WPT = (WITEMS + 255) / 256;
   constexpr int XPT = MT * 8 / 256;
-
-  // XCD-aware remap: hardware workgroup i runs on XCD i % 8; give each XCD a
-  // contiguous range of (individual, row tile) pairs so one individual's row
-  // tiles share that XCD's L2.
-  const int T = n_mt * pop;
-  const int i = blockIdx.x;
-  const int q = T >> 3;
-  const int r = T & 7;
-  const int xcd = i & 7;
-  const int kk = i >> 3;
-  const int L = xcd < r ? xcd * (q + 1) + kk : r * (q + 1) + (xcd - r) * q + kk;
-  const int j = L / n_mt;
-  const int mt = L - j * n_mt;
 
   const int tid = threadIdx.x;
   const int m0 = mt * MT;
@@ -278,6 +278,29 @@ __global__ __launch_bounds__(256) void eval_large_kernel(const float* __restrict
   __syncthreads();
   tail_and_fitness<4>(lds, lo, nd, genome, 0, MT / 16, rows, m0, y, tail_vec != 0,
                    partial + (int64_t)j * n_mt + mt);
+}
+
+// XCD-aware order (hardware workgroup i runs on XCD i % 8): each XCD gets a
+// contiguous range of logical ids, so one individual's row tiles share that
+// XCD's L2.
+__device__ __forceinline__ int xcd_order(int i, int total) {
+  const int q = total >> 3;
+  const int r = total & 7;
+  const int xcd = i & 7;
+  const int kk = i >> 3;
+  return xcd < r ? xcd * (q + 1) + kk : r * (q + 1) + (xcd - r) * q + kk;
+}
+
+template <int NT, int MW>
+__global__ __launch_bounds__(256) void eval_large_kernel(const float* __restrict__ genomes,
+                                                         NetDesc nd, const float* __restrict__ x,
+                                                         const int32_t* __restrict__ y, int b,
+                                                         float2* __restrict__ partial,
+                                                         EvalLds lo, int n_mt, int pop,
+                                                         int tail_vec) {
+  const int L = xcd_order(blockIdx.x, n_mt * pop);
+  const int j = L / n_mt;
+  eval_large_body<NT, MW>(j, L - j * n_mt, genomes, nd, x, y, b, partial, lo, n_mt, tail_vec);
 }
 
 // -------------------------------------------------------------- dispatch --
@@ -433,16 +456,147 @@ hipError_t launch_evaluate_small_lp(int dt, const float* genomes, const NetDesc&
 
 #undef LEEA_NT_SWITCH
 
+// ------------------------------------------------------------- shapes --
+
+static size_t large_lds_rt(const NetDesc& nd, int nt, int mw, EvalLds* out) {
+  EvalLds lo = tail_layout(nd, 64 * mw);
+  const int staging = 2 * (8 * nt * 16 * 4 + 8 * 64 * mw * 4);
+  lo.total = lo.total > staging ? lo.total : staging;
+  if (out) *out = lo;
+  return (size_t)lo.total * 4;
+}
+
+bool eval_shape_f32(const NetDesc& nd, int b, int kind, int mw, EvalShape* out) {
+  const int nt = (nd.w[1] + 15) / 16;
+  if (nt < 1 || nt > 16 || b < 1) return false;
+  if (kind < 0) kind = use_small(b) ? 0 : 1;
+  EvalShape sh;
+  memset(&sh, 0, sizeof sh);
+  sh.tail_vec = tail_vectorizable(nd) ? 1 : 0;
+  if (kind == 0) {
+    if (b > 16) return false;
+    sh.kind = 0;
+    sh.mw = 1;
+    sh.n_wt = 1;
+    sh.n_pt = 1;
+    sh.pass_rows = 16;
+    sh.lds = small_lds_bytes(nd, &sh.lo);
+  } else if (kind == 1) {
+    if (mw <= 0) mw = (b > 64 && large_lds_rt(nd, nt, 2, nullptr) <= kTwoPerCu) ? 2 : 1;
+    if (mw != 1 && mw != 2) return false;
+    sh.kind = 1;
+    sh.mw = mw;
+    sh.n_wt = (b + 64 * mw - 1) / (64 * mw);
+    sh.n_pt = sh.n_wt;
+    sh.pass_rows = 64 * mw;
+    sh.lds = large_lds_rt(nd, nt, mw, &sh.lo);
+  } else {
+    return false;
+  }
+  if (sh.lds > kMaxLds) return false;
+  *out = sh;
+  return true;
+}
+
+// ------------------------------------------------- grouped (many runs) --
+// Population buffer: the one made by this generation's variation (the
+// state advances right after it) or the initial one.
+
+template <int NT, int DT>
+__global__ __launch_bounds__(256, 4) void runs_eval_small_kernel(
+    const RunDesc* __restrict__ runs, const BatchState* __restrict__ st,
+    const int* __restrict__ off, const int* __restrict__ ids, int n) {
+  const int i = find_group(off, n, blockIdx.x);
+  const RunDesc& d = runs[ids[i]];
+  const float* x = DT ? reinterpret_cast<const float*>(d.xq) : d.xb;
+  eval_small_body<NT, DT>(blockIdx.x - off[i], d.genomes[st->cur], d.nd, x, d.yb, d.b, d.partial,
+                          d.lo, d.tail_vec, nullptr, nullptr);
+}
+
+template <int NT, int MW>
+__global__ __launch_bounds__(256) void runs_eval_large_kernel(const RunDesc* __restrict__ runs,
+                                                              const BatchState* __restrict__ st,
+                                                              const int* __restrict__ off,
+                                                              const int* __restrict__ ids, int n,
+                                                              int total) {
+  const int L = xcd_order(blockIdx.x, total);
+  const int i = find_group(off, n, L);
+  const RunDesc& d = runs[ids[i]];
+  const int local = L - off[i];
+  const int j = local / d.n_wt;
+  eval_large_body<NT, MW>(j, local - j * d.n_wt, d.genomes[st->cur], d.nd, d.xb, d.yb, d.b,
+                          d.partial, d.lo, d.n_wt, d.tail_vec);
+}
+
+template <typename K>
+static hipError_t allow_lds_any(K kernel, size_t bytes) {
+  if (bytes <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
+template <int NT>
+static hipError_t launch_runs_eval_nt(int kind, int mw, int dt, const RunDesc* runs,
+                                      const BatchState* st, const Group& g, hipStream_t s) {
+  hipError_t e;
+  if (kind == 0) {
+    if (dt == 0) {
+      e = allow_lds_any(runs_eval_small_kernel<NT, 0>, g.lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((runs_eval_small_kernel<NT, 0>), dim3((unsigned)g.blocks), dim3(256),
+                         g.lds, s, runs, st, g.off, g.ids, g.n);
+    } else if (dt == 1) {
+      e = allow_lds_any(runs_eval_small_kernel<NT, 1>, g.lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((runs_eval_small_kernel<NT, 1>), dim3((unsigned)g.blocks), dim3(256),
+                         g.lds, s, runs, st, g.off, g.ids, g.n);
+    } else {
+      return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
+  if (kind == 1) {
+    if (mw == 1) {
+      e = allow_lds_any(runs_eval_large_kernel<NT, 1>, g.lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((runs_eval_large_kernel<NT, 1>), dim3((unsigned)g.blocks), dim3(256),
+                         g.lds, s, runs, st, g.off, g.ids, g.n, g.blocks);
+    } else {
+      e = allow_lds_any(runs_eval_large_kernel<NT, 2>, g.lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((runs_eval_large_kernel<NT, 2>), dim3((unsigned)g.blocks), dim3(256),
+                         g.lds, s, runs, st, g.off, g.ids, g.n, g.blocks);
+    }
+    return hipGetLastError();
+  }
+  return launch_runs_eval_lp(NT, mw, dt, runs, st, g, s);
+}
+
+hipError_t launch_runs_eval(int kind, int nt, int mw, int dt, const RunDesc* runs,
+                            const BatchState* st, const Group& g, hipStream_t s) {
+  switch (nt) {
+#define LEEA_RUNS_CASE(N) \
+  case N:                 \
+    return launch_runs_eval_nt<N>(kind, mw, dt, runs, st, g, s);
+    LEEA_RUNS_CASE(1) LEEA_RUNS_CASE(2) LEEA_RUNS_CASE(3) LEEA_RUNS_CASE(4) LEEA_RUNS_CASE(5)
+    LEEA_RUNS_CASE(6) LEEA_RUNS_CASE(7) LEEA_RUNS_CASE(8) LEEA_RUNS_CASE(9) LEEA_RUNS_CASE(10)
+    LEEA_RUNS_CASE(11) LEEA_RUNS_CASE(12) LEEA_RUNS_CASE(13) LEEA_RUNS_CASE(14)
+    LEEA_RUNS_CASE(15) LEEA_RUNS_CASE(16)
+#undef LEEA_RUNS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
 // Fitness = (sum of per-sample log-likelihoods) / b, accuracy = correct / b,
 // summed over row tiles in order; then the inheritance weighting
 // f_adj = fl(fl((1 - alpha) f_inh) + fl(alpha f)) (section 3.1).
-__global__ void finalize_kernel(const float2* __restrict__ partial, int pop, int n_mt, int b,
-                                const float* __restrict__ f_inh, int use_inh, float alpha,
-                                float* f_adj, float* f_raw, float* acc, float* f_adj_out,
-                                float* f_raw_out, float* acc_out) {
+__device__ __forceinline__ void finalize_one(int j, const float2* __restrict__ partial,
+                                             int n_mt, int b, const float* __restrict__ f_inh,
+                                             int use_inh, float alpha, float* f_adj, float* f_raw,
+                                             float* acc, float* f_adj_out, float* f_raw_out,
+                                             float* acc_out) {
 #pragma clang fp contract(off)
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= pop) return;
   float s = 0.0f, c = 0.0f;
   for (int t = 0; t < n_mt; ++t) {
     const float2 p = partial[(int64_t)j * n_mt + t];
@@ -465,6 +619,36 @@ __global__ void finalize_kernel(const float2* __restrict__ partial, int pop, int
   if (f_adj_out) f_adj_out[j] = fa;
   if (f_raw_out) f_raw_out[j] = f;
   if (acc_out) acc_out[j] = a;
+}
+
+__global__ void finalize_kernel(const float2* __restrict__ partial, int pop, int n_mt, int b,
+                                const float* __restrict__ f_inh, int use_inh, float alpha,
+                                float* f_adj, float* f_raw, float* acc, float* f_adj_out,
+                                float* f_raw_out, float* acc_out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= pop) return;
+  finalize_one(j, partial, n_mt, b, f_inh, use_inh, alpha, f_adj, f_raw, acc, f_adj_out,
+               f_raw_out, acc_out);
+}
+
+__global__ void runs_finalize_kernel(const RunDesc* __restrict__ runs,
+                                     const BatchState* __restrict__ st,
+                                     const int* __restrict__ off, const int* __restrict__ ids,
+                                     int n) {
+  const int i = find_group(off, n, blockIdx.x);
+  const RunDesc& d = runs[ids[i]];
+  const int j = (blockIdx.x - off[i]) * 256 + threadIdx.x;
+  if (j >= d.pop) return;
+  const int use_inh = st->has_inh && d.alpha != 1.0f;
+  finalize_one(j, d.partial, d.n_pt, d.b, d.f_inh[st->inh], use_inh, d.alpha, d.f_adj, d.f_raw,
+               d.acc, nullptr, nullptr, nullptr);
+}
+
+hipError_t launch_runs_finalize(const RunDesc* runs, const BatchState* st, const Group& g,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(runs_finalize_kernel, dim3((unsigned)g.blocks), dim3(256), 0, s, runs, st,
+                     g.off, g.ids, g.n);
+  return hipGetLastError();
 }
 
 hipError_t launch_finalize(const float2* partial, int pop, int n_mt, int b, const float* f_inh,

@@ -21,8 +21,11 @@
 // LDS rows hold 32 elements (64 or 32 bytes) in four 8-element slots; slot s
 // of row r is stored at slot s ^ ((r >> SH) & 3), which spreads the 16 lanes
 // reading one slot column of 16 rows over distinct banks.
+#include <string.h>
+
 #include "eval_common.hpp"
 #include "lowp.hpp"
+#include "runs.hpp"
 
 namespace leea {
 
@@ -71,15 +74,15 @@ struct Lp<2> {  // OCP FP8 E4M3
   }
 };
 
+// Body of one workgroup: network j, row tile wt (rows 64*MW*wt ...).
 template <int NT, int MW, int DT, int D>
-__global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lp_kernel(const float* __restrict__ genomes,
-                                                      NetDesc nd, const void* __restrict__ xq,
-                                                      int kp, const uint32_t* __restrict__ w_amax,
-                                                      const uint32_t* __restrict__ x_amax,
-                                                      const int32_t* __restrict__ y, int b,
-                                                      float2* __restrict__ partial, EvalLds lo,
-                                                      int n_wt, int n_pt, int pass_rows, int pop,
-                                                      int tail_vec) {
+__device__ __forceinline__ void eval_lp_body(int j, int wt, const float* __restrict__ genomes,
+                                             const NetDesc& nd, const void* __restrict__ xq,
+                                             int kp, const uint32_t* __restrict__ w_amax,
+                                             const uint32_t* __restrict__ x_amax,
+                                             const int32_t* __restrict__ y, int b,
+                                             float2* __restrict__ partial, const EvalLds& lo,
+                                             int n_pt, int pass_rows, int tail_vec) {
   typedef Lp<DT> T;
   typedef typename T::Frag Frag;
   extern __shared__ float lds[];
@@ -92,18 +95,6 @@ __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lp_kernel(con
   constexpr int WITEMS = NR * 4;    // slots of a W chunk
   constexpr int WPT = (WITEMS + 255) / 256;
   constexpr int XPT = MT * 4 / 256;  // = MW
-
-  // XCD-aware remap (hardware workgroup i runs on XCD i % 8): one network's
-  // row tiles get consecutive ids on the same XCD and share its L2.
-  const int Tn = n_wt * pop;
-  const int i = blockIdx.x;
-  const int q = Tn >> 3;
-  const int r8 = Tn & 7;
-  const int xcd = i & 7;
-  const int kk = i >> 3;
-  const int Lw = xcd < r8 ? xcd * (q + 1) + kk : r8 * (q + 1) + (xcd - r8) * q + kk;
-  const int j = Lw / n_wt;
-  const int wt = Lw - j * n_wt;
 
   const int tid = threadIdx.x;
   const int m0 = wt * MT;
@@ -264,6 +255,31 @@ __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lp_kernel(con
   }
 }
 
+// XCD-aware order (hardware workgroup i runs on XCD i % 8): consecutive
+// logical ids go to the same XCD, so one network's row tiles share its L2.
+__device__ __forceinline__ int xcd_logical(int i, int total) {
+  const int q = total >> 3;
+  const int r8 = total & 7;
+  const int xcd = i & 7;
+  const int kk = i >> 3;
+  return xcd < r8 ? xcd * (q + 1) + kk : r8 * (q + 1) + (xcd - r8) * q + kk;
+}
+
+template <int NT, int MW, int DT, int D>
+__global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lp_kernel(const float* __restrict__ genomes,
+                                                      NetDesc nd, const void* __restrict__ xq,
+                                                      int kp, const uint32_t* __restrict__ w_amax,
+                                                      const uint32_t* __restrict__ x_amax,
+                                                      const int32_t* __restrict__ y, int b,
+                                                      float2* __restrict__ partial, EvalLds lo,
+                                                      int n_wt, int n_pt, int pass_rows, int pop,
+                                                      int tail_vec) {
+  const int Lw = xcd_logical(blockIdx.x, n_wt * pop);
+  const int j = Lw / n_wt;
+  eval_lp_body<NT, MW, DT, D>(j, Lw - j * n_wt, genomes, nd, xq, kp, w_amax, x_amax, y, b,
+                              partial, lo, n_pt, pass_rows, tail_vec);
+}
+
 // ------------------------------------------------------------- dispatch --
 
 static int round16i(int v) { return (v + 15) & ~15; }
@@ -335,6 +351,107 @@ int eval_lp_ptiles(const NetDesc& nd, int b, int dt) {
 bool eval_lp_supported(const NetDesc& nd, int b, int dt) {
   LpShape sh;
   return lp_shape(nd, b, dt, &sh);
+}
+
+bool eval_shape_lp(const NetDesc& nd, int b, int dt, int kind, int mw, EvalShape* out) {
+  const int nt = (nd.w[1] + 15) / 16;
+  if (nt < 1 || nt > 16 || b < 1 || (dt != 1 && dt != 2)) return false;
+  if (kind < 0) kind = b <= 16 ? 0 : 2;
+  if (kind == 0) {
+    if (!eval_shape_f32(nd, b, 0, 1, out)) return false;
+    return true;  // small-batch kernel on quantised values
+  }
+  if (kind != 2) return false;
+  LpShape sh;
+  if (!lp_shape(nd, b, dt, &sh)) return false;
+  if (mw > 0 && mw != sh.mw) {
+    if (mw != 1 && mw != 2) return false;
+    if (mw * nt > 32) return false;
+    const int es = dt == 1 ? 2 : 1;
+    bool found = false;
+    for (int pr = 64 * mw < 128 ? 64 * mw : 128; pr >= 64 && !found; pr >>= 1) {
+      EvalLds lo;
+      const size_t bytes = lp_bytes(nd, mw, pr, es, &lo);
+      if (bytes <= kLdsMax) {
+        sh.mw = mw;
+        sh.pass_rows = pr;
+        sh.lds = bytes;
+        sh.lo = lo;
+        found = true;
+      }
+    }
+    if (!found) return false;
+  }
+  EvalShape r;
+  memset(&r, 0, sizeof r);
+  r.kind = 2;
+  r.mw = sh.mw;
+  r.n_wt = (b + 64 * sh.mw - 1) / (64 * sh.mw);
+  r.n_pt = (b + sh.pass_rows - 1) / sh.pass_rows;
+  r.pass_rows = sh.pass_rows;
+  r.tail_vec = 1;
+  for (int l = 1; l < nd.L; ++l)
+    if (nd.w[l] % 4 != 0) r.tail_vec = 0;
+  r.lds = sh.lds;
+  r.lo = sh.lo;
+  *out = r;
+  return true;
+}
+
+// ------------------------------------------------- grouped (many runs) --
+
+template <int NT, int MW, int DT>
+__global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void runs_eval_lp_kernel(
+    const RunDesc* __restrict__ runs, const BatchState* __restrict__ st,
+    const int* __restrict__ off, const int* __restrict__ ids, int n, int total) {
+  const int L = xcd_logical(blockIdx.x, total);
+  const int i = find_group(off, n, L);
+  const RunDesc& d = runs[ids[i]];
+  const int local = L - off[i];
+  const int j = local / d.n_wt;
+  eval_lp_body<NT, MW, DT, kLpStages>(j, local - j * d.n_wt, d.genomes[st->cur], d.nd, d.xq, d.kp,
+                                      nullptr, nullptr, d.yb, d.b, d.partial, d.lo, d.n_pt,
+                                      d.pass_rows, d.tail_vec);
+}
+
+template <int NT, int MW>
+static hipError_t launch_runs_lp3(const RunDesc* runs, const BatchState* st, const Group& g,
+                                  hipStream_t s) {
+  auto kern = runs_eval_lp_kernel<NT, MW, 1>;
+  if (g.lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, dim3((unsigned)g.blocks), dim3(256), g.lds, s, runs, st, g.off, g.ids,
+                     g.n, g.blocks);
+  return hipGetLastError();
+}
+
+template <int NT>
+static hipError_t launch_runs_lp_nt(int mw, const RunDesc* runs, const BatchState* st,
+                                    const Group& g, hipStream_t s) {
+  if (mw == 2) return launch_runs_lp3<NT, 2>(runs, st, g, s);
+  return launch_runs_lp3<NT, 1>(runs, st, g, s);
+}
+
+// Grouped launches exist for the bfloat16 first layer (the FP8 scales are
+// tracked by the single-run path only).
+hipError_t launch_runs_eval_lp(int nt, int mw, int dt, const RunDesc* runs, const BatchState* st,
+                               const Group& g, hipStream_t s) {
+  if (dt != 1) return hipErrorInvalidValue;
+  switch (nt) {
+#define LEEA_RLP_CASE(N) \
+  case N:                \
+    return launch_runs_lp_nt<N>(mw, runs, st, g, s);
+    LEEA_RLP_CASE(1) LEEA_RLP_CASE(2) LEEA_RLP_CASE(3) LEEA_RLP_CASE(4) LEEA_RLP_CASE(5)
+    LEEA_RLP_CASE(6) LEEA_RLP_CASE(7) LEEA_RLP_CASE(8) LEEA_RLP_CASE(9) LEEA_RLP_CASE(10)
+    LEEA_RLP_CASE(11) LEEA_RLP_CASE(12) LEEA_RLP_CASE(13) LEEA_RLP_CASE(14) LEEA_RLP_CASE(15)
+    LEEA_RLP_CASE(16)
+#undef LEEA_RLP_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 template <int NT, int MW, int DT>

@@ -4,6 +4,7 @@
 // 4 (mutation) or 128 (uniform crossover) genes.
 #include "internal.hpp"
 #include "lowp.hpp"
+#include "runs.hpp"
 #include "vary_common.hpp"
 
 namespace leea {
@@ -65,26 +66,25 @@ hipError_t launch_init(float* genomes, const NetDesc& nd, const Glorot& ga, int 
 // kAmax: also accumulate the largest magnitude of each child's W_1 (genes
 // [0, w1n), whole float4s since n0 % 4 == 0) into amax[j] (cleared
 // beforehand), the FP8 scale of the next evaluation.
+// Body of one workgroup: slot j, gene groups 4 gx .. 4 gx + 3 (one per wave).
 template <int kXoKind, bool kAmax>
-__global__ __launch_bounds__(256) void vary_kernel(const float* __restrict__ cur,
-                                                   float* __restrict__ nxt,
-                                                   const int4* __restrict__ plan,
-                                                   int64_t stride, int64_t genes, float sigma,
-                                                   uint64_t thr, Key key, uint32_t gen, int pop,
-                                                   uint32_t mul, const float* __restrict__ sig_cur,
-                                                   float* __restrict__ sig_next, float tau,
-                                                   uint32_t* __restrict__ amax, int64_t w1n) {
+__device__ __forceinline__ void vary_body(int j, int gx, const float* __restrict__ cur,
+                                          float* __restrict__ nxt, const int4* __restrict__ plan,
+                                          int64_t stride, int64_t genes, float sigma,
+                                          uint64_t thr, Key key, uint32_t gen,
+                                          const float* __restrict__ sig_cur,
+                                          float* __restrict__ sig_next, float tau,
+                                          uint32_t* __restrict__ amax, int64_t w1n) {
 #pragma clang fp contract(off)
-  const int j = (int)(((uint64_t)blockIdx.y * mul) % (uint32_t)pop);
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int64_t G = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t G = (int64_t)gx * 4 + wave;
   const int64_t n4 = stride >> 2;
   const int64_t base4 = G * 2048 + lane;
   const int4 pl = plan[j];
   if (sig_cur) {
     sigma = child_sigma(pl, sig_cur, key, gen, (uint32_t)j, tau);
-    if (blockIdx.x == 0 && threadIdx.x == 0) sig_next[j] = sigma;
+    if (gx == 0 && threadIdx.x == 0) sig_next[j] = sigma;
   }
   if (G * 2048 >= n4) return;
   const float4* __restrict__ a4 = reinterpret_cast<const float4*>(cur + (int64_t)pl.y * stride);
@@ -178,6 +178,20 @@ __global__ __launch_bounds__(256) void vary_kernel(const float* __restrict__ cur
   }
 }
 
+template <int kXoKind, bool kAmax>
+__global__ __launch_bounds__(256) void vary_kernel(const float* __restrict__ cur,
+                                                   float* __restrict__ nxt,
+                                                   const int4* __restrict__ plan,
+                                                   int64_t stride, int64_t genes, float sigma,
+                                                   uint64_t thr, Key key, uint32_t gen, int pop,
+                                                   uint32_t mul, const float* __restrict__ sig_cur,
+                                                   float* __restrict__ sig_next, float tau,
+                                                   uint32_t* __restrict__ amax, int64_t w1n) {
+  const int j = (int)(((uint64_t)blockIdx.y * mul) % (uint32_t)pop);
+  vary_body<kXoKind, kAmax>(j, blockIdx.x, cur, nxt, plan, stride, genes, sigma, thr, key, gen,
+                            sig_cur, sig_next, tau, amax, w1n);
+}
+
 // A multiplier near pop * 0.618 that is coprime to pop: slot = (y * mul) mod
 // pop visits every slot once and spreads the operators over the dispatch.
 uint32_t slot_multiplier(int pop) {
@@ -236,13 +250,11 @@ __device__ __forceinline__ float max4_nan(float a, float b, float c, float d) {
 // copies one row (float4 granularity; n_in is a multiple of 4).  With
 // side > 0 the rows are side x side images that are 2x2 max-pooled on the
 // way (section 4.1: the network pools its 28x28 inputs first).
-__global__ __launch_bounds__(256) void draw_batch_kernel(const float* __restrict__ x_train,
-                                                         const int32_t* __restrict__ y_train,
-                                                         int64_t n_train, int n_in, int side,
-                                                         float* __restrict__ x_out,
-                                                         int32_t* __restrict__ y_out, Key key,
-                                                         uint32_t gen) {
-  const int k = blockIdx.x;
+__device__ __forceinline__ void draw_row(int k, const float* __restrict__ x_train,
+                                         const int32_t* __restrict__ y_train, int64_t n_train,
+                                         int n_in, int side, float* __restrict__ x_out,
+                                         int32_t* __restrict__ y_out, const Key& key,
+                                         uint32_t gen) {
   const uint4 w = draw(key, kBatch, gen, 0u, (uint32_t)(k >> 2));
   const uint64_t idx = ((uint64_t)word_of(w, k & 3) * (uint64_t)n_train) >> 32;
   if (side == 0) {
@@ -260,6 +272,15 @@ __global__ __launch_bounds__(256) void draw_batch_kernel(const float* __restrict
     }
   }
   if (threadIdx.x == 0) y_out[k] = y_train[idx];
+}
+
+__global__ __launch_bounds__(256) void draw_batch_kernel(const float* __restrict__ x_train,
+                                                         const int32_t* __restrict__ y_train,
+                                                         int64_t n_train, int n_in, int side,
+                                                         float* __restrict__ x_out,
+                                                         int32_t* __restrict__ y_out, Key key,
+                                                         uint32_t gen) {
+  draw_row(blockIdx.x, x_train, y_train, n_train, n_in, side, x_out, y_out, key, gen);
 }
 
 hipError_t launch_draw_batch(const float* x_train, const int32_t* y_train, int64_t n_train,
@@ -300,6 +321,76 @@ __global__ void fill_kernel(float* __restrict__ p, int n, float v) {
 
 hipError_t launch_fill(float* p, int n, float v, hipStream_t s) {
   hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------- grouped (many runs) --
+
+// Batch rows of every run: workgroup = (run, row); generation = completed
+// generations + step (step 0 draws the initial batch).
+__global__ __launch_bounds__(256) void runs_draw_kernel(const RunDesc* __restrict__ runs,
+                                                        const BatchState* __restrict__ st,
+                                                        const int* __restrict__ off,
+                                                        const int* __restrict__ ids, int n,
+                                                        const float* __restrict__ x_train,
+                                                        const int32_t* __restrict__ y_train,
+                                                        int64_t n_train, int step) {
+  const int i = find_group(off, n, blockIdx.x);
+  const RunDesc& d = runs[ids[i]];
+  draw_row(blockIdx.x - off[i], x_train, y_train, n_train, d.nd.w[0], d.side, d.xb, d.yb, d.key,
+           st->gen + (uint32_t)step);
+}
+
+hipError_t launch_runs_draw(const RunDesc* runs, const BatchState* st, const Group& g,
+                            const float* x_train, const int32_t* y_train, int64_t n_train,
+                            int step, hipStream_t s) {
+  hipLaunchKernelGGL(runs_draw_kernel, dim3((unsigned)g.blocks), dim3(256), 0, s, runs, st, g.off,
+                     g.ids, g.n, x_train, y_train, n_train, step);
+  return hipGetLastError();
+}
+
+// Variation of every run: workgroup = (run, slot order y, gene-group block
+// x) in the same order as the single-run launch; constant sigma.
+__global__ __launch_bounds__(256) void runs_vary_kernel(const RunDesc* __restrict__ runs,
+                                                        const BatchState* __restrict__ st,
+                                                        const int* __restrict__ off,
+                                                        const int* __restrict__ ids, int n) {
+  const int i = find_group(off, n, blockIdx.x);
+  const RunDesc& d = runs[ids[i]];
+  const int local = blockIdx.x - off[i];
+  const int y = local / d.vgx;
+  const int x = local - y * d.vgx;
+  const int j = (int)(((uint64_t)y * d.mul) % (uint32_t)d.pop);
+  const int c = st->cur;
+  const uint32_t g = st->gen + 1;
+  if (d.crossover == 0)
+    vary_body<0, false>(j, x, d.genomes[c], d.genomes[c ^ 1], d.plan, d.nd.stride, d.nd.genes,
+                        d.sigma, d.thr, d.key, g, nullptr, nullptr, 0.0f, nullptr, 0);
+  else
+    vary_body<1, false>(j, x, d.genomes[c], d.genomes[c ^ 1], d.plan, d.nd.stride, d.nd.genes,
+                        d.sigma, d.thr, d.key, g, nullptr, nullptr, 0.0f, nullptr, 0);
+}
+
+hipError_t launch_runs_vary(const RunDesc* runs, const BatchState* st, const Group& g,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(runs_vary_kernel, dim3((unsigned)g.blocks), dim3(256), 0, s, runs, st, g.off,
+                     g.ids, g.n);
+  return hipGetLastError();
+}
+
+// The new populations become current: one generation more, buffers and
+// inherited fitness swap (every run at once).
+__global__ void runs_advance_kernel(BatchState* st) {
+  if (threadIdx.x == 0) {
+    st->gen += 1;
+    st->cur ^= 1;
+    st->inh ^= 1;
+    st->has_inh = 1;
+  }
+}
+
+hipError_t launch_runs_advance(BatchState* st, hipStream_t s) {
+  hipLaunchKernelGGL(runs_advance_kernel, dim3(1), dim3(64), 0, s, st);
   return hipGetLastError();
 }
 

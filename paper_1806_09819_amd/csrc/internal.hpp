@@ -13,6 +13,31 @@ struct Glorot {
   float a[kMaxLayers];
 };
 
+// LDS carve-up of the evaluation kernels (offsets and strides in floats).
+struct EvalLds {
+  int h1;     // layer-1 activations [rows][ld1]; later reused as a tail buffer
+  int ld1;
+  int ta;     // tail activations [rows][ldt]
+  int ldt;
+  int ll;     // [rows] per-sample log-likelihood
+  int cor;    // [rows] per-sample correctness (int)
+  int total;  // floats of dynamic LDS
+};
+
+// Launch shape of the evaluation of one network population on b rows:
+// kind 0 small-batch kernel (b <= 16), 1 FP32 large-batch, 2 reduced-precision
+// large-batch; mw row tiles of 16 per wave; n_wt workgroups per network;
+// n_pt partial row tiles per network.
+struct EvalShape {
+  int kind, mw, n_wt, n_pt, pass_rows, tail_vec;
+  size_t lds;
+  EvalLds lo;
+};
+// kind < 0 / mw <= 0: the default choice.  Returns false if the requested
+// shape does not exist for these widths and b.
+bool eval_shape_f32(const NetDesc& nd, int b, int kind, int mw, EvalShape* out);
+bool eval_shape_lp(const NetDesc& nd, int b, int dt, int kind, int mw, EvalShape* out);
+
 // init.hip / vary.hip / batch.hip
 hipError_t launch_init(float* genomes, const NetDesc& nd, const Glorot& ga, int pop,
                        const Key& key, hipStream_t s);

@@ -2,6 +2,7 @@
 // magnitudes for the FP8 scales (of the batch, and of every network's W_1)
 // and the quantised copy of the batch that the evaluation kernels read.
 #include "lowp.hpp"
+#include "runs.hpp"
 
 namespace leea {
 
@@ -137,6 +138,40 @@ hipError_t launch_quantize_x(int dt, bool packed, const float* x, int b, int n0,
       hipLaunchKernelGGL(quantize_values_kernel<2>, dim3(grid_for(n)), dim3(256), 0, s, x, n,
                          x_amax, (float*)out);
   }
+  return hipGetLastError();
+}
+
+// Quantised batch of every bfloat16 run: values [b][n0] for the small-batch
+// kernel (b <= 16), packed [b][kp] otherwise; 256 items per workgroup.
+__global__ __launch_bounds__(256) void runs_quantize_kernel(const RunDesc* __restrict__ runs,
+                                                            const int* __restrict__ off,
+                                                            const int* __restrict__ ids, int n) {
+  const int i = find_group(off, n, blockIdx.x);
+  const RunDesc& d = runs[ids[i]];
+  const int64_t it = (int64_t)(blockIdx.x - off[i]) * 256 + threadIdx.x;
+  const int n0 = d.nd.w[0];
+  if (d.ekind == 0) {
+    if (it < (int64_t)d.b * n0) reinterpret_cast<float*>(d.xq)[it] = round_bf16(d.xb[it]);
+    return;
+  }
+  const int per_row = d.kp >> 3;
+  if (it >= (int64_t)d.b * per_row) return;
+  const int m = (int)(it / per_row);
+  const int k = (int)(it - (int64_t)m * per_row) * 8;
+  float v[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) v[e] = k + e < n0 ? d.xb[(int64_t)m * n0 + k + e] : 0.0f;
+  uint4 o;
+  o.x = pack_bf16x2(v[0], v[1]);
+  o.y = pack_bf16x2(v[2], v[3]);
+  o.z = pack_bf16x2(v[4], v[5]);
+  o.w = pack_bf16x2(v[6], v[7]);
+  reinterpret_cast<uint4*>(d.xq)[it] = o;
+}
+
+hipError_t launch_runs_quantize(const RunDesc* runs, const Group& g, hipStream_t s) {
+  hipLaunchKernelGGL(runs_quantize_kernel, dim3((unsigned)g.blocks), dim3(256), 0, s, runs, g.off,
+                     g.ids, g.n);
   return hipGetLastError();
 }
 

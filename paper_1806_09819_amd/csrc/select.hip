@@ -7,6 +7,7 @@
 // the result independent of the sorting algorithm; an LDS bitonic sort over
 // the next power of two (padding keys all-ones) then gives the order.
 #include "internal.hpp"
+#include "runs.hpp"
 
 namespace leea {
 
@@ -46,15 +47,13 @@ __device__ __forceinline__ uint32_t parent_rank(const Key& key, uint32_t gen, ui
   return best;
 }
 
-__global__ __launch_bounds__(1024) void select_kernel(const float* __restrict__ f_adj, int pop,
-                                                      int n2, int n_elite, int n_cross,
-                                                      int n_trunc, int selection, int tk,
-                                                      Key key, uint32_t gen,
-                                                      int4* __restrict__ plan,
-                                                      float* __restrict__ f_inh_next,
-                                                      int32_t* __restrict__ order_out) {
+// Rank + plan of one population by the 1024 threads of a workgroup; keys is
+// LDS of n2 (the next power of two >= pop) 64-bit entries.
+__device__ void select_body(uint64_t* keys, const float* __restrict__ f_adj, int pop, int n2,
+                            int n_elite, int n_cross, int n_trunc, int selection, int tk,
+                            const Key& key, uint32_t gen, int4* __restrict__ plan,
+                            float* __restrict__ f_inh_next, int32_t* __restrict__ order_out) {
 #pragma clang fp contract(off)
-  extern __shared__ uint64_t keys[];
   const int tid = threadIdx.x;
   for (int i = tid; i < n2; i += 1024)
     keys[i] = i < pop ? rank_key(f_adj[i], (uint32_t)i) : ~0ull;
@@ -107,6 +106,18 @@ __global__ __launch_bounds__(1024) void select_kernel(const float* __restrict__ 
   }
 }
 
+__global__ __launch_bounds__(1024) void select_kernel(const float* __restrict__ f_adj, int pop,
+                                                      int n2, int n_elite, int n_cross,
+                                                      int n_trunc, int selection, int tk,
+                                                      Key key, uint32_t gen,
+                                                      int4* __restrict__ plan,
+                                                      float* __restrict__ f_inh_next,
+                                                      int32_t* __restrict__ order_out) {
+  extern __shared__ uint64_t keys[];
+  select_body(keys, f_adj, pop, n2, n_elite, n_cross, n_trunc, selection, tk, key, gen, plan,
+              f_inh_next, order_out);
+}
+
 hipError_t launch_select(const float* f_adj, int pop, int n_elite, int n_cross, int n_trunc,
                          int selection, int tk, const Key& key, uint32_t gen, int4* plan,
                          float* f_inh_next, int32_t* order, hipStream_t s) {
@@ -116,6 +127,24 @@ hipError_t launch_select(const float* f_adj, int pop, int n_elite, int n_cross, 
   const size_t lds = (size_t)n2 * sizeof(uint64_t);
   hipLaunchKernelGGL(select_kernel, dim3(1), dim3(1024), lds, s, f_adj, pop, n2, n_elite,
                      n_cross, n_trunc, selection, tk, key, gen, plan, f_inh_next, order);
+  return hipGetLastError();
+}
+
+// Rank + plan of every run: one workgroup per run; the plan's inherited
+// fitness goes to the run's next inherited-fitness buffer.
+__global__ __launch_bounds__(1024) void runs_select_kernel(const RunDesc* __restrict__ runs,
+                                                           const BatchState* __restrict__ st,
+                                                           const int* __restrict__ ids) {
+  extern __shared__ uint64_t keys[];
+  const RunDesc& d = runs[ids[blockIdx.x]];
+  select_body(keys, d.f_adj, d.pop, d.n2, d.n_elite, d.n_cross, d.n_trunc, d.selection, d.tk,
+              d.key, st->gen + 1, d.plan, d.f_inh[st->inh ^ 1], nullptr);
+}
+
+hipError_t launch_runs_select(const RunDesc* runs, const BatchState* st, const Group& g,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(runs_select_kernel, dim3((unsigned)g.n), dim3(1024), g.lds, s, runs, st,
+                     g.ids);
   return hipGetLastError();
 }
 

@@ -107,6 +107,26 @@ def library():
     lib.leea_last_error.restype = ctypes.c_char_p
     lib.leea_destroy.argtypes = [P]
     lib.leea_destroy.restype = None
+    runs_sig = {
+        "leea_runs_workspace_bytes": [P, I32, ctypes.POINTER(ctypes.c_size_t)],
+        "leea_runs_create": [P, I32, P, ctypes.c_size_t, P, ctypes.POINTER(P)],
+        "leea_runs_generation": [P, P, P, I64],
+        "leea_runs_set_graph": [P, I32],
+        "leea_runs_generation_count": [P, ctypes.POINTER(U32)],
+        "leea_runs_population": [P, I32, ctypes.POINTER(P), ctypes.POINTER(I64), ctypes.POINTER(P),
+                                 ctypes.POINTER(P), ctypes.POINTER(P)],
+        "leea_runs_shape": [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)],
+        "leea_runs_set_shape": [P, I32, I32, I32],
+        "leea_runs_autotune": [P, P, P, I64, P, P, P],
+    }
+    for name, args in runs_sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.leea_runs_last_error.argtypes = [P]
+    lib.leea_runs_last_error.restype = ctypes.c_char_p
+    lib.leea_runs_destroy.argtypes = [P]
+    lib.leea_runs_destroy.restype = None
     _lib = lib
     return lib
 
@@ -351,3 +371,102 @@ def rng_normal_pairs(ab):
     z = torch.empty(ab.shape, dtype=torch.float32, device=ab.device)
     _check(library().leea_rng_normal_pairs(_ptr(ab), _ptr(z), ab.shape[0], _stream()))
     return z
+
+
+# ------------------------------------------------------ many runs at once --
+
+def _rcheck(st, m=None):
+    if st != OK:
+        msg = library().leea_runs_last_error(m)
+        raise LeeaError(st, msg.decode() if msg else "")
+
+
+class Runs:
+    """Many independent EA runs (one leea_config each) advanced together by
+    grouped launches replayed from a captured HIP graph.  The runs use their
+    own (non-default) stream; sync() waits for it."""
+
+    def __init__(self, cfgs, device="cuda"):
+        lib = library()
+        self.cfgs = list(cfgs)
+        self.n = len(self.cfgs)
+        arr = (Config * self.n)(*self.cfgs)
+        self._arr = arr
+        self.device = torch.device(device)
+        nbytes = ctypes.c_size_t()
+        _rcheck(lib.leea_runs_workspace_bytes(arr, self.n, ctypes.byref(nbytes)))
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        torch.cuda.current_stream(self.device).synchronize()
+        m = ctypes.c_void_p()
+        _rcheck(lib.leea_runs_create(arr, self.n, _ptr(self.workspace), nbytes.value,
+                                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(m)))
+        self._m = m
+
+    def close(self):
+        if getattr(self, "_m", None):
+            self.sync()
+            library().leea_runs_destroy(self._m)
+            self._m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync(self):
+        self.stream.synchronize()
+
+    def generation(self, x_train, y_train):
+        """Generation 0 on the first call, then one generation per call."""
+        torch.cuda.current_stream(self.device).synchronize()
+        _rcheck(library().leea_runs_generation(self._m, _ptr(x_train), _ptr(y_train),
+                                               x_train.shape[0]), self._m)
+
+    def set_graph(self, enable):
+        _rcheck(library().leea_runs_set_graph(self._m, 1 if enable else 0), self._m)
+
+    @property
+    def generation_count(self):
+        g = ctypes.c_uint32()
+        _rcheck(library().leea_runs_generation_count(self._m, ctypes.byref(g)), self._m)
+        return g.value
+
+    def _view(self, ptr, nbytes):
+        off = ptr - self.workspace.data_ptr()
+        assert 0 <= off and off + nbytes <= self.workspace.numel()
+        return self.workspace[off:off + nbytes]
+
+    def population(self, r):
+        """(genomes [pop, stride], f_adj, f_raw, acc) of run r -- borrowed
+        views, valid until the next generation (call sync() first)."""
+        g, fa, fr, ac = (ctypes.c_void_p() for _ in range(4))
+        stride = ctypes.c_int64()
+        _rcheck(library().leea_runs_population(self._m, r, ctypes.byref(g), ctypes.byref(stride),
+                                               ctypes.byref(fa), ctypes.byref(fr),
+                                               ctypes.byref(ac)), self._m)
+        pop = self.cfgs[r].pop
+        genomes = self._view(g.value, pop * stride.value * 4).view(torch.float32)
+        f = [self._view(p.value, pop * 4).view(torch.float32) for p in (fa, fr, ac)]
+        return (genomes.view(pop, stride.value), *f)
+
+    def shape(self, r):
+        k, mw = ctypes.c_int32(), ctypes.c_int32()
+        _rcheck(library().leea_runs_shape(self._m, r, ctypes.byref(k), ctypes.byref(mw)), self._m)
+        return k.value, mw.value
+
+    def set_shape(self, r, kind, mw):
+        _rcheck(library().leea_runs_set_shape(self._m, r, kind, mw), self._m)
+
+    def autotune(self, x_train, y_train):
+        """Pick the fastest evaluation shape per (pop, widths, batch, dtype);
+        returns (kind[n], mw[n], microseconds[n])."""
+        kind = np.zeros(self.n, dtype=np.int32)
+        mw = np.zeros(self.n, dtype=np.int32)
+        us = np.zeros(self.n, dtype=np.float32)
+        torch.cuda.current_stream(self.device).synchronize()
+        _rcheck(library().leea_runs_autotune(self._m, _ptr(x_train), _ptr(y_train),
+                                             x_train.shape[0], kind.ctypes.data, mw.ctypes.data,
+                                             us.ctypes.data), self._m)
+        return kind, mw, us

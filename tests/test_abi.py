@@ -109,3 +109,27 @@ def test_calls_without_ctx_fail_cleanly(lib):
     assert lib.leea_step(None, None, None, 1, None, None, None) == B.EINVAL
     assert lib.leea_rng_philox(None, 0, None, 1, None) == B.EINVAL
     lib.leea_destroy(None)
+
+
+def test_runs_workspace_and_validation(lib):
+    n = ctypes.c_size_t()
+    good = [paper_cfg(widths=(784, h, 10), pop=p, max_batch=b, eval_dtype="bf16")
+            for h, p, b in ((16, 32, 8), (256, 2048, 256), (112, 500, 64))]
+    arr = (B.Config * 3)(*good)
+    assert lib.leea_runs_workspace_bytes(arr, 3, ctypes.byref(n)) == 0
+    singles = 0
+    for c in good:
+        m = ctypes.c_size_t()
+        assert lib.leea_workspace_bytes(ctypes.byref(c), ctypes.byref(m)) == 0
+        singles += m.value
+    assert n.value >= 0.9 * singles
+    for bad in (paper_cfg(eval_dtype="fp8"), paper_cfg(sigma_mode="decay", sigma_decay_k=5.0),
+                paper_cfg(widths=(783, 10))):
+        arr2 = (B.Config * 2)(good[0], bad)
+        assert lib.leea_runs_workspace_bytes(arr2, 2, ctypes.byref(n)) == B.EINVAL
+    assert lib.leea_runs_workspace_bytes(arr, 0, ctypes.byref(n)) == B.EINVAL
+    m = ctypes.c_void_p()
+    assert lib.leea_runs_create(arr, 3, None, n.value, None, ctypes.byref(m)) == B.EINVAL
+    assert m.value is None
+    assert lib.leea_runs_generation(None, None, None, 1) == B.EINVAL
+    lib.leea_runs_destroy(None)
