@@ -374,19 +374,21 @@ def vary(pop, ops, p1, p2, cfg, gen, sigma=None, slots=None):
     return out
 
 
-def _child(pop, ops, p1, p2, cfg, gen, sigma, threshold, j, c):
-    """Offspring of slot j (one row of ``vary``)."""
+def _child(pop, ops, p1, p2, cfg, gen, sigma, threshold, j, c, slot=None):
+    """Offspring of slot j (one row of ``vary``); its random draws use slot
+    ``slot`` (default j) of the generation's streams."""
+    s = j if slot is None else slot
     a = pop[p1[j]]
     if ops[j] == ELITE:
         return a.copy()
     if ops[j] == CROSS:
         b = pop[p2[j]]
         if cfg.crossover == "uniform":
-            return np.where(uniform_mask(cfg.seed, gen, j, c, cfg.run), b, a)
+            return np.where(uniform_mask(cfg.seed, gen, s, c, cfg.run), b, a)
         if cfg.crossover == "arithmetic":
             return (a + b) * F32(0.5)
         raise ValueError(cfg.crossover)
-    mutated, z = mutation_parts(cfg.seed, gen, j, c, threshold, cfg.run)
+    mutated, z = mutation_parts(cfg.seed, gen, s, c, threshold, cfg.run)
     noise = sigma * z
     return np.where(mutated, a + noise, a)
 

@@ -43,6 +43,7 @@ MUTMASK = 3   # per-gene mutation decisions
 MUTNORM = 4   # Gaussian mutation noise
 SIGMA = 5     # sigma self-adaptation noise (reserved)
 BATCH = 6     # minibatch example indices
+SURR = 7      # fitness-surrogate projection signs and initial weights
 
 _MASK32 = np.uint64(0xFFFFFFFF)
 
