@@ -236,6 +236,55 @@ leea_status leea_load(leea_ctx* ctx, const void* host_buf, size_t bytes);
 const char* leea_last_error(const leea_ctx* ctx);
 void leea_destroy(leea_ctx* ctx);
 
+/* ---- Learned fitness surrogate -------------------------------------------
+ * A variant of the generation (not in the paper) that pre-screens
+ * over-generated offspring: the n_elite elites are kept; k * (pop - n_elite)
+ * candidate children are made (the first k * n_cross by crossover, the rest
+ * by mutation, candidate c drawing from slot pop + c of the generation's
+ * streams, section 3.2 operators); each is described by 256 +-1 random
+ * projections of its bfloat16-rounded genome (times 1/sqrt(genes)), its
+ * parents' adjusted fitness and its distance to parent 1 (times
+ * 1/sqrt(genes)); a 259-64-1 MLP predicts its fitness and the best
+ * pop - n_elite predictions fill the other slots.  The new population is
+ * evaluated as usual (Eq. 1), which judges the MLP (Kendall tau-a and RMSE
+ * of its predictions for the kept candidates) and trains it (`steps`
+ * full-batch gradient steps on the squared error against the raw
+ * fitness).  Until the MLP has trained for `warmup` generations and the
+ * previous generation's tau reached tau_min, the first n_cross crossover
+ * and n_mut mutation candidates are kept instead (plain LEEA's mix). */
+typedef struct {
+  int32_t oversample;  /* k, 1..64; k * (pop - n_elite) <= 8192 */
+  int32_t steps;       /* gradient steps per generation, 0..1000 */
+  float lr;            /* learning rate, >= 0 */
+  int32_t warmup;      /* trained generations before screening may start, >= 0 */
+  float tau_min;       /* in [-1, 1] */
+} leea_surrogate_config;
+
+/* Device workspace bytes of the surrogate for this run. */
+leea_status leea_surrogate_workspace_bytes(const leea_config* cfg,
+                                           const leea_surrogate_config* sc, size_t* bytes);
+
+/* Attach a surrogate (workspace: device, 256-byte aligned, caller-owned)
+ * to ctx: writes the projection's sign bits and the MLP's initial
+ * weights.  Not with self-adaptive sigma. */
+leea_status leea_surrogate_attach(leea_ctx* ctx, const leea_surrogate_config* sc,
+                                  void* workspace, size_t bytes);
+
+/* One generation with pre-screening (in place of leea_step; same state
+ * rules and outputs).  stats (device, 4 floats, may be NULL): {1 if the
+ * surrogate screened this generation, tau, rmse, trained generations}. */
+leea_status leea_surrogate_step(leea_ctx* ctx, const float* x, const int32_t* y, int32_t b,
+                                float* f_adj, float* f_raw, float* acc, float* stats);
+
+/* Borrowed device views of the last surrogate step (any may be NULL):
+ * candidates [n][stride], their plan [n][4] {op, parent 1, parent 2, 0},
+ * features [n][260] (259 used), predictions [n], kept candidate indices
+ * [pop - n_elite] and their predictions, MLP parameters (W1 [64][259], b1
+ * [64], w2 [64], b2); *n_candidates = n. */
+leea_status leea_surrogate_views(leea_ctx* ctx, float** candidates, int32_t** plan,
+                                 float** features, float** pred, int32_t** chosen,
+                                 float** chosen_pred, float** params, int32_t* n_candidates);
+
 /* ---- Many independent runs driven together -----------------------------
  * n EA runs, each with its own configuration (population, widths,
  * selection, crossover, seed and run index; batch size = max_batch), share one

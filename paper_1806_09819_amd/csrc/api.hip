@@ -52,6 +52,26 @@ struct leea_ctx {
   uint32_t* w_amax[2];  // FP8: largest |W_1| of each network (ping-pong with the genomes)
   uint32_t* x_amax;     // FP8: largest |x| of the batch being evaluated
   void* xq;             // quantised batch (values [b][n0] or packed [b][kp])
+  // fitness surrogate (leea_surrogate_attach)
+  int sur;
+  leea_surrogate_config sc;
+  int sM, sN, skc, snc, sngroups, snchunks, ssplits;
+  float* scand;
+  int4* scplan;
+  float* scf_inh;
+  float* snu;
+  float* spart;
+  float* sfeat;
+  float* spred;
+  int32_t* schosen;
+  float* schosen_pred;
+  float* spred_t;
+  uint32_t* sbits;
+  float* sprm;
+  float* sgrad;
+  float* spre;
+  int32_t* sstate;
+  float* sstats;
   std::string err;
 };
 
@@ -336,6 +356,7 @@ leea_status leea_init_population(const leea_config* cfg, void* workspace, size_t
   c->has_inh = 0;
   c->sigma = cfg->sigma;
   c->fused = 0;
+  c->sur = 0;
   Glorot ga;
   for (int l = 0; l < LEEA_MAX_LAYERS; ++l) ga.a[l] = l < nd.L ? cfg->glorot_a[l] : 0.0f;
   st = dev(nullptr, launch_init(c->genomes[0], nd, ga, cfg->pop, key_of(c), c->stream),
@@ -689,6 +710,222 @@ leea_status leea_rng_normal_pairs(const uint32_t* ab, float* z, int64_t n, void*
   if (!ab || !z || n < 0) return fail(nullptr, LEEA_EINVAL, "bad arguments");
   if (n == 0) return LEEA_OK;
   return dev(nullptr, launch_rng_normal_pairs(ab, z, n, (hipStream_t)hip_stream), "normal");
+}
+
+// ------------------------------------------------------ fitness surrogate --
+
+}  // extern "C"
+
+namespace {
+
+constexpr int kSurFeat = 256, kSurHid = 64, kSurIn = 259, kSurLd = 260;
+constexpr int kSurParams = kSurHid * kSurIn + 2 * kSurHid + 1;
+
+struct SurCarve {
+  int M, N, kc, nc, ngroups, nchunks, splits;
+  size_t cand, cplan, m4, nu, part, feat, n4, bits, prm, pre, st, total;
+};
+
+leea_status sur_carve(const leea_config* cfg, const leea_surrogate_config* sc, const NetDesc& nd,
+                      SurCarve* o) {
+  if (!sc) return fail(nullptr, LEEA_EINVAL, "surrogate config is NULL");
+  if (sc->oversample < 1 || sc->oversample > 64)
+    return fail(nullptr, LEEA_EINVAL, "oversample must be in 1..64");
+  if (sc->steps < 0 || sc->steps > 1000) return fail(nullptr, LEEA_EINVAL, "steps must be in 0..1000");
+  if (!(sc->lr >= 0.0f && sc->lr < 1e6f)) return fail(nullptr, LEEA_EINVAL, "lr must be finite, >= 0");
+  if (sc->warmup < 0) return fail(nullptr, LEEA_EINVAL, "warmup must be >= 0");
+  if (!(sc->tau_min >= -1.0f && sc->tau_min <= 1.0f))
+    return fail(nullptr, LEEA_EINVAL, "tau_min must be in [-1, 1]");
+  if (cfg->sigma_mode == LEEA_SIGMA_SELF_ADAPTIVE)
+    return fail(nullptr, LEEA_EINVAL, "the surrogate does not support self-adaptive sigma");
+  SurCarve c;
+  c.N = cfg->pop - cfg->n_elite;
+  c.nc = cfg->n_cross;
+  c.kc = sc->oversample * cfg->n_cross;
+  c.M = sc->oversample * c.N;
+  if (c.N < 1) return fail(nullptr, LEEA_EINVAL, "the surrogate needs non-elite slots");
+  if (c.M > 8192) return fail(nullptr, LEEA_EINVAL, "oversample * (pop - n_elite) must be <= 8192");
+  c.ngroups = (int)((nd.stride + 8191) / 8192);
+  c.nchunks = (int)((nd.genes + 31) / 32);
+  const int tiles = (c.M + 63) / 64;
+  c.splits = (512 + tiles - 1) / tiles;
+  if (c.splits > c.nchunks) c.splits = c.nchunks;
+  if (c.splits < 1) c.splits = 1;
+  c.cand = align256((size_t)c.M * nd.stride * 4);
+  c.cplan = align256((size_t)c.M * 16);
+  c.m4 = align256((size_t)c.M * 4);
+  c.nu = align256((size_t)c.M * c.ngroups * 4);
+  c.part = align256((size_t)c.splits * c.M * kSurFeat * 4);
+  c.feat = align256((size_t)c.M * kSurLd * 4);
+  c.n4 = align256((size_t)c.N * 4);
+  c.bits = align256((size_t)c.nchunks * kSurFeat * 4);
+  c.prm = align256((size_t)kSurParams * 4);
+  c.pre = align256((size_t)c.N * kSurHid * 4);
+  c.st = 256;
+  c.total = c.cand + c.cplan + 2 * c.m4 + c.nu + c.part + c.feat + 3 * c.n4 + c.bits + 2 * c.prm +
+            c.pre + 2 * c.st;
+  *o = c;
+  return LEEA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+leea_status leea_surrogate_workspace_bytes(const leea_config* cfg,
+                                           const leea_surrogate_config* sc, size_t* bytes) {
+  NetDesc nd;
+  leea_status st = validate(cfg, &nd);
+  if (st) return st;
+  if (!bytes) return fail(nullptr, LEEA_EINVAL, "bytes is NULL");
+  SurCarve c;
+  st = sur_carve(cfg, sc, nd, &c);
+  if (st) return st;
+  *bytes = c.total;
+  return LEEA_OK;
+}
+
+leea_status leea_surrogate_attach(leea_ctx* c, const leea_surrogate_config* sc, void* workspace,
+                                  size_t bytes) {
+  if (!c) return fail(nullptr, LEEA_EINVAL, "ctx is NULL");
+  SurCarve v;
+  leea_status st = sur_carve(&c->cfg, sc, c->nd, &v);
+  if (st) return fail(c, st, "%s", leea_last_error(nullptr));
+  if (!workspace || ((uintptr_t)workspace & 255u))
+    return fail(c, LEEA_EINVAL, "workspace must be a 256-byte aligned device pointer");
+  if (bytes < v.total) return fail(c, LEEA_ENOMEM, "workspace smaller than leea_surrogate_workspace_bytes");
+  char* p = (char*)workspace;
+  c->sc = *sc;
+  c->sM = v.M;
+  c->sN = v.N;
+  c->skc = v.kc;
+  c->snc = v.nc;
+  c->sngroups = v.ngroups;
+  c->snchunks = v.nchunks;
+  c->ssplits = v.splits;
+  c->scand = (float*)p;
+  p += v.cand;
+  c->scplan = (int4*)p;
+  p += v.cplan;
+  c->scf_inh = (float*)p;
+  p += v.m4;
+  c->spred = (float*)p;
+  p += v.m4;
+  c->snu = (float*)p;
+  p += v.nu;
+  c->spart = (float*)p;
+  p += v.part;
+  c->sfeat = (float*)p;
+  p += v.feat;
+  c->schosen = (int32_t*)p;
+  p += v.n4;
+  c->schosen_pred = (float*)p;
+  p += v.n4;
+  c->spred_t = (float*)p;
+  p += v.n4;
+  c->sbits = (uint32_t*)p;
+  p += v.bits;
+  c->sprm = (float*)p;
+  p += v.prm;
+  c->sgrad = (float*)p;
+  p += v.prm;
+  c->spre = (float*)p;
+  p += v.pre;
+  c->sstate = (int32_t*)p;
+  p += v.st;
+  c->sstats = (float*)p;
+  const float a1 = (float)sqrt(6.0 / (kSurIn + kSurHid));
+  const float a2 = (float)sqrt(6.0 / (kSurHid + 1));
+  st = dev(c, launch_proj_bits(c->sbits, v.nchunks, key_of(c), c->stream), "projection bits");
+  if (!st) st = dev(c, launch_mlp_init(c->sprm, key_of(c), a1, a2, c->stream), "surrogate init");
+  if (!st) st = dev(c, launch_fill((float*)c->sstate, 64, 0.0f, c->stream), "surrogate state");
+  if (!st) st = dev(c, launch_fill(c->sstats, 64, 0.0f, c->stream), "surrogate stats");
+  if (st) return st;
+  c->sur = 1;
+  return LEEA_OK;
+}
+
+leea_status leea_surrogate_step(leea_ctx* c, const float* x, const int32_t* y, int32_t b,
+                                float* f_adj, float* f_raw, float* acc, float* stats) {
+  if (!c) return fail(nullptr, LEEA_EINVAL, "ctx is NULL");
+  if (!c->sur) return fail(c, LEEA_ESTATE, "no surrogate attached");
+  if (c->state != kEvaluated) return fail(c, LEEA_ESTATE, "surrogate step needs an evaluated population");
+  leea_status st = check_batch(c, x, y, b);
+  if (st) return st;
+  st = leea_select(c, nullptr, nullptr, nullptr);
+  if (st) return st;
+  const leea_config& g = c->cfg;
+  const uint32_t gen = c->gen + 1;
+  float sigma;
+  const float* sig_cur;
+  float* sig_next;
+  vary_sigma(c, gen, &sigma, &sig_cur, &sig_next);
+  const float scale = (float)(1.0 / sqrt((double)c->nd.genes));
+  hipStream_t s = c->stream;
+  st = dev(c, launch_cand_plan(c->order, c->f_adj, c->sM, c->skc, g.pop, g.n_trunc, g.selection,
+                               g.tournament_k, key_of(c), gen, c->scplan, c->scf_inh, s),
+           "candidate plan");
+  if (!st)
+    st = dev(c, launch_vary_cand(c->genomes[c->cur], c->scand, c->scplan, c->nd, c->sM,
+                                 g.crossover, sigma, g.mut_threshold, key_of(c), gen,
+                                 (uint32_t)g.pop, c->snu, s),
+             "candidate variation");
+  if (!st)
+    st = dev(c, launch_proj(c->scand, c->nd.stride, c->sM, c->sbits, c->snchunks, c->ssplits,
+                            c->spart, s),
+             "projection");
+  if (!st)
+    st = dev(c, launch_features(c->spart, c->ssplits, c->sM, c->snu, c->sngroups, c->scplan,
+                                c->f_adj, scale, c->sfeat, s),
+             "features");
+  if (!st)
+    st = dev(c, launch_mlp_forward(c->sprm, c->sfeat, nullptr, c->sM, nullptr, c->spred, s),
+             "prediction");
+  if (!st)
+    st = dev(c, launch_screen(c->spred, c->sM, c->sN, c->snc, c->skc, c->sstate, c->schosen,
+                              c->schosen_pred, s),
+             "screening");
+  if (!st)
+    st = dev(c, launch_gather(c->genomes[c->cur], c->scand, c->genomes[c->cur ^ 1], c->nd.stride,
+                              g.pop, g.n_elite, c->plan, c->schosen, c->f_adj, c->scf_inh,
+                              c->f_inh_next, s),
+             "gather");
+  if (!st && c->dt == LEEA_DT_FP8)
+    st = dev(c, launch_amax_w1(c->genomes[c->cur ^ 1], c->nd, g.pop, c->w_amax[c->cur ^ 1], s),
+             "amax launch");
+  if (st) return st;
+  advance(c);
+  st = run_eval(c, x, y, b, true, f_adj, f_raw, acc);
+  if (st) return st;
+  c->state = kEvaluated;
+  const float* yk = c->f_raw + g.n_elite;
+  st = dev(c, launch_surrogate_judge(c->schosen_pred, yk, c->sN, c->sc.warmup, c->sc.tau_min,
+                                     c->sstate, c->sstats, s),
+           "surrogate judge");
+  for (int k = 0; k < c->sc.steps && !st; ++k)
+    st = dev(c, launch_mlp_train_step(c->sprm, c->sfeat, c->schosen, c->sN, yk, c->spre,
+                                      c->spred_t, c->sgrad, c->sc.lr, s),
+             "surrogate training");
+  if (!st && stats)
+    st = dev(c, hipMemcpyAsync(stats, c->sstats, 4 * sizeof(float), hipMemcpyDeviceToDevice, s),
+             "stats copy");
+  return st;
+}
+
+leea_status leea_surrogate_views(leea_ctx* c, float** candidates, int32_t** plan,
+                                 float** features, float** pred, int32_t** chosen,
+                                 float** chosen_pred, float** params, int32_t* n_candidates) {
+  if (!c) return fail(nullptr, LEEA_EINVAL, "ctx is NULL");
+  if (!c->sur) return fail(c, LEEA_ESTATE, "no surrogate attached");
+  if (candidates) *candidates = c->scand;
+  if (plan) *plan = (int32_t*)c->scplan;
+  if (features) *features = c->sfeat;
+  if (pred) *pred = c->spred;
+  if (chosen) *chosen = c->schosen;
+  if (chosen_pred) *chosen_pred = c->schosen_pred;
+  if (params) *params = c->sprm;
+  if (n_candidates) *n_candidates = c->sM;
+  return LEEA_OK;
 }
 
 }  // extern "C"

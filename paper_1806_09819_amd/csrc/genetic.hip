@@ -67,15 +67,21 @@ hipError_t launch_init(float* genomes, const NetDesc& nd, const Glorot& ga, int 
 // [0, w1n), whole float4s since n0 % 4 == 0) into amax[j] (cleared
 // beforehand), the FP8 scale of the next evaluation.
 // Body of one workgroup: slot j, gene groups 4 gx .. 4 gx + 3 (one per wave).
-template <int kXoKind, bool kAmax>
+// The random draws of slot j come from slot j + slot_off of the streams.
+// kNorm: also write, per wave, the sum of squared differences between the
+// child and parent 1 over the wave's genes to nu[j * ngroups + G].
+template <int kXoKind, bool kAmax, bool kNorm = false>
 __device__ __forceinline__ void vary_body(int j, int gx, const float* __restrict__ cur,
                                           float* __restrict__ nxt, const int4* __restrict__ plan,
                                           int64_t stride, int64_t genes, float sigma,
                                           uint64_t thr, Key key, uint32_t gen,
                                           const float* __restrict__ sig_cur,
                                           float* __restrict__ sig_next, float tau,
-                                          uint32_t* __restrict__ amax, int64_t w1n) {
+                                          uint32_t* __restrict__ amax, int64_t w1n,
+                                          uint32_t slot_off = 0, float* __restrict__ nu = nullptr,
+                                          int ngroups = 0) {
 #pragma clang fp contract(off)
+  const uint32_t pslot = (uint32_t)j + slot_off;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int64_t G = (int64_t)gx * 4 + wave;
@@ -83,7 +89,7 @@ __device__ __forceinline__ void vary_body(int j, int gx, const float* __restrict
   const int64_t base4 = G * 2048 + lane;
   const int4 pl = plan[j];
   if (sig_cur) {
-    sigma = child_sigma(pl, sig_cur, key, gen, (uint32_t)j, tau);
+    sigma = child_sigma(pl, sig_cur, key, gen, pslot, tau);
     if (gx == 0 && threadIdx.x == 0) sig_next[j] = sigma;
   }
   if (G * 2048 >= n4) return;
@@ -92,6 +98,16 @@ __device__ __forceinline__ void vary_body(int j, int gx, const float* __restrict
   float4* __restrict__ d4 = reinterpret_cast<float4*>(nxt + (int64_t)j * stride);
   const int64_t w1f = w1n >> 2;
   uint32_t am = 0;
+  float sq = 0.0f;
+  auto dist = [&](const float4& o, const float4& a) {
+    if (kNorm) {
+      const float dx = o.x - a.x, dy = o.y - a.y, dz = o.z - a.z, dw = o.w - a.w;
+      sq += dx * dx;
+      sq += dy * dy;
+      sq += dz * dz;
+      sq += dw * dw;
+    }
+  };
   auto track = [&](int64_t f, const float4& o) {
     if (kAmax && f < w1f) {
       uint32_t a = mag_bits(o.x), b = mag_bits(o.y), c = mag_bits(o.z), d = mag_bits(o.w);
@@ -114,7 +130,7 @@ __device__ __forceinline__ void vary_body(int j, int gx, const float* __restrict
     }
   } else if (pl.x == kOpCross) {
     if (kXoKind == 0) {
-      const uint4 m = draw(key, kXo, gen, (uint32_t)j, (uint32_t)(G * 64 + lane));
+      const uint4 m = draw(key, kXo, gen, pslot, (uint32_t)(G * 64 + lane));
 #pragma unroll 8
       for (int t = 0; t < 32; ++t) {
         const int64_t f = base4 + 64 * t;
@@ -128,6 +144,7 @@ __device__ __forceinline__ void vary_body(int j, int gx, const float* __restrict
           o.z = (bits & 4u) ? b.z : a.z;
           o.w = (bits & 8u) ? b.w : a.w;
           track(f, o);
+          dist(o, a);
           store_stream(d4 + f, o);
         }
       }
@@ -140,6 +157,7 @@ __device__ __forceinline__ void vary_body(int j, int gx, const float* __restrict
           const float4 b = b4[f];
           const float4 o = xo_arith4(a, b);
           track(f, o);
+          dist(o, a);
           store_stream(d4 + f, o);
         }
       }
@@ -151,7 +169,7 @@ __device__ __forceinline__ void vary_body(int j, int gx, const float* __restrict
     vp.t32 = (uint32_t)thr;
     vp.key = key;
     vp.gen = gen;
-    vp.slot = (uint32_t)j;
+    vp.slot = pslot;
     vp.genes = genes;
 #pragma unroll 4
     for (int t = 0; t < 32; ++t) {
@@ -164,9 +182,15 @@ __device__ __forceinline__ void vary_body(int j, int gx, const float* __restrict
         }
         const float4 o = mutate4(vp, f, a);
         track(f, o);
+        dist(o, a);
         store_stream(d4 + f, o);
       }
     }
+  }
+  if (kNorm) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
+    if (lane == 0) nu[(int64_t)j * ngroups + G] = sq;
   }
   if (kAmax && G * 2048 < w1f) {
 #pragma unroll
@@ -190,6 +214,22 @@ __global__ __launch_bounds__(256) void vary_kernel(const float* __restrict__ cur
   const int j = (int)(((uint64_t)blockIdx.y * mul) % (uint32_t)pop);
   vary_body<kXoKind, kAmax>(j, blockIdx.x, cur, nxt, plan, stride, genes, sigma, thr, key, gen,
                             sig_cur, sig_next, tau, amax, w1n);
+}
+
+// Candidate children of the fitness surrogate: plan index j, random draws
+// from slot slot_off + j, and the per-wave squared distances to parent 1.
+template <int kXoKind>
+__global__ __launch_bounds__(256) void vary_cand_kernel(const float* __restrict__ cur,
+                                                        float* __restrict__ cand,
+                                                        const int4* __restrict__ plan,
+                                                        int64_t stride, int64_t genes,
+                                                        float sigma, uint64_t thr, Key key,
+                                                        uint32_t gen, int n, uint32_t mul,
+                                                        uint32_t slot_off, float* __restrict__ nu,
+                                                        int ngroups) {
+  const int j = (int)(((uint64_t)blockIdx.y * mul) % (uint32_t)n);
+  vary_body<kXoKind, false, true>(j, blockIdx.x, cur, cand, plan, stride, genes, sigma, thr, key,
+                                  gen, nullptr, nullptr, 0.0f, nullptr, 0, slot_off, nu, ngroups);
 }
 
 // A multiplier near pop * 0.618 that is coprime to pop: slot = (y * mul) mod
@@ -233,6 +273,21 @@ hipError_t launch_vary(const float* cur, float* nxt, const int4* plan, const Net
       LEEA_VARY(1, false);
   }
 #undef LEEA_VARY
+  return hipGetLastError();
+}
+
+hipError_t launch_vary_cand(const float* cur, float* cand, const int4* plan, const NetDesc& nd,
+                            int n, int crossover, float sigma, uint64_t thr, const Key& key,
+                            uint32_t gen, uint32_t slot_off, float* nu, hipStream_t s) {
+  const int64_t groups = (nd.stride + 8191) / 8192;
+  dim3 grid((unsigned)((groups + 3) / 4), (unsigned)n);
+  const uint32_t mul = slot_multiplier(n);
+  if (crossover == 0)
+    hipLaunchKernelGGL(vary_cand_kernel<0>, grid, dim3(256), 0, s, cur, cand, plan, nd.stride,
+                       nd.genes, sigma, thr, key, gen, n, mul, slot_off, nu, (int)groups);
+  else
+    hipLaunchKernelGGL(vary_cand_kernel<1>, grid, dim3(256), 0, s, cur, cand, plan, nd.stride,
+                       nd.genes, sigma, thr, key, gen, n, mul, slot_off, nu, (int)groups);
   return hipGetLastError();
 }
 

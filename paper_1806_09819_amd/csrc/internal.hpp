@@ -91,6 +91,34 @@ hipError_t launch_amax_w1(const float* genomes, const NetDesc& nd, int pop, uint
 hipError_t launch_quantize_x(int dt, bool packed, const float* x, int b, int n0, int kp,
                              const uint32_t* x_amax, void* out, hipStream_t s);
 
+// genetic.hip / surrogate.hip: the fitness surrogate
+hipError_t launch_vary_cand(const float* cur, float* cand, const int4* plan, const NetDesc& nd,
+                            int n, int crossover, float sigma, uint64_t thr, const Key& key,
+                            uint32_t gen, uint32_t slot_off, float* nu, hipStream_t s);
+hipError_t launch_proj_bits(uint32_t* bits, int nchunks, const Key& key, hipStream_t s);
+hipError_t launch_mlp_init(float* prm, const Key& key, float a1, float a2, hipStream_t s);
+hipError_t launch_cand_plan(const int32_t* order, const float* f_adj, int M, int kc, int pop,
+                            int n_trunc, int selection, int tk, const Key& key, uint32_t gen,
+                            int4* cplan, float* cf_inh, hipStream_t s);
+hipError_t launch_proj(const float* cand, int64_t stride, int M, const uint32_t* bits,
+                       int nchunks, int splits, float* part, hipStream_t s);
+hipError_t launch_features(const float* part, int splits, int M, const float* nu, int ngroups,
+                           const int4* cplan, const float* f_adj, float scale, float* feat,
+                           hipStream_t s);
+hipError_t launch_mlp_forward(const float* prm, const float* feat, const int32_t* idx, int n,
+                              float* pre, float* pred, hipStream_t s);
+hipError_t launch_screen(const float* pred, int M, int N, int n_c, int kc, const int32_t* flag,
+                         int32_t* chosen, float* chosen_pred, hipStream_t s);
+hipError_t launch_gather(const float* cur, const float* cand, float* nxt, int64_t stride,
+                         int pop, int n_e, const int4* plan, const int32_t* chosen,
+                         const float* f_adj, const float* cf_inh, float* f_inh_next,
+                         hipStream_t s);
+hipError_t launch_mlp_train_step(float* prm, const float* feat, const int32_t* idx, int N,
+                                 const float* y, float* pre, float* pred, float* grad, float lr,
+                                 hipStream_t s);
+hipError_t launch_surrogate_judge(const float* pred, const float* y, int N, int warmup,
+                                  float tau_min, int32_t* state, float* stats, hipStream_t s);
+
 // rng.hip (generator entry points)
 hipError_t launch_rng_philox(const uint32_t* ctr, uint64_t key, uint32_t* out, int64_t n,
                              hipStream_t s);

@@ -8,44 +8,9 @@
 // the next power of two (padding keys all-ones) then gives the order.
 #include "internal.hpp"
 #include "runs.hpp"
+#include "select_common.hpp"
 
 namespace leea {
-
-__device__ __forceinline__ uint64_t rank_key(float f, uint32_t slot) {
-  uint32_t hi;
-  if (f != f) {
-    hi = 0xFFFFFFFFu;
-  } else {
-    uint32_t b = __float_as_uint(f);
-    if ((b << 1) == 0u) b = 0u;  // -0 -> +0
-    hi = (b & 0x80000000u) ? b : (~b & 0x7FFFFFFFu);
-  }
-  return ((uint64_t)hi << 32) | slot;
-}
-
-// Rank of one parent: truncation = floor(w * n_trunc / 2^32) from word p;
-// tournament = best of k ranks floor(w * pop / 2^32) from words p*k + c.
-__device__ __forceinline__ uint32_t parent_rank(const Key& key, uint32_t gen, uint32_t slot,
-                                                int p, int selection, int tk, uint32_t n_trunc,
-                                                uint32_t pop) {
-  if (selection == 0) {
-    const uint4 w = draw(key, kSel, gen, slot, 0u);
-    return (uint32_t)(((uint64_t)word_of(w, p) * n_trunc) >> 32);
-  }
-  uint32_t best = 0xFFFFFFFFu;
-  int blk = -1;
-  uint4 w = make_uint4(0u, 0u, 0u, 0u);
-  for (int c = 0; c < tk; ++c) {
-    const int idx = p * tk + c;
-    if ((idx >> 2) != blk) {
-      blk = idx >> 2;
-      w = draw(key, kSel, gen, slot, (uint32_t)blk);
-    }
-    const uint32_t r = (uint32_t)(((uint64_t)word_of(w, idx & 3) * pop) >> 32);
-    best = r < best ? r : best;
-  }
-  return best;
-}
 
 // Rank + plan of one population by the 1024 threads of a workgroup; keys is
 // LDS of n2 (the next power of two >= pop) 64-bit entries.

@@ -59,6 +59,12 @@ class Config(ctypes.Structure):
     ]
 
 
+class SurrogateConfig(ctypes.Structure):
+    """leea_surrogate_config."""
+    _fields_ = [("oversample", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("lr", ctypes.c_float), ("warmup", ctypes.c_int32), ("tau_min", ctypes.c_float)]
+
+
 _lib = None
 
 
@@ -120,6 +126,17 @@ def library():
         "leea_runs_autotune": [P, P, P, I64, P, P, P],
     }
     for name, args in runs_sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    SP = ctypes.POINTER(SurrogateConfig)
+    sur_sig = {
+        "leea_surrogate_workspace_bytes": [CP, SP, ctypes.POINTER(ctypes.c_size_t)],
+        "leea_surrogate_attach": [P, SP, P, ctypes.c_size_t],
+        "leea_surrogate_step": [P, P, P, I32, P, P, P, P],
+        "leea_surrogate_views": [P] + [ctypes.POINTER(P)] * 7 + [ctypes.POINTER(I32)],
+    }
+    for name, args in sur_sig.items():
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
@@ -331,6 +348,54 @@ class Leea:
     def set_state(self, genomes=None, f_adj=None, f_inh=None):
         _check(library().leea_set_state(self._ctx, _ptr(genomes), _ptr(f_adj), _ptr(f_inh)),
                self._ctx)
+
+    # --------------------------------------------------- fitness surrogate --
+
+    def attach_surrogate(self, oversample=4, steps=4, lr=0.01, warmup=2, tau_min=0.2):
+        lib = library()
+        sc = SurrogateConfig(oversample, steps, lr, warmup, tau_min)
+        n = ctypes.c_size_t()
+        _check(lib.leea_surrogate_workspace_bytes(ctypes.byref(self.cfg), ctypes.byref(sc),
+                                                  ctypes.byref(n)))
+        self.sur_workspace = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        _check(lib.leea_surrogate_attach(self._ctx, ctypes.byref(sc), _ptr(self.sur_workspace),
+                                         n.value), self._ctx)
+        self.sur_cfg = sc
+
+    def surrogate_step(self, x, y):
+        """One pre-screened generation: (f_adj, f_raw, acc, stats[4])."""
+        f_adj, f_raw, acc = self._out(), self._out(), self._out()
+        stats = torch.empty(4, dtype=torch.float32, device=self.device)
+        _check(library().leea_surrogate_step(self._ctx, _ptr(x), _ptr(y), x.shape[0],
+                                             _ptr(f_adj), _ptr(f_raw), _ptr(acc), _ptr(stats)),
+               self._ctx)
+        return f_adj, f_raw, acc, stats
+
+    def surrogate_views(self):
+        """Borrowed views of the last surrogate step: dict of candidates
+        [n, stride], plan [n, 4], features [n, 260], pred [n], chosen
+        [pop - n_elite], chosen_pred, params [16769]."""
+        ptrs = [ctypes.c_void_p() for _ in range(7)]
+        n = ctypes.c_int32()
+        _check(library().leea_surrogate_views(self._ctx, *[ctypes.byref(q) for q in ptrs],
+                                              ctypes.byref(n)), self._ctx)
+        M = n.value
+        N = self.pop - self.cfg.n_elite
+        ws = self.sur_workspace
+
+        def view(ptr, count, dtype, esize):
+            off = ptr - ws.data_ptr()
+            assert 0 <= off and off + count * esize <= ws.numel()
+            return ws[off:off + count * esize].view(dtype)
+
+        return dict(
+            candidates=view(ptrs[0].value, M * self.stride, torch.float32, 4).view(M, self.stride),
+            plan=view(ptrs[1].value, M * 4, torch.int32, 4).view(M, 4),
+            features=view(ptrs[2].value, M * 260, torch.float32, 4).view(M, 260),
+            pred=view(ptrs[3].value, M, torch.float32, 4),
+            chosen=view(ptrs[4].value, N, torch.int32, 4),
+            chosen_pred=view(ptrs[5].value, N, torch.float32, 4),
+            params=view(ptrs[6].value, 64 * 259 + 2 * 64 + 1, torch.float32, 4))
 
     def save(self):
         n = ctypes.c_size_t()

@@ -1,0 +1,148 @@
+"""GPU parity of the fitness surrogate against the oracle, teacher-forced
+with the device's float32 fitness and MLP parameters each generation:
+candidate plans, candidate genomes, screening and the new population
+bit-exact; features, predictions, the training step and Kendall tau
+within tolerances derived from float32 accumulation.  A longer run at the
+surrogate's configuration (784-32-10, P = 1000, b = 64) reports its
+screening error and accuracy next to plain LEEA."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import FIT_ATOL, FIT_RTOL, F32, genomes_np, make_run, say, to_dev, to_np
+from oracle import leea as O
+from oracle import surrogate as S
+from oracle.precision import round_bf16
+from paper_1806_09819_amd import datagen
+from paper_1806_09819_amd import presets
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -24
+
+
+def _teacher_forced(params, gens, k, steps, lr, warmup, tau_min, seed=0):
+    b = params["batch"]
+    run, ocfg = make_run(params, max_batch=b)
+    run.attach_surrogate(oversample=k, steps=steps, lr=lr, warmup=warmup, tau_min=tau_min)
+    widths = tuple(params["widths"])
+    g_genes = O.param_count(widths)
+    x, y = datagen.prototype_data(2000, seed=seed) if widths[0] == 784 else (
+        datagen.uniform_inputs((2000, widths[0]), seed), datagen.labels(2000, widths[-1], seed + 1))
+    xd, yd = to_dev(x), to_dev(y)
+    R = S.projection_signs(g_genes, ocfg.seed, ocfg.run)
+    n_e, n_c, n_m, _ = O.counts(ocfg.pop, ocfg.p_elite, ocfg.p_cross, ocfg.p_mut, ocfg.rho)
+    pop_o = O.init_population(ocfg)
+    xb, yb = run.draw_batch(0, xd, yd, b)
+    f_adj, _, _ = run.evaluate(xb, yb)
+    used = []
+    for g in range(1, gens + 1):
+        say("surrogate generation", g)
+        f_prev = to_np(f_adj).copy()
+        views0 = run.surrogate_views()
+        prm0 = to_np(views0["params"]).copy()
+        xb, yb = run.draw_batch(g, xd, yd, b)
+        f_adj, f_raw, acc, stats = run.surrogate_step(xb, yb)
+        v = run.surrogate_views()
+        st = to_np(stats)
+        used.append(int(st[0]))
+        # candidate plan and genomes: bit-exact
+        order = O.rank(f_prev)
+        ops, p1, p2, _ = S.candidate_plan(order, f_prev, ocfg, g, k)
+        plan = to_np(v["plan"])
+        assert np.array_equal(plan[:, 0], ops) and np.array_equal(plan[:, 1], p1), g
+        assert np.array_equal(plan[:, 2], p2), g
+        kids = S.candidates(pop_o, ops, p1, p2, ocfg, g)
+        assert np.array_equal(to_np(v["candidates"])[:, :g_genes].view(np.uint32),
+                              kids.view(np.uint32)), g
+        # features within the float32 accumulation bound
+        X = S.features(kids, pop_o[p1], f_prev[p1], f_prev[p2], R)
+        Xd = to_np(v["features"])[:, :S.INPUTS].astype(np.float64)
+        mag = (np.abs(round_bf16(kids).astype(np.float64)).sum(axis=1)
+               * float(S.scale(g_genes)))[:, None]
+        nchunks = (g_genes + 31) // 32
+        bound = (nchunks + 40) * U * mag + 2 * U * np.abs(X[:, :256]) + 1e-30
+        assert np.all(np.abs(Xd[:, :256] - X[:, :256]) <= bound), g
+        assert np.array_equal(Xd[:, 256:258], X[:, 256:258]), g
+        assert np.allclose(Xd[:, 258], X[:, 258], rtol=1e-5, atol=1e-9), g
+        # predictions from the device's features and parameters
+        prm = {"W1": prm0[:64 * 259].reshape(64, 259), "b1": prm0[64 * 259:64 * 260],
+               "w2": prm0[64 * 260:64 * 261], "b2": prm0[64 * 261]}
+        pred_o, _ = S.mlp_forward(prm, Xd)
+        pred = to_np(v["pred"]).astype(np.float64)
+        scl = np.abs(Xd) @ np.abs(prm["W1"].astype(np.float64)).T
+        pbound = 600 * U * (np.maximum(scl, 1e-30) @ np.abs(prm["w2"].astype(np.float64))) + 1e-6
+        assert np.all(np.abs(pred - pred_o) <= pbound), g
+        # screening (device float32 predictions) and the new population
+        keep = S.screen(to_np(v["pred"]), ocfg.pop - n_e, bool(st[0]), k, n_c, n_m)
+        assert np.array_equal(to_np(v["chosen"]), keep), g
+        new_o = np.concatenate([pop_o[order[:n_e]], kids[keep]])
+        assert np.array_equal(genomes_np(run).view(np.uint32), new_o.view(np.uint32)), g
+        idx = O.batch_indices(ocfg.seed, g, b, x.shape[0], ocfg.run)
+        fo, _ = O.evaluate(new_o, widths, x[idx], y[idx])
+        fr = to_np(f_raw).astype(np.float64)
+        assert np.all(np.abs(fr - fo) <= FIT_RTOL * np.abs(fo) + FIT_ATOL), g
+        # judge and training
+        yk = to_np(f_raw)[n_e:].astype(np.float64)
+        cp = to_np(v["chosen_pred"]).astype(np.float64)
+        assert abs(S.kendall_tau_a(cp, yk) - float(st[1])) < 1e-6, g
+        p_o = prm
+        for _ in range(steps):
+            p_o = S.mlp_gradient_step(p_o, Xd[keep], yk, lr)
+        prm1 = to_np(v["params"]).astype(np.float64)
+        ref = np.concatenate([p_o["W1"].ravel(), p_o["b1"], p_o["w2"], [p_o["b2"]]])
+        assert np.allclose(prm1, ref, rtol=2e-4, atol=2e-6), (g, np.max(np.abs(prm1 - ref)))
+        pop_o = new_o
+    return used
+
+
+def test_surrogate_teacher_forced_small():
+    params = dict(presets.PAPER, widths=(96, 24, 5), pop=30, batch=16, sigma=0.05, p_gene=0.5,
+                  seed=4)
+    used = _teacher_forced(params, gens=5, k=3, steps=3, lr=0.05, warmup=1, tau_min=-1.0)
+    assert used[0] == 0 and all(u == 1 for u in used[1:])      # off for warm-up, then on
+
+
+def test_surrogate_teacher_forced_arithmetic_tournament():
+    params = dict(presets.PAPER, widths=(100, 20, 12, 3), pop=23, batch=33, sigma=0.02,
+                  crossover="arithmetic", selection="tournament", alpha=0.5, seed=5)
+    used = _teacher_forced(params, gens=3, k=2, steps=2, lr=0.02, warmup=0, tau_min=0.0)
+    assert len(used) == 3
+
+
+def test_surrogate_report_small_config_at_scale():
+    """784-32-10, P = 1000, b = 64, k = 4: surrogate screening error over
+    20 generations and the best network's validation accuracy against
+    plain LEEA from the same seed."""
+    data = datagen.splits("teacher", sizes=(20000, 2000, 0))
+    xt, yt = to_dev(data["x_train"]), to_dev(data["y_train"])
+    xv, yv = to_dev(data["x_val"]), to_dev(data["y_val"])
+    params = dict(presets.SMALL, pop=1000, batch=64, sigma=0.01, p_gene=0.1)
+    out = {}
+    for mode in ("plain", "surrogate"):
+        run, _ = make_run(params, max_batch=max(64, xv.shape[0]))
+        if mode == "surrogate":
+            run.attach_surrogate(oversample=4, steps=8, lr=0.01, warmup=2, tau_min=0.1)
+        xb, yb = run.draw_batch(0, xt, yt, 64)
+        run.evaluate(xb, yb)
+        taus, rmses, used = [], [], 0
+        for g in range(1, 21):
+            xb, yb = run.draw_batch(g, xt, yt, 64)
+            if mode == "surrogate":
+                _, _, _, st = run.surrogate_step(xb, yb)
+                st = to_np(st)
+                taus.append(float(st[1]))
+                rmses.append(float(st[2]))
+                used += int(st[0])
+            else:
+                run.step(xb, yb)
+        f_raw, acc = run.score(xv, yv)
+        _, f_adj = run.population()
+        best = int(torch.argmax(f_adj).item())
+        out[mode] = dict(val_acc_best=float(to_np(acc)[best]), val_acc_max=float(to_np(acc).max()),
+                         tau_last5=float(np.mean(taus[-5:])) if taus else None,
+                         rmse_last5=float(np.mean(rmses[-5:])) if rmses else None,
+                         screened_generations=used)
+    say("surrogate report", out)
+    assert out["surrogate"]["screened_generations"] >= 0
+    assert np.isfinite(out["surrogate"]["tau_last5"])
