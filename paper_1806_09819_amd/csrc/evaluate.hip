@@ -136,7 +136,7 @@ __device__ __forceinline__ void eval_small_body(int j, const float* __restrict__
 }
 
 template <int NT, int DT>
-__global__ __launch_bounds__(256, 4) void eval_small_kernel(const float* __restrict__ genomes,
+__global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void eval_small_kernel(const float* __restrict__ genomes,
                                                          NetDesc nd, const float* __restrict__ x,
                                                          const int32_t* __restrict__ y, int b,
                                                          float2* __restrict__ partial,
@@ -503,7 +503,7 @@ bool eval_shape_f32(const NetDesc& nd, int b, int kind, int mw, EvalShape* out) 
 // state advances right after it) or the initial one.
 
 template <int NT, int DT>
-__global__ __launch_bounds__(256, 4) void runs_eval_small_kernel(
+__global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void runs_eval_small_kernel(
     const RunDesc* __restrict__ runs, const BatchState* __restrict__ st,
     const int* __restrict__ off, const int* __restrict__ ids, int n) {
   const int i = find_group(off, n, blockIdx.x);
