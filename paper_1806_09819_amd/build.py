@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libleea.so")
 SOURCES = ("api.hip", "genetic.hip", "rng.hip", "select.hip", "evaluate.hip", "fused.hip",
-           "evaluate_lp.hip", "quant.hip", "runs_api.hip",
+           "evaluate_lp.hip", "evaluate_lpw.hip", "quant.hip", "runs_api.hip",
            "surrogate.hip")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

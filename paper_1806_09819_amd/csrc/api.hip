@@ -51,7 +51,9 @@ struct leea_ctx {
   int kp;          // n0 rounded up to 32 (packed quantised batch row)
   uint32_t* w_amax[2];  // FP8: largest |W_1| of each network (ping-pong with the genomes)
   uint32_t* x_amax;     // FP8: largest |x| of the batch being evaluated
-  void* xq;             // quantised batch (values [b][n0] or packed [b][kp])
+  void* xq;             // quantised batch (values [b][n0], packed [b][kp] or chunk-major)
+  W1Shadow wsh;         // bfloat16 copy of every W_1 (large-batch bfloat16 kernel), or none
+  int wsh_ok;           // the copy matches the current population
   // fitness surrogate (leea_surrogate_attach)
   int sur;
   leea_surrogate_config sc;
@@ -179,10 +181,22 @@ leea_status validate(const leea_config* cfg, NetDesc* nd) {
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Carve {
-  size_t genomes, scalars, plan, order, partial, xq, total;
+  size_t genomes, scalars, plan, order, partial, xq, wsh, total;
 };
 
 int padded_k(int n0) { return (n0 + 31) & ~31; }
+int round128(int v) { return (v + 127) & ~127; }
+
+// bfloat16 W_1 copy: kept when batches above 16 rows can reach the
+// large-batch bfloat16 kernel that reads it (n0 % 4 == 0, hidden width <= 256,
+// W_1 below 2^24 genes)
+bool uses_shadow(const leea_config* cfg, const NetDesc& nd) {
+  return cfg->eval_dtype == LEEA_DT_BF16 && cfg->max_batch > 16 && nd.w[0] % 4 == 0 &&
+         nd.w[1] <= 256 && (int64_t)nd.w[0] * nd.w[1] < (1 << 24);
+}
+int64_t shadow_net(const NetDesc& nd) {
+  return (int64_t)(padded_k(nd.w[0]) / 32) * ((nd.w[1] + 15) & ~15) * 32;
+}
 
 Carve carve(const leea_config* cfg, const NetDesc& nd) {
   Carve c;
@@ -194,13 +208,17 @@ Carve carve(const leea_config* cfg, const NetDesc& nd) {
   c.order = align256(P * 4);
   c.partial = align256(P * (size_t)n_mt * 8);
   c.xq = 0;
+  c.wsh = 0;
   if (cfg->eval_dtype != LEEA_DT_F32) {
-    const size_t row = (size_t)nd.w[0] * 4 > (size_t)padded_k(nd.w[0]) * 2
-                           ? (size_t)nd.w[0] * 4
-                           : (size_t)padded_k(nd.w[0]) * 2;
-    c.xq = align256((size_t)cfg->max_batch * row) + 256;  // + the batch amax
+    const size_t kp = (size_t)padded_k(nd.w[0]);
+    const size_t row = (size_t)nd.w[0] * 4 > kp * 2 ? (size_t)nd.w[0] * 4 : kp * 2;
+    const size_t chunked = (size_t)round128(cfg->max_batch) * kp * 2;
+    const size_t q = (size_t)cfg->max_batch * row > chunked ? (size_t)cfg->max_batch * row
+                                                            : chunked;
+    c.xq = align256(q) + 256;  // + the batch amax
+    if (uses_shadow(cfg, nd)) c.wsh = align256(P * (size_t)shadow_net(nd) * 2);
   }
-  c.total = 2 * c.genomes + 9 * c.scalars + c.plan + c.order + c.partial + c.xq;
+  c.total = 2 * c.genomes + 9 * c.scalars + c.plan + c.order + c.partial + c.xq + c.wsh;
   return c;
 }
 
@@ -232,6 +250,25 @@ leea_status run_eval_lp(leea_ctx* c, const float* x, const int32_t* y, int32_t b
     if (st) return st;
   }
   const bool small = b <= 16;
+  if (!small && c->wsh.p && eval_lpw_supported(c->nd, b)) {
+    // large batch from the bfloat16 W_1 copy (rebuilt if the population
+    // changed other than through crossover_mutate)
+    if (!c->wsh_ok) {
+      st = dev(c, launch_shadow_w1(c->genomes[c->cur], c->nd, c->cfg.pop, c->wsh, c->stream),
+               "W1 copy launch");
+      if (st) return st;
+      c->wsh_ok = 1;
+    }
+    const int bpad = round128(b);
+    st = dev(c, launch_quantize_x_chunks(x, b, n0, c->kp, bpad, (uint16_t*)c->xq, c->stream),
+             "quantize launch");
+    if (st) return st;
+    *n_mt = eval_lpw_ptiles(c->nd, b);
+    return dev(c, launch_evaluate_lpw(c->genomes[c->cur], c->nd, c->cfg.pop, c->wsh,
+                                      (const uint16_t*)c->xq, c->kp, bpad, y, b, c->partial,
+                                      c->stream),
+               "evaluate launch");
+  }
   if (!small && !eval_lp_supported(c->nd, b, c->dt))
     return fail(c, LEEA_EINVAL, "reduced-precision evaluation does not fit this batch");
   st = dev(c, launch_quantize_x(c->dt, !small, x, b, n0, c->kp, c->x_amax, c->xq, c->stream),
@@ -340,6 +377,13 @@ leea_status leea_init_population(const leea_config* cfg, void* workspace, size_t
   p += cv.scalars;
   c->x_amax = cv.xq ? (uint32_t*)p : nullptr;
   c->xq = cv.xq ? (void*)(p + 256) : nullptr;
+  p += cv.xq;
+  c->wsh.p = cv.wsh ? (uint16_t*)p : nullptr;
+  c->wsh.net = shadow_net(nd);
+  c->wsh.n0 = nd.w[0];
+  c->wsh.nrp = (nd.w[1] + 15) & ~15;
+  c->wsh.rcp_n0 = 1.0f / (float)nd.w[0];
+  c->wsh_ok = 0;
   c->dt = cfg->eval_dtype;
   c->kp = padded_k(nd.w[0]);
   c->n_mt_max = (cfg->max_batch + 63) / 64;
@@ -366,6 +410,11 @@ leea_status leea_init_population(const leea_config* cfg, void* workspace, size_t
   if (!st && c->dt == LEEA_DT_FP8)
     st = dev(nullptr, launch_amax_w1(c->genomes[0], nd, cfg->pop, c->w_amax[0], c->stream),
              "amax launch");
+  // the whole copy, padding included (the variation writes only W_1 itself)
+  if (!st && c->wsh.p)
+    st = dev(nullptr, launch_shadow_w1(c->genomes[0], nd, cfg->pop, c->wsh, c->stream),
+             "W1 copy launch");
+  c->wsh_ok = c->wsh.p ? 1 : 0;
   if (st) {
     delete c;
     return st;
@@ -481,9 +530,10 @@ leea_status leea_crossover_mutate(leea_ctx* c) {
   st = dev(c,
            launch_vary(c->genomes[c->cur], c->genomes[c->cur ^ 1], c->plan, c->nd, c->cfg.pop,
                        c->cfg.crossover, sigma, c->cfg.mut_threshold, key_of(c), g, sig_cur,
-                       sig_next, c->tau, amax, c->stream),
+                       sig_next, c->tau, amax, c->wsh, c->stream),
            "vary launch");
   if (st) return st;
+  c->wsh_ok = c->wsh.p ? 1 : 0;  // the variation wrote the children's copies
   advance(c);
   return LEEA_OK;
 }
@@ -596,6 +646,7 @@ leea_status leea_set_state(leea_ctx* c, const float* src, const float* f_adj,
     st = dev(c, launch_amax_w1(c->genomes[c->cur], c->nd, c->cfg.pop, c->w_amax[c->cur],
                                c->stream), "amax launch");
   if (st) return st;
+  if (src) c->wsh_ok = 0;
   c->has_inh = f_inh ? 1 : 0;
   c->state = f_adj ? kEvaluated : kNeedEval;
   return LEEA_OK;
@@ -674,6 +725,7 @@ leea_status leea_load(leea_ctx* c, const void* host_buf, size_t bytes) {
     st = dev(c, launch_amax_w1(c->genomes[c->cur], c->nd, c->cfg.pop, c->w_amax[c->cur],
                                c->stream), "amax launch");
   if (st) return st;
+  c->wsh_ok = 0;
   c->gen = h.gen;
   // a checkpoint taken between select and crossover_mutate resumes at select
   c->state = h.state == kSelected ? kEvaluated : (int)h.state;
@@ -894,6 +946,7 @@ leea_status leea_surrogate_step(leea_ctx* c, const float* x, const int32_t* y, i
     st = dev(c, launch_amax_w1(c->genomes[c->cur ^ 1], c->nd, g.pop, c->w_amax[c->cur ^ 1], s),
              "amax launch");
   if (st) return st;
+  c->wsh_ok = 0;  // the new population came from the candidates
   advance(c);
   st = run_eval(c, x, y, b, true, f_adj, f_raw, acc);
   if (st) return st;

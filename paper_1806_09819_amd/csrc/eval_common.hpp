@@ -114,6 +114,29 @@ static __device__ void mfma_layer(const float* in, int ldi, int n_in, float* out
   }
 }
 
+// mfma_layer with as many row tiles per group as this wave has (up to GMAX):
+// a wave with fewer row tiles than the group size would multiply copies of
+// its last tile for nothing.  The result does not depend on the group size.
+template <int GMAX>
+static __device__ void mfma_layer_fit(const float* in, int ldi, int n_in, float* out, int ldo,
+                                      int n_out, const float* W, const float* bias, bool relu,
+                                      int mtiles) {
+  const int wave = threadIdx.x >> 6;
+  const int ntiles = (n_out + 15) >> 4;
+  int mt0 = 0, mstep = 1;
+  if (ntiles < 4) {
+    mstep = 4 / ntiles;
+    mt0 = wave / ntiles;
+  }
+  const int r = mt0 < mtiles ? (mtiles - mt0 + mstep - 1) / mstep : 0;
+  if (GMAX >= 4 && r >= 3)
+    mfma_layer<(GMAX >= 4 ? 4 : 1)>(in, ldi, n_in, out, ldo, n_out, W, bias, relu, mtiles);
+  else if (GMAX >= 2 && r == 2)
+    mfma_layer<(GMAX >= 2 ? 2 : 1)>(in, ldi, n_in, out, ldo, n_out, W, bias, relu, mtiles);
+  else
+    mfma_layer<1>(in, ldi, n_in, out, ldo, n_out, W, bias, relu, mtiles);
+}
+
 // The same layer on VALU, for hidden widths that are not multiples of 4.
 static __device__ void scalar_layer(const float* in, int ldi, int n_in, float* out, int ldo, int n_out,
                              const float* W, const float* bias, bool relu, int rows) {
@@ -141,11 +164,13 @@ static __device__ void scalar_layer(const float* in, int ldi, int n_in, float* o
 // Layer weights come from tw: W_l at tw + (woff[l] - toff) (the genome in
 // global memory with toff = 0, or a copy of the genome's tail in LDS).
 // G: row tiles per matrix-core group in the hidden layers (see mfma_layer).
+// y == nullptr: the label of row threadIdx.x is ylab (rows <= blockDim.x),
+// loaded by the caller ahead of time.
 template <int G>
 static __device__ void tail_and_fitness(float* lds, const EvalLds& lo, const NetDesc& nd,
                                  const float* tw, int64_t toff, int mtiles, int rows,
                                  int m0, const int32_t* __restrict__ y, bool tail_vec,
-                                 float2* __restrict__ out) {
+                                 float2* __restrict__ out, int ylab = 0) {
   const float* in = lds + lo.h1;
   int ldi = lo.ld1;
   float* dst = lds + lo.ta;
@@ -154,7 +179,7 @@ static __device__ void tail_and_fitness(float* lds, const EvalLds& lo, const Net
     const float* bias = tw + (nd.boff[l] - toff);
     const bool relu = l < nd.L - 1;
     if (tail_vec)
-      mfma_layer<G>(in, ldi, nd.w[l], dst, lo.ldt, nd.w[l + 1], W, bias, relu, mtiles);
+      mfma_layer_fit<G>(in, ldi, nd.w[l], dst, lo.ldt, nd.w[l + 1], W, bias, relu, mtiles);
     else
       scalar_layer(in, ldi, nd.w[l], dst, lo.ldt, nd.w[l + 1], W, bias, relu, 16 * mtiles);
     __syncthreads();
@@ -167,7 +192,7 @@ static __device__ void tail_and_fitness(float* lds, const EvalLds& lo, const Net
   int* cor = reinterpret_cast<int*>(lds + lo.cor);
   for (int m = threadIdx.x; m < rows; m += blockDim.x) {
     const float* z = in + m * ldi;
-    const int yy = y[m0 + m];
+    const int yy = y ? y[m0 + m] : ylab;
     float mx = z[0];
     int best = 0;
     for (int k = 1; k < d; ++k)

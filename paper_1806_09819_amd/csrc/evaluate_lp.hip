@@ -13,8 +13,10 @@
 //   staged (bfloat16, or E4M3 of w * 2^-e_w); the batch arrives already
 //   quantised and packed [b][kp] (kp = n0 rounded up to 32).
 // * A workgroup owns 64*MW rows (MW 1 or 2); the tail layers and the
-//   fitness run in passes of 64 or 128 rows over the LDS tile, each pass
-//   writing its own partial sums.  (Four row tiles per wave measured slower:
+//   fitness run in passes over the LDS tile, each pass writing its own
+//   partial sums: 64 rows for bfloat16 (the grouping of the kernel that reads
+//   the bfloat16 W_1 copy, so both give bit-identical fitness), 64 MW up to
+//   128 for FP8.  (Four row tiles per wave measured slower:
 //   their accumulators push the kernel to one wave per SIMD and into
 //   accumulator-register shuffling.)
 // * FP8 products are rescaled by 2^(e_x + e_w) (exact) before the bias.
@@ -23,8 +25,8 @@
 // reading one slot column of 16 rows over distinct banks.
 #include <string.h>
 
-#include "eval_common.hpp"
 #include "lowp.hpp"
+#include "lp_common.hpp"
 #include "runs.hpp"
 
 namespace leea {
@@ -215,54 +217,11 @@ __device__ __forceinline__ void eval_lp_body(int j, int wt, const float* __restr
     }
   }
   __syncthreads();  // staging is dead from here on
-
-  // epilogue in passes of pass_rows rows: the waves owning those rows write
-  // scale * acc + bias (ReLU unless it is the output layer) into the LDS
-  // tile, then the tail layers and the fitness of the pass run
   const float fac = DT == 2 ? fp8_factor(*x_amax, w_amax[j]) : 1.0f;
-  const float* __restrict__ b1 = genome + nd.boff[0];
-  const bool hidden = nd.L > 1;
-  float* h1 = lds + lo.h1;
-  const int passes = MT / pass_rows;
-  for (int p = 0; p < passes; ++p) {
-    const int pr0 = p * pass_rows;
-    const int prow = rows - pr0 < pass_rows ? rows - pr0 : pass_rows;
-    const int pidx = wt * passes + p;
-    if (prow <= 0 || pidx >= n_pt) break;  // uniform across the workgroup
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int n = t * 16 + mn;
-      const bool nv = n < n1;
-      const float bb = nv ? b1[n] : 0.0f;
-#pragma unroll
-      for (int mi = 0; mi < MW; ++mi)
-#pragma unroll
-        for (int i2 = 0; i2 < 4; ++i2) {
-          const int m = wave * MW * 16 + mi * 16 + 4 * kq + i2 - pr0;
-          if (m >= 0 && m < pass_rows) {
-            float v = acc[mi][t][i2];
-            if (DT == 2) v = v * fac;
-            v = v + bb;
-            if (hidden) v = relu_keep_nan(v);
-            h1[m * lo.ld1 + n] = nv ? v : 0.0f;
-          }
-        }
-    }
-    __syncthreads();
-    tail_and_fitness<4>(lds, lo, nd, genome, 0, pass_rows / 16, prow, m0 + pr0, y, tail_vec != 0,
-                     partial + (int64_t)j * n_pt + pidx);
-    __syncthreads();
-  }
-}
-
-// XCD-aware order (hardware workgroup i runs on XCD i % 8): consecutive
-// logical ids go to the same XCD, so one network's row tiles share its L2.
-__device__ __forceinline__ int xcd_logical(int i, int total) {
-  const int q = total >> 3;
-  const int r8 = total & 7;
-  const int xcd = i & 7;
-  const int kk = i >> 3;
-  return xcd < r8 ? xcd * (q + 1) + kk : r8 * (q + 1) + (xcd - r8) * q + kk;
+  const float nob[NT] = {};
+  const int noy[MW] = {};
+  lp_epilogue<NT, MW, DT>(lds, acc, fac, j, wt, genome, genome, 0, nd, y, b, partial, lo, n_pt,
+                          pass_rows, tail_vec, nob, noy);
 }
 
 template <int NT, int MW, int DT, int D>
@@ -281,23 +240,6 @@ __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lp_kernel(con
 }
 
 // ------------------------------------------------------------- dispatch --
-
-static int round16i(int v) { return (v + 15) & ~15; }
-
-static EvalLds lp_tail_layout(const NetDesc& nd, int rows) {
-  EvalLds lo;
-  lo.ld1 = round16i(nd.w[1]) + 4;
-  int w = 4;
-  for (int l = 2; l <= nd.L; ++l) w = nd.w[l] > w ? nd.w[l] : w;
-  lo.ldt = round16i(w) + 4;
-  const int ldmax = lo.ld1 > lo.ldt ? lo.ld1 : lo.ldt;
-  lo.h1 = 0;
-  lo.ta = rows * ldmax;
-  lo.ll = lo.ta + rows * lo.ldt;
-  lo.cor = lo.ll + rows;
-  lo.total = lo.cor + rows;
-  return lo;
-}
 
 struct LpShape {
   int mw, pass_rows;
@@ -327,7 +269,8 @@ static bool lp_shape(const NetDesc& nd, int b, int dt, LpShape* out) {
   int mw = b > 64 ? 2 : 1;
   while (mw > 1 && mw * nt > 32) mw >>= 1;
   for (; mw >= 1; mw >>= 1) {
-    for (int pr = 64 * mw < 128 ? 64 * mw : 128; pr >= 64; pr >>= 1) {
+    // bfloat16: 64-row passes like the kernel on the bfloat16 W_1 copy
+    for (int pr = dt == 1 ? 64 : (64 * mw < 128 ? 64 * mw : 128); pr >= 64; pr >>= 1) {
       EvalLds lo;
       const size_t bytes = lp_bytes(nd, mw, pr, es, &lo);
       if (bytes <= kLdsMax) {
@@ -369,7 +312,7 @@ bool eval_shape_lp(const NetDesc& nd, int b, int dt, int kind, int mw, EvalShape
     if (mw * nt > 32) return false;
     const int es = dt == 1 ? 2 : 1;
     bool found = false;
-    for (int pr = 64 * mw < 128 ? 64 * mw : 128; pr >= 64 && !found; pr >>= 1) {
+    for (int pr = dt == 1 ? 64 : (64 * mw < 128 ? 64 * mw : 128); pr >= 64 && !found; pr >>= 1) {
       EvalLds lo;
       const size_t bytes = lp_bytes(nd, mw, pr, es, &lo);
       if (bytes <= kLdsMax) {

@@ -1,0 +1,338 @@
+// Large-batch population forward pass with a bfloat16 first layer that reads
+// W_1 from its bfloat16 copy (W1Shadow, written by the variation kernel as
+// each child is made) instead of converting the float32 genome on the fly.
+//
+// Same product as the other bfloat16 kernel (section 3.3: X * [W1_1 .. W1_P]^T,
+// one v_mfma_f32_16x16x32_bf16 per (row tile, column tile, 32-wide K chunk),
+// FP32 accumulation in K order, then the FP32 tail and fitness), with the
+// staging done by the memory system instead of registers:
+// * Both operands are chunk-major in global memory, so the 16 rows x 64 bytes
+//   of one chunk are 1 KiB contiguous.  global_load_lds_dwordx4 copies such a
+//   block straight into LDS (lane l writes bytes 16 l .. 16 l + 15 of it);
+//   lane l reads the 16-byte slot that the bank swizzle places at its
+//   position, so the copy is coalesced and the swizzle costs nothing.
+// * S stages, S - 1 chunks in flight: chunk ch + S - 1 is requested right
+//   after the barrier of chunk ch.  The stages are separate static LDS
+//   arrays, so the compiler can tell a stage being read from the stages
+//   being copied into and adds no wait for copies still in flight (with one
+//   array, or the dynamic LDS, it drains every copy before each read).
+//   Stage 0 is large enough for the tail's LDS, which reuses it.  Every wave
+//   issues the same number Q of block copies per chunk (a wave with no block
+//   left re-copies its previous one: same bytes to the same place), so
+//   "chunk ch has landed" is vmcnt <= (S-2) Q, waited for explicitly before
+//   the barrier.  Past the last chunk the last one is copied again into the
+//   free stage, which keeps that count exact.
+// * No register staging, no conversion: the main loop is copy issue, LDS
+//   fragment reads and matrix instructions.
+#include <type_traits>
+
+#include "lowp.hpp"
+#include "lp_common.hpp"
+
+namespace leea {
+
+typedef __bf16 bf16x8w __attribute__((ext_vector_type(8)));
+
+// s_waitcnt immediate: vmcnt <= n, lgkmcnt = 0, expcnt untouched.
+constexpr int waitcnt_vm_lgkm0(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4); }
+
+// Device-only helpers: the lambdas of the kernel are compiled for the host
+// too, where these builtins do not exist.
+__device__ __forceinline__ void copy16_to_lds(const char* g, char* l) {
+  __builtin_amdgcn_global_load_lds(g, l, 16, 0, 0);
+}
+
+__device__ __forceinline__ floatx4 mfma_bf16(const uint4& a, const uint4& b, const floatx4& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8w, a),
+                                                 __builtin_bit_cast(bf16x8w, b), c, 0, 0, 0);
+}
+
+// Wait until at most N copies of this wave are in flight and its LDS reads
+// are done, then the workgroup barrier; the compiler moves no memory access
+// across either side.
+template <int N>
+__device__ __forceinline__ void wait_copies_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(N));
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// LDS plan (bytes): a stage holds NT 16-row blocks of W_1 and 4 MW of the
+// batch, 64 bytes per row; the tail of a 64-row pass needs h1 [64][16 NT + 4],
+// a [64][<= 68] buffer (tail widths up to 64) and two [64] vectors; three
+// stages while the whole plan fits 80 KiB (two workgroups per CU), else two.
+constexpr int lpw_stage_bytes(int nt, int mw) { return (nt * 16 + 64 * mw) * 64; }
+// Stage 1 also takes the network's tail genes (W_2 .. b_L) for the tail
+// layers when they fit 16 KiB (the 784-112-32-10 network's take 15.4 KiB).
+constexpr int kTailGenesCap = 16 * 1024;
+constexpr int lpw_stage1_bytes(int nt, int mw) {
+  return lpw_stage_bytes(nt, mw) > kTailGenesCap ? lpw_stage_bytes(nt, mw) : kTailGenesCap;
+}
+constexpr int lpw_tail_cap(int nt) { return 64 * (16 * nt + 4) * 4 + 64 * 68 * 4 + 2 * 64 * 4; }
+constexpr int lpw_stage0_bytes(int nt, int mw) {
+  return lpw_stage_bytes(nt, mw) > lpw_tail_cap(nt) ? lpw_stage_bytes(nt, mw) : lpw_tail_cap(nt);
+}
+constexpr int lpw_stages(int nt, int mw) {
+  return lpw_stage0_bytes(nt, mw) + lpw_stage1_bytes(nt, mw) + lpw_stage_bytes(nt, mw) <=
+                 80 * 1024
+             ? 3
+             : 2;
+}
+constexpr int lpw_lds_bytes(int nt, int mw) {
+  return lpw_stage0_bytes(nt, mw) + lpw_stage1_bytes(nt, mw) +
+         (lpw_stages(nt, mw) - 2) * lpw_stage_bytes(nt, mw);
+}
+
+template <int NT, int MW>
+__global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lpw_kernel(
+    const float* __restrict__ genomes, NetDesc nd, W1Shadow wsh, const uint16_t* __restrict__ xq,
+    int nch, int bpad, const int32_t* __restrict__ y, int b, float2* __restrict__ partial,
+    EvalLds lo, int n_wt, int n_pt, int pass_rows, int pop, int tail_vec) {
+  constexpr int S = lpw_stages(NT, MW);
+  constexpr int RB = 64;                // bytes per staged row (32 bfloat16)
+  constexpr int MT = 64 * MW;           // rows per workgroup
+  constexpr int NR = NT * 16;           // staged weight rows
+  constexpr int STG = (NR + MT) * RB;   // bytes per stage
+  constexpr int NB = NT + MT / 16;      // 1 KiB blocks per stage
+  constexpr int Q = (NB + 3) / 4;       // block copies per wave per stage
+  static_assert(Q >= 2, "duplicate copies need a previous block");
+  __shared__ __attribute__((aligned(16))) char st0[lpw_stage0_bytes(NT, MW)];
+  __shared__ __attribute__((aligned(16))) char st1[lpw_stage1_bytes(NT, MW)];
+  __shared__ __attribute__((aligned(16))) char st2[S == 3 ? STG : 16];
+  // stage by a compile-time index, so that every LDS access names one array
+  auto stage_ptr = [&](auto sc) -> char* {
+    constexpr int st = decltype(sc)::value;
+    if constexpr (st == 0) return st0;
+    else if constexpr (st == 1) return st1;
+    else return st2;
+  };
+
+  const int Lw = xcd_logical(blockIdx.x, n_wt * pop);
+  const int j = Lw / n_wt;
+  const int wt = Lw - j * n_wt;
+  const int m0 = wt * MT;
+  const float* __restrict__ genome = genomes + (int64_t)j * nd.stride;
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  // this lane's 16 bytes of a block: row r = lane / 4, physical slot lane % 4,
+  // which holds logical slot (lane % 4) ^ ((r >> 1) & 3)
+  const int r = lane >> 2;
+  const int lane_off = r * RB + (((lane & 3) ^ ((r >> 1) & 3)) * 16);
+  const char* src[Q];
+  int64_t cstride[Q];
+  int dst[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    int i = q * 4 + wave;
+    if (i >= NB) i -= 4;
+    if (i < NT) {
+      src[q] = reinterpret_cast<const char*>(wsh.p + (int64_t)j * wsh.net) + i * 1024 + lane_off;
+      cstride[q] = (int64_t)NR * RB;
+      dst[q] = i * 1024;
+    } else {
+      src[q] = reinterpret_cast<const char*>(xq) + (int64_t)(m0 + 16 * (i - NT)) * RB + lane_off;
+      cstride[q] = (int64_t)bpad * RB;
+      dst[q] = NR * RB + (i - NT) * 1024;
+    }
+  }
+  auto issue = [&](int ch, auto sc) {
+    const int64_t c = ch < nch ? ch : nch - 1;
+    char* d = stage_ptr(sc);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+      copy16_to_lds(src[q] + c * cstride[q], d + dst[q]);
+  };
+
+  const int mn = lane & 15;
+  const int kq = lane >> 4;
+
+  // What the epilogue and the tail read from global memory, requested now so
+  // that it arrives during the main loop: layer 1's bias, the labels of this
+  // thread's row in each 64-row pass, and the tail genes (W_2 .. b_L,
+  // contiguous from woff[1]), which go to stage 1 after the loop.
+  float b1v[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int n = t * 16 + mn;
+    b1v[t] = n < nd.w[1] ? genome[nd.boff[0] + n] : 0.0f;
+  }
+  int ylab[MW];
+#pragma unroll
+  for (int p = 0; p < MW; ++p) {
+    const int m = m0 + 64 * p + tid;
+    ylab[p] = (tid < 64 && m < b) ? y[m] : 0;
+  }
+  const int64_t toff = nd.L > 1 ? nd.woff[1] : 0;
+  const int tn = (int)(nd.genes - toff);
+  const bool tcopy = nd.L > 1 && tail_vec && (toff & 3) == 0 && tn * 4 <= kTailGenesCap;
+  constexpr int TQ = kTailGenesCap / 16 / 256;  // float4 per thread
+  float4 tv[TQ];
+#pragma unroll
+  for (int q = 0; q < TQ; ++q) {
+    const int i = tid + 256 * q;
+    tv[q] = (tcopy && 4 * i < tn) ? reinterpret_cast<const float4*>(genome + toff)[i]
+                                  : float4{0.f, 0.f, 0.f, 0.f};
+  }
+
+  floatx4 acc[MW][NT];
+#pragma unroll
+  for (int mi = 0; mi < MW; ++mi)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[mi][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  // Fragment offsets within a stage: row m = 16 MW wave + 16 mi + mn of the
+  // batch part, row n = 16 t + mn of the weight part, slot kq swizzled by
+  // row bits 1..2 (those of mn).  The per-lane parts are hidden from the
+  // optimiser: a read at an offset it cannot bound may alias its own
+  // stage's copy (whose wait the explicit vmcnt already covers) and nothing
+  // else; a read it proves disjoint from every copy gets a wait for all of
+  // them.
+  int xoff = NR * RB + (wave * MW * 16 + mn) * RB + ((kq ^ ((mn >> 1) & 3)) * 16);
+  int woff = mn * RB + ((kq ^ ((mn >> 1) & 3)) * 16);
+  asm("" : "+v"(xoff));
+  asm("" : "+v"(woff));
+  auto compute = [&](auto sc) {
+    const char* st = stage_ptr(sc);
+    uint4 a[MW], bq[NT];
+#pragma unroll
+    for (int mi = 0; mi < MW; ++mi)
+      a[mi] = *reinterpret_cast<const uint4*>(st + xoff + mi * 16 * RB);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) bq[t] = *reinterpret_cast<const uint4*>(st + woff + t * 16 * RB);
+#pragma unroll
+    for (int mi = 0; mi < MW; ++mi)
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        acc[mi][t] = mfma_bf16(a[mi], bq[t], acc[mi][t]);
+  };
+
+  // Stage of chunk ch is ch % S; the loop is unrolled by S so that every
+  // stage offset is a constant.  Before the barrier of chunk ch each wave
+  // waits for its own copies of chunk ch (later chunks stay in flight) and
+  // for its LDS reads of chunk ch - 1, whose stage the copy issued after the
+  // barrier overwrites.
+  // The main loop runs whole groups of S chunks without a branch inside: at
+  // a control-flow join the compiler's own wait analysis forgets which stage
+  // a copy in flight targets and drains them all.
+  auto step = [&](int ch0, auto sc) {
+    constexpr int s = decltype(sc)::value;
+    wait_copies_barrier<(S - 2) * Q>();
+    issue(ch0 + s + S - 1, std::integral_constant<int, (s + S - 1) % S>{});
+    compute(sc);
+  };
+  issue(0, std::integral_constant<int, 0>{});
+  if constexpr (S == 3) issue(1, std::integral_constant<int, 1>{});
+  int ch0 = 0;
+  for (; ch0 + S <= nch; ch0 += S) {
+    step(ch0, std::integral_constant<int, 0>{});
+    step(ch0, std::integral_constant<int, 1>{});
+    if constexpr (S == 3) step(ch0, std::integral_constant<int, 2>{});
+  }
+  if (ch0 < nch) step(ch0, std::integral_constant<int, 0>{});  // uniform branches
+  if constexpr (S == 3)
+    if (ch0 + 1 < nch) step(ch0, std::integral_constant<int, 1>{});
+  // every copy has landed and every wave is done with the stages before the
+  // epilogue reuses the LDS
+  wait_copies_barrier<0>();
+  if (tcopy) {
+#pragma unroll
+    for (int q = 0; q < TQ; ++q) reinterpret_cast<float4*>(st1)[tid + 256 * q] = tv[q];
+  }
+  lp_epilogue<NT, MW, 1, true>(reinterpret_cast<float*>(st0), acc, 1.0f, j, wt, genome,
+                               tcopy ? reinterpret_cast<const float*>(st1) : genome,
+                               tcopy ? toff : 0, nd, y, b, partial, lo, n_pt, pass_rows, tail_vec,
+                               b1v, ylab);
+}
+
+// ------------------------------------------------------------- dispatch --
+
+namespace {
+
+struct LpwShape {
+  int mw, pass_rows;
+  size_t lds;
+  EvalLds lo;
+};
+
+constexpr size_t kLdsMaxW = 160 * 1024;
+
+// Tail passes of 64 rows in stage 0 (no dynamic LDS).
+bool lpw_shape(const NetDesc& nd, int b, LpwShape* out) {
+  const int nt = (nd.w[1] + 15) / 16;
+  if (nt < 1 || nt > 16 || nd.w[0] % 4 != 0 || b <= 16) return false;
+  int mw = b > 64 ? 2 : 1;
+  while (mw > 1 && mw * nt > 32) mw >>= 1;
+  const EvalLds lo = lp_tail_layout(nd, 64);
+  if ((size_t)lo.total * 4 > (size_t)lpw_tail_cap(nt)) return false;
+  for (; mw >= 1; mw >>= 1) {
+    if ((size_t)lpw_lds_bytes(nt, mw) <= kLdsMaxW) {
+      out->mw = mw;
+      out->pass_rows = 64;
+      out->lds = 0;
+      out->lo = lo;
+      return true;
+    }
+  }
+  return false;
+}
+
+template <int NT, int MW>
+hipError_t launch_lpw3(const float* genomes, const NetDesc& nd, int pop, const W1Shadow& wsh,
+                       const uint16_t* xq, int kp, int bpad, const int32_t* y, int b,
+                       float2* partial, const LpwShape& sh, int tv, hipStream_t s) {
+  auto kern = eval_lpw_kernel<NT, MW>;
+  const int n_wt = (b + 64 * MW - 1) / (64 * MW);
+  const int n_pt = (b + sh.pass_rows - 1) / sh.pass_rows;
+  hipLaunchKernelGGL(kern, dim3((unsigned)(n_wt * pop)), dim3(256), sh.lds, s, genomes, nd, wsh,
+                     xq, kp >> 5, bpad, y, b, partial, sh.lo, n_wt, n_pt, sh.pass_rows, pop, tv);
+  return hipGetLastError();
+}
+
+template <int NT>
+hipError_t launch_lpw_nt(const float* genomes, const NetDesc& nd, int pop, const W1Shadow& wsh,
+                         const uint16_t* xq, int kp, int bpad, const int32_t* y, int b,
+                         float2* partial, hipStream_t s) {
+  LpwShape sh;
+  if (!lpw_shape(nd, b, &sh)) return hipErrorInvalidValue;
+  int tv = 1;
+  for (int l = 1; l < nd.L; ++l)
+    if (nd.w[l] % 4 != 0) tv = 0;
+  if (sh.mw == 2)
+    return launch_lpw3<NT, 2>(genomes, nd, pop, wsh, xq, kp, bpad, y, b, partial, sh, tv, s);
+  return launch_lpw3<NT, 1>(genomes, nd, pop, wsh, xq, kp, bpad, y, b, partial, sh, tv, s);
+}
+
+}  // namespace
+
+bool eval_lpw_supported(const NetDesc& nd, int b) {
+  LpwShape sh;
+  return lpw_shape(nd, b, &sh);
+}
+
+int eval_lpw_ptiles(const NetDesc& nd, int b) {
+  LpwShape sh;
+  if (!lpw_shape(nd, b, &sh)) return 1;
+  return (b + sh.pass_rows - 1) / sh.pass_rows;
+}
+
+hipError_t launch_evaluate_lpw(const float* genomes, const NetDesc& nd, int pop,
+                               const W1Shadow& wsh, const uint16_t* xq, int kp, int bpad,
+                               const int32_t* y, int b, float2* partial, hipStream_t s) {
+  if (!wsh.p || bpad % 128 != 0 || bpad < b) return hipErrorInvalidValue;
+  switch ((nd.w[1] + 15) / 16) {
+#define LEEA_LPW_CASE(N) \
+  case N:                \
+    return launch_lpw_nt<N>(genomes, nd, pop, wsh, xq, kp, bpad, y, b, partial, s);
+    LEEA_LPW_CASE(1) LEEA_LPW_CASE(2) LEEA_LPW_CASE(3) LEEA_LPW_CASE(4) LEEA_LPW_CASE(5)
+    LEEA_LPW_CASE(6) LEEA_LPW_CASE(7) LEEA_LPW_CASE(8) LEEA_LPW_CASE(9) LEEA_LPW_CASE(10)
+    LEEA_LPW_CASE(11) LEEA_LPW_CASE(12) LEEA_LPW_CASE(13) LEEA_LPW_CASE(14) LEEA_LPW_CASE(15)
+    LEEA_LPW_CASE(16)
+#undef LEEA_LPW_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace leea

@@ -70,7 +70,10 @@ hipError_t launch_init(float* genomes, const NetDesc& nd, const Glorot& ga, int 
 // The random draws of slot j come from slot j + slot_off of the streams.
 // kNorm: also write, per wave, the sum of squared differences between the
 // child and parent 1 over the wave's genes to nu[j * ngroups + G].
-template <int kXoKind, bool kAmax, bool kNorm = false>
+// kShadow: also write the child's W_1 rounded to bfloat16 into its W1Shadow
+// slot (n0 % 4 == 0: a float4 of W_1 is 4 consecutive k of one row and one
+// 32-wide chunk, one 8-byte store).
+template <int kXoKind, bool kAmax, bool kNorm = false, bool kShadow = false>
 __device__ __forceinline__ void vary_body(int j, int gx, const float* __restrict__ cur,
                                           float* __restrict__ nxt, const int4* __restrict__ plan,
                                           int64_t stride, int64_t genes, float sigma,
@@ -79,7 +82,7 @@ __device__ __forceinline__ void vary_body(int j, int gx, const float* __restrict
                                           float* __restrict__ sig_next, float tau,
                                           uint32_t* __restrict__ amax, int64_t w1n,
                                           uint32_t slot_off = 0, float* __restrict__ nu = nullptr,
-                                          int ngroups = 0) {
+                                          int ngroups = 0, W1Shadow wsh = W1Shadow{}) {
 #pragma clang fp contract(off)
   const uint32_t pslot = (uint32_t)j + slot_off;
   const int wave = threadIdx.x >> 6;
@@ -108,7 +111,24 @@ __device__ __forceinline__ void vary_body(int j, int gx, const float* __restrict
       sq += dw * dw;
     }
   };
+  uint16_t* __restrict__ sh = kShadow ? wsh.p + (int64_t)j * wsh.net : nullptr;
   auto track = [&](int64_t f, const float4& o) {
+    if (kShadow && f < w1f) {
+      const int g = (int)(4 * f);
+      int n = (int)((float)g * wsh.rcp_n0);  // g < 2^24: off by at most one
+      int k = g - n * wsh.n0;
+      if (k < 0) {
+        n -= 1;
+        k += wsh.n0;
+      } else if (k >= wsh.n0) {
+        n += 1;
+        k -= wsh.n0;
+      }
+      uint2 v;
+      v.x = pack_bf16x2(o.x, o.y);
+      v.y = pack_bf16x2(o.z, o.w);
+      *reinterpret_cast<uint2*>(sh + ((int64_t)(k >> 5) * wsh.nrp + n) * 32 + (k & 31)) = v;
+    }
     if (kAmax && f < w1f) {
       uint32_t a = mag_bits(o.x), b = mag_bits(o.y), c = mag_bits(o.z), d = mag_bits(o.w);
       a = a > b ? a : b;
@@ -202,7 +222,7 @@ __device__ __forceinline__ void vary_body(int j, int gx, const float* __restrict
   }
 }
 
-template <int kXoKind, bool kAmax>
+template <int kXoKind, bool kAmax, bool kShadow>
 __global__ __launch_bounds__(256) void vary_kernel(const float* __restrict__ cur,
                                                    float* __restrict__ nxt,
                                                    const int4* __restrict__ plan,
@@ -210,10 +230,12 @@ __global__ __launch_bounds__(256) void vary_kernel(const float* __restrict__ cur
                                                    uint64_t thr, Key key, uint32_t gen, int pop,
                                                    uint32_t mul, const float* __restrict__ sig_cur,
                                                    float* __restrict__ sig_next, float tau,
-                                                   uint32_t* __restrict__ amax, int64_t w1n) {
+                                                   uint32_t* __restrict__ amax, int64_t w1n,
+                                                   W1Shadow wsh) {
   const int j = (int)(((uint64_t)blockIdx.y * mul) % (uint32_t)pop);
-  vary_body<kXoKind, kAmax>(j, blockIdx.x, cur, nxt, plan, stride, genes, sigma, thr, key, gen,
-                            sig_cur, sig_next, tau, amax, w1n);
+  vary_body<kXoKind, kAmax, false, kShadow>(j, blockIdx.x, cur, nxt, plan, stride, genes, sigma,
+                                            thr, key, gen, sig_cur, sig_next, tau, amax, w1n, 0,
+                                            nullptr, 0, wsh);
 }
 
 // Candidate children of the fitness surrogate: plan index j, random draws
@@ -252,25 +274,30 @@ uint32_t slot_multiplier(int pop) {
 hipError_t launch_vary(const float* cur, float* nxt, const int4* plan, const NetDesc& nd,
                        int pop, int crossover, float sigma, uint64_t mut_threshold,
                        const Key& key, uint32_t gen, const float* sig_cur, float* sig_next,
-                       float tau, uint32_t* amax, hipStream_t s) {
+                       float tau, uint32_t* amax, const W1Shadow& wsh, hipStream_t s) {
   const int64_t groups = (nd.stride + 8191) / 8192;
   dim3 grid((unsigned)((groups + 3) / 4), (unsigned)pop);
   const uint32_t mul = slot_multiplier(pop);
   const int64_t w1n = (int64_t)nd.w[0] * nd.w[1];
-#define LEEA_VARY(XO, AM)                                                                   \
-  hipLaunchKernelGGL((vary_kernel<XO, AM>), grid, dim3(256), 0, s, cur, nxt, plan, nd.stride, \
-                     nd.genes, sigma, mut_threshold, key, gen, pop, mul, sig_cur, sig_next, tau, \
-                     amax, w1n)
+#define LEEA_VARY(XO, AM, SH)                                                                 \
+  hipLaunchKernelGGL((vary_kernel<XO, AM, SH>), grid, dim3(256), 0, s, cur, nxt, plan,         \
+                     nd.stride, nd.genes, sigma, mut_threshold, key, gen, pop, mul, sig_cur,     \
+                     sig_next, tau, amax, w1n, wsh)
+  const int kind = amax ? 1 : (wsh.p ? 2 : 0);
   if (crossover == 0) {
-    if (amax)
-      LEEA_VARY(0, true);
+    if (kind == 1)
+      LEEA_VARY(0, true, false);
+    else if (kind == 2)
+      LEEA_VARY(0, false, true);
     else
-      LEEA_VARY(0, false);
+      LEEA_VARY(0, false, false);
   } else {
-    if (amax)
-      LEEA_VARY(1, true);
+    if (kind == 1)
+      LEEA_VARY(1, true, false);
+    else if (kind == 2)
+      LEEA_VARY(1, false, true);
     else
-      LEEA_VARY(1, false);
+      LEEA_VARY(1, false, false);
   }
 #undef LEEA_VARY
   return hipGetLastError();

@@ -38,13 +38,24 @@ struct EvalShape {
 bool eval_shape_f32(const NetDesc& nd, int b, int kind, int mw, EvalShape* out);
 bool eval_shape_lp(const NetDesc& nd, int b, int dt, int kind, int mw, EvalShape* out);
 
+// bfloat16 copy of every network's W_1 read by the large-batch bfloat16
+// kernel, chunk-major: element (n, k) of network j is
+// p[j * net + ((k >> 5) * nrp + n) * 32 + (k & 31)], with the rows padded to
+// nrp = n1 rounded up to 16 and K to 32 (padding zero).  p == nullptr: none.
+struct W1Shadow {
+  uint16_t* p;
+  int64_t net;  // elements per network = (kp / 32) * nrp * 32
+  int n0, nrp;
+  float rcp_n0;  // 1 / n0 (row of a W_1 gene index below 2^24: one fix-up step)
+};
+
 // init.hip / vary.hip / batch.hip
 hipError_t launch_init(float* genomes, const NetDesc& nd, const Glorot& ga, int pop,
                        const Key& key, hipStream_t s);
 hipError_t launch_vary(const float* cur, float* nxt, const int4* plan, const NetDesc& nd,
                        int pop, int crossover, float sigma, uint64_t mut_threshold,
                        const Key& key, uint32_t gen, const float* sig_cur, float* sig_next,
-                       float tau, uint32_t* amax, hipStream_t s);
+                       float tau, uint32_t* amax, const W1Shadow& wsh, hipStream_t s);
 hipError_t launch_draw_batch(const float* x_train, const int32_t* y_train, int64_t n_train,
                              int n_in, int side, int b, float* x_out, int32_t* y_out,
                              const Key& key, uint32_t gen, hipStream_t s);
@@ -90,6 +101,19 @@ hipError_t launch_amax_w1(const float* genomes, const NetDesc& nd, int pop, uint
                           hipStream_t s);
 hipError_t launch_quantize_x(int dt, bool packed, const float* x, int b, int n0, int kp,
                              const uint32_t* x_amax, void* out, hipStream_t s);
+// The large-batch bfloat16 kernel on the W_1 copy: availability, partial row
+// tiles, the batch quantised chunk-major (xq[((k >> 5) * bpad + m) * 32 +
+// (k & 31)], rows b .. bpad - 1 zero, bpad = b rounded up to 128), the copy
+// rebuilt from the genomes, and the launch.
+bool eval_lpw_supported(const NetDesc& nd, int b);
+int eval_lpw_ptiles(const NetDesc& nd, int b);
+hipError_t launch_quantize_x_chunks(const float* x, int b, int n0, int kp, int bpad,
+                                    uint16_t* xq, hipStream_t s);
+hipError_t launch_shadow_w1(const float* genomes, const NetDesc& nd, int pop,
+                            const W1Shadow& wsh, hipStream_t s);
+hipError_t launch_evaluate_lpw(const float* genomes, const NetDesc& nd, int pop,
+                               const W1Shadow& wsh, const uint16_t* xq, int kp, int bpad,
+                               const int32_t* y, int b, float2* partial, hipStream_t s);
 
 // genetic.hip / surrogate.hip: the fitness surrogate
 hipError_t launch_vary_cand(const float* cur, float* cand, const int4* plan, const NetDesc& nd,

@@ -141,6 +141,73 @@ hipError_t launch_quantize_x(int dt, bool packed, const float* x, int b, int n0,
   return hipGetLastError();
 }
 
+// Batch in bfloat16, chunk-major for the large-batch kernel that reads W_1
+// from its bfloat16 copy: slot it (8 elements) = chunk it / (4 bpad), row
+// (it / 4) mod bpad, elements 8 (it mod 4) .. + 7 of the chunk; rows at or
+// past b and k at or past n0 are zero.
+__global__ __launch_bounds__(256) void quantize_chunks_kernel(const float* __restrict__ x, int b,
+                                                              int n0, int bpad, int64_t items,
+                                                              uint4* __restrict__ out) {
+  for (int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x; it < items;
+       it += (int64_t)gridDim.x * 256) {
+    const int64_t rs = it >> 2;
+    const int ch = (int)(rs / bpad);
+    const int m = (int)(rs - (int64_t)ch * bpad);
+    const int k = ch * 32 + 8 * (int)(it & 3);
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = (m < b && k + e < n0) ? x[(int64_t)m * n0 + k + e] : 0.0f;
+    uint4 o;
+    o.x = pack_bf16x2(v[0], v[1]);
+    o.y = pack_bf16x2(v[2], v[3]);
+    o.z = pack_bf16x2(v[4], v[5]);
+    o.w = pack_bf16x2(v[6], v[7]);
+    out[it] = o;
+  }
+}
+
+hipError_t launch_quantize_x_chunks(const float* x, int b, int n0, int kp, int bpad,
+                                    uint16_t* xq, hipStream_t s) {
+  const int64_t items = (int64_t)(kp >> 5) * bpad * 4;
+  hipLaunchKernelGGL(quantize_chunks_kernel, dim3(grid_for(items)), dim3(256), 0, s, x, b, n0,
+                     bpad, items, reinterpret_cast<uint4*>(xq));
+  return hipGetLastError();
+}
+
+// The bfloat16 W_1 copy rebuilt from the genomes (after initialisation or a
+// population replaced from outside): slot it of network blockIdx.y = chunk
+// it / (4 nrp), row (it / 4) mod nrp, elements 8 (it mod 4) .. + 7.
+__global__ __launch_bounds__(256) void shadow_w1_kernel(const float* __restrict__ genomes,
+                                                        NetDesc nd, W1Shadow wsh,
+                                                        int64_t items) {
+  const int j = blockIdx.y;
+  const int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (it >= items) return;
+  const float* __restrict__ W1 = genomes + (int64_t)j * nd.stride + nd.woff[0];
+  const int n0 = nd.w[0], n1 = nd.w[1];
+  const int64_t rs = it >> 2;
+  const int ch = (int)(rs / wsh.nrp);
+  const int n = (int)(rs - (int64_t)ch * wsh.nrp);
+  const int k = ch * 32 + 8 * (int)(it & 3);
+  float v[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) v[e] = (n < n1 && k + e < n0) ? W1[(int64_t)n * n0 + k + e] : 0.0f;
+  uint4 o;
+  o.x = pack_bf16x2(v[0], v[1]);
+  o.y = pack_bf16x2(v[2], v[3]);
+  o.z = pack_bf16x2(v[4], v[5]);
+  o.w = pack_bf16x2(v[6], v[7]);
+  reinterpret_cast<uint4*>(wsh.p + (int64_t)j * wsh.net)[it] = o;
+}
+
+hipError_t launch_shadow_w1(const float* genomes, const NetDesc& nd, int pop,
+                            const W1Shadow& wsh, hipStream_t s) {
+  const int64_t items = wsh.net / 8;
+  dim3 grid((unsigned)((items + 255) / 256), (unsigned)pop);
+  hipLaunchKernelGGL(shadow_w1_kernel, grid, dim3(256), 0, s, genomes, nd, wsh, items);
+  return hipGetLastError();
+}
+
 // Quantised batch of every bfloat16 run: values [b][n0] for the small-batch
 // kernel (b <= 16), packed [b][kp] otherwise; 256 items per workgroup.
 __global__ __launch_bounds__(256) void runs_quantize_kernel(const RunDesc* __restrict__ runs,

@@ -117,12 +117,15 @@ def test_runs_workspace_and_validation(lib):
             for h, p, b in ((16, 32, 8), (256, 2048, 256), (112, 500, 64))]
     arr = (B.Config * 3)(*good)
     assert lib.leea_runs_workspace_bytes(arr, 3, ctypes.byref(n)) == 0
-    singles = 0
+    genomes = 0     # every run keeps two generations of genomes in the group's workspace
     for c in good:
         m = ctypes.c_size_t()
         assert lib.leea_workspace_bytes(ctypes.byref(c), ctypes.byref(m)) == 0
-        singles += m.value
-    assert n.value >= 0.9 * singles
+        genes, stride = ctypes.c_int64(), ctypes.c_int64()
+        assert lib.leea_param_count(ctypes.byref(c), ctypes.byref(genes), ctypes.byref(stride)) == 0
+        genomes += 2 * c.pop * stride.value * 4
+        assert m.value >= 2 * c.pop * stride.value * 4
+    assert n.value >= genomes
     for bad in (paper_cfg(eval_dtype="fp8"), paper_cfg(sigma_mode="decay", sigma_decay_k=5.0),
                 paper_cfg(widths=(783, 10))):
         arr2 = (B.Config * 2)(good[0], bad)

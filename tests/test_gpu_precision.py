@@ -151,6 +151,68 @@ def test_fp8_scales_from_the_variation_kernel(b):
         check(to_np(f_raw), to_np(acc), f_ref, acc_ref, amb, b, "fp8 gen %d" % g)
 
 
+def test_bf16_copy_written_by_the_variation_kernel():
+    """bfloat16 generations at batches that alternate between the
+    small-batch kernel and the large-batch kernel reading the bfloat16 copy
+    of W_1 that the variation kernel writes with each child; a checkpoint
+    load and a replaced population in between (the copy is rebuilt from
+    the genomes).  Teacher-forced with the device's adjusted fitness; every
+    child bit-exact, every fitness within the float32 tolerance."""
+    x, y = datagen.prototype_data(2000, seed=0)
+    params = dict(PAPER, pop=20, eval_dtype="bf16", p_gene=0.5, sigma=0.02)
+    widths = params["widths"]
+    run, ocfg = make_run(params, max_batch=300)
+    xd, yd = to_dev(x), to_dev(y)
+    pop_o = O.init_population(ocfg)
+    batches = [64, 8, 300, 17, 130, 64]
+    xb, yb = run.draw_batch(0, xd, yd, batches[0])
+    f_adj, _, _ = run.evaluate(xb, yb)
+    for g in range(1, len(batches)):
+        b = batches[g]
+        say("bf16 generation", g, "b", b)
+        if g == 3:                                     # checkpoint round trip
+            ck = run.save()
+            run.load(ck)
+        f_prev = to_np(f_adj).copy()
+        xb, yb = run.draw_batch(g, xd, yd, b)
+        run.select()
+        run.crossover_mutate()
+        f_adj, f_raw, acc = run.evaluate(xb, yb)
+        ops, p1, p2, _ = O.plan(O.rank(f_prev), f_prev, ocfg, g)
+        pop_o = O.vary(pop_o, ops, p1, p2, ocfg, g)
+        assert np.array_equal(genomes_np(run).view(np.uint32), pop_o.view(np.uint32)), g
+        idx = O.batch_indices(ocfg.seed, g, b, x.shape[0], ocfg.run)
+        f_ref, acc_ref, amb = lowp_oracle(pop_o, widths, x[idx], y[idx], "bf16")
+        check(to_np(f_raw), to_np(acc), f_ref, acc_ref, amb, b, "bf16 gen %d" % g)
+    # a population replaced from outside, then scored at a large batch
+    pop = special_population(run, widths, 13)
+    xv, yv = x[:257], y[:257]
+    f_raw, acc = run.score(to_dev(xv), to_dev(yv))
+    f_ref, acc_ref, amb = lowp_oracle(pop, widths, xv, yv, "bf16")
+    check(to_np(f_raw), to_np(acc), f_ref, acc_ref, amb, 257, "bf16 replaced")
+
+
+def test_bf16_copy_after_surrogate_step():
+    """The surrogate's new population comes from its candidate buffer, not
+    from the variation kernel: the bfloat16 copy is rebuilt before it is
+    evaluated at b = 64."""
+    x, y = datagen.prototype_data(2000, seed=0)
+    params = dict(PAPER, widths=(96, 24, 5), pop=30, eval_dtype="bf16", seed=4)
+    widths = params["widths"]
+    run, _ = make_run(params, max_batch=64)
+    run.attach_surrogate(oversample=3, steps=2, lr=0.05, warmup=0, tau_min=-1.0)
+    xs = datagen.uniform_inputs((2000, 96), 4)
+    ys = datagen.labels(2000, 5, 5)
+    xd, yd = to_dev(xs), to_dev(ys)
+    xb, yb = run.draw_batch(0, xd, yd, 64)
+    run.evaluate(xb, yb)
+    for g in range(1, 4):
+        xb, yb = run.draw_batch(g, xd, yd, 64)
+        _, f_raw, acc, _ = run.surrogate_step(xb, yb)
+        f_ref, acc_ref, amb = lowp_oracle(genomes_np(run), widths, to_np(xb), to_np(yb), "bf16")
+        check(to_np(f_raw), to_np(acc), f_ref, acc_ref, amb, 64, "surrogate bf16 gen %d" % g)
+
+
 def test_fp8_scales_after_restore():
     widths = (784, 112, 32, 10)
     params = dict(PAPER, pop=10, eval_dtype="fp8")
