@@ -188,11 +188,11 @@ int padded_k(int n0) { return (n0 + 31) & ~31; }
 int round128(int v) { return (v + 127) & ~127; }
 
 // bfloat16 W_1 copy: kept when batches above 16 rows can reach the
-// large-batch bfloat16 kernel that reads it (n0 % 4 == 0, hidden width <= 256,
-// W_1 below 2^24 genes)
+// large-batch bfloat16 kernel that reads it (W_1 below 2^24 genes, and the
+// shapes that kernel takes)
 bool uses_shadow(const leea_config* cfg, const NetDesc& nd) {
-  return cfg->eval_dtype == LEEA_DT_BF16 && cfg->max_batch > 16 && nd.w[0] % 4 == 0 &&
-         nd.w[1] <= 256 && (int64_t)nd.w[0] * nd.w[1] < (1 << 24);
+  return cfg->eval_dtype == LEEA_DT_BF16 && cfg->max_batch > 16 &&
+         (int64_t)nd.w[0] * nd.w[1] < (1 << 24) && eval_lpw_supported(nd, cfg->max_batch);
 }
 int64_t shadow_net(const NetDesc& nd) {
   return (int64_t)(padded_k(nd.w[0]) / 32) * ((nd.w[1] + 15) & ~15) * 32;

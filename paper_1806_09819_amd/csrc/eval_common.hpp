@@ -28,6 +28,22 @@ __device__ __forceinline__ void mfma_superstep(const float4& a, const float4 (&b
   for (int t = 0; t < NT; ++t) acc[t] = mfma(a.w, b[t].w, acc[t]);
 }
 
+// The same super-step with the operands swapped: acc[t] accumulates
+// W X^T (neuron 16 t + 4 kq + i of row mn in lane mn + 16 kq), the layout
+// the register tail reads.
+template <int NT>
+__device__ __forceinline__ void mfma_superstep_t(const float4& a, const float4 (&b)[NT],
+                                                 floatx4 (&acc)[NT]) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = mfma(b[t].x, a.x, acc[t]);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = mfma(b[t].y, a.y, acc[t]);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = mfma(b[t].z, a.z, acc[t]);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = mfma(b[t].w, a.w, acc[t]);
+}
+
 __device__ __forceinline__ float relu_keep_nan(float v) { return v < 0.0f ? 0.0f : v; }
 
 __device__ __forceinline__ float4 zero4() { return make_float4(0.f, 0.f, 0.f, 0.f); }
@@ -64,11 +80,19 @@ static __device__ void mfma_layer(const float* in, int ldi, int n_in, float* out
     const int n = nt * 16 + mn;
     const bool nv = n < n_out;
     const float* wr = W + (int64_t)(nv ? n : 0) * n_in;
+    // weight fragments: every lane loads from a valid address (row 0 for
+    // columns past n_out, column 0 past n_in) and masks the value, so the
+    // loads need no per-lane branch; s < kss is uniform across the wave
     float4 bf[16];
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-      const int k = 16 * s + 4 * kq;
-      bf[s] = (s < kss && nv && k < n_in) ? *reinterpret_cast<const float4*>(wr + k) : zero4();
+      bf[s] = zero4();
+      if (s < kss) {
+        const int k = 16 * s + 4 * kq;
+        const bool kv = k < n_in;
+        const float4 v = *reinterpret_cast<const float4*>(wr + (kv ? k : 0));
+        if (nv && kv) bf[s] = v;
+      }
     }
     const float bb = nv ? bias[n] : 0.0f;
     for (int mt = mt0; mt < mtiles; mt += G * mstep) {
@@ -129,12 +153,19 @@ static __device__ void mfma_layer_fit(const float* in, int ldi, int n_in, float*
     mt0 = wave / ntiles;
   }
   const int r = mt0 < mtiles ? (mtiles - mt0 + mstep - 1) / mstep : 0;
-  if (GMAX >= 4 && r >= 3)
-    mfma_layer<(GMAX >= 4 ? 4 : 1)>(in, ldi, n_in, out, ldo, n_out, W, bias, relu, mtiles);
-  else if (GMAX >= 2 && r == 2)
-    mfma_layer<(GMAX >= 2 ? 2 : 1)>(in, ldi, n_in, out, ldo, n_out, W, bias, relu, mtiles);
-  else
-    mfma_layer<1>(in, ldi, n_in, out, ldo, n_out, W, bias, relu, mtiles);
+  if constexpr (GMAX >= 4) {
+    if (r >= 3) {
+      mfma_layer<4>(in, ldi, n_in, out, ldo, n_out, W, bias, relu, mtiles);
+      return;
+    }
+  }
+  if constexpr (GMAX >= 2) {
+    if (r == 2) {
+      mfma_layer<2>(in, ldi, n_in, out, ldo, n_out, W, bias, relu, mtiles);
+      return;
+    }
+  }
+  mfma_layer<1>(in, ldi, n_in, out, ldo, n_out, W, bias, relu, mtiles);
 }
 
 // The same layer on VALU, for hidden widths that are not multiples of 4.

@@ -33,6 +33,7 @@
 
 #include "eval_common.hpp"
 #include "lowp.hpp"
+#include "lp_common.hpp"
 #include "runs.hpp"
 
 namespace leea {
@@ -148,13 +149,16 @@ __global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void eval_small_kernel(const f
 }
 
 // ---------------------------------------------------------------- large b --
-// Body of one workgroup: network j, row tile mt (rows 64*MW*mt ...).
-template <int NT, int MW>
+// Body of one workgroup: network j, row tile mt (rows 64*MW*mt ...).  RT:
+// the tail from registers (networks reg_tail_ok() takes), else from an LDS
+// activation tile; separate kernels, so that neither carries the other's
+// registers.
+template <int NT, int MW, bool RT>
 __device__ __forceinline__ void eval_large_body(int j, int mt, const float* __restrict__ genomes,
                                                 const NetDesc& nd, const float* __restrict__ x,
                                                 const int32_t* __restrict__ y, int b,
                                                 float2* __restrict__ partial, const EvalLds& lo,
-                                                int n_mt, int tail_vec) {
+                                                int n_pt, int tail_vec) {
   extern __shared__ float lds[];
   constexpr int MT = 64 * MW;              // rows per workgroup
   constexpr int NR = NT * 16;              // staged weight rows
@@ -248,36 +252,31 @@ __device__ __forceinline__ void eval_large_body(int j, int mt, const float* __re
         for (int t = 0; t < NT; ++t)
           wb[t] = *reinterpret_cast<const float4*>(wst + (c * NR + ((t * 16 + mn) ^ (2 * c))) * 4);
 #pragma unroll
-        for (int mi = 0; mi < MW; ++mi) mfma_superstep<NT>(xa[mi], wb, acc[mi]);
+        for (int mi = 0; mi < MW; ++mi) mfma_superstep_t<NT>(xa[mi], wb, acc[mi]);
       }
     }
     if (ch + 1 < nch) sstore(buf ^ 1);
     __syncthreads();
   }
 
-  // epilogue: bias + ReLU into the LDS layer-1 tile (staging is dead now);
-  // columns n1 .. NT*16-1 are written as zeros for the next layer's K loop
-  const float* __restrict__ b1 = genome + nd.boff[0];
-  const bool hidden = nd.L > 1;
-  float* h1 = lds + lo.h1;
+  // epilogue (staging is dead now): the tail from registers when the
+  // network allows it (tail genes copied to LDS first), else 64-row passes
+  // over an LDS activation tile; one partial per 64 rows either way
+  if constexpr (RT) {
+    copy_tail_genes(genome, nd, lds);
+    int ylab[MW];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int n = t * 16 + mn;
-    const bool nv = n < n1;
-    const float bb = nv ? b1[n] : 0.0f;
-#pragma unroll
-    for (int mi = 0; mi < MW; ++mi)
-#pragma unroll
-      for (int i2 = 0; i2 < 4; ++i2) {
-        const int m = wave * MW * 16 + mi * 16 + 4 * kq + i2;
-        float v = acc[mi][t][i2] + bb;
-        if (hidden) v = relu_keep_nan(v);
-        h1[m * lo.ld1 + n] = nv ? v : 0.0f;
-      }
+    for (int mi = 0; mi < MW; ++mi) {
+      const int r = m0 + wave * MW * 16 + mi * 16 + mn;
+      ylab[mi] = r < b ? y[r] : 0;
+    }
+    float* red = lds + ((reg_tail_genes(nd) + 3) & ~3);
+    __syncthreads();
+    reg_tail<NT, MW>(acc, 1.0f, lds, nd, m0, wave * MW * 16, b, ylab, red,
+                     partial + (int64_t)j * n_pt, m0 / 64);
+  } else {
+    lds_epilogue<NT, MW>(lds, acc, 1.0f, j, mt, genome, nd, y, b, partial, lo, n_pt, tail_vec);
   }
-  __syncthreads();
-  tail_and_fitness<4>(lds, lo, nd, genome, 0, MT / 16, rows, m0, y, tail_vec != 0,
-                   partial + (int64_t)j * n_mt + mt);
 }
 
 // XCD-aware order (hardware workgroup i runs on XCD i % 8): each XCD gets a
@@ -291,16 +290,16 @@ __device__ __forceinline__ int xcd_order(int i, int total) {
   return xcd < r ? xcd * (q + 1) + kk : r * (q + 1) + (xcd - r) * q + kk;
 }
 
-template <int NT, int MW>
-__global__ __launch_bounds__(256) void eval_large_kernel(const float* __restrict__ genomes,
+template <int NT, int MW, bool RT>
+__global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_large_kernel(const float* __restrict__ genomes,
                                                          NetDesc nd, const float* __restrict__ x,
                                                          const int32_t* __restrict__ y, int b,
                                                          float2* __restrict__ partial,
-                                                         EvalLds lo, int n_mt, int pop,
+                                                         EvalLds lo, int n_wt, int n_pt, int pop,
                                                          int tail_vec) {
-  const int L = xcd_order(blockIdx.x, n_mt * pop);
-  const int j = L / n_mt;
-  eval_large_body<NT, MW>(j, L - j * n_mt, genomes, nd, x, y, b, partial, lo, n_mt, tail_vec);
+  const int L = xcd_order(blockIdx.x, n_wt * pop);
+  const int j = L / n_wt;
+  eval_large_body<NT, MW, RT>(j, L - j * n_wt, genomes, nd, x, y, b, partial, lo, n_pt, tail_vec);
 }
 
 // -------------------------------------------------------------- dispatch --
@@ -342,13 +341,11 @@ static size_t small_lds_bytes(const NetDesc& nd, EvalLds* out) {
   return (size_t)lo.total * 4;
 }
 
+static size_t large_lds_rt(const NetDesc& nd, int nt, int mw, EvalLds* out);
+
 template <int NT, int MW>
 static size_t large_lds_bytes(const NetDesc& nd, EvalLds* out) {
-  EvalLds lo = tail_layout(nd, 64 * MW);
-  const int staging = 2 * (8 * NT * 16 * 4 + 8 * 64 * MW * 4);
-  lo.total = lo.total > staging ? lo.total : staging;
-  if (out) *out = lo;
-  return (size_t)lo.total * 4;
+  return large_lds_rt(nd, NT, MW, out);
 }
 
 static constexpr size_t kMaxLds = 160 * 1024;
@@ -370,11 +367,11 @@ static hipError_t allow_lds(K kernel, size_t bytes) {
                              (int)bytes);
 }
 
+// Partial row sums per network: one (small batches) or one per 64 rows.
 template <int NT>
 static int mtiles_nt(const NetDesc& nd, int b) {
   if (use_small(b)) return 1;
-  const int mt = 64 * large_mw<NT>(nd, b);
-  return (b + mt - 1) / mt;
+  return (b + 63) / 64;
 }
 
 template <int NT, int DT>
@@ -391,6 +388,20 @@ static hipError_t launch_small(const float* genomes, const NetDesc& nd, int pop,
   return hipGetLastError();
 }
 
+template <int NT, int MW, bool RT>
+static hipError_t launch_large(const float* genomes, const NetDesc& nd, int pop, const float* x,
+                               const int32_t* y, int b, float2* partial, int n_pt, int tv,
+                               hipStream_t s) {
+  EvalLds lo;
+  const int n_wt = (b + 64 * MW - 1) / (64 * MW);
+  const size_t bytes = large_lds_bytes<NT, MW>(nd, &lo);
+  hipError_t e = allow_lds(eval_large_kernel<NT, MW, RT>, bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((eval_large_kernel<NT, MW, RT>), dim3((unsigned)(n_wt * pop)), dim3(256),
+                     bytes, s, genomes, nd, x, y, b, partial, lo, n_wt, n_pt, pop, tv);
+  return hipGetLastError();
+}
+
 template <int NT>
 static hipError_t launch_nt(const float* genomes, const NetDesc& nd, int pop, const float* x,
                             const int32_t* y, int b, float2* partial, hipStream_t s) {
@@ -398,21 +409,13 @@ static hipError_t launch_nt(const float* genomes, const NetDesc& nd, int pop, co
   EvalLds lo;
   if (use_small(b))
     return launch_small<NT, 0>(genomes, nd, pop, x, y, b, partial, nullptr, nullptr, s);
-  const int n_mt = mtiles_nt<NT>(nd, b);
-  if (large_mw<NT>(nd, b) == 2) {
-    const size_t bytes = large_lds_bytes<NT, 2>(nd, &lo);
-    hipError_t e = allow_lds(eval_large_kernel<NT, 2>, bytes);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((eval_large_kernel<NT, 2>), dim3((unsigned)(n_mt * pop)), dim3(256),
-                       bytes, s, genomes, nd, x, y, b, partial, lo, n_mt, pop, tv);
-  } else {
-    const size_t bytes = large_lds_bytes<NT, 1>(nd, &lo);
-    hipError_t e = allow_lds(eval_large_kernel<NT, 1>, bytes);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((eval_large_kernel<NT, 1>), dim3((unsigned)(n_mt * pop)), dim3(256),
-                       bytes, s, genomes, nd, x, y, b, partial, lo, n_mt, pop, tv);
-  }
-  return hipGetLastError();
+  const int n_pt = mtiles_nt<NT>(nd, b);
+  const bool rt = reg_tail_ok(nd);
+  if (large_mw<NT>(nd, b) == 2)
+    return rt ? launch_large<NT, 2, true>(genomes, nd, pop, x, y, b, partial, n_pt, tv, s)
+              : launch_large<NT, 2, false>(genomes, nd, pop, x, y, b, partial, n_pt, tv, s);
+  return rt ? launch_large<NT, 1, true>(genomes, nd, pop, x, y, b, partial, n_pt, tv, s)
+            : launch_large<NT, 1, false>(genomes, nd, pop, x, y, b, partial, n_pt, tv, s);
 }
 
 #define LEEA_NT_SWITCH(EXPR, DEFAULT)                                               \
@@ -438,6 +441,8 @@ static hipError_t launch_nt(const float* genomes, const NetDesc& nd, int pop, co
 
 int eval_mtiles(const NetDesc& nd, int b) { LEEA_NT_SWITCH((mtiles_nt<N>(nd, b)), 1) }
 
+bool large_reg_tail(const NetDesc& nd) { return reg_tail_ok(nd); }
+
 hipError_t launch_evaluate(const float* genomes, const NetDesc& nd, int pop, const float* x,
                            const int32_t* y, int b, float2* partial, hipStream_t s) {
   LEEA_NT_SWITCH((launch_nt<N>(genomes, nd, pop, x, y, b, partial, s)), hipErrorInvalidValue)
@@ -458,10 +463,16 @@ hipError_t launch_evaluate_small_lp(int dt, const float* genomes, const NetDesc&
 
 // ------------------------------------------------------------- shapes --
 
+// LDS of the large-batch kernel (floats): the staging double buffer, then
+// either the tail genes and the row-sum scratch of the register tail or the
+// 64-row activation tile of the LDS epilogue.
 static size_t large_lds_rt(const NetDesc& nd, int nt, int mw, EvalLds* out) {
-  EvalLds lo = tail_layout(nd, 64 * mw);
+  EvalLds lo = lp_tail_layout(nd, 64);
   const int staging = 2 * (8 * nt * 16 * 4 + 8 * 64 * mw * 4);
-  lo.total = lo.total > staging ? lo.total : staging;
+  const int rt = reg_tail_ok(nd) ? (int)((reg_tail_genes(nd) + 3) & ~3) + 8 * mw : 0;
+  int total = lo.total > staging ? lo.total : staging;
+  total = total > rt ? total : rt;
+  lo.total = total;
   if (out) *out = lo;
   return (size_t)lo.total * 4;
 }
@@ -487,8 +498,8 @@ bool eval_shape_f32(const NetDesc& nd, int b, int kind, int mw, EvalShape* out) 
     sh.kind = 1;
     sh.mw = mw;
     sh.n_wt = (b + 64 * mw - 1) / (64 * mw);
-    sh.n_pt = sh.n_wt;
-    sh.pass_rows = 64 * mw;
+    sh.n_pt = (b + 63) / 64;
+    sh.pass_rows = 64;
     sh.lds = large_lds_rt(nd, nt, mw, &sh.lo);
   } else {
     return false;
@@ -513,8 +524,8 @@ __global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void runs_eval_small_kernel(
                           d.lo, d.tail_vec, nullptr, nullptr);
 }
 
-template <int NT, int MW>
-__global__ __launch_bounds__(256) void runs_eval_large_kernel(const RunDesc* __restrict__ runs,
+template <int NT, int MW, bool RT>
+__global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void runs_eval_large_kernel(const RunDesc* __restrict__ runs,
                                                               const BatchState* __restrict__ st,
                                                               const int* __restrict__ off,
                                                               const int* __restrict__ ids, int n,
@@ -524,8 +535,8 @@ __global__ __launch_bounds__(256) void runs_eval_large_kernel(const RunDesc* __r
   const RunDesc& d = runs[ids[i]];
   const int local = L - off[i];
   const int j = local / d.n_wt;
-  eval_large_body<NT, MW>(j, local - j * d.n_wt, d.genomes[st->cur], d.nd, d.xb, d.yb, d.b,
-                          d.partial, d.lo, d.n_wt, d.tail_vec);
+  eval_large_body<NT, MW, RT>(j, local - j * d.n_wt, d.genomes[st->cur], d.nd, d.xb, d.yb, d.b,
+                              d.partial, d.lo, d.n_pt, d.tail_vec);
 }
 
 template <typename K>
@@ -535,8 +546,18 @@ static hipError_t allow_lds_any(K kernel, size_t bytes) {
                              (int)bytes);
 }
 
+template <int NT, int MW, bool RT>
+static hipError_t launch_runs_large(const RunDesc* runs, const BatchState* st, const Group& g,
+                                    hipStream_t s) {
+  hipError_t e = allow_lds_any(runs_eval_large_kernel<NT, MW, RT>, g.lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((runs_eval_large_kernel<NT, MW, RT>), dim3((unsigned)g.blocks), dim3(256),
+                     g.lds, s, runs, st, g.off, g.ids, g.n, g.blocks);
+  return hipGetLastError();
+}
+
 template <int NT>
-static hipError_t launch_runs_eval_nt(int kind, int mw, int dt, const RunDesc* runs,
+static hipError_t launch_runs_eval_nt(int kind, int mw, int dt, int rt, const RunDesc* runs,
                                       const BatchState* st, const Group& g, hipStream_t s) {
   hipError_t e;
   if (kind == 0) {
@@ -556,28 +577,21 @@ static hipError_t launch_runs_eval_nt(int kind, int mw, int dt, const RunDesc* r
     return hipGetLastError();
   }
   if (kind == 1) {
-    if (mw == 1) {
-      e = allow_lds_any(runs_eval_large_kernel<NT, 1>, g.lds);
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL((runs_eval_large_kernel<NT, 1>), dim3((unsigned)g.blocks), dim3(256),
-                         g.lds, s, runs, st, g.off, g.ids, g.n, g.blocks);
-    } else {
-      e = allow_lds_any(runs_eval_large_kernel<NT, 2>, g.lds);
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL((runs_eval_large_kernel<NT, 2>), dim3((unsigned)g.blocks), dim3(256),
-                         g.lds, s, runs, st, g.off, g.ids, g.n, g.blocks);
-    }
-    return hipGetLastError();
+    if (mw == 1)
+      return rt ? launch_runs_large<NT, 1, true>(runs, st, g, s)
+                : launch_runs_large<NT, 1, false>(runs, st, g, s);
+    return rt ? launch_runs_large<NT, 2, true>(runs, st, g, s)
+              : launch_runs_large<NT, 2, false>(runs, st, g, s);
   }
-  return launch_runs_eval_lp(NT, mw, dt, runs, st, g, s);
+  return launch_runs_eval_lp(NT, mw, dt, rt, runs, st, g, s);
 }
 
-hipError_t launch_runs_eval(int kind, int nt, int mw, int dt, const RunDesc* runs,
+hipError_t launch_runs_eval(int kind, int nt, int mw, int dt, int rt, const RunDesc* runs,
                             const BatchState* st, const Group& g, hipStream_t s) {
   switch (nt) {
 #define LEEA_RUNS_CASE(N) \
   case N:                 \
-    return launch_runs_eval_nt<N>(kind, mw, dt, runs, st, g, s);
+    return launch_runs_eval_nt<N>(kind, mw, dt, rt, runs, st, g, s);
     LEEA_RUNS_CASE(1) LEEA_RUNS_CASE(2) LEEA_RUNS_CASE(3) LEEA_RUNS_CASE(4) LEEA_RUNS_CASE(5)
     LEEA_RUNS_CASE(6) LEEA_RUNS_CASE(7) LEEA_RUNS_CASE(8) LEEA_RUNS_CASE(9) LEEA_RUNS_CASE(10)
     LEEA_RUNS_CASE(11) LEEA_RUNS_CASE(12) LEEA_RUNS_CASE(13) LEEA_RUNS_CASE(14)

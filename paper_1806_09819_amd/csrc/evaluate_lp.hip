@@ -4,7 +4,7 @@
 //
 // Same decomposition as the FP32 large-batch kernel (section 3.3: one
 // shared-input product X * [W1_1 .. W1_P]^T, then each network's tail and
-// fitness on its LDS tile), with these differences:
+// fitness), with these differences:
 // * v_mfma_f32_16x16x32_{bf16,fp8_fp8}: lane l supplies A[l%16][8(l/16)+e]
 //   and B[8(l/16)+e][l%16] for e = 0..7 (16 bytes of bf16, 8 bytes of fp8)
 //   and receives D[4(l/16)+i][l%16]; one instruction covers a 32-wide K
@@ -12,11 +12,10 @@
 // * W_1 is read as float32 from the genome and converted while it is
 //   staged (bfloat16, or E4M3 of w * 2^-e_w); the batch arrives already
 //   quantised and packed [b][kp] (kp = n0 rounded up to 32).
-// * A workgroup owns 64*MW rows (MW 1 or 2); the tail layers and the
-//   fitness run in passes over the LDS tile, each pass writing its own
-//   partial sums: 64 rows for bfloat16 (the grouping of the kernel that reads
-//   the bfloat16 W_1 copy, so both give bit-identical fitness), 64 MW up to
-//   128 for FP8.  (Four row tiles per wave measured slower:
+// * Layer 1 is computed transposed (W_1 X^T) for the register tail; a
+//   workgroup owns 64*MW rows (MW 1 or 2) and writes one partial sum per 64
+//   rows, like the other large-batch kernels, so every shape and kernel
+//   gives bit-identical fitness.  (Four row tiles per wave measured slower:
 //   their accumulators push the kernel to one wave per SIMD and into
 //   accumulator-register shuffling.)
 // * FP8 products are rescaled by 2^(e_x + e_w) (exact) before the bias.
@@ -77,14 +76,14 @@ struct Lp<2> {  // OCP FP8 E4M3
 };
 
 // Body of one workgroup: network j, row tile wt (rows 64*MW*wt ...).
-template <int NT, int MW, int DT, int D>
+template <int NT, int MW, int DT, int D, bool RT>
 __device__ __forceinline__ void eval_lp_body(int j, int wt, const float* __restrict__ genomes,
                                              const NetDesc& nd, const void* __restrict__ xq,
                                              int kp, const uint32_t* __restrict__ w_amax,
                                              const uint32_t* __restrict__ x_amax,
                                              const int32_t* __restrict__ y, int b,
                                              float2* __restrict__ partial, const EvalLds& lo,
-                                             int n_pt, int pass_rows, int tail_vec) {
+                                             int n_pt, int tail_vec) {
   typedef Lp<DT> T;
   typedef typename T::Frag Frag;
   extern __shared__ float lds[];
@@ -196,7 +195,7 @@ __device__ __forceinline__ void eval_lp_body(int j, int wt, const float* __restr
 #pragma unroll
     for (int mi = 0; mi < MW; ++mi)
 #pragma unroll
-      for (int t = 0; t < NT; ++t) acc[mi][t] = T::mma(a[mi], bq[t], acc[mi][t]);
+      for (int t = 0; t < NT; ++t) acc[mi][t] = T::mma(bq[t], a[mi], acc[mi][t]);
   };
 
   // double-buffered LDS: the store of chunk ch (buffer ch & 1) follows the
@@ -218,25 +217,35 @@ __device__ __forceinline__ void eval_lp_body(int j, int wt, const float* __restr
   }
   __syncthreads();  // staging is dead from here on
   const float fac = DT == 2 ? fp8_factor(*x_amax, w_amax[j]) : 1.0f;
-  const float nob[NT] = {};
-  const int noy[MW] = {};
-  lp_epilogue<NT, MW, DT>(lds, acc, fac, j, wt, genome, genome, 0, nd, y, b, partial, lo, n_pt,
-                          pass_rows, tail_vec, nob, noy);
+  if constexpr (RT) {  // networks reg_tail_ok() takes
+    copy_tail_genes(genome, nd, lds);
+    int ylab[MW];
+#pragma unroll
+    for (int mi = 0; mi < MW; ++mi) {
+      const int r = m0 + wave * MW * 16 + mi * 16 + mn;
+      ylab[mi] = r < b ? y[r] : 0;
+    }
+    float* red = lds + ((reg_tail_genes(nd) + 3) & ~3);
+    __syncthreads();
+    reg_tail<NT, MW>(acc, fac, lds, nd, m0, wave * MW * 16, b, ylab, red,
+                     partial + (int64_t)j * n_pt, m0 / 64);
+  } else {
+    lds_epilogue<NT, MW>(lds, acc, fac, j, wt, genome, nd, y, b, partial, lo, n_pt, tail_vec);
+  }
 }
 
-template <int NT, int MW, int DT, int D>
+template <int NT, int MW, int DT, int D, bool RT>
 __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lp_kernel(const float* __restrict__ genomes,
                                                       NetDesc nd, const void* __restrict__ xq,
                                                       int kp, const uint32_t* __restrict__ w_amax,
                                                       const uint32_t* __restrict__ x_amax,
                                                       const int32_t* __restrict__ y, int b,
                                                       float2* __restrict__ partial, EvalLds lo,
-                                                      int n_wt, int n_pt, int pass_rows, int pop,
-                                                      int tail_vec) {
+                                                      int n_wt, int n_pt, int pop, int tail_vec) {
   const int Lw = xcd_logical(blockIdx.x, n_wt * pop);
   const int j = Lw / n_wt;
-  eval_lp_body<NT, MW, DT, D>(j, Lw - j * n_wt, genomes, nd, xq, kp, w_amax, x_amax, y, b,
-                              partial, lo, n_pt, pass_rows, tail_vec);
+  eval_lp_body<NT, MW, DT, D, RT>(j, Lw - j * n_wt, genomes, nd, xq, kp, w_amax, x_amax, y, b,
+                                  partial, lo, n_pt, tail_vec);
 }
 
 // ------------------------------------------------------------- dispatch --
@@ -250,11 +259,15 @@ struct LpShape {
 static constexpr size_t kLdsMax = 160 * 1024;
 constexpr int kLpStages = 2;
 
-static size_t lp_bytes(const NetDesc& nd, int mw, int pass_rows, int es, EvalLds* lo) {
+// Dynamic LDS: the staging double buffer, then either the register tail's
+// tail genes and row-sum scratch or the 64-row tile of the LDS epilogue.
+static size_t lp_bytes(const NetDesc& nd, int mw, int es, EvalLds* lo) {
   const int nt = (nd.w[1] + 15) / 16;
   const size_t staging = 2 * (size_t)(nt * 16 + 64 * mw) * 32 * es;
-  *lo = lp_tail_layout(nd, pass_rows);
-  const size_t tail = (size_t)lo->total * 4;
+  *lo = lp_tail_layout(nd, 64);
+  const size_t tail = reg_tail_ok(nd)
+                          ? (size_t)(((reg_tail_genes(nd) + 3) & ~3) + 8 * mw) * 4
+                          : (size_t)lo->total * 4;
   const size_t bytes = staging > tail ? staging : tail;
   lo->total = (int)((bytes + 3) / 4);
   return bytes;
@@ -269,17 +282,14 @@ static bool lp_shape(const NetDesc& nd, int b, int dt, LpShape* out) {
   int mw = b > 64 ? 2 : 1;
   while (mw > 1 && mw * nt > 32) mw >>= 1;
   for (; mw >= 1; mw >>= 1) {
-    // bfloat16: 64-row passes like the kernel on the bfloat16 W_1 copy
-    for (int pr = dt == 1 ? 64 : (64 * mw < 128 ? 64 * mw : 128); pr >= 64; pr >>= 1) {
-      EvalLds lo;
-      const size_t bytes = lp_bytes(nd, mw, pr, es, &lo);
-      if (bytes <= kLdsMax) {
-        out->mw = mw;
-        out->pass_rows = pr;
-        out->lds = bytes;
-        out->lo = lo;
-        return true;
-      }
+    EvalLds lo;
+    const size_t bytes = lp_bytes(nd, mw, es, &lo);
+    if (bytes <= kLdsMax) {
+      out->mw = mw;
+      out->pass_rows = 64;
+      out->lds = bytes;
+      out->lo = lo;
+      return true;
     }
   }
   return false;
@@ -311,19 +321,13 @@ bool eval_shape_lp(const NetDesc& nd, int b, int dt, int kind, int mw, EvalShape
     if (mw != 1 && mw != 2) return false;
     if (mw * nt > 32) return false;
     const int es = dt == 1 ? 2 : 1;
-    bool found = false;
-    for (int pr = dt == 1 ? 64 : (64 * mw < 128 ? 64 * mw : 128); pr >= 64 && !found; pr >>= 1) {
-      EvalLds lo;
-      const size_t bytes = lp_bytes(nd, mw, pr, es, &lo);
-      if (bytes <= kLdsMax) {
-        sh.mw = mw;
-        sh.pass_rows = pr;
-        sh.lds = bytes;
-        sh.lo = lo;
-        found = true;
-      }
-    }
-    if (!found) return false;
+    EvalLds lo;
+    const size_t bytes = lp_bytes(nd, mw, es, &lo);
+    if (bytes > kLdsMax) return false;
+    sh.mw = mw;
+    sh.pass_rows = 64;
+    sh.lds = bytes;
+    sh.lo = lo;
   }
   EvalShape r;
   memset(&r, 0, sizeof r);
@@ -343,7 +347,7 @@ bool eval_shape_lp(const NetDesc& nd, int b, int dt, int kind, int mw, EvalShape
 
 // ------------------------------------------------- grouped (many runs) --
 
-template <int NT, int MW, int DT>
+template <int NT, int MW, int DT, bool RT>
 __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void runs_eval_lp_kernel(
     const RunDesc* __restrict__ runs, const BatchState* __restrict__ st,
     const int* __restrict__ off, const int* __restrict__ ids, int n, int total) {
@@ -352,15 +356,15 @@ __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void runs_eval_lp_kerne
   const RunDesc& d = runs[ids[i]];
   const int local = L - off[i];
   const int j = local / d.n_wt;
-  eval_lp_body<NT, MW, DT, kLpStages>(j, local - j * d.n_wt, d.genomes[st->cur], d.nd, d.xq, d.kp,
-                                      nullptr, nullptr, d.yb, d.b, d.partial, d.lo, d.n_pt,
-                                      d.pass_rows, d.tail_vec);
+  eval_lp_body<NT, MW, DT, kLpStages, RT>(j, local - j * d.n_wt, d.genomes[st->cur], d.nd, d.xq,
+                                          d.kp, nullptr, nullptr, d.yb, d.b, d.partial, d.lo,
+                                          d.n_pt, d.tail_vec);
 }
 
-template <int NT, int MW>
+template <int NT, int MW, bool RT>
 static hipError_t launch_runs_lp3(const RunDesc* runs, const BatchState* st, const Group& g,
                                   hipStream_t s) {
-  auto kern = runs_eval_lp_kernel<NT, MW, 1>;
+  auto kern = runs_eval_lp_kernel<NT, MW, 1, RT>;
   if (g.lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds);
@@ -372,21 +376,24 @@ static hipError_t launch_runs_lp3(const RunDesc* runs, const BatchState* st, con
 }
 
 template <int NT>
-static hipError_t launch_runs_lp_nt(int mw, const RunDesc* runs, const BatchState* st,
+static hipError_t launch_runs_lp_nt(int mw, int rt, const RunDesc* runs, const BatchState* st,
                                     const Group& g, hipStream_t s) {
-  if (mw == 2) return launch_runs_lp3<NT, 2>(runs, st, g, s);
-  return launch_runs_lp3<NT, 1>(runs, st, g, s);
+  if (mw == 2)
+    return rt ? launch_runs_lp3<NT, 2, true>(runs, st, g, s)
+              : launch_runs_lp3<NT, 2, false>(runs, st, g, s);
+  return rt ? launch_runs_lp3<NT, 1, true>(runs, st, g, s)
+            : launch_runs_lp3<NT, 1, false>(runs, st, g, s);
 }
 
 // Grouped launches exist for the bfloat16 first layer (the FP8 scales are
 // tracked by the single-run path only).
-hipError_t launch_runs_eval_lp(int nt, int mw, int dt, const RunDesc* runs, const BatchState* st,
-                               const Group& g, hipStream_t s) {
+hipError_t launch_runs_eval_lp(int nt, int mw, int dt, int rt, const RunDesc* runs,
+                               const BatchState* st, const Group& g, hipStream_t s) {
   if (dt != 1) return hipErrorInvalidValue;
   switch (nt) {
 #define LEEA_RLP_CASE(N) \
   case N:                \
-    return launch_runs_lp_nt<N>(mw, runs, st, g, s);
+    return launch_runs_lp_nt<N>(mw, rt, runs, st, g, s);
     LEEA_RLP_CASE(1) LEEA_RLP_CASE(2) LEEA_RLP_CASE(3) LEEA_RLP_CASE(4) LEEA_RLP_CASE(5)
     LEEA_RLP_CASE(6) LEEA_RLP_CASE(7) LEEA_RLP_CASE(8) LEEA_RLP_CASE(9) LEEA_RLP_CASE(10)
     LEEA_RLP_CASE(11) LEEA_RLP_CASE(12) LEEA_RLP_CASE(13) LEEA_RLP_CASE(14) LEEA_RLP_CASE(15)
@@ -397,22 +404,34 @@ hipError_t launch_runs_eval_lp(int nt, int mw, int dt, const RunDesc* runs, cons
   }
 }
 
-template <int NT, int MW, int DT>
-static hipError_t launch_lp3(const float* genomes, const NetDesc& nd, int pop, const void* xq,
+template <int NT, int MW, int DT, bool RT>
+static hipError_t launch_lp4(const float* genomes, const NetDesc& nd, int pop, const void* xq,
                              int kp, const uint32_t* w_amax, const uint32_t* x_amax,
                              const int32_t* y, int b, float2* partial, const LpShape& sh,
                              int tv, hipStream_t s) {
-  auto kern = eval_lp_kernel<NT, MW, DT, kLpStages>;
+  auto kern = eval_lp_kernel<NT, MW, DT, kLpStages, RT>;
   if (sh.lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh.lds);
     if (e != hipSuccess) return e;
   }
   const int n_wt = (b + 64 * MW - 1) / (64 * MW);
-  const int n_pt = (b + sh.pass_rows - 1) / sh.pass_rows;
+  const int n_pt = (b + 63) / 64;
   hipLaunchKernelGGL(kern, dim3((unsigned)(n_wt * pop)), dim3(256), sh.lds, s, genomes, nd, xq,
-                     kp, w_amax, x_amax, y, b, partial, sh.lo, n_wt, n_pt, sh.pass_rows, pop, tv);
+                     kp, w_amax, x_amax, y, b, partial, sh.lo, n_wt, n_pt, pop, tv);
   return hipGetLastError();
+}
+
+template <int NT, int MW, int DT>
+static hipError_t launch_lp3(const float* genomes, const NetDesc& nd, int pop, const void* xq,
+                             int kp, const uint32_t* w_amax, const uint32_t* x_amax,
+                             const int32_t* y, int b, float2* partial, const LpShape& sh,
+                             int tv, hipStream_t s) {
+  if (reg_tail_ok(nd))
+    return launch_lp4<NT, MW, DT, true>(genomes, nd, pop, xq, kp, w_amax, x_amax, y, b, partial,
+                                        sh, tv, s);
+  return launch_lp4<NT, MW, DT, false>(genomes, nd, pop, xq, kp, w_amax, x_amax, y, b, partial,
+                                       sh, tv, s);
 }
 
 template <int NT, int DT>

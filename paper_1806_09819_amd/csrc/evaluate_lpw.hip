@@ -16,7 +16,9 @@
 //   arrays, so the compiler can tell a stage being read from the stages
 //   being copied into and adds no wait for copies still in flight (with one
 //   array, or the dynamic LDS, it drains every copy before each read).
-//   Stage 0 is large enough for the tail's LDS, which reuses it.  Every wave
+// * Layer 1 comes out transposed (W_1 X^T) and the tail layers and the
+//   fitness run from registers (reg_tail.hpp), reading the tail genes that
+//   were requested before the main loop and parked in stage 1 after it.  Every wave
 //   issues the same number Q of block copies per chunk (a wave with no block
 //   left re-copies its previous one: same bytes to the same place), so
 //   "chunk ch has landed" is vmcnt <= (S-2) Q, waited for explicitly before
@@ -59,36 +61,27 @@ __device__ __forceinline__ void wait_copies_barrier() {
 }
 
 // LDS plan (bytes): a stage holds NT 16-row blocks of W_1 and 4 MW of the
-// batch, 64 bytes per row; the tail of a 64-row pass needs h1 [64][16 NT + 4],
-// a [64][<= 68] buffer (tail widths up to 64) and two [64] vectors; three
-// stages while the whole plan fits 80 KiB (two workgroups per CU), else two.
+// batch, 64 bytes per row.  After the main loop stage 1 takes the tail genes
+// (b_1 .. b_L, up to 20 KiB; the 784-112-32-10 network's take 15.9 KiB) that
+// the register tail reads, and stage 0 its row-sum scratch.  Three stages
+// while the plan fits 80 KiB (two workgroups per CU), else two.
 constexpr int lpw_stage_bytes(int nt, int mw) { return (nt * 16 + 64 * mw) * 64; }
-// Stage 1 also takes the network's tail genes (W_2 .. b_L) for the tail
-// layers when they fit 16 KiB (the 784-112-32-10 network's take 15.4 KiB).
-constexpr int kTailGenesCap = 16 * 1024;
+constexpr int kTailGenesCap = 20 * 1024;
 constexpr int lpw_stage1_bytes(int nt, int mw) {
   return lpw_stage_bytes(nt, mw) > kTailGenesCap ? lpw_stage_bytes(nt, mw) : kTailGenesCap;
 }
-constexpr int lpw_tail_cap(int nt) { return 64 * (16 * nt + 4) * 4 + 64 * 68 * 4 + 2 * 64 * 4; }
-constexpr int lpw_stage0_bytes(int nt, int mw) {
-  return lpw_stage_bytes(nt, mw) > lpw_tail_cap(nt) ? lpw_stage_bytes(nt, mw) : lpw_tail_cap(nt);
-}
 constexpr int lpw_stages(int nt, int mw) {
-  return lpw_stage0_bytes(nt, mw) + lpw_stage1_bytes(nt, mw) + lpw_stage_bytes(nt, mw) <=
-                 80 * 1024
-             ? 3
-             : 2;
+  return lpw_stage1_bytes(nt, mw) + 2 * lpw_stage_bytes(nt, mw) <= 80 * 1024 ? 3 : 2;
 }
 constexpr int lpw_lds_bytes(int nt, int mw) {
-  return lpw_stage0_bytes(nt, mw) + lpw_stage1_bytes(nt, mw) +
-         (lpw_stages(nt, mw) - 2) * lpw_stage_bytes(nt, mw);
+  return lpw_stage1_bytes(nt, mw) + (lpw_stages(nt, mw) - 1) * lpw_stage_bytes(nt, mw);
 }
 
 template <int NT, int MW>
 __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lpw_kernel(
     const float* __restrict__ genomes, NetDesc nd, W1Shadow wsh, const uint16_t* __restrict__ xq,
     int nch, int bpad, const int32_t* __restrict__ y, int b, float2* __restrict__ partial,
-    EvalLds lo, int n_wt, int n_pt, int pass_rows, int pop, int tail_vec) {
+    int n_wt, int n_pt, int pop) {
   constexpr int S = lpw_stages(NT, MW);
   constexpr int RB = 64;                // bytes per staged row (32 bfloat16)
   constexpr int MT = 64 * MW;           // rows per workgroup
@@ -97,7 +90,7 @@ __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lpw_kernel(
   constexpr int NB = NT + MT / 16;      // 1 KiB blocks per stage
   constexpr int Q = (NB + 3) / 4;       // block copies per wave per stage
   static_assert(Q >= 2, "duplicate copies need a previous block");
-  __shared__ __attribute__((aligned(16))) char st0[lpw_stage0_bytes(NT, MW)];
+  __shared__ __attribute__((aligned(16))) char st0[STG];
   __shared__ __attribute__((aligned(16))) char st1[lpw_stage1_bytes(NT, MW)];
   __shared__ __attribute__((aligned(16))) char st2[S == 3 ? STG : 16];
   // stage by a compile-time index, so that every LDS access names one array
@@ -149,32 +142,24 @@ __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lpw_kernel(
   const int mn = lane & 15;
   const int kq = lane >> 4;
 
-  // What the epilogue and the tail read from global memory, requested now so
-  // that it arrives during the main loop: layer 1's bias, the labels of this
-  // thread's row in each 64-row pass, and the tail genes (W_2 .. b_L,
-  // contiguous from woff[1]), which go to stage 1 after the loop.
-  float b1v[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int n = t * 16 + mn;
-    b1v[t] = n < nd.w[1] ? genome[nd.boff[0] + n] : 0.0f;
-  }
+  // What the tail reads from global memory, requested now so that it
+  // arrives during the main loop: the labels of this lane's rows and the
+  // tail genes (b_1 .. b_L, contiguous from boff[0]), which go to stage 1
+  // after the loop.
   int ylab[MW];
 #pragma unroll
-  for (int p = 0; p < MW; ++p) {
-    const int m = m0 + 64 * p + tid;
-    ylab[p] = (tid < 64 && m < b) ? y[m] : 0;
+  for (int mi = 0; mi < MW; ++mi) {
+    const int r = m0 + wave * MW * 16 + mi * 16 + mn;
+    ylab[mi] = r < b ? y[r] : 0;
   }
-  const int64_t toff = nd.L > 1 ? nd.woff[1] : 0;
-  const int tn = (int)(nd.genes - toff);
-  const bool tcopy = nd.L > 1 && tail_vec && (toff & 3) == 0 && tn * 4 <= kTailGenesCap;
+  const int tn = (int)reg_tail_genes(nd);
   constexpr int TQ = kTailGenesCap / 16 / 256;  // float4 per thread
   float4 tv[TQ];
 #pragma unroll
   for (int q = 0; q < TQ; ++q) {
     const int i = tid + 256 * q;
-    tv[q] = (tcopy && 4 * i < tn) ? reinterpret_cast<const float4*>(genome + toff)[i]
-                                  : float4{0.f, 0.f, 0.f, 0.f};
+    tv[q] = 4 * i < tn ? reinterpret_cast<const float4*>(genome + nd.boff[0])[i]
+                       : float4{0.f, 0.f, 0.f, 0.f};
   }
 
   floatx4 acc[MW][NT];
@@ -205,7 +190,7 @@ __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lpw_kernel(
     for (int mi = 0; mi < MW; ++mi)
 #pragma unroll
       for (int t = 0; t < NT; ++t)
-        acc[mi][t] = mfma_bf16(a[mi], bq[t], acc[mi][t]);
+        acc[mi][t] = mfma_bf16(bq[t], a[mi], acc[mi][t]);  // W_1 X^T
   };
 
   // Stage of chunk ch is ch % S; the loop is unrolled by S so that every
@@ -236,57 +221,40 @@ __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lpw_kernel(
   // every copy has landed and every wave is done with the stages before the
   // epilogue reuses the LDS
   wait_copies_barrier<0>();
-  if (tcopy) {
 #pragma unroll
-    for (int q = 0; q < TQ; ++q) reinterpret_cast<float4*>(st1)[tid + 256 * q] = tv[q];
-  }
-  lp_epilogue<NT, MW, 1, true>(reinterpret_cast<float*>(st0), acc, 1.0f, j, wt, genome,
-                               tcopy ? reinterpret_cast<const float*>(st1) : genome,
-                               tcopy ? toff : 0, nd, y, b, partial, lo, n_pt, pass_rows, tail_vec,
-                               b1v, ylab);
+  for (int q = 0; q < TQ; ++q) reinterpret_cast<float4*>(st1)[tid + 256 * q] = tv[q];
+  __syncthreads();
+  reg_tail<NT, MW>(acc, 1.0f, reinterpret_cast<const float*>(st1), nd, m0, wave * MW * 16, b,
+                   ylab, reinterpret_cast<float*>(st0), partial + (int64_t)j * n_pt, m0 / 64);
 }
 
 // ------------------------------------------------------------- dispatch --
 
 namespace {
 
-struct LpwShape {
-  int mw, pass_rows;
-  size_t lds;
-  EvalLds lo;
-};
-
 constexpr size_t kLdsMaxW = 160 * 1024;
 
-// Tail passes of 64 rows in stage 0 (no dynamic LDS).
-bool lpw_shape(const NetDesc& nd, int b, LpwShape* out) {
+// Networks the register tail takes, with their tail genes from boff[0] (a
+// multiple of 4) fitting stage 1.  Returns the row tiles per wave (0: none).
+int lpw_mw(const NetDesc& nd, int b) {
   const int nt = (nd.w[1] + 15) / 16;
-  if (nt < 1 || nt > 16 || nd.w[0] % 4 != 0 || b <= 16) return false;
+  if (nt < 1 || nt > 16 || nd.w[0] % 4 != 0 || b <= 16) return 0;
+  if (!reg_tail_ok(nd) || nd.boff[0] % 4 != 0 || reg_tail_genes(nd) * 4 > kTailGenesCap) return 0;
   int mw = b > 64 ? 2 : 1;
   while (mw > 1 && mw * nt > 32) mw >>= 1;
-  const EvalLds lo = lp_tail_layout(nd, 64);
-  if ((size_t)lo.total * 4 > (size_t)lpw_tail_cap(nt)) return false;
-  for (; mw >= 1; mw >>= 1) {
-    if ((size_t)lpw_lds_bytes(nt, mw) <= kLdsMaxW) {
-      out->mw = mw;
-      out->pass_rows = 64;
-      out->lds = 0;
-      out->lo = lo;
-      return true;
-    }
-  }
-  return false;
+  for (; mw >= 1; mw >>= 1)
+    if ((size_t)lpw_lds_bytes(nt, mw) <= kLdsMaxW) return mw;
+  return 0;
 }
 
 template <int NT, int MW>
 hipError_t launch_lpw3(const float* genomes, const NetDesc& nd, int pop, const W1Shadow& wsh,
                        const uint16_t* xq, int kp, int bpad, const int32_t* y, int b,
-                       float2* partial, const LpwShape& sh, int tv, hipStream_t s) {
-  auto kern = eval_lpw_kernel<NT, MW>;
+                       float2* partial, hipStream_t s) {
   const int n_wt = (b + 64 * MW - 1) / (64 * MW);
-  const int n_pt = (b + sh.pass_rows - 1) / sh.pass_rows;
-  hipLaunchKernelGGL(kern, dim3((unsigned)(n_wt * pop)), dim3(256), sh.lds, s, genomes, nd, wsh,
-                     xq, kp >> 5, bpad, y, b, partial, sh.lo, n_wt, n_pt, sh.pass_rows, pop, tv);
+  const int n_pt = (b + 63) / 64;
+  hipLaunchKernelGGL((eval_lpw_kernel<NT, MW>), dim3((unsigned)(n_wt * pop)), dim3(256), 0, s,
+                     genomes, nd, wsh, xq, kp >> 5, bpad, y, b, partial, n_wt, n_pt, pop);
   return hipGetLastError();
 }
 
@@ -294,28 +262,17 @@ template <int NT>
 hipError_t launch_lpw_nt(const float* genomes, const NetDesc& nd, int pop, const W1Shadow& wsh,
                          const uint16_t* xq, int kp, int bpad, const int32_t* y, int b,
                          float2* partial, hipStream_t s) {
-  LpwShape sh;
-  if (!lpw_shape(nd, b, &sh)) return hipErrorInvalidValue;
-  int tv = 1;
-  for (int l = 1; l < nd.L; ++l)
-    if (nd.w[l] % 4 != 0) tv = 0;
-  if (sh.mw == 2)
-    return launch_lpw3<NT, 2>(genomes, nd, pop, wsh, xq, kp, bpad, y, b, partial, sh, tv, s);
-  return launch_lpw3<NT, 1>(genomes, nd, pop, wsh, xq, kp, bpad, y, b, partial, sh, tv, s);
+  const int mw = lpw_mw(nd, b);
+  if (mw == 2) return launch_lpw3<NT, 2>(genomes, nd, pop, wsh, xq, kp, bpad, y, b, partial, s);
+  if (mw == 1) return launch_lpw3<NT, 1>(genomes, nd, pop, wsh, xq, kp, bpad, y, b, partial, s);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-bool eval_lpw_supported(const NetDesc& nd, int b) {
-  LpwShape sh;
-  return lpw_shape(nd, b, &sh);
-}
+bool eval_lpw_supported(const NetDesc& nd, int b) { return lpw_mw(nd, b) > 0; }
 
-int eval_lpw_ptiles(const NetDesc& nd, int b) {
-  LpwShape sh;
-  if (!lpw_shape(nd, b, &sh)) return 1;
-  return (b + sh.pass_rows - 1) / sh.pass_rows;
-}
+int eval_lpw_ptiles(const NetDesc& nd, int b) { return (b + 63) / 64; }
 
 hipError_t launch_evaluate_lpw(const float* genomes, const NetDesc& nd, int pop,
                                const W1Shadow& wsh, const uint16_t* xq, int kp, int bpad,

@@ -78,6 +78,8 @@ hipError_t launch_select(const float* f_adj, int pop, int n_elite, int n_cross, 
 
 // evaluate.hip
 int eval_mtiles(const NetDesc& nd, int b);
+// Whether the large-batch kernels run this network's tail from registers.
+bool large_reg_tail(const NetDesc& nd);
 hipError_t launch_evaluate(const float* genomes, const NetDesc& nd, int pop, const float* x,
                            const int32_t* y, int b, float2* partial, hipStream_t s);
 hipError_t launch_finalize(const float2* partial, int pop, int n_mt, int b, const float* f_inh,

@@ -1,33 +1,30 @@
-// Pieces shared by the reduced-precision large-batch kernels: the epilogue
-// that turns layer-1 accumulators into the LDS activation tile and runs the
-// FP32 tail and fitness, the XCD-aware workgroup order, and the LDS layout
-// of the tail.
+// Pieces shared by the large-batch kernels: the LDS-tile epilogue for
+// networks the register tail does not take, the XCD-aware workgroup order,
+// and the LDS layout of that epilogue's tail.
 #pragma once
 
 #include "eval_common.hpp"
+#include "reg_tail.hpp"
 
 namespace leea {
 
-// Epilogue in passes of pass_rows rows (LDS tile at lds): the waves owning those rows write
-// fac * acc + bias (ReLU unless it is the output layer) into the LDS tile,
-// then the tail layers and the fitness of the pass run.  A wave's 16 MW rows
-// lie inside one pass (pass_rows is a multiple of 64), so whether it writes
-// is uniform across the wave.
-// The tail layers read their weights from tw + (offset - toff): the genome
-// (toff = 0) or a copy of its tail in LDS.  kPre: layer 1's bias
-// (b1v[t] = b_1[16 t + lane % 16]) and the labels (ylab[p] = y of row
-// 64 p + threadIdx.x, passes of 64 rows) were loaded by the caller before
-// its main loop, so no global load waits here.
-template <int NT, int MW, int DT, bool kPre = false>
-__device__ __forceinline__ void lp_epilogue(float* lds, const floatx4 (&acc)[MW][NT], float fac,
-                                            int j, int wt, const float* __restrict__ genome,
-                                            const float* tw, int64_t toff,
-                                            const NetDesc& nd, const int32_t* __restrict__ y,
-                                            int b, float2* __restrict__ partial,
-                                            const EvalLds& lo, int n_pt, int pass_rows,
-                                            int tail_vec, const float (&b1v)[NT],
-                                            const int (&ylab)[MW]) {
+// Epilogue of the large-batch kernels for networks the register tail does
+// not take (more than three layers, wide or odd-width tail layers): passes
+// of 64 rows over an LDS activation tile.  acc holds layer 1 transposed
+// (W_1 X^T: acc[mi][t][i] = neuron 16 t + 4 kq + i of row 16 mi + mn of the
+// wave's rows).  The waves owning a pass's rows write fac * acc + b_1 (ReLU
+// unless it is the output layer) into the tile, then the tail layers and the
+// fitness of the pass run; each pass writes partial[j * n_pt + m0 / 64 + p].
+// The tail layers read their weights from tw + (offset - toff) (the genome:
+// toff = 0).
+template <int NT, int MW>
+__device__ __forceinline__ void lds_epilogue(float* lds, const floatx4 (&acc)[MW][NT], float fac,
+                                             int j, int wt, const float* __restrict__ genome,
+                                             const NetDesc& nd, const int32_t* __restrict__ y,
+                                             int b, float2* __restrict__ partial,
+                                             const EvalLds& lo, int n_pt, int tail_vec) {
   constexpr int MT = 64 * MW;
+  constexpr int PR = 64;  // rows per pass
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int mn = lane & 15;
@@ -38,41 +35,37 @@ __device__ __forceinline__ void lp_epilogue(float* lds, const floatx4 (&acc)[MW]
   const float* __restrict__ b1 = genome + nd.boff[0];
   const bool hidden = nd.L > 1;
   float* h1 = lds + lo.h1;
-  const int passes = MT / pass_rows;
-  const int wr0 = wave * MW * 16;  // first row of this wave
-  for (int p = 0; p < passes; ++p) {
-    const int pr0 = p * pass_rows;
-    const int prow = rows - pr0 < pass_rows ? rows - pr0 : pass_rows;
-    const int pidx = wt * passes + p;
-    if (prow <= 0 || pidx >= n_pt) break;  // uniform across the workgroup
-    if (wr0 >= pr0 && wr0 < pr0 + pass_rows) {
+  const int wr0 = wave * MW * 16;  // first row of this wave, inside one pass
+  for (int p = 0; p < MW; ++p) {
+    const int pr0 = p * PR;
+    const int prow = rows - pr0 < PR ? rows - pr0 : PR;
+    if (prow <= 0) break;  // uniform across the workgroup
+    if (wr0 >= pr0 && wr0 < pr0 + PR) {
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        const int n = t * 16 + mn;
-        const bool nv = n < n1;
-        const float bb = kPre ? b1v[t] : (nv ? b1[n] : 0.0f);
+        const int c = t * 16 + 4 * kq;
+        float bb[4];
 #pragma unroll
-        for (int mi = 0; mi < MW; ++mi)
+        for (int i = 0; i < 4; ++i) bb[i] = c + i < n1 ? b1[c + i] : 0.0f;
 #pragma unroll
-          for (int i2 = 0; i2 < 4; ++i2) {
-            const int m = wr0 + mi * 16 + 4 * kq + i2 - pr0;
-            float v = acc[mi][t][i2];
-            if (DT == 2) v = v * fac;
-            v = v + bb;
-            if (hidden) v = relu_keep_nan(v);
-            h1[m * lo.ld1 + n] = nv ? v : 0.0f;
+        for (int mi = 0; mi < MW; ++mi) {
+          float v[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            float u = acc[mi][t][i];
+            if (fac != 1.0f) u = u * fac;
+            u = u + bb[i];
+            if (hidden) u = relu_keep_nan(u);
+            v[i] = c + i < n1 ? u : 0.0f;
           }
+          const int m = wr0 + mi * 16 + mn - pr0;
+          *reinterpret_cast<float4*>(h1 + m * lo.ld1 + c) = make_float4(v[0], v[1], v[2], v[3]);
+        }
       }
     }
     __syncthreads();
-    int yl = 0;
-    if (kPre) {
-#pragma unroll
-      for (int q = 0; q < MW; ++q)
-        if (q == p) yl = ylab[q];
-    }
-    tail_and_fitness<4>(lds, lo, nd, tw, toff, pass_rows / 16, prow, m0 + pr0, kPre ? nullptr : y,
-                        tail_vec != 0, partial + (int64_t)j * n_pt + pidx, yl);
+    tail_and_fitness<4>(lds, lo, nd, genome, 0, PR / 16, prow, m0 + pr0, y, tail_vec != 0,
+                        partial + (int64_t)j * n_pt + m0 / 64 + p);
     __syncthreads();
   }
 }

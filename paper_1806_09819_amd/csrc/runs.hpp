@@ -80,11 +80,12 @@ hipError_t launch_runs_select(const RunDesc* runs, const BatchState* st, const G
 hipError_t launch_runs_vary(const RunDesc* runs, const BatchState* st, const Group& g,
                             hipStream_t s);
 hipError_t launch_runs_quantize(const RunDesc* runs, const Group& g, hipStream_t s);
-// one evaluation class: every run of the group shares (kind, NT, MW, dt)
-hipError_t launch_runs_eval(int kind, int nt, int mw, int dt, const RunDesc* runs,
+// one evaluation class: every run of the group shares (kind, NT, MW, dt) and
+// rt, whether the large-batch kernels run its tail from registers
+hipError_t launch_runs_eval(int kind, int nt, int mw, int dt, int rt, const RunDesc* runs,
                             const BatchState* st, const Group& g, hipStream_t s);
-hipError_t launch_runs_eval_lp(int nt, int mw, int dt, const RunDesc* runs, const BatchState* st,
-                               const Group& g, hipStream_t s);
+hipError_t launch_runs_eval_lp(int nt, int mw, int dt, int rt, const RunDesc* runs,
+                               const BatchState* st, const Group& g, hipStream_t s);
 hipError_t launch_runs_finalize(const RunDesc* runs, const BatchState* st, const Group& g,
                                 hipStream_t s);
 hipError_t launch_runs_advance(BatchState* st, hipStream_t s);

@@ -35,7 +35,7 @@ struct RunHost {
 };
 
 struct EvalClass {
-  int kind, nt, mw, dt;
+  int kind, nt, mw, dt, rt;
   std::vector<int> runs;
 };
 
@@ -208,18 +208,19 @@ leea_status build_groups(leea_runs* m) {
   m->any_lp = !q_ids.empty();
   if (m->any_lp) add_group(q_ids, q_blocks, 0, &m->g_quant);
   // evaluation classes
-  std::map<std::tuple<int, int, int, int>, std::vector<int>> cls;
+  std::map<std::tuple<int, int, int, int, int>, std::vector<int>> cls;
   for (int r = 0; r < m->n; ++r) {
     const RunDesc& d = m->desc[r];
     const int nt = (d.nd.w[1] + 15) / 16;
     const int mw = d.ekind == 0 ? 1 : d.emw;
-    cls[std::make_tuple(d.ekind, nt, mw, d.dt)].push_back(r);
+    const int rt = d.ekind != 0 && large_reg_tail(d.nd) ? 1 : 0;
+    cls[std::make_tuple(d.ekind, nt, mw, d.dt, rt)].push_back(r);
   }
   m->classes.clear();
   m->g_eval.clear();
   for (auto& kv : cls) {
     EvalClass ec;
-    std::tie(ec.kind, ec.nt, ec.mw, ec.dt) = kv.first;
+    std::tie(ec.kind, ec.nt, ec.mw, ec.dt, ec.rt) = kv.first;
     ec.runs = kv.second;
     std::vector<int> blocks;
     size_t lds = 0;
@@ -264,7 +265,7 @@ leea_status enqueue(leea_runs* m, int step, const float* x, const int32_t* y, in
     st = rdev(m, launch_runs_quantize(m->d_desc, m->g_quant, s), "grouped quantize");
   for (size_t c = 0; c < m->classes.size() && !st; ++c) {
     const EvalClass& ec = m->classes[c];
-    st = rdev(m, launch_runs_eval(ec.kind, ec.nt, ec.mw, ec.dt, m->d_desc, m->d_state,
+    st = rdev(m, launch_runs_eval(ec.kind, ec.nt, ec.mw, ec.dt, ec.rt, m->d_desc, m->d_state,
                                   m->g_eval[c], s),
               "grouped evaluate");
   }
@@ -562,8 +563,9 @@ leea_status leea_runs_autotune(leea_runs* m, const float* x_train, const int32_t
         const int nt = (h.nd.w[1] + 15) / 16;
         for (int k = 0; k < 7 && !st; ++k) {
           if (k == 2) hipEventRecord(e0, m->stream);
-          st = rdev(m, launch_runs_eval(sh.kind, nt, sh.kind == 0 ? 1 : sh.mw, d.dt, m->d_desc,
-                                        m->d_state, g, m->stream),
+          const int rt = sh.kind != 0 && large_reg_tail(h.nd) ? 1 : 0;
+          st = rdev(m, launch_runs_eval(sh.kind, nt, sh.kind == 0 ? 1 : sh.mw, d.dt, rt,
+                                        m->d_desc, m->d_state, g, m->stream),
                     "evaluate");
         }
         hipEventRecord(e1, m->stream);
