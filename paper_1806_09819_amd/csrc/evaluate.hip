@@ -270,7 +270,7 @@ __device__ __forceinline__ void eval_large_body(int j, int mt, const float* __re
       const int r = m0 + wave * MW * 16 + mi * 16 + mn;
       ylab[mi] = r < b ? y[r] : 0;
     }
-    float* red = lds + ((reg_tail_genes(nd) + 3) & ~3);
+    float* red = lds + reg_tail_copy_floats(nd);
     __syncthreads();
     reg_tail<NT, MW>(acc, 1.0f, lds, nd, m0, wave * MW * 16, b, ylab, red,
                      partial + (int64_t)j * n_pt, m0 / 64);
@@ -469,7 +469,7 @@ hipError_t launch_evaluate_small_lp(int dt, const float* genomes, const NetDesc&
 static size_t large_lds_rt(const NetDesc& nd, int nt, int mw, EvalLds* out) {
   EvalLds lo = lp_tail_layout(nd, 64);
   const int staging = 2 * (8 * nt * 16 * 4 + 8 * 64 * mw * 4);
-  const int rt = reg_tail_ok(nd) ? (int)((reg_tail_genes(nd) + 3) & ~3) + 8 * mw : 0;
+  const int rt = reg_tail_ok(nd) ? reg_tail_copy_floats(nd) + 8 * mw : 0;
   int total = lo.total > staging ? lo.total : staging;
   total = total > rt ? total : rt;
   lo.total = total;

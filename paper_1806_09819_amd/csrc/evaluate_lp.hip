@@ -225,7 +225,7 @@ __device__ __forceinline__ void eval_lp_body(int j, int wt, const float* __restr
       const int r = m0 + wave * MW * 16 + mi * 16 + mn;
       ylab[mi] = r < b ? y[r] : 0;
     }
-    float* red = lds + ((reg_tail_genes(nd) + 3) & ~3);
+    float* red = lds + reg_tail_copy_floats(nd);
     __syncthreads();
     reg_tail<NT, MW>(acc, fac, lds, nd, m0, wave * MW * 16, b, ylab, red,
                      partial + (int64_t)j * n_pt, m0 / 64);
@@ -266,7 +266,7 @@ static size_t lp_bytes(const NetDesc& nd, int mw, int es, EvalLds* lo) {
   const size_t staging = 2 * (size_t)(nt * 16 + 64 * mw) * 32 * es;
   *lo = lp_tail_layout(nd, 64);
   const size_t tail = reg_tail_ok(nd)
-                          ? (size_t)(((reg_tail_genes(nd) + 3) & ~3) + 8 * mw) * 4
+                          ? (size_t)(reg_tail_copy_floats(nd) + 8 * mw) * 4
                           : (size_t)lo->total * 4;
   const size_t bytes = staging > tail ? staging : tail;
   lo->total = (int)((bytes + 3) / 4);

@@ -239,7 +239,8 @@ constexpr size_t kLdsMaxW = 160 * 1024;
 int lpw_mw(const NetDesc& nd, int b) {
   const int nt = (nd.w[1] + 15) / 16;
   if (nt < 1 || nt > 16 || nd.w[0] % 4 != 0 || b <= 16) return 0;
-  if (!reg_tail_ok(nd) || nd.boff[0] % 4 != 0 || reg_tail_genes(nd) * 4 > kTailGenesCap) return 0;
+  if (!reg_tail_ok(nd) || nd.boff[0] % 4 != 0 || reg_tail_copy_floats(nd) * 4 > kTailGenesCap)
+    return 0;
   int mw = b > 64 ? 2 : 1;
   while (mw > 1 && mw * nt > 32) mw >>= 1;
   for (; mw >= 1; mw >>= 1)

@@ -42,66 +42,103 @@ __host__ __device__ inline int64_t reg_tail_genes(const NetDesc& nd) {
   return nd.genes - nd.boff[0];
 }
 
-// Copy of those genes into LDS by the whole workgroup (256 threads); the
-// words past them up to the next multiple of 4 are zero (the last bias is
-// read in fours).  Caller synchronises afterwards.
+// Floats of the LDS copy: the genes, zeros up to the next multiple of 4
+// (the last bias is read in fours), then four more zeros that weight
+// fragments past n_in read instead of masking.
+__host__ __device__ inline int reg_tail_copy_floats(const NetDesc& nd) {
+  return (int)((reg_tail_genes(nd) + 3) & ~3) + 4;
+}
+
+// That copy, made by the whole workgroup (256 threads).  Caller
+// synchronises afterwards.
 __device__ __forceinline__ void copy_tail_genes(const float* __restrict__ genome,
                                                 const NetDesc& nd, float* tl) {
   const int tn = (int)reg_tail_genes(nd);
   const float* src = genome + nd.boff[0];
-  const int tn4 = (tn + 3) & ~3;
-  for (int i = threadIdx.x; i < tn4; i += 256) tl[i] = i < tn ? src[i] : 0.0f;
+  const int n = reg_tail_copy_floats(nd);
+  for (int i = threadIdx.x; i < n; i += 256) tl[i] = i < tn ? src[i] : 0.0f;
 }
 
-// One tail layer: out[mi][o] (column tile o < n_out tiles) = in * W^T + b
-// with `in` = TI column tiles in the transposed layout, ReLU if hidden.
-// W (n_out x n_in, row-major) and b are in LDS.  Columns past n_out come out
-// as zeros.
-template <int MW, int TI>
-__device__ __forceinline__ void reg_layer(const floatx4 (&in)[MW][TI], int ti_used,
-                                          floatx4 (&out)[MW][kRegTailMax], const float* W,
-                                          const float* bias, int n_in, int n_out, bool relu) {
+// One tail layer: out[mi][o] (column tile o < TO) = in * W^T + b with `in` =
+// the first TI column tiles of the transposed layout, ReLU if hidden; tiles
+// TO .. kRegTailMax - 1 of out are zero, and so are columns past n_out.  W
+// (n_out x n_in, row-major) and b are in LDS; z4 points at four zeros there.
+// Fragments of rows past n_out read row 0 (those columns are zeroed
+// afterwards); fragments past n_in read z4 (zero times the zero activations
+// there, where a clamped weight could be infinite or NaN).  Every K-step
+// loads its TO weight fragments first and then runs its 4 TO MW products
+// across all the accumulators, so consecutive products never wait on each
+// other; each accumulator still sums its K-steps in order (t, then i).
+template <int MW, int TI, int TO, int TIN>
+__device__ __forceinline__ void reg_layer_t(const floatx4 (&in)[MW][TIN],
+                                            floatx4 (&out)[MW][kRegTailMax], const float* W,
+                                            const float* bias, const float* z4, int n_in,
+                                            int n_out, bool relu) {
+  static_assert(TI <= TIN && TO <= kRegTailMax, "tile counts");
   const int lane = threadIdx.x & 63;
   const int mn = lane & 15;
   const int kq = lane >> 4;
-  const int to = (n_out + 15) >> 4;
+  const float* wr[TO];
+#pragma unroll
+  for (int o = 0; o < TO; ++o) {
+    const int n = 16 * o + mn;
+    wr[o] = W + (n < n_out ? n : 0) * n_in;
+  }
 #pragma unroll
   for (int o = 0; o < kRegTailMax; ++o)
 #pragma unroll
     for (int mi = 0; mi < MW; ++mi) out[mi][o] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int o = 0; o < kRegTailMax; ++o) {
-    if (o < to) {  // uniform
-      const int n = 16 * o + mn;
-      const bool nv = n < n_out;
-      const float* wr = W + (nv ? n : 0) * n_in;
+  for (int t = 0; t < TI; ++t) {
+    const int k = 16 * t + 4 * kq;
+    float4 w[TO];
 #pragma unroll
-      for (int t = 0; t < TI; ++t) {
-        if (t < ti_used) {  // uniform
-          const int k = 16 * t + 4 * kq;
-          const bool kv = k < n_in;
-          float4 w = *reinterpret_cast<const float4*>(wr + (kv ? k : 0));
-          if (!(nv && kv)) w = zero4();
+    for (int o = 0; o < TO; ++o)
+      w[o] = *reinterpret_cast<const float4*>(k < n_in ? wr[o] + k : z4);
 #pragma unroll
-          for (int mi = 0; mi < MW; ++mi) {
-            out[mi][o] = mfma(w.x, in[mi][t][0], out[mi][o]);
-            out[mi][o] = mfma(w.y, in[mi][t][1], out[mi][o]);
-            out[mi][o] = mfma(w.z, in[mi][t][2], out[mi][o]);
-            out[mi][o] = mfma(w.w, in[mi][t][3], out[mi][o]);
-          }
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int o = 0; o < TO; ++o)
+#pragma unroll
+        for (int mi = 0; mi < MW; ++mi) {
+          const float wv = i == 0 ? w[o].x : i == 1 ? w[o].y : i == 2 ? w[o].z : w[o].w;
+          out[mi][o] = mfma(wv, in[mi][t][i], out[mi][o]);
         }
+  }
+#pragma unroll
+  for (int o = 0; o < TO; ++o) {
+    const int c = 16 * o + 4 * kq;
+    const float4 bv = *reinterpret_cast<const float4*>(bias + (c < n_out ? c : 0));
+#pragma unroll
+    for (int mi = 0; mi < MW; ++mi)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float v = out[mi][o][i] + (i == 0 ? bv.x : i == 1 ? bv.y : i == 2 ? bv.z : bv.w);
+        if (relu) v = relu_keep_nan(v);
+        out[mi][o][i] = c + i < n_out ? v : 0.0f;
       }
-      const int c = 16 * o + 4 * kq;
-      const float4 bv = *reinterpret_cast<const float4*>(bias + (c < n_out ? c : 0));
-#pragma unroll
-      for (int mi = 0; mi < MW; ++mi)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          float v = out[mi][o][i] + (i == 0 ? bv.x : i == 1 ? bv.y : i == 2 ? bv.z : bv.w);
-          if (relu) v = relu_keep_nan(v);
-          out[mi][o][i] = c + i < n_out ? v : 0.0f;
-        }
-    }
+  }
+}
+
+// reg_layer_t with TO = the column tiles of n_out (1 .. kRegTailMax).
+template <int MW, int TI, int TIN>
+__device__ __forceinline__ void reg_layer(const floatx4 (&in)[MW][TIN],
+                                          floatx4 (&out)[MW][kRegTailMax], const float* W,
+                                          const float* bias, const float* z4, int n_in, int n_out,
+                                          bool relu) {
+  switch ((n_out + 15) >> 4) {
+    case 1:
+      reg_layer_t<MW, TI, 1, TIN>(in, out, W, bias, z4, n_in, n_out, relu);
+      break;
+    case 2:
+      reg_layer_t<MW, TI, 2, TIN>(in, out, W, bias, z4, n_in, n_out, relu);
+      break;
+    case 3:
+      reg_layer_t<MW, TI, 3, TIN>(in, out, W, bias, z4, n_in, n_out, relu);
+      break;
+    default:
+      reg_layer_t<MW, TI, 4, TIN>(in, out, W, bias, z4, n_in, n_out, relu);
+      break;
   }
 }
 
@@ -173,7 +210,7 @@ __device__ __forceinline__ void reg_fitness(const floatx4 (&z)[MW][TC], int tc_u
 // Whole tail from the layer-1 accumulators z (transposed layout, NT tiles):
 // bias and activation, layers 2..L, fitness, and the partial sums of this
 // workgroup's 64-row groups.  fac scales the accumulators first (FP8).
-// tl: the tail genes b_1 .. b_L in LDS (tl[0] = b_1[0]); red: LDS scratch of
+// tl: the copy_tail_genes copy in LDS (tl[0] = b_1[0]); red: LDS scratch of
 // 2 * 4 * MW floats; rows of this wave: r0 + 16 mi + mn (r0 relative to the
 // workgroup's first row m0); labels ylab[mi] of those rows (any value for
 // rows at or past b).  partial: the network's partials, one per 64-row group,
@@ -219,16 +256,31 @@ __device__ __forceinline__ void reg_tail(floatx4 (&z)[MW][NT], float fac, const 
   if (nd.L == 1) {
     reg_fitness<MW, NT>(z, NT, n1, ylab, ll, cor);
   } else {
+    const float* z4 = tl + reg_tail_copy_floats(nd) - 4;
     floatx4 h2[MW][kRegTailMax];
-    reg_layer<MW, NT>(z, NT, h2, tl + (nd.woff[1] - base), tl + (nd.boff[1] - base), n1, nd.w[2],
-                      nd.L > 2);
+    reg_layer<MW, NT, NT>(z, h2, tl + (nd.woff[1] - base), tl + (nd.boff[1] - base), z4, n1,
+                          nd.w[2], nd.L > 2);
     const int t2 = (nd.w[2] + 15) >> 4;
     if (nd.L == 2) {
       reg_fitness<MW, kRegTailMax>(h2, t2, nd.w[2], ylab, ll, cor);
     } else {
       floatx4 h3[MW][kRegTailMax];
-      reg_layer<MW, kRegTailMax>(h2, t2, h3, tl + (nd.woff[2] - base), tl + (nd.boff[2] - base),
-                                 nd.w[2], nd.w[3], false);
+      const float* W3 = tl + (nd.woff[2] - base);
+      const float* b3 = tl + (nd.boff[2] - base);
+      switch (t2) {
+        case 1:
+          reg_layer<MW, 1, kRegTailMax>(h2, h3, W3, b3, z4, nd.w[2], nd.w[3], false);
+          break;
+        case 2:
+          reg_layer<MW, 2, kRegTailMax>(h2, h3, W3, b3, z4, nd.w[2], nd.w[3], false);
+          break;
+        case 3:
+          reg_layer<MW, 3, kRegTailMax>(h2, h3, W3, b3, z4, nd.w[2], nd.w[3], false);
+          break;
+        default:
+          reg_layer<MW, 4, kRegTailMax>(h2, h3, W3, b3, z4, nd.w[2], nd.w[3], false);
+          break;
+      }
       reg_fitness<MW, kRegTailMax>(h3, (nd.w[3] + 15) >> 4, nd.w[3], ylab, ll, cor);
     }
   }
