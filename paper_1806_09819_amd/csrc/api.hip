@@ -195,7 +195,7 @@ bool uses_shadow(const leea_config* cfg, const NetDesc& nd) {
          (int64_t)nd.w[0] * nd.w[1] < (1 << 24) && eval_lpw_supported(nd, cfg->max_batch);
 }
 int64_t shadow_net(const NetDesc& nd) {
-  return (int64_t)(padded_k(nd.w[0]) / 32) * ((nd.w[1] + 15) & ~15) * 32;
+  return (int64_t)padded_k(nd.w[0]) * ((nd.w[1] + 15) & ~15);
 }
 
 Carve carve(const leea_config* cfg, const NetDesc& nd) {
@@ -382,6 +382,7 @@ leea_status leea_init_population(const leea_config* cfg, void* workspace, size_t
   c->wsh.net = shadow_net(nd);
   c->wsh.n0 = nd.w[0];
   c->wsh.nrp = (nd.w[1] + 15) & ~15;
+  c->wsh.kp = padded_k(nd.w[0]);
   c->wsh.rcp_n0 = 1.0f / (float)nd.w[0];
   c->wsh_ok = 0;
   c->dt = cfg->eval_dtype;

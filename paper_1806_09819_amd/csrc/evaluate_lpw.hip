@@ -6,11 +6,14 @@
 // one v_mfma_f32_16x16x32_bf16 per (row tile, column tile, 32-wide K chunk),
 // FP32 accumulation in K order, then the FP32 tail and fitness), with the
 // staging done by the memory system instead of registers:
-// * Both operands are chunk-major in global memory, so the 16 rows x 64 bytes
-//   of one chunk are 1 KiB contiguous.  global_load_lds_dwordx4 copies such a
-//   block straight into LDS (lane l writes bytes 16 l .. 16 l + 15 of it);
-//   lane l reads the 16-byte slot that the bank swizzle places at its
-//   position, so the copy is coalesced and the swizzle costs nothing.
+// * global_load_lds_dwordx4 copies a block of 16 rows x 64 bytes (one
+//   32-wide K chunk) straight into LDS: lane l writes bytes 16 l .. 16 l + 15
+//   of the 1 KiB block and reads the 16-byte slot that the bank swizzle
+//   places at its position, so the swizzle costs nothing.  The batch is
+//   chunk-major (a block is 1 KiB contiguous); the W_1 copy is row-major
+//   (a block is 16 row pieces of 64 bytes, L2 lines shared with the
+//   neighbouring chunk), which keeps the variation kernel's writes of it
+//   contiguous.
 // * S stages, S - 1 chunks in flight: chunk ch + S - 1 is requested right
 //   after the barrier of chunk ch.  The stages are separate static LDS
 //   arrays, so the compiler can tell a stage being read from the stages
@@ -113,7 +116,8 @@ __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lpw_kernel(
   // this lane's 16 bytes of a block: row r = lane / 4, physical slot lane % 4,
   // which holds logical slot (lane % 4) ^ ((r >> 1) & 3)
   const int r = lane >> 2;
-  const int lane_off = r * RB + (((lane & 3) ^ ((r >> 1) & 3)) * 16);
+  const int slot = ((lane & 3) ^ ((r >> 1) & 3)) * 16;
+  const int64_t wrow = (int64_t)wsh.kp * 2;  // bytes per row of the W_1 copy
   const char* src[Q];
   int64_t cstride[Q];
   int dst[Q];
@@ -122,11 +126,12 @@ __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lpw_kernel(
     int i = q * 4 + wave;
     if (i >= NB) i -= 4;
     if (i < NT) {
-      src[q] = reinterpret_cast<const char*>(wsh.p + (int64_t)j * wsh.net) + i * 1024 + lane_off;
-      cstride[q] = (int64_t)NR * RB;
+      src[q] = reinterpret_cast<const char*>(wsh.p + (int64_t)j * wsh.net) +
+               (16 * i + r) * wrow + slot;
+      cstride[q] = RB;
       dst[q] = i * 1024;
     } else {
-      src[q] = reinterpret_cast<const char*>(xq) + (int64_t)(m0 + 16 * (i - NT)) * RB + lane_off;
+      src[q] = reinterpret_cast<const char*>(xq) + (int64_t)(m0 + 16 * (i - NT) + r) * RB + slot;
       cstride[q] = (int64_t)bpad * RB;
       dst[q] = NR * RB + (i - NT) * 1024;
     }

@@ -71,8 +71,8 @@ hipError_t launch_init(float* genomes, const NetDesc& nd, const Glorot& ga, int 
 // kNorm: also write, per wave, the sum of squared differences between the
 // child and parent 1 over the wave's genes to nu[j * ngroups + G].
 // kShadow: also write the child's W_1 rounded to bfloat16 into its W1Shadow
-// slot (n0 % 4 == 0: a float4 of W_1 is 4 consecutive k of one row and one
-// 32-wide chunk, one 8-byte store).
+// slot (n0 % 4 == 0: a float4 of W_1 is 4 consecutive k of one row, one
+// 8-byte store; a wave's stores are contiguous within each row).
 template <int kXoKind, bool kAmax, bool kNorm = false, bool kShadow = false>
 __device__ __forceinline__ void vary_body(int j, int gx, const float* __restrict__ cur,
                                           float* __restrict__ nxt, const int4* __restrict__ plan,
@@ -127,7 +127,7 @@ __device__ __forceinline__ void vary_body(int j, int gx, const float* __restrict
       uint2 v;
       v.x = pack_bf16x2(o.x, o.y);
       v.y = pack_bf16x2(o.z, o.w);
-      *reinterpret_cast<uint2*>(sh + ((int64_t)(k >> 5) * wsh.nrp + n) * 32 + (k & 31)) = v;
+      *reinterpret_cast<uint2*>(sh + (int64_t)n * wsh.kp + k) = v;
     }
     if (kAmax && f < w1f) {
       uint32_t a = mag_bits(o.x), b = mag_bits(o.y), c = mag_bits(o.z), d = mag_bits(o.w);

@@ -39,13 +39,13 @@ bool eval_shape_f32(const NetDesc& nd, int b, int kind, int mw, EvalShape* out);
 bool eval_shape_lp(const NetDesc& nd, int b, int dt, int kind, int mw, EvalShape* out);
 
 // bfloat16 copy of every network's W_1 read by the large-batch bfloat16
-// kernel, chunk-major: element (n, k) of network j is
-// p[j * net + ((k >> 5) * nrp + n) * 32 + (k & 31)], with the rows padded to
-// nrp = n1 rounded up to 16 and K to 32 (padding zero).  p == nullptr: none.
+// kernel, row-major with padding: element (n, k) of network j is
+// p[j * net + n * kp + k], with the rows padded to nrp = n1 rounded up to 16
+// and K to kp = n0 rounded up to 32 (padding zero).  p == nullptr: none.
 struct W1Shadow {
   uint16_t* p;
-  int64_t net;  // elements per network = (kp / 32) * nrp * 32
-  int n0, nrp;
+  int64_t net;  // elements per network = nrp * kp
+  int n0, nrp, kp;
   float rcp_n0;  // 1 / n0 (row of a W_1 gene index below 2^24: one fix-up step)
 };
 

@@ -175,8 +175,8 @@ hipError_t launch_quantize_x_chunks(const float* x, int b, int n0, int kp, int b
 }
 
 // The bfloat16 W_1 copy rebuilt from the genomes (after initialisation or a
-// population replaced from outside): slot it of network blockIdx.y = chunk
-// it / (4 nrp), row (it / 4) mod nrp, elements 8 (it mod 4) .. + 7.
+// population replaced from outside): slot it of network blockIdx.y = row
+// it / (kp / 8), elements 8 (it mod (kp / 8)) .. + 7.
 __global__ __launch_bounds__(256) void shadow_w1_kernel(const float* __restrict__ genomes,
                                                         NetDesc nd, W1Shadow wsh,
                                                         int64_t items) {
@@ -185,10 +185,9 @@ __global__ __launch_bounds__(256) void shadow_w1_kernel(const float* __restrict_
   if (it >= items) return;
   const float* __restrict__ W1 = genomes + (int64_t)j * nd.stride + nd.woff[0];
   const int n0 = nd.w[0], n1 = nd.w[1];
-  const int64_t rs = it >> 2;
-  const int ch = (int)(rs / wsh.nrp);
-  const int n = (int)(rs - (int64_t)ch * wsh.nrp);
-  const int k = ch * 32 + 8 * (int)(it & 3);
+  const int per_row = wsh.kp >> 3;
+  const int n = (int)(it / per_row);
+  const int k = (int)(it - (int64_t)n * per_row) * 8;
   float v[8];
 #pragma unroll
   for (int e = 0; e < 8; ++e) v[e] = (n < n1 && k + e < n0) ? W1[(int64_t)n * n0 + k + e] : 0.0f;
