@@ -44,29 +44,50 @@ def workload(batch, eval_dtype="f32"):
     return p
 
 
+OPERAND_BYTES = {"f32": 4, "bf16": 2, "fp8": 1}
+
+
 def algorithmic(params, genes, b):
     """Per-launch algorithmic FLOPs and HBM bytes of the evaluation kernel:
     2 * sum n_{l-1} n_l FLOPs per network-sample; every weight read once
-    plus the shared batch."""
+    plus the shared batch, the first layer's weights and the batch at the
+    first layer's operand size (its bfloat16 / FP8 copy), the other genes in
+    float32."""
     w = params["widths"]
     per_sample = 2 * sum(w[i] * w[i + 1] for i in range(len(w) - 1))
     P = params["pop"]
     flops = float(per_sample) * P * b
-    nbytes = 4.0 * P * genes + 4.0 * b * (w[0] + 1) + 8.0 * P
+    ob = OPERAND_BYTES[params.get("eval_dtype", "f32")]
+    w1 = w[0] * w[1]
+    nbytes = P * (ob * w1 + 4.0 * (genes - w1)) + b * (ob * w[0] + 4.0) + 8.0 * P
     return flops, nbytes
+
+
+def layer1_flops(params, b):
+    """FLOPs of the first layer alone (the reduced-precision product)."""
+    w = params["widths"]
+    return 2.0 * w[0] * w[1] * params["pop"] * b
 
 
 def vary_bytes(params, genes):
     """Algorithmic bytes of one variation launch: every child written once;
-    elites and mutants read one parent, crossover children two."""
+    elites and mutants read one parent, crossover children two; with a
+    bfloat16 first layer at batches above 16, also each child's W_1 written
+    once more in bfloat16 (the copy the evaluation reads)."""
     from paper_1806_09819_amd import leea as B
     n_e, n_c, n_m, _ = B.counts(params["pop"], params["p_elite"], params["p_cross"],
                                 params["p_mut"], params["rho"])
-    return 4.0 * genes * (2 * n_e + 3 * n_c + 2 * n_m)
+    nbytes = 4.0 * genes * (2 * n_e + 3 * n_c + 2 * n_m)
+    if params.get("eval_dtype", "f32") == "bf16" and params.get("batch", 0) > 16:
+        w = params["widths"]
+        nbytes += 2.0 * w[0] * w[1] * params["pop"]
+    return nbytes
 
 
 TRAFFIC_SOURCES = ("paper_1806_09819_amd/csrc/evaluate.hip",
                    "paper_1806_09819_amd/csrc/eval_common.hpp",
+                   "paper_1806_09819_amd/csrc/lp_common.hpp",
+                   "paper_1806_09819_amd/csrc/reg_tail.hpp",
                    "paper_1806_09819_amd/csrc/device.hpp")
 
 
@@ -193,11 +214,20 @@ def roofline_of(params, r, b):
                     per_launch=dict(bytes=nbytes, avg_ms=r["phases_ms"]["vary+evaluate"]))
     flops, nbytes = algorithmic(params, r["genes"], b)
     sec = r["phases_ms"]["evaluate"] * 1e-3
-    peak = MFMA_PEAK[params.get("eval_dtype", "f32")]
+    dt = params.get("eval_dtype", "f32")
+    # reduced precision: layer 1 at its operand type's peak, the tail layers
+    # at the FP32 peak; the effective peak is the total over that ideal time
+    l1 = layer1_flops(params, b) if dt != "f32" else flops
+    ideal = l1 / MFMA_PEAK[dt] + (flops - l1) / MFMA_F32_PEAK
+    peak = flops / ideal
     if flops / nbytes > peak / HBM_PEAK:
         achieved = flops / sec / 1e12
         roof = dict(bound="mfma", achieved=achieved, peak=peak / 1e12,
                     unit="TFLOP/s", frac=achieved / (peak / 1e12))
+        if dt != "f32":
+            roof["peak_note"] = ("effective peak of the mix: layer 1 at %.1f TFLOP/s (%s), "
+                                 "the float32 tail at %.1f" % (MFMA_PEAK[dt] / 1e12, dt,
+                                                               MFMA_F32_PEAK / 1e12))
     else:
         achieved = nbytes / sec / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK / 1e9, unit="GB/s",
