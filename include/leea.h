@@ -116,7 +116,9 @@ typedef struct {
   float tau;                              /* self-adaptation rate in [0, 10]; 0 = 1/sqrt(genes) */
   int32_t input_pool;                     /* 0, or 2: draw_batch max-pools 2x2 from square images
                                              of 4*widths[0] pixels (section 4.1) */
-  int32_t eval_dtype;                     /* LEEA_DT_*: arithmetic of the first layer */
+  int32_t eval_dtype;                     /* LEEA_DT_*: arithmetic of the first layer (BF16
+                                             with max_batch > 16 adds a bfloat16 copy of
+                                             every W_1 to the workspace) */
 } leea_config;
 
 /* Genes per network (c) and the padded per-individual stride in floats. */
@@ -216,7 +218,10 @@ leea_status leea_set_sigmas(leea_ctx* ctx, const float* sigmas);
 leea_status leea_generation(const leea_ctx* ctx, uint32_t* gen);
 
 /* Borrowed device pointers, valid until the next crossover_mutate/step:
- * the current population ([pop][stride] floats) and its f_adj [pop]. */
+ * the current population ([pop][stride] floats) and its f_adj [pop].  Read
+ * only: replace a population with leea_set_state, which keeps the data the
+ * reduced-precision paths derive from it (FP8 scales, the bfloat16 copy of
+ * W_1 kept for batches above 16) in step. */
 leea_status leea_population(leea_ctx* ctx, float** genomes, int64_t* stride,
                             float** f_adj);
 
