@@ -181,7 +181,8 @@ leea_status leea_select(leea_ctx* ctx, int32_t* plan_out, float* f_inh_out,
  * sigma.  Advances the generation counter.  Requires a preceding select. */
 leea_status leea_crossover_mutate(leea_ctx* ctx);
 
-/* select -> crossover_mutate -> evaluate, one generation.  For b <= 16 (and
+/* select -> crossover_mutate -> evaluate, one generation.  With the fused
+ * path allowed (leea_set_fused_step), for float32 batches of 5..16 rows (and
  * hidden widths that are multiples of 4, with the genes after layer 1's
  * weights small enough for LDS) the variation and the evaluation run as one
  * kernel that builds each child from its parents in registers and evaluates
@@ -198,9 +199,10 @@ leea_status leea_crossover_mutate_evaluate(leea_ctx* ctx, const float* x, const 
 /* Allow (enable != 0) or forbid (the default) the fused small-batch path of
  * leea_step and leea_crossover_mutate_evaluate: one kernel that builds each
  * child from its parents and evaluates it without writing and re-reading it
- * (batches of at most 16, hidden widths multiples of 4).  Results are
- * bit-identical either way; it is off by default because the separate
- * variation and evaluation kernels measured faster. */
+ * (float32 batches of 5..16 rows, hidden widths multiples of 4; batches of at
+ * most 4 always take the separate calls and their row-streaming evaluation).
+ * Results are bit-identical either way; it is off by default because the
+ * separate variation and evaluation kernels measured faster. */
 leea_status leea_set_fused_step(leea_ctx* ctx, int32_t enable);
 
 /* Base mutation strength for the following crossover_mutate calls; with
@@ -335,7 +337,8 @@ leea_status leea_runs_population(leea_runs* m, int32_t r, float** genomes, int64
                                  float** f_adj, float** f_raw, float** acc);
 
 /* Evaluation shape of run r: kind 0 small-batch kernel (b <= 16), 1 float32
- * large-batch, 2 bfloat16 large-batch; mw = row tiles of 16 rows per wave.
+ * large-batch, 2 bfloat16 large-batch, 3 float32 row-streaming (b <= 4, the
+ * float32 default there); mw = row tiles of 16 rows per wave.
  * set_shape fails with LEEA_EINVAL for a shape that does not exist there.
  * A different shape may change the last bits of the fitness (the per-row
  * sums are grouped differently). */

@@ -148,6 +148,141 @@ __global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void eval_small_kernel(const f
                           x_amax);
 }
 
+// ------------------------------------------------------- b <= 4, FP32 --
+// Layer 1 on the vector ALUs with W_1 streamed row by row: a wave takes rows
+// n = wave, wave + 4, ... and reads each in 1 KiB contiguous instructions
+// (lane l: elements 256 kb + 4 l .. + 3), against the batch held in
+// registers (MB rows padded to a power of two, up to 8; launched for b <= 4).  At
+// tiny batches the matrix cores multiply mostly padding and need the 16-row
+// fragment walk of W_1; measured per evaluation at P = 1000, 784-112-32-10:
+// 74 / 83 / 90 us at b = 1 / 4 / 8 against 79 / 82 / 84 us for the
+// small-batch kernel, so it takes b <= 4 only.
+// Each row's MB lane-partial sums are reduced over the wave by a
+// reduce-scatter butterfly (halving the values at xor 32, 16, ... then
+// summing the last one), a fixed order.  Layer-1 activations go to the LDS
+// tile of the small-batch kernel, whose tail and fitness follow.
+constexpr int kStreamBlocks = 4;  // 256-float blocks per row: n0 <= 1024
+
+template <int MB>
+__device__ __forceinline__ void eval_stream_body(int j, const float* __restrict__ genomes,
+                                                 const NetDesc& nd, const float* __restrict__ x,
+                                                 const int32_t* __restrict__ y, int b,
+                                                 float2* __restrict__ partial,
+                                                 const EvalLds& lo, int tail_vec) {
+  extern __shared__ float lds[];
+  constexpr int KB = kStreamBlocks;
+  constexpr int LOG2MB = MB == 1 ? 0 : MB == 2 ? 1 : MB == 4 ? 2 : 3;
+  static_assert((1 << LOG2MB) == MB, "MB is 1, 2, 4 or 8");
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const float* __restrict__ genome = genomes + (int64_t)j * nd.stride;
+  const float* __restrict__ W1 = genome + nd.woff[0];
+  const float* __restrict__ b1 = genome + nd.boff[0];
+  const int n0 = nd.w[0];
+  const int n1 = nd.w[1];
+  const int kb_used = (n0 + 255) >> 8;
+  const bool hidden = nd.L > 1;
+  const int ld1 = lo.ld1;
+  float* h1 = lds + lo.h1;
+  // the 16-row activation tile starts as zeros (padding rows and columns)
+  for (int i = tid; i < 16 * ld1; i += 256) h1[i] = 0.0f;
+
+  float4 xr[MB][KB];
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      const int k = 256 * kb + 4 * lane;
+      xr[m][kb] = (m < b && k < n0) ? *reinterpret_cast<const float4*>(x + (int64_t)m * n0 + k)
+                                    : zero4();
+    }
+  auto loadrow = [&](int n, float4 (&w)[KB], float& bias) {
+    const float* wr = W1 + (int64_t)n * n0;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      w[kb] = zero4();
+      if (kb < kb_used) {  // uniform
+        const int k = 256 * kb + 4 * lane;
+        const float4 v = *reinterpret_cast<const float4*>(wr + (k < n0 ? k : 0));
+        if (k < n0) w[kb] = v;
+      }
+    }
+    bias = b1[n];
+  };
+  __syncthreads();  // the zeroed tile before any row is written
+
+  // RF rows of this wave in flight: a ring of row buffers, the load of row
+  // r + RF issued as soon as row r has been multiplied
+  constexpr int RF = MB == 8 ? 3 : 4;
+  float4 w[RF][KB];
+  float bias[RF];
+  const int R = wave < n1 ? (n1 - wave + 3) >> 2 : 0;  // rows wave, wave + 4, ...
+#pragma unroll
+  for (int q = 0; q < RF; ++q)
+    if (q < R) loadrow(wave + 4 * q, w[q], bias[q]);
+  for (int r0 = 0; r0 < R; r0 += RF) {
+#pragma unroll
+    for (int q = 0; q < RF; ++q) {
+      const int r = r0 + q;
+      if (r < R) {  // uniform
+        const int n = wave + 4 * r;
+        float v[MB];
+#pragma unroll
+        for (int m = 0; m < MB; ++m) v[m] = 0.0f;
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+          for (int m = 0; m < MB; ++m) {
+            v[m] = fmaf(w[q][kb].x, xr[m][kb].x, v[m]);
+            v[m] = fmaf(w[q][kb].y, xr[m][kb].y, v[m]);
+            v[m] = fmaf(w[q][kb].z, xr[m][kb].z, v[m]);
+            v[m] = fmaf(w[q][kb].w, xr[m][kb].w, v[m]);
+          }
+        const float bq = bias[q];
+        if (r + RF < R) loadrow(n + 4 * RF, w[q], bias[q]);
+        // reduce-scatter: after the level with offset 32 >> lvl, a lane
+        // with that bit set holds the upper half of the remaining values
+#pragma unroll
+        for (int lvl = 0; lvl < LOG2MB; ++lvl) {
+          const int off = 32 >> lvl;
+          const int half = MB >> (lvl + 1);
+          const bool hi = (lane & off) != 0;
+#pragma unroll
+          for (int i = 0; i < half; ++i) {
+            const float mine = hi ? v[i + half] : v[i];
+            const float send = hi ? v[i] : v[i + half];
+            v[i] = mine + __shfl_xor(send, off);
+          }
+        }
+#pragma unroll
+        for (int off = 32 >> LOG2MB; off >= 1; off >>= 1) v[0] += __shfl_xor(v[0], off);
+        int m = 0;
+#pragma unroll
+        for (int lvl = 0; lvl < LOG2MB; ++lvl)
+          if (lane & (32 >> lvl)) m += MB >> (lvl + 1);
+        if ((lane & (64 / MB - 1)) == 0 && m < b) {
+          float o = v[0] + bq;
+          if (hidden) o = relu_keep_nan(o);
+          h1[m * ld1 + n] = o;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  tail_and_fitness<1>(lds, lo, nd, genome, 0, 1, b, 0, y, tail_vec != 0, partial + j);
+}
+
+template <int MB>
+__global__ __launch_bounds__(256, 2) void eval_stream_kernel(const float* __restrict__ genomes,
+                                                             NetDesc nd,
+                                                             const float* __restrict__ x,
+                                                             const int32_t* __restrict__ y, int b,
+                                                             float2* __restrict__ partial,
+                                                             EvalLds lo, int tail_vec) {
+  eval_stream_body<MB>(blockIdx.x, genomes, nd, x, y, b, partial, lo, tail_vec);
+}
+
 // ---------------------------------------------------------------- large b --
 // Body of one workgroup: network j, row tile mt (rows 64*MW*mt ...).  RT:
 // the tail from registers (networks reg_tail_ok() takes), else from an LDS
@@ -402,11 +537,47 @@ static hipError_t launch_large(const float* genomes, const NetDesc& nd, int pop,
   return hipGetLastError();
 }
 
+// Row-streaming kernel for b <= 4: n0 a multiple of 4 and at most 1024.
+static constexpr int kStreamMaxRows = 4;
+static bool stream_ok(const NetDesc& nd, int b) {
+  return b >= 1 && b <= kStreamMaxRows && nd.w[0] % 4 == 0 &&
+         nd.w[0] <= 256 * kStreamBlocks && small_lds_bytes(nd, nullptr) <= kMaxLds;
+}
+
+static int stream_rows(int b) { return b <= 1 ? 1 : b <= 2 ? 2 : 4; }
+
+template <int MB>
+static hipError_t launch_stream_mb(const float* genomes, const NetDesc& nd, int pop,
+                                   const float* x, const int32_t* y, int b, float2* partial,
+                                   hipStream_t s) {
+  const int tv = tail_vectorizable(nd) ? 1 : 0;
+  EvalLds lo;
+  const size_t bytes = small_lds_bytes(nd, &lo);
+  hipError_t e = allow_lds(eval_stream_kernel<MB>, bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((eval_stream_kernel<MB>), dim3((unsigned)pop), dim3(256), bytes, s, genomes,
+                     nd, x, y, b, partial, lo, tv);
+  return hipGetLastError();
+}
+
+static hipError_t launch_stream(const float* genomes, const NetDesc& nd, int pop, const float* x,
+                                const int32_t* y, int b, float2* partial, hipStream_t s) {
+  switch (stream_rows(b)) {
+    case 1:
+      return launch_stream_mb<1>(genomes, nd, pop, x, y, b, partial, s);
+    case 2:
+      return launch_stream_mb<2>(genomes, nd, pop, x, y, b, partial, s);
+    default:
+      return launch_stream_mb<4>(genomes, nd, pop, x, y, b, partial, s);
+  }
+}
+
 template <int NT>
 static hipError_t launch_nt(const float* genomes, const NetDesc& nd, int pop, const float* x,
                             const int32_t* y, int b, float2* partial, hipStream_t s) {
   const int tv = tail_vectorizable(nd) ? 1 : 0;
   EvalLds lo;
+  if (stream_ok(nd, b)) return launch_stream(genomes, nd, pop, x, y, b, partial, s);
   if (use_small(b))
     return launch_small<NT, 0>(genomes, nd, pop, x, y, b, partial, nullptr, nullptr, s);
   const int n_pt = mtiles_nt<NT>(nd, b);
@@ -442,6 +613,8 @@ static hipError_t launch_nt(const float* genomes, const NetDesc& nd, int pop, co
 int eval_mtiles(const NetDesc& nd, int b) { LEEA_NT_SWITCH((mtiles_nt<N>(nd, b)), 1) }
 
 bool large_reg_tail(const NetDesc& nd) { return reg_tail_ok(nd); }
+
+bool eval_stream_supported(const NetDesc& nd, int b) { return stream_ok(nd, b); }
 
 hipError_t launch_evaluate(const float* genomes, const NetDesc& nd, int pop, const float* x,
                            const int32_t* y, int b, float2* partial, hipStream_t s) {
@@ -480,11 +653,19 @@ static size_t large_lds_rt(const NetDesc& nd, int nt, int mw, EvalLds* out) {
 bool eval_shape_f32(const NetDesc& nd, int b, int kind, int mw, EvalShape* out) {
   const int nt = (nd.w[1] + 15) / 16;
   if (nt < 1 || nt > 16 || b < 1) return false;
-  if (kind < 0) kind = use_small(b) ? 0 : 1;
+  if (kind < 0) kind = stream_ok(nd, b) ? 3 : (use_small(b) ? 0 : 1);
   EvalShape sh;
   memset(&sh, 0, sizeof sh);
   sh.tail_vec = tail_vectorizable(nd) ? 1 : 0;
-  if (kind == 0) {
+  if (kind == 3) {
+    if (!stream_ok(nd, b)) return false;
+    sh.kind = 3;
+    sh.mw = 1;
+    sh.n_wt = 1;
+    sh.n_pt = 1;
+    sh.pass_rows = 16;
+    sh.lds = small_lds_bytes(nd, &sh.lo);
+  } else if (kind == 0) {
     if (b > 16) return false;
     sh.kind = 0;
     sh.mw = 1;
@@ -524,6 +705,19 @@ __global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void runs_eval_small_kernel(
                           d.lo, d.tail_vec, nullptr, nullptr);
 }
 
+// Row-streaming evaluation of the float32 runs with b <= 4: the batch
+// registers sized for 4 rows whatever each run's b (the per-row sums and
+// their butterfly tree do not depend on that size, so each run gets
+// bitwise what it gets alone).
+__global__ __launch_bounds__(256, 2) void runs_eval_stream_kernel(
+    const RunDesc* __restrict__ runs, const BatchState* __restrict__ st,
+    const int* __restrict__ off, const int* __restrict__ ids, int n) {
+  const int i = find_group(off, n, blockIdx.x);
+  const RunDesc& d = runs[ids[i]];
+  eval_stream_body<4>(blockIdx.x - off[i], d.genomes[st->cur], d.nd, d.xb, d.yb, d.b, d.partial,
+                      d.lo, d.tail_vec);
+}
+
 template <int NT, int MW, bool RT>
 __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void runs_eval_large_kernel(const RunDesc* __restrict__ runs,
                                                               const BatchState* __restrict__ st,
@@ -560,6 +754,14 @@ template <int NT>
 static hipError_t launch_runs_eval_nt(int kind, int mw, int dt, int rt, const RunDesc* runs,
                                       const BatchState* st, const Group& g, hipStream_t s) {
   hipError_t e;
+  if (kind == 3) {
+    if (dt != 0) return hipErrorInvalidValue;
+    e = allow_lds_any(runs_eval_stream_kernel, g.lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(runs_eval_stream_kernel, dim3((unsigned)g.blocks), dim3(256), g.lds, s, runs,
+                       st, g.off, g.ids, g.n);
+    return hipGetLastError();
+  }
   if (kind == 0) {
     if (dt == 0) {
       e = allow_lds_any(runs_eval_small_kernel<NT, 0>, g.lds);

@@ -26,8 +26,8 @@ struct EvalLds {
 
 // Launch shape of the evaluation of one network population on b rows:
 // kind 0 small-batch kernel (b <= 16), 1 FP32 large-batch, 2 reduced-precision
-// large-batch; mw row tiles of 16 per wave; n_wt workgroups per network;
-// n_pt partial row tiles per network.
+// large-batch, 3 FP32 row-streaming (b <= 4); mw row tiles of 16 per wave;
+// n_wt workgroups per network; n_pt partial sums per network.
 struct EvalShape {
   int kind, mw, n_wt, n_pt, pass_rows, tail_vec;
   size_t lds;
@@ -80,6 +80,8 @@ hipError_t launch_select(const float* f_adj, int pop, int n_elite, int n_cross, 
 int eval_mtiles(const NetDesc& nd, int b);
 // Whether the large-batch kernels run this network's tail from registers.
 bool large_reg_tail(const NetDesc& nd);
+// Whether float32 evaluation of b rows takes the row-streaming kernel (b <= 4).
+bool eval_stream_supported(const NetDesc& nd, int b);
 hipError_t launch_evaluate(const float* genomes, const NetDesc& nd, int pop, const float* x,
                            const int32_t* y, int b, float2* partial, hipStream_t s);
 hipError_t launch_finalize(const float2* partial, int pop, int n_mt, int b, const float* f_inh,

@@ -213,7 +213,7 @@ leea_status build_groups(leea_runs* m) {
     const RunDesc& d = m->desc[r];
     const int nt = (d.nd.w[1] + 15) / 16;
     const int mw = d.ekind == 0 ? 1 : d.emw;
-    const int rt = d.ekind != 0 && large_reg_tail(d.nd) ? 1 : 0;
+    const int rt = (d.ekind == 1 || d.ekind == 2) && large_reg_tail(d.nd) ? 1 : 0;
     cls[std::make_tuple(d.ekind, nt, mw, d.dt, rt)].push_back(r);
   }
   m->classes.clear();
@@ -516,7 +516,7 @@ leea_status leea_runs_autotune(leea_runs* m, const float* x_train, const int32_t
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return rfail(m, LEEA_EDEVICE, "event creation failed");
   std::map<std::vector<int64_t>, std::pair<EvalShape, float>> best;
-  const int cands[5][2] = {{0, 1}, {1, 1}, {1, 2}, {2, 1}, {2, 2}};
+  const int cands[6][2] = {{0, 1}, {3, 1}, {1, 1}, {1, 2}, {2, 1}, {2, 2}};
   for (int r = 0; r < m->n && !st; ++r) {
     const RunHost& h = m->host[r];
     std::vector<int64_t> key = {h.cfg.pop, h.cfg.max_batch, h.cfg.eval_dtype, h.nd.L};
@@ -528,7 +528,7 @@ leea_status leea_runs_autotune(leea_runs* m, const float* x_train, const int32_t
       bool any = false;
       for (const auto& c : cands) {
         if (h.cfg.eval_dtype == LEEA_DT_F32 && c[0] == 2) continue;
-        if (h.cfg.eval_dtype != LEEA_DT_F32 && c[0] == 1) continue;
+        if (h.cfg.eval_dtype != LEEA_DT_F32 && (c[0] == 1 || c[0] == 3)) continue;
         EvalShape sh;
         if (!shape_of(h, c[0], c[1], &sh)) continue;
         // a one-run group in this shape
@@ -563,7 +563,7 @@ leea_status leea_runs_autotune(leea_runs* m, const float* x_train, const int32_t
         const int nt = (h.nd.w[1] + 15) / 16;
         for (int k = 0; k < 7 && !st; ++k) {
           if (k == 2) hipEventRecord(e0, m->stream);
-          const int rt = sh.kind != 0 && large_reg_tail(h.nd) ? 1 : 0;
+          const int rt = (sh.kind == 1 || sh.kind == 2) && large_reg_tail(h.nd) ? 1 : 0;
           st = rdev(m, launch_runs_eval(sh.kind, nt, sh.kind == 0 ? 1 : sh.mw, d.dt, rt,
                                         m->d_desc, m->d_state, g, m->stream),
                     "evaluate");

@@ -34,6 +34,13 @@ CASES = [
     ("wide_input_small_b", (2048, 64, 10), 4, 8, None),
     ("n1_256_small_b", (100, 256, 10), 4, 11, None),
     ("b_max_tile_edge", (52, 16, 7), 2, 128, None),
+    # row-streaming layer 1 (b <= 4, n0 <= 1024), and its fall-back past 1024
+    ("paper_b2", (784, 112, 32, 10), 40, 2, None),
+    ("paper_b4", (784, 112, 32, 10), 1000, 4, 24),
+    ("stream_ragged", (100, 20, 12, 3), 5, 3, None),
+    ("stream_single_layer", (64, 10), 8, 4, None),
+    ("stream_wide_input", (1024, 40, 6), 4, 2, None),
+    ("wide_input_b2", (2048, 40, 6), 3, 2, None),
 ]
 
 

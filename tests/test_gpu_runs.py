@@ -32,6 +32,7 @@ def run_params():
         (12, 64, 100, "uniform", "truncation", "f32"),
         (5, 16, 17, "arithmetic", "truncation", "bf16"),
         (26, 256, 64, "uniform", "truncation", "bf16"),
+        (15, 64, 3, "arithmetic", "tournament", "f32"),
     ]
     out = []
     for r, (pop, h, b, xo, sel, dt) in enumerate(spec):
@@ -119,7 +120,7 @@ def test_runs_autotune_choices():
         assert us[r] > 0
         if p["batch"] > 16:
             assert kind[r] != 0                       # the small-batch kernel needs b <= 16
-        assert kind[r] in ((0, 1) if p["eval_dtype"] == "f32" else (0, 2))
+        assert kind[r] in ((0, 1, 3) if p["eval_dtype"] == "f32" else (0, 2))
     # the tuned group still evaluates what the single runs evaluate
     runs.generation(xd, yd)
     runs.sync()
