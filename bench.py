@@ -85,6 +85,7 @@ def vary_bytes(params, genes):
 
 
 TRAFFIC_SOURCES = ("paper_1806_09819_amd/csrc/evaluate.hip",
+                   "paper_1806_09819_amd/csrc/evaluate_lpw.hip",
                    "paper_1806_09819_amd/csrc/eval_common.hpp",
                    "paper_1806_09819_amd/csrc/lp_common.hpp",
                    "paper_1806_09819_amd/csrc/reg_tail.hpp",

@@ -48,6 +48,13 @@ __device__ __forceinline__ float relu_keep_nan(float v) { return v < 0.0f ? 0.0f
 
 __device__ __forceinline__ float4 zero4() { return make_float4(0.f, 0.f, 0.f, 0.f); }
 
+// Non-temporal 16-byte load, for weights that are read exactly once and
+// whose cache lines no other wave shares.
+__device__ __forceinline__ float4 load_once(const float* p) {
+  const floatx4 v = __builtin_nontemporal_load(reinterpret_cast<const floatx4*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
 // One fully connected layer on the matrix cores for rows [0, 16*mtiles):
 // out = act(in * W^T + bias).  `in` (LDS, row stride ldi) must hold zeros in
 // columns [n_in, round16(n_in)); `out` gets zeros in [n_out, round16(n_out)).

@@ -154,9 +154,10 @@ __global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void eval_small_kernel(const f
 // (lane l: elements 256 kb + 4 l .. + 3), against the batch held in
 // registers (MB rows padded to a power of two, up to 8; launched for b <= 4).  At
 // tiny batches the matrix cores multiply mostly padding and need the 16-row
-// fragment walk of W_1; measured per evaluation at P = 1000, 784-112-32-10:
-// 74 / 83 / 90 us at b = 1 / 4 / 8 against 79 / 82 / 84 us for the
-// small-batch kernel, so it takes b <= 4 only.
+// fragment walk of W_1.  The rows are loaded non-temporally (each is read
+// once, by one wave): 74 -> 68 us at b = 1.  Measured per evaluation at
+// P = 1000, 784-112-32-10: 68 / 79 / 84 us at b = 1 / 4 / 8 against
+// 79 / 82 / 82 us for the small-batch kernel, so it takes b <= 4 only.
 // Each row's MB lane-partial sums are reduced over the wave by a
 // reduce-scatter butterfly (halving the values at xor 32, 16, ... then
 // summing the last one), a fixed order.  Layer-1 activations go to the LDS
@@ -204,7 +205,7 @@ __device__ __forceinline__ void eval_stream_body(int j, const float* __restrict_
       w[kb] = zero4();
       if (kb < kb_used) {  // uniform
         const int k = 256 * kb + 4 * lane;
-        const float4 v = *reinterpret_cast<const float4*>(wr + (k < n0 ? k : 0));
+        const float4 v = load_once(wr + (k < n0 ? k : 0));
         if (k < n0) w[kb] = v;
       }
     }
@@ -582,6 +583,8 @@ static hipError_t launch_nt(const float* genomes, const NetDesc& nd, int pop, co
     return launch_small<NT, 0>(genomes, nd, pop, x, y, b, partial, nullptr, nullptr, s);
   const int n_pt = mtiles_nt<NT>(nd, b);
   const bool rt = reg_tail_ok(nd);
+  if (rt && eval_lfw_supported(nd, b, large_mw<NT>(nd, b), x))
+    return launch_evaluate_lfw(genomes, nd, pop, x, y, b, large_mw<NT>(nd, b), partial, s);
   if (large_mw<NT>(nd, b) == 2)
     return rt ? launch_large<NT, 2, true>(genomes, nd, pop, x, y, b, partial, n_pt, tv, s)
               : launch_large<NT, 2, false>(genomes, nd, pop, x, y, b, partial, n_pt, tv, s);

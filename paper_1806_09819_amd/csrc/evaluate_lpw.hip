@@ -233,6 +233,157 @@ __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lpw_kernel(
                    ylab, reinterpret_cast<float*>(st0), partial + (int64_t)j * n_pt, m0 / 64);
 }
 
+// ------------------------------------------------ float32 first layer --
+// The same pipeline for the float32 product: 16-float K chunks (64 bytes per
+// row, so the blocks, the swizzle and the stage plan are those above) copied
+// global -> LDS straight from the genomes' W_1 rows and the row-major batch,
+// in place of the register double buffer of the other float32 kernel
+// (whose staging loads and LDS stores cost about a tenth of its time at
+// b = 512).  Lane (mn, kq) reads the float4 at k = 4 kq .. 4 kq + 3 of its
+// row and runs four v_mfma_f32_16x16x4_f32 per tile pair, component e taking
+// K-step k = 4 kq + e: the products and their order are exactly those of the
+// other kernel, so its results are bitwise equal.  Taken when n0 and n1 are
+// multiples of 16 (every copied row is a W_1 row and every chunk is whole);
+// batch rows past b are copies of row b - 1, which the register tail leaves
+// out of every sum.
+constexpr int lfw_stages(int nt, int mw) {
+  return lpw_stage1_bytes(nt, mw) + 3 * lpw_stage_bytes(nt, mw) <= 80 * 1024 ? 4
+         : lpw_stage1_bytes(nt, mw) + 2 * lpw_stage_bytes(nt, mw) <= 80 * 1024 ? 3 : 2;
+}
+constexpr int lfw_lds_bytes(int nt, int mw) {
+  return lpw_stage1_bytes(nt, mw) + (lfw_stages(nt, mw) - 1) * lpw_stage_bytes(nt, mw);
+}
+
+template <int NT, int MW>
+__global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lfw_kernel(
+    const float* __restrict__ genomes, NetDesc nd, const float* __restrict__ x,
+    const int32_t* __restrict__ y, int b, float2* __restrict__ partial, int n_wt, int n_pt,
+    int pop) {
+  constexpr int S = lfw_stages(NT, MW);
+  constexpr int RB = 64;                // bytes per staged row (16 floats)
+  constexpr int MT = 64 * MW;           // rows per workgroup
+  constexpr int NR = NT * 16;           // staged weight rows
+  constexpr int STG = (NR + MT) * RB;   // bytes per stage
+  constexpr int NB = NT + MT / 16;      // 1 KiB blocks per stage
+  constexpr int Q = (NB + 3) / 4;       // block copies per wave per stage
+  static_assert(Q >= 2, "duplicate copies need a previous block");
+  __shared__ __attribute__((aligned(16))) char st0[STG];
+  __shared__ __attribute__((aligned(16))) char st1[lpw_stage1_bytes(NT, MW)];
+  __shared__ __attribute__((aligned(16))) char st2[S >= 3 ? STG : 16];
+  __shared__ __attribute__((aligned(16))) char st3[S >= 4 ? STG : 16];
+  auto stage_ptr = [&](auto sc) -> char* {
+    constexpr int st = decltype(sc)::value;
+    if constexpr (st == 0) return st0;
+    else if constexpr (st == 1) return st1;
+    else if constexpr (st == 2) return st2;
+    else return st3;
+  };
+
+  const int Lw = xcd_logical(blockIdx.x, n_wt * pop);
+  const int j = Lw / n_wt;
+  const int wt = Lw - j * n_wt;
+  const int m0 = wt * MT;
+  const float* __restrict__ genome = genomes + (int64_t)j * nd.stride;
+  const int n0 = nd.w[0];
+  const int nch = n0 >> 4;
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int r = lane >> 2;
+  const int slot = ((lane & 3) ^ ((r >> 1) & 3)) * 16;
+  const char* src[Q];
+  int dst[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    int i = q * 4 + wave;
+    if (i >= NB) i -= 4;
+    if (i < NT) {
+      src[q] = reinterpret_cast<const char*>(genome + nd.woff[0] + (int64_t)(16 * i + r) * n0) +
+               slot;
+      dst[q] = i * 1024;
+    } else {
+      int m = m0 + 16 * (i - NT) + r;
+      m = m < b ? m : b - 1;
+      src[q] = reinterpret_cast<const char*>(x + (int64_t)m * n0) + slot;
+      dst[q] = NR * RB + (i - NT) * 1024;
+    }
+  }
+  auto issue = [&](int ch, auto sc) {
+    const int64_t c = ch < nch ? ch : nch - 1;
+    char* d = stage_ptr(sc);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) copy16_to_lds(src[q] + c * RB, d + dst[q]);
+  };
+
+  const int mn = lane & 15;
+  const int kq = lane >> 4;
+  int ylab[MW];
+#pragma unroll
+  for (int mi = 0; mi < MW; ++mi) {
+    const int rr = m0 + wave * MW * 16 + mi * 16 + mn;
+    ylab[mi] = rr < b ? y[rr] : 0;
+  }
+  const int tn = (int)reg_tail_genes(nd);
+  constexpr int TQ = kTailGenesCap / 16 / 256;
+  float4 tv[TQ];
+#pragma unroll
+  for (int q = 0; q < TQ; ++q) {
+    const int i = tid + 256 * q;
+    tv[q] = 4 * i < tn ? reinterpret_cast<const float4*>(genome + nd.boff[0])[i]
+                       : float4{0.f, 0.f, 0.f, 0.f};
+  }
+
+  floatx4 acc[MW][NT];
+#pragma unroll
+  for (int mi = 0; mi < MW; ++mi)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[mi][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  int xoff = NR * RB + (wave * MW * 16 + mn) * RB + ((kq ^ ((mn >> 1) & 3)) * 16);
+  int woff = mn * RB + ((kq ^ ((mn >> 1) & 3)) * 16);
+  asm("" : "+v"(xoff));
+  asm("" : "+v"(woff));
+  auto compute = [&](auto sc) {
+    const char* st = stage_ptr(sc);
+    float4 a[MW], bq[NT];
+#pragma unroll
+    for (int mi = 0; mi < MW; ++mi)
+      a[mi] = *reinterpret_cast<const float4*>(st + xoff + mi * 16 * RB);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) bq[t] = *reinterpret_cast<const float4*>(st + woff + t * 16 * RB);
+#pragma unroll
+    for (int mi = 0; mi < MW; ++mi) mfma_superstep_t<NT>(a[mi], bq, acc[mi]);  // W_1 X^T
+  };
+
+  auto step = [&](int ch0, auto sc) {
+    constexpr int s = decltype(sc)::value;
+    wait_copies_barrier<(S - 2) * Q>();
+    issue(ch0 + s + S - 1, std::integral_constant<int, (s + S - 1) % S>{});
+    compute(sc);
+  };
+  issue(0, std::integral_constant<int, 0>{});
+  if constexpr (S >= 3) issue(1, std::integral_constant<int, 1>{});
+  if constexpr (S >= 4) issue(2, std::integral_constant<int, 2>{});
+  int ch0 = 0;
+  for (; ch0 + S <= nch; ch0 += S) {
+    step(ch0, std::integral_constant<int, 0>{});
+    step(ch0, std::integral_constant<int, 1>{});
+    if constexpr (S >= 3) step(ch0, std::integral_constant<int, 2>{});
+    if constexpr (S >= 4) step(ch0, std::integral_constant<int, 3>{});
+  }
+  if (ch0 < nch) step(ch0, std::integral_constant<int, 0>{});  // uniform branches
+  if constexpr (S >= 3)
+    if (ch0 + 1 < nch) step(ch0, std::integral_constant<int, 1>{});
+  if constexpr (S >= 4)
+    if (ch0 + 2 < nch) step(ch0, std::integral_constant<int, 2>{});
+  wait_copies_barrier<0>();
+#pragma unroll
+  for (int q = 0; q < TQ; ++q) reinterpret_cast<float4*>(st1)[tid + 256 * q] = tv[q];
+  __syncthreads();
+  reg_tail<NT, MW>(acc, 1.0f, reinterpret_cast<const float*>(st1), nd, m0, wave * MW * 16, b,
+                   ylab, reinterpret_cast<float*>(st0), partial + (int64_t)j * n_pt, m0 / 64);
+}
+
 // ------------------------------------------------------------- dispatch --
 
 namespace {
@@ -277,6 +428,47 @@ hipError_t launch_lpw_nt(const float* genomes, const NetDesc& nd, int pop, const
 }  // namespace
 
 bool eval_lpw_supported(const NetDesc& nd, int b) { return lpw_mw(nd, b) > 0; }
+
+bool eval_lfw_supported(const NetDesc& nd, int b, int mw, const float* x) {
+  const int nt = (nd.w[1] + 15) / 16;
+  if (nt < 1 || nt > 16 || (mw != 1 && mw != 2) || b <= 16) return false;
+  if (nd.w[0] % 16 != 0 || nd.w[1] % 16 != 0 || nd.stride % 4 != 0 || nd.woff[0] % 4 != 0)
+    return false;
+  if (reinterpret_cast<uintptr_t>(x) % 16 != 0) return false;
+  if (!reg_tail_ok(nd) || nd.boff[0] % 4 != 0 || reg_tail_copy_floats(nd) * 4 > kTailGenesCap)
+    return false;
+  return (size_t)(mw == 2 ? lfw_lds_bytes(nt, 2) : lfw_lds_bytes(nt, 1)) <= kLdsMaxW;
+}
+
+namespace {
+template <int NT, int MW>
+hipError_t launch_lfw3(const float* genomes, const NetDesc& nd, int pop, const float* x,
+                       const int32_t* y, int b, float2* partial, hipStream_t s) {
+  const int n_wt = (b + 64 * MW - 1) / (64 * MW);
+  const int n_pt = (b + 63) / 64;
+  hipLaunchKernelGGL((eval_lfw_kernel<NT, MW>), dim3((unsigned)(n_wt * pop)), dim3(256), 0, s,
+                     genomes, nd, x, y, b, partial, n_wt, n_pt, pop);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_evaluate_lfw(const float* genomes, const NetDesc& nd, int pop, const float* x,
+                               const int32_t* y, int b, int mw, float2* partial, hipStream_t s) {
+  if (!eval_lfw_supported(nd, b, mw, x)) return hipErrorInvalidValue;
+  switch ((nd.w[1] + 15) / 16) {
+#define LEEA_LFW_CASE(N)                                                            \
+  case N:                                                                           \
+    return mw == 2 ? launch_lfw3<N, 2>(genomes, nd, pop, x, y, b, partial, s)       \
+                   : launch_lfw3<N, 1>(genomes, nd, pop, x, y, b, partial, s);
+    LEEA_LFW_CASE(1) LEEA_LFW_CASE(2) LEEA_LFW_CASE(3) LEEA_LFW_CASE(4) LEEA_LFW_CASE(5)
+    LEEA_LFW_CASE(6) LEEA_LFW_CASE(7) LEEA_LFW_CASE(8) LEEA_LFW_CASE(9) LEEA_LFW_CASE(10)
+    LEEA_LFW_CASE(11) LEEA_LFW_CASE(12) LEEA_LFW_CASE(13) LEEA_LFW_CASE(14) LEEA_LFW_CASE(15)
+    LEEA_LFW_CASE(16)
+#undef LEEA_LFW_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
 
 int eval_lpw_ptiles(const NetDesc& nd, int b) { return (b + 63) / 64; }
 

@@ -118,6 +118,13 @@ hipError_t launch_shadow_w1(const float* genomes, const NetDesc& nd, int pop,
 hipError_t launch_evaluate_lpw(const float* genomes, const NetDesc& nd, int pop,
                                const W1Shadow& wsh, const uint16_t* xq, int kp, int bpad,
                                const int32_t* y, int b, float2* partial, hipStream_t s);
+// The float32 large-batch kernel with LDS staging by global -> LDS copies
+// (bitwise equal to the register-staged one): whether it takes a network,
+// batch size, row tiles per wave (1 or 2) and batch pointer, and the launch
+// (same partials as launch_evaluate).
+bool eval_lfw_supported(const NetDesc& nd, int b, int mw, const float* x);
+hipError_t launch_evaluate_lfw(const float* genomes, const NetDesc& nd, int pop, const float* x,
+                               const int32_t* y, int b, int mw, float2* partial, hipStream_t s);
 
 // genetic.hip / surrogate.hip: the fitness surrogate
 hipError_t launch_vary_cand(const float* cur, float* cand, const int4* plan, const NetDesc& nd,

@@ -41,6 +41,12 @@ CASES = [
     ("stream_single_layer", (64, 10), 8, 4, None),
     ("stream_wide_input", (1024, 40, 6), 4, 2, None),
     ("wide_input_b2", (2048, 40, 6), 3, 2, None),
+    # float32 large-batch kernel with global -> LDS staging: chunk counts
+    # below, at and past a multiple of its stage count, one column tile,
+    # ragged last row tiles
+    ("lfw_ragged", (48, 32, 10), 7, 130, None),
+    ("lfw_nt1", (64, 16, 4), 5, 100, None),
+    ("lfw_wide", (1040, 64, 10), 4, 77, None),
 ]
 
 
