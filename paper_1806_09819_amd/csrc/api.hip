@@ -291,16 +291,22 @@ leea_status run_eval(leea_ctx* c, const float* x, const int32_t* y, int32_t b, b
                      float* f_adj, float* f_raw, float* acc) {
   int n_mt = 1;
   leea_status st;
+  const int use_inh = update && c->has_inh && c->cfg.alpha != 1.0f;
   if (c->dt == LEEA_DT_F32) {
+    // batches of up to 16 rows: the evaluation kernel finishes each network
+    // itself (no finalize launch)
+    const FinArgs fin{c->f_inh, update ? c->f_adj : nullptr, update ? c->f_raw : nullptr,
+                      update ? c->acc : nullptr, f_adj, f_raw, acc, c->cfg.alpha, use_inh, 1};
+    bool finalized = false;
     st = dev(c, launch_evaluate(c->genomes[c->cur], c->nd, c->cfg.pop, x, y, b, c->partial,
-                                c->stream),
+                                c->stream, &fin, &finalized),
              "evaluate launch");
+    if (st || finalized) return st;
     n_mt = eval_mtiles(c->nd, b);
   } else {
     st = run_eval_lp(c, x, y, b, &n_mt);
   }
   if (st) return st;
-  const int use_inh = update && c->has_inh && c->cfg.alpha != 1.0f;
   st = dev(c, launch_finalize(c->partial, c->cfg.pop, n_mt, b, c->f_inh, use_inh, c->cfg.alpha,
                               update ? c->f_adj : nullptr, update ? c->f_raw : nullptr,
                               update ? c->acc : nullptr, f_adj, f_raw, acc, c->stream),

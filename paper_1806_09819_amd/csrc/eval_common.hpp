@@ -48,6 +48,16 @@ __device__ __forceinline__ float relu_keep_nan(float v) { return v < 0.0f ? 0.0f
 
 __device__ __forceinline__ float4 zero4() { return make_float4(0.f, 0.f, 0.f, 0.f); }
 
+// s_waitcnt immediate: vmcnt <= n, lgkmcnt = 0, expcnt untouched.
+constexpr int waitcnt_vm_lgkm0(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4); }
+
+// global_load_lds_dwordx4: lane l copies 16 bytes from g to l + 16 l (the
+// LDS base is the wave's).  A device function: kernel lambdas are compiled
+// for the host too, where the builtin does not exist.
+__device__ __forceinline__ void copy16_to_lds(const char* g, char* l) {
+  __builtin_amdgcn_global_load_lds(g, l, 16, 0, 0);
+}
+
 // Non-temporal 16-byte load, for weights that are read exactly once and
 // whose cache lines no other wave shares.
 __device__ __forceinline__ float4 load_once(const float* p) {
@@ -205,7 +215,7 @@ static __device__ void scalar_layer(const float* in, int ldi, int n_in, float* o
 // y == nullptr: the label of row threadIdx.x is ylab (rows <= blockDim.x),
 // loaded by the caller ahead of time.
 template <int G>
-static __device__ void tail_and_fitness(float* lds, const EvalLds& lo, const NetDesc& nd,
+static __device__ float2 tail_and_fitness(float* lds, const EvalLds& lo, const NetDesc& nd,
                                  const float* tw, int64_t toff, int mtiles, int rows,
                                  int m0, const int32_t* __restrict__ y, bool tail_vec,
                                  float2* __restrict__ out, int ylab = 0) {
@@ -244,6 +254,7 @@ static __device__ void tail_and_fitness(float* lds, const EvalLds& lo, const Net
     cor[m] = (best == yy) ? 1 : 0;
   }
   __syncthreads();
+  float2 r = make_float2(0.0f, 0.0f);
   if (threadIdx.x < 64) {
     float s = 0.0f;
     int c = 0;
@@ -256,8 +267,12 @@ static __device__ void tail_and_fitness(float* lds, const EvalLds& lo, const Net
       s += __shfl_xor(s, off);
       c += __shfl_xor(c, off);
     }
-    if (threadIdx.x == 0) *out = make_float2(s, (float)c);
+    if (threadIdx.x == 0) {
+      r = make_float2(s, (float)c);
+      *out = r;
+    }
   }
+  return r;  // thread 0: the partial it wrote
 }
 
 

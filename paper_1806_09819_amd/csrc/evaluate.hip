@@ -38,6 +38,45 @@
 
 namespace leea {
 
+// Per-network finish from the summed partials s (log-likelihoods) and c
+// (correct rows): fitness s / b, accuracy c / b, then the inheritance
+// weighting f_adj = fl(fl((1 - alpha) f_inh) + fl(alpha f)) (section 3.1).
+__device__ __forceinline__ void finalize_values(int j, float s, float c, int b,
+                                                const float* __restrict__ f_inh, int use_inh,
+                                                float alpha, float* f_adj, float* f_raw,
+                                                float* acc, float* f_adj_out, float* f_raw_out,
+                                                float* acc_out) {
+#pragma clang fp contract(off)
+  const float fb = (float)b;
+  const float f = s / fb;
+  const float a = c / fb;
+  float fa = f;
+  if (use_inh) {
+    const float oma = 1.0f - alpha;
+    const float t1 = oma * f_inh[j];
+    const float t2 = alpha * f;
+    fa = t1 + t2;
+  }
+  if (f_adj) f_adj[j] = fa;
+  if (f_raw) f_raw[j] = f;
+  if (acc) acc[j] = a;
+  if (f_adj_out) f_adj_out[j] = fa;
+  if (f_raw_out) f_raw_out[j] = f;
+  if (acc_out) acc_out[j] = a;
+}
+
+// The same finish inside an evaluation kernel whose workgroup wrote the
+// network's only partial p (thread 0 holds it): the sum over one tile
+// starts from zero as finalize_one's does, so the results are bitwise its.
+__device__ __forceinline__ void finalize_in_kernel(int j, float2 p, int b, const FinArgs& fin) {
+#pragma clang fp contract(off)
+  float s = 0.0f, c = 0.0f;
+  s += p.x;
+  c += p.y;
+  finalize_values(j, s, c, b, fin.f_inh, fin.use_inh, fin.alpha, fin.f_adj, fin.f_raw, fin.acc,
+                  fin.f_adj_out, fin.f_raw_out, fin.acc_out);
+}
+
 // ---------------------------------------------------------------- small b --
 // DT selects the first layer's arithmetic (0 float32; 1 bfloat16, 2 FP8
 // E4M3: x holds the batch already quantised, the weight fragments are
@@ -49,7 +88,8 @@ __device__ __forceinline__ void eval_small_body(int j, const float* __restrict__
                                                 const int32_t* __restrict__ y, int b,
                                                 float2* __restrict__ partial, const EvalLds& lo,
                                                 int tail_vec, const uint32_t* __restrict__ w_amax,
-                                                const uint32_t* __restrict__ x_amax) {
+                                                const uint32_t* __restrict__ x_amax,
+                                                const FinArgs& fin) {
   extern __shared__ float lds[];
   const int tid = threadIdx.x;
   const int neg_ew = DT == 2 ? -fp8_exponent(w_amax[j]) : 0;
@@ -133,7 +173,9 @@ __device__ __forceinline__ void eval_small_body(int j, const float* __restrict__
     lds[m * ld1 + n] = v;
   }
   __syncthreads();
-  tail_and_fitness<1>(lds, lo, nd, genome, 0, 1, b, 0, y, tail_vec != 0, partial + j);
+  const float2 r = tail_and_fitness<1>(lds, lo, nd, genome, 0, 1, b, 0, y, tail_vec != 0,
+                                       partial + j);
+  if (fin.on && tid == 0) finalize_in_kernel(j, r, b, fin);
 }
 
 template <int NT, int DT>
@@ -143,9 +185,10 @@ __global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void eval_small_kernel(const f
                                                          float2* __restrict__ partial,
                                                          EvalLds lo, int tail_vec,
                                                          const uint32_t* __restrict__ w_amax,
-                                                         const uint32_t* __restrict__ x_amax) {
+                                                         const uint32_t* __restrict__ x_amax,
+                                                         FinArgs fin) {
   eval_small_body<NT, DT>(blockIdx.x, genomes, nd, x, y, b, partial, lo, tail_vec, w_amax,
-                          x_amax);
+                          x_amax, fin);
 }
 
 // ------------------------------------------------------- b <= 4, FP32 --
@@ -169,7 +212,8 @@ __device__ __forceinline__ void eval_stream_body(int j, const float* __restrict_
                                                  const NetDesc& nd, const float* __restrict__ x,
                                                  const int32_t* __restrict__ y, int b,
                                                  float2* __restrict__ partial,
-                                                 const EvalLds& lo, int tail_vec) {
+                                                 const EvalLds& lo, int tail_vec,
+                                                 const FinArgs& fin) {
   extern __shared__ float lds[];
   constexpr int KB = kStreamBlocks;
   constexpr int LOG2MB = MB == 1 ? 0 : MB == 2 ? 1 : MB == 4 ? 2 : 3;
@@ -271,7 +315,9 @@ __device__ __forceinline__ void eval_stream_body(int j, const float* __restrict_
     }
   }
   __syncthreads();
-  tail_and_fitness<1>(lds, lo, nd, genome, 0, 1, b, 0, y, tail_vec != 0, partial + j);
+  const float2 r = tail_and_fitness<1>(lds, lo, nd, genome, 0, 1, b, 0, y, tail_vec != 0,
+                                       partial + j);
+  if (fin.on && tid == 0) finalize_in_kernel(j, r, b, fin);
 }
 
 template <int MB>
@@ -280,8 +326,9 @@ __global__ __launch_bounds__(256, 2) void eval_stream_kernel(const float* __rest
                                                              const float* __restrict__ x,
                                                              const int32_t* __restrict__ y, int b,
                                                              float2* __restrict__ partial,
-                                                             EvalLds lo, int tail_vec) {
-  eval_stream_body<MB>(blockIdx.x, genomes, nd, x, y, b, partial, lo, tail_vec);
+                                                             EvalLds lo, int tail_vec,
+                                                             FinArgs fin) {
+  eval_stream_body<MB>(blockIdx.x, genomes, nd, x, y, b, partial, lo, tail_vec, fin);
 }
 
 // ---------------------------------------------------------------- large b --
@@ -513,14 +560,14 @@ static int mtiles_nt(const NetDesc& nd, int b) {
 template <int NT, int DT>
 static hipError_t launch_small(const float* genomes, const NetDesc& nd, int pop, const float* x,
                                const int32_t* y, int b, float2* partial, const uint32_t* w_amax,
-                               const uint32_t* x_amax, hipStream_t s) {
+                               const uint32_t* x_amax, hipStream_t s, const FinArgs& fin) {
   const int tv = tail_vectorizable(nd) ? 1 : 0;
   EvalLds lo;
   const size_t bytes = small_lds_bytes(nd, &lo);
   hipError_t e = allow_lds(eval_small_kernel<NT, DT>, bytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((eval_small_kernel<NT, DT>), dim3((unsigned)pop), dim3(256), bytes, s,
-                     genomes, nd, x, y, b, partial, lo, tv, w_amax, x_amax);
+                     genomes, nd, x, y, b, partial, lo, tv, w_amax, x_amax, fin);
   return hipGetLastError();
 }
 
@@ -541,8 +588,8 @@ static hipError_t launch_large(const float* genomes, const NetDesc& nd, int pop,
 // Row-streaming kernel for b <= 4: n0 a multiple of 4 and at most 1024.
 static constexpr int kStreamMaxRows = 4;
 static bool stream_ok(const NetDesc& nd, int b) {
-  return b >= 1 && b <= kStreamMaxRows && nd.w[0] % 4 == 0 &&
-         nd.w[0] <= 256 * kStreamBlocks && small_lds_bytes(nd, nullptr) <= kMaxLds;
+  return b >= 1 && b <= kStreamMaxRows && nd.w[0] % 4 == 0 && nd.w[0] <= 256 * kStreamBlocks &&
+         small_lds_bytes(nd, nullptr) <= kMaxLds;
 }
 
 static int stream_rows(int b) { return b <= 1 ? 1 : b <= 2 ? 2 : 4; }
@@ -550,37 +597,43 @@ static int stream_rows(int b) { return b <= 1 ? 1 : b <= 2 ? 2 : 4; }
 template <int MB>
 static hipError_t launch_stream_mb(const float* genomes, const NetDesc& nd, int pop,
                                    const float* x, const int32_t* y, int b, float2* partial,
-                                   hipStream_t s) {
+                                   hipStream_t s, const FinArgs& fin) {
   const int tv = tail_vectorizable(nd) ? 1 : 0;
-  EvalLds lo;
-  const size_t bytes = small_lds_bytes(nd, &lo);
+  const EvalLds lo = tail_layout(nd, 16);  // the activation tile and the tail buffers only
+  const size_t bytes = (size_t)lo.total * 4;
   hipError_t e = allow_lds(eval_stream_kernel<MB>, bytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((eval_stream_kernel<MB>), dim3((unsigned)pop), dim3(256), bytes, s, genomes,
-                     nd, x, y, b, partial, lo, tv);
+                     nd, x, y, b, partial, lo, tv, fin);
   return hipGetLastError();
 }
 
 static hipError_t launch_stream(const float* genomes, const NetDesc& nd, int pop, const float* x,
-                                const int32_t* y, int b, float2* partial, hipStream_t s) {
+                                const int32_t* y, int b, float2* partial, hipStream_t s,
+                                const FinArgs& fin) {
   switch (stream_rows(b)) {
     case 1:
-      return launch_stream_mb<1>(genomes, nd, pop, x, y, b, partial, s);
+      return launch_stream_mb<1>(genomes, nd, pop, x, y, b, partial, s, fin);
     case 2:
-      return launch_stream_mb<2>(genomes, nd, pop, x, y, b, partial, s);
+      return launch_stream_mb<2>(genomes, nd, pop, x, y, b, partial, s, fin);
     default:
-      return launch_stream_mb<4>(genomes, nd, pop, x, y, b, partial, s);
+      return launch_stream_mb<4>(genomes, nd, pop, x, y, b, partial, s, fin);
   }
 }
 
 template <int NT>
 static hipError_t launch_nt(const float* genomes, const NetDesc& nd, int pop, const float* x,
-                            const int32_t* y, int b, float2* partial, hipStream_t s) {
+                            const int32_t* y, int b, float2* partial, hipStream_t s,
+                            const FinArgs* fin, bool* finalized) {
   const int tv = tail_vectorizable(nd) ? 1 : 0;
-  EvalLds lo;
-  if (stream_ok(nd, b)) return launch_stream(genomes, nd, pop, x, y, b, partial, s);
+  const FinArgs none{};
+  const bool one_tile = stream_ok(nd, b) || use_small(b);
+  if (finalized) *finalized = fin && one_tile;
+  if (stream_ok(nd, b))
+    return launch_stream(genomes, nd, pop, x, y, b, partial, s, fin ? *fin : none);
   if (use_small(b))
-    return launch_small<NT, 0>(genomes, nd, pop, x, y, b, partial, nullptr, nullptr, s);
+    return launch_small<NT, 0>(genomes, nd, pop, x, y, b, partial, nullptr, nullptr, s,
+                               fin ? *fin : none);
   const int n_pt = mtiles_nt<NT>(nd, b);
   const bool rt = reg_tail_ok(nd);
   if (rt && eval_lfw_supported(nd, b, large_mw<NT>(nd, b), x))
@@ -620,8 +673,11 @@ bool large_reg_tail(const NetDesc& nd) { return reg_tail_ok(nd); }
 bool eval_stream_supported(const NetDesc& nd, int b) { return stream_ok(nd, b); }
 
 hipError_t launch_evaluate(const float* genomes, const NetDesc& nd, int pop, const float* x,
-                           const int32_t* y, int b, float2* partial, hipStream_t s) {
-  LEEA_NT_SWITCH((launch_nt<N>(genomes, nd, pop, x, y, b, partial, s)), hipErrorInvalidValue)
+                           const int32_t* y, int b, float2* partial, hipStream_t s,
+                           const FinArgs* fin, bool* finalized) {
+  if (finalized) *finalized = false;
+  LEEA_NT_SWITCH((launch_nt<N>(genomes, nd, pop, x, y, b, partial, s, fin, finalized)),
+                 hipErrorInvalidValue)
 }
 
 hipError_t launch_evaluate_small_lp(int dt, const float* genomes, const NetDesc& nd, int pop,
@@ -629,9 +685,11 @@ hipError_t launch_evaluate_small_lp(int dt, const float* genomes, const NetDesc&
                                     const uint32_t* w_amax, const uint32_t* x_amax,
                                     hipStream_t s) {
   if (dt == 1)
-    LEEA_NT_SWITCH((launch_small<N, 1>(genomes, nd, pop, xq, y, b, partial, w_amax, x_amax, s)),
+    LEEA_NT_SWITCH((launch_small<N, 1>(genomes, nd, pop, xq, y, b, partial, w_amax, x_amax, s,
+                                       FinArgs{})),
                    hipErrorInvalidValue)
-  LEEA_NT_SWITCH((launch_small<N, 2>(genomes, nd, pop, xq, y, b, partial, w_amax, x_amax, s)),
+  LEEA_NT_SWITCH((launch_small<N, 2>(genomes, nd, pop, xq, y, b, partial, w_amax, x_amax, s,
+                                     FinArgs{})),
                  hipErrorInvalidValue)
 }
 
@@ -667,7 +725,8 @@ bool eval_shape_f32(const NetDesc& nd, int b, int kind, int mw, EvalShape* out) 
     sh.n_wt = 1;
     sh.n_pt = 1;
     sh.pass_rows = 16;
-    sh.lds = small_lds_bytes(nd, &sh.lo);
+    sh.lo = tail_layout(nd, 16);
+    sh.lds = (size_t)sh.lo.total * 4;
   } else if (kind == 0) {
     if (b > 16) return false;
     sh.kind = 0;
@@ -705,7 +764,7 @@ __global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void runs_eval_small_kernel(
   const RunDesc& d = runs[ids[i]];
   const float* x = DT ? reinterpret_cast<const float*>(d.xq) : d.xb;
   eval_small_body<NT, DT>(blockIdx.x - off[i], d.genomes[st->cur], d.nd, x, d.yb, d.b, d.partial,
-                          d.lo, d.tail_vec, nullptr, nullptr);
+                          d.lo, d.tail_vec, nullptr, nullptr, FinArgs{});
 }
 
 // Row-streaming evaluation of the float32 runs with b <= 4: the batch
@@ -718,7 +777,7 @@ __global__ __launch_bounds__(256, 2) void runs_eval_stream_kernel(
   const int i = find_group(off, n, blockIdx.x);
   const RunDesc& d = runs[ids[i]];
   eval_stream_body<4>(blockIdx.x - off[i], d.genomes[st->cur], d.nd, d.xb, d.yb, d.b, d.partial,
-                      d.lo, d.tail_vec);
+                      d.lo, d.tail_vec, FinArgs{});
 }
 
 template <int NT, int MW, bool RT>
@@ -808,8 +867,7 @@ hipError_t launch_runs_eval(int kind, int nt, int mw, int dt, int rt, const RunD
 }
 
 // Fitness = (sum of per-sample log-likelihoods) / b, accuracy = correct / b,
-// summed over row tiles in order; then the inheritance weighting
-// f_adj = fl(fl((1 - alpha) f_inh) + fl(alpha f)) (section 3.1).
+// summed over row tiles in order (finalize_values).
 __device__ __forceinline__ void finalize_one(int j, const float2* __restrict__ partial,
                                              int n_mt, int b, const float* __restrict__ f_inh,
                                              int use_inh, float alpha, float* f_adj, float* f_raw,
@@ -822,22 +880,8 @@ __device__ __forceinline__ void finalize_one(int j, const float2* __restrict__ p
     s += p.x;
     c += p.y;
   }
-  const float fb = (float)b;
-  const float f = s / fb;
-  const float a = c / fb;
-  float fa = f;
-  if (use_inh) {
-    const float oma = 1.0f - alpha;
-    const float t1 = oma * f_inh[j];
-    const float t2 = alpha * f;
-    fa = t1 + t2;
-  }
-  if (f_adj) f_adj[j] = fa;
-  if (f_raw) f_raw[j] = f;
-  if (acc) acc[j] = a;
-  if (f_adj_out) f_adj_out[j] = fa;
-  if (f_raw_out) f_raw_out[j] = f;
-  if (acc_out) acc_out[j] = a;
+  finalize_values(j, s, c, b, f_inh, use_inh, alpha, f_adj, f_raw, acc, f_adj_out, f_raw_out,
+                  acc_out);
 }
 
 __global__ void finalize_kernel(const float2* __restrict__ partial, int pop, int n_mt, int b,

@@ -38,15 +38,6 @@ namespace leea {
 
 typedef __bf16 bf16x8w __attribute__((ext_vector_type(8)));
 
-// s_waitcnt immediate: vmcnt <= n, lgkmcnt = 0, expcnt untouched.
-constexpr int waitcnt_vm_lgkm0(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4); }
-
-// Device-only helpers: the lambdas of the kernel are compiled for the host
-// too, where these builtins do not exist.
-__device__ __forceinline__ void copy16_to_lds(const char* g, char* l) {
-  __builtin_amdgcn_global_load_lds(g, l, 16, 0, 0);
-}
-
 __device__ __forceinline__ floatx4 mfma_bf16(const uint4& a, const uint4& b, const floatx4& c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8w, a),
                                                  __builtin_bit_cast(bf16x8w, b), c, 0, 0, 0);
@@ -66,15 +57,18 @@ __device__ __forceinline__ void wait_copies_barrier() {
 // LDS plan (bytes): a stage holds NT 16-row blocks of W_1 and 4 MW of the
 // batch, 64 bytes per row.  After the main loop stage 1 takes the tail genes
 // (b_1 .. b_L, up to 20 KiB; the 784-112-32-10 network's take 15.9 KiB) that
-// the register tail reads, and stage 0 its row-sum scratch.  Three stages
-// while the plan fits 80 KiB (two workgroups per CU), else two.
+// the register tail reads, and stage 0 its row-sum scratch.  As many stages
+// (up to four) as fit 80 KiB, which keeps two workgroups per CU; at
+// b = 512 four stages measured 3 % faster than three.
 constexpr int lpw_stage_bytes(int nt, int mw) { return (nt * 16 + 64 * mw) * 64; }
 constexpr int kTailGenesCap = 20 * 1024;
 constexpr int lpw_stage1_bytes(int nt, int mw) {
   return lpw_stage_bytes(nt, mw) > kTailGenesCap ? lpw_stage_bytes(nt, mw) : kTailGenesCap;
 }
 constexpr int lpw_stages(int nt, int mw) {
-  return lpw_stage1_bytes(nt, mw) + 2 * lpw_stage_bytes(nt, mw) <= 80 * 1024 ? 3 : 2;
+  return lpw_stage1_bytes(nt, mw) + 3 * lpw_stage_bytes(nt, mw) <= 80 * 1024   ? 4
+         : lpw_stage1_bytes(nt, mw) + 2 * lpw_stage_bytes(nt, mw) <= 80 * 1024 ? 3
+                                                                                : 2;
 }
 constexpr int lpw_lds_bytes(int nt, int mw) {
   return lpw_stage1_bytes(nt, mw) + (lpw_stages(nt, mw) - 1) * lpw_stage_bytes(nt, mw);
@@ -95,13 +89,15 @@ __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lpw_kernel(
   static_assert(Q >= 2, "duplicate copies need a previous block");
   __shared__ __attribute__((aligned(16))) char st0[STG];
   __shared__ __attribute__((aligned(16))) char st1[lpw_stage1_bytes(NT, MW)];
-  __shared__ __attribute__((aligned(16))) char st2[S == 3 ? STG : 16];
+  __shared__ __attribute__((aligned(16))) char st2[S >= 3 ? STG : 16];
+  __shared__ __attribute__((aligned(16))) char st3[S >= 4 ? STG : 16];
   // stage by a compile-time index, so that every LDS access names one array
   auto stage_ptr = [&](auto sc) -> char* {
     constexpr int st = decltype(sc)::value;
     if constexpr (st == 0) return st0;
     else if constexpr (st == 1) return st1;
-    else return st2;
+    else if constexpr (st == 2) return st2;
+    else return st3;
   };
 
   const int Lw = xcd_logical(blockIdx.x, n_wt * pop);
@@ -213,16 +209,20 @@ __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lpw_kernel(
     compute(sc);
   };
   issue(0, std::integral_constant<int, 0>{});
-  if constexpr (S == 3) issue(1, std::integral_constant<int, 1>{});
+  if constexpr (S >= 3) issue(1, std::integral_constant<int, 1>{});
+  if constexpr (S >= 4) issue(2, std::integral_constant<int, 2>{});
   int ch0 = 0;
   for (; ch0 + S <= nch; ch0 += S) {
     step(ch0, std::integral_constant<int, 0>{});
     step(ch0, std::integral_constant<int, 1>{});
-    if constexpr (S == 3) step(ch0, std::integral_constant<int, 2>{});
+    if constexpr (S >= 3) step(ch0, std::integral_constant<int, 2>{});
+    if constexpr (S >= 4) step(ch0, std::integral_constant<int, 3>{});
   }
   if (ch0 < nch) step(ch0, std::integral_constant<int, 0>{});  // uniform branches
-  if constexpr (S == 3)
+  if constexpr (S >= 3)
     if (ch0 + 1 < nch) step(ch0, std::integral_constant<int, 1>{});
+  if constexpr (S >= 4)
+    if (ch0 + 2 < nch) step(ch0, std::integral_constant<int, 2>{});
   // every copy has landed and every wave is done with the stages before the
   // epilogue reuses the LDS
   wait_copies_barrier<0>();
@@ -246,20 +246,13 @@ __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lpw_kernel(
 // multiples of 16 (every copied row is a W_1 row and every chunk is whole);
 // batch rows past b are copies of row b - 1, which the register tail leaves
 // out of every sum.
-constexpr int lfw_stages(int nt, int mw) {
-  return lpw_stage1_bytes(nt, mw) + 3 * lpw_stage_bytes(nt, mw) <= 80 * 1024 ? 4
-         : lpw_stage1_bytes(nt, mw) + 2 * lpw_stage_bytes(nt, mw) <= 80 * 1024 ? 3 : 2;
-}
-constexpr int lfw_lds_bytes(int nt, int mw) {
-  return lpw_stage1_bytes(nt, mw) + (lfw_stages(nt, mw) - 1) * lpw_stage_bytes(nt, mw);
-}
 
 template <int NT, int MW>
 __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lfw_kernel(
     const float* __restrict__ genomes, NetDesc nd, const float* __restrict__ x,
     const int32_t* __restrict__ y, int b, float2* __restrict__ partial, int n_wt, int n_pt,
     int pop) {
-  constexpr int S = lfw_stages(NT, MW);
+  constexpr int S = lpw_stages(NT, MW);
   constexpr int RB = 64;                // bytes per staged row (16 floats)
   constexpr int MT = 64 * MW;           // rows per workgroup
   constexpr int NR = NT * 16;           // staged weight rows
@@ -437,7 +430,7 @@ bool eval_lfw_supported(const NetDesc& nd, int b, int mw, const float* x) {
   if (reinterpret_cast<uintptr_t>(x) % 16 != 0) return false;
   if (!reg_tail_ok(nd) || nd.boff[0] % 4 != 0 || reg_tail_copy_floats(nd) * 4 > kTailGenesCap)
     return false;
-  return (size_t)(mw == 2 ? lfw_lds_bytes(nt, 2) : lfw_lds_bytes(nt, 1)) <= kLdsMaxW;
+  return (size_t)(mw == 2 ? lpw_lds_bytes(nt, 2) : lpw_lds_bytes(nt, 1)) <= kLdsMaxW;
 }
 
 namespace {

@@ -82,8 +82,26 @@ int eval_mtiles(const NetDesc& nd, int b);
 bool large_reg_tail(const NetDesc& nd);
 // Whether float32 evaluation of b rows takes the row-streaming kernel (b <= 4).
 bool eval_stream_supported(const NetDesc& nd, int b);
+// What finalize_kernel writes for one network (fitness = sum / b, accuracy,
+// inheritance), for evaluation kernels that hold a network's whole batch in
+// one workgroup and finish it themselves; on = 0: they do not.
+struct FinArgs {
+  const float* f_inh;
+  float* f_adj;
+  float* f_raw;
+  float* acc;
+  float* f_adj_out;
+  float* f_raw_out;
+  float* acc_out;
+  float alpha;
+  int use_inh;
+  int on;
+};
+// With fin given, the kernels for b <= 16 also do the finalisation (the
+// partials are written either way); *finalized tells whether they did.
 hipError_t launch_evaluate(const float* genomes, const NetDesc& nd, int pop, const float* x,
-                           const int32_t* y, int b, float2* partial, hipStream_t s);
+                           const int32_t* y, int b, float2* partial, hipStream_t s,
+                           const FinArgs* fin = nullptr, bool* finalized = nullptr);
 hipError_t launch_finalize(const float2* partial, int pop, int n_mt, int b, const float* f_inh,
                            int use_inh, float alpha, float* f_adj, float* f_raw, float* acc,
                            float* f_adj_out, float* f_raw_out, float* acc_out, hipStream_t s);
