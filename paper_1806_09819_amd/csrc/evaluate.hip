@@ -242,15 +242,27 @@ __device__ __forceinline__ void eval_stream_body(int j, const float* __restrict_
       xr[m][kb] = (m < b && k < n0) ? *reinterpret_cast<const float4*>(x + (int64_t)m * n0 + k)
                                     : zero4();
     }
+  // For MB = 2 the row loads are branch-free (blocks past n0, or past the
+  // used ones, re-read the row's first 16 bytes and are zeroed) and so is
+  // the main loop below (measured at b = 2: 81 -> 71 us; the same form is
+  // slower at b = 1, 66 -> 70 us, where its extra registers cost a
+  // workgroup per CU, and no faster at b = 4).
+  constexpr bool kBranchFree = MB == 2;
   auto loadrow = [&](int n, float4 (&w)[KB], float& bias) {
     const float* wr = W1 + (int64_t)n * n0;
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
-      w[kb] = zero4();
-      if (kb < kb_used) {  // uniform
-        const int k = 256 * kb + 4 * lane;
-        const float4 v = load_once(wr + (k < n0 ? k : 0));
-        if (k < n0) w[kb] = v;
+      const int k = 256 * kb + 4 * lane;
+      if constexpr (kBranchFree) {
+        const bool in = kb < kb_used && k < n0;
+        const float4 v = load_once(wr + (in ? k : 0));
+        w[kb] = in ? v : zero4();
+      } else {
+        w[kb] = zero4();
+        if (kb < kb_used) {  // uniform
+          const float4 v = load_once(wr + (k < n0 ? k : 0));
+          if (k < n0) w[kb] = v;
+        }
       }
     }
     bias = b1[n];
@@ -263,56 +275,63 @@ __device__ __forceinline__ void eval_stream_body(int j, const float* __restrict_
   float4 w[RF][KB];
   float bias[RF];
   const int R = wave < n1 ? (n1 - wave + 3) >> 2 : 0;  // rows wave, wave + 4, ...
+  auto row = [&](int r, int q, bool next) {
+    const int n = wave + 4 * r;
+    float v[MB];
+#pragma unroll
+    for (int m = 0; m < MB; ++m) v[m] = 0.0f;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+      for (int m = 0; m < MB; ++m) {
+        v[m] = fmaf(w[q][kb].x, xr[m][kb].x, v[m]);
+        v[m] = fmaf(w[q][kb].y, xr[m][kb].y, v[m]);
+        v[m] = fmaf(w[q][kb].z, xr[m][kb].z, v[m]);
+        v[m] = fmaf(w[q][kb].w, xr[m][kb].w, v[m]);
+      }
+    const float bq = bias[q];
+    if (next) loadrow(n + 4 * RF, w[q], bias[q]);
+    // reduce-scatter: after the level with offset 32 >> lvl, a lane with
+    // that bit set holds the upper half of the remaining values
+#pragma unroll
+    for (int lvl = 0; lvl < LOG2MB; ++lvl) {
+      const int off = 32 >> lvl;
+      const int half = MB >> (lvl + 1);
+      const bool hi = (lane & off) != 0;
+#pragma unroll
+      for (int i = 0; i < half; ++i) {
+        const float mine = hi ? v[i + half] : v[i];
+        const float send = hi ? v[i] : v[i + half];
+        v[i] = mine + __shfl_xor(send, off);
+      }
+    }
+#pragma unroll
+    for (int off = 32 >> LOG2MB; off >= 1; off >>= 1) v[0] += __shfl_xor(v[0], off);
+    int m = 0;
+#pragma unroll
+    for (int lvl = 0; lvl < LOG2MB; ++lvl)
+      if (lane & (32 >> lvl)) m += MB >> (lvl + 1);
+    if ((lane & (64 / MB - 1)) == 0 && m < b) {
+      float o = v[0] + bq;
+      if (hidden) o = relu_keep_nan(o);
+      h1[m * ld1 + n] = o;
+    }
+  };
 #pragma unroll
   for (int q = 0; q < RF; ++q)
     if (q < R) loadrow(wave + 4 * q, w[q], bias[q]);
-  for (int r0 = 0; r0 < R; r0 += RF) {
+  int r0 = 0;
+  if constexpr (kBranchFree) {
+    // whole groups whose next rows all exist, without a branch
+    for (; r0 + 2 * RF <= R; r0 += RF) {
 #pragma unroll
-    for (int q = 0; q < RF; ++q) {
-      const int r = r0 + q;
-      if (r < R) {  // uniform
-        const int n = wave + 4 * r;
-        float v[MB];
-#pragma unroll
-        for (int m = 0; m < MB; ++m) v[m] = 0.0f;
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb)
-#pragma unroll
-          for (int m = 0; m < MB; ++m) {
-            v[m] = fmaf(w[q][kb].x, xr[m][kb].x, v[m]);
-            v[m] = fmaf(w[q][kb].y, xr[m][kb].y, v[m]);
-            v[m] = fmaf(w[q][kb].z, xr[m][kb].z, v[m]);
-            v[m] = fmaf(w[q][kb].w, xr[m][kb].w, v[m]);
-          }
-        const float bq = bias[q];
-        if (r + RF < R) loadrow(n + 4 * RF, w[q], bias[q]);
-        // reduce-scatter: after the level with offset 32 >> lvl, a lane
-        // with that bit set holds the upper half of the remaining values
-#pragma unroll
-        for (int lvl = 0; lvl < LOG2MB; ++lvl) {
-          const int off = 32 >> lvl;
-          const int half = MB >> (lvl + 1);
-          const bool hi = (lane & off) != 0;
-#pragma unroll
-          for (int i = 0; i < half; ++i) {
-            const float mine = hi ? v[i + half] : v[i];
-            const float send = hi ? v[i] : v[i + half];
-            v[i] = mine + __shfl_xor(send, off);
-          }
-        }
-#pragma unroll
-        for (int off = 32 >> LOG2MB; off >= 1; off >>= 1) v[0] += __shfl_xor(v[0], off);
-        int m = 0;
-#pragma unroll
-        for (int lvl = 0; lvl < LOG2MB; ++lvl)
-          if (lane & (32 >> lvl)) m += MB >> (lvl + 1);
-        if ((lane & (64 / MB - 1)) == 0 && m < b) {
-          float o = v[0] + bq;
-          if (hidden) o = relu_keep_nan(o);
-          h1[m * ld1 + n] = o;
-        }
-      }
+      for (int q = 0; q < RF; ++q) row(r0 + q, q, true);
     }
+  }
+  for (; r0 < R; r0 += RF) {
+#pragma unroll
+    for (int q = 0; q < RF; ++q)
+      if (r0 + q < R) row(r0 + q, q, r0 + q + RF < R);  // uniform
   }
   __syncthreads();
   const float2 r = tail_and_fitness<1>(lds, lo, nd, genome, 0, 1, b, 0, y, tail_vec != 0,
