@@ -29,6 +29,9 @@ VARIANTS = [
                                                crossover="arithmetic")),
     ("paper_like_small_pop", dict(widths=(784, 112, 32, 10), pop=48, sigma=0.001, p_gene=1.0,
                                   rho=0.5, batch=8)),
+    # inheritance done inside the small-batch and row-streaming kernels
+    ("small_batch_alpha_half", dict(alpha=0.5, batch=8)),
+    ("stream_alpha_quarter", dict(alpha=0.25, batch=3)),
 ]
 
 
