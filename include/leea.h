@@ -152,12 +152,15 @@ leea_status leea_draw_batch(leea_ctx* ctx, uint32_t gen, const float* x_train,
  * (lowest class wins ties), then f_adj = (1-alpha) f_inh + alpha fitness
  * (section 3.1) once a selection has produced inherited values.  The three
  * outputs (device, [pop] floats each) may be NULL.  Labels outside [0, d)
- * give a NaN fitness for that network.  1 <= b <= max_batch. */
+ * give a NaN fitness for that network.  1 <= b <= max_batch; x must be
+ * 16-byte aligned (LEEA_EINVAL otherwise: the kernels read it in 16-byte
+ * pieces). */
 leea_status leea_evaluate(leea_ctx* ctx, const float* x, const int32_t* y, int32_t b,
                           float* f_adj, float* f_raw, float* acc);
 
 /* Fitness and accuracy of the current population on n examples without
- * touching the EA state (validation / test scoring).  1 <= n <= max_batch. */
+ * touching the EA state (validation / test scoring).  1 <= n <= max_batch;
+ * x 16-byte aligned as for leea_evaluate. */
 leea_status leea_score(leea_ctx* ctx, const float* x, const int32_t* y, int32_t n,
                        float* f_raw, float* acc);
 

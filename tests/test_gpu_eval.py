@@ -10,6 +10,7 @@ from gpu_helpers import (F32, batch, check_fitness, genomes_np, make_run, oracle
                          to_dev, to_np)
 from oracle import leea as O
 from paper_1806_09819_amd import presets
+from paper_1806_09819_amd.leea import LeeaError
 
 pytestmark = pytest.mark.gpu
 
@@ -122,3 +123,24 @@ def test_evaluate_is_deterministic():
     a = run.evaluate(to_dev(x), to_dev(y))[1].clone()
     b = run.evaluate(to_dev(x), to_dev(y))[1]
     assert torch.equal(a, b)
+
+
+def test_unaligned_batch_is_rejected():
+    # the kernels read the batch in 16-byte pieces; a batch at a 4-byte
+    # offset is refused with LEEA_EINVAL and leaves the state untouched
+    say("evaluate: batch at a 4-byte offset")
+    run, _ = make_run(BASE, widths=(784, 112, 32, 10), pop=24, max_batch=200, seed=4)
+    x, y = batch(784, 200, 10, 12)
+    xs, ys = to_dev(x), to_dev(y)
+    big = torch.empty(200 * 784 + 1, dtype=torch.float32, device="cuda")
+    xu = big[1:].view(200, 784)
+    xu.copy_(xs)
+    assert xu.data_ptr() % 16 == 4
+    before = run.score(xs, ys)[0].clone()
+    for b in (3, 17, 200):
+        with pytest.raises(LeeaError) as e:
+            run.score(xu[:b], ys[:b])
+        assert e.value.status == 1 and "aligned" in str(e.value), b
+        with pytest.raises(LeeaError):
+            run.evaluate(xu[:b], ys[:b])
+    assert torch.equal(run.score(xs, ys)[0].view(torch.int32), before.view(torch.int32))
