@@ -860,6 +860,7 @@ static hipError_t launch_runs_eval_nt(int kind, int mw, int dt, int rt, const Ru
     return hipGetLastError();
   }
   if (kind == 1) {
+    if (rt == 2) return launch_runs_lfw(NT, mw, runs, st, g, s);
     if (mw == 1)
       return rt ? launch_runs_large<NT, 1, true>(runs, st, g, s)
                 : launch_runs_large<NT, 1, false>(runs, st, g, s);

@@ -33,6 +33,7 @@
 
 #include "lowp.hpp"
 #include "lp_common.hpp"
+#include "runs.hpp"
 
 namespace leea {
 
@@ -247,11 +248,12 @@ __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lpw_kernel(
 // batch rows past b are copies of row b - 1, which the register tail leaves
 // out of every sum.
 
+// Body of one workgroup: network j, row tile wt (rows 64 MW wt ...).
 template <int NT, int MW>
-__global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lfw_kernel(
-    const float* __restrict__ genomes, NetDesc nd, const float* __restrict__ x,
-    const int32_t* __restrict__ y, int b, float2* __restrict__ partial, int n_wt, int n_pt,
-    int pop) {
+__device__ __forceinline__ void eval_lfw_body(int j, int wt, const float* __restrict__ genomes,
+                                              const NetDesc& nd, const float* __restrict__ x,
+                                              const int32_t* __restrict__ y, int b,
+                                              float2* __restrict__ partial, int n_pt) {
   constexpr int S = lpw_stages(NT, MW);
   constexpr int RB = 64;                // bytes per staged row (16 floats)
   constexpr int MT = 64 * MW;           // rows per workgroup
@@ -272,9 +274,6 @@ __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lfw_kernel(
     else return st3;
   };
 
-  const int Lw = xcd_logical(blockIdx.x, n_wt * pop);
-  const int j = Lw / n_wt;
-  const int wt = Lw - j * n_wt;
   const int m0 = wt * MT;
   const float* __restrict__ genome = genomes + (int64_t)j * nd.stride;
   const int n0 = nd.w[0];
@@ -377,6 +376,31 @@ __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lfw_kernel(
                    ylab, reinterpret_cast<float*>(st0), partial + (int64_t)j * n_pt, m0 / 64);
 }
 
+template <int NT, int MW>
+__global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lfw_kernel(
+    const float* __restrict__ genomes, NetDesc nd, const float* __restrict__ x,
+    const int32_t* __restrict__ y, int b, float2* __restrict__ partial, int n_wt, int n_pt,
+    int pop) {
+  const int Lw = xcd_logical(blockIdx.x, n_wt * pop);
+  const int j = Lw / n_wt;
+  eval_lfw_body<NT, MW>(j, Lw - j * n_wt, genomes, nd, x, y, b, partial, n_pt);
+}
+
+// The grouped float32 runs whose networks this kernel takes (one launch per
+// class of equal column tiles and row tiles per wave).
+template <int NT, int MW>
+__global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void runs_eval_lfw_kernel(
+    const RunDesc* __restrict__ runs, const BatchState* __restrict__ st,
+    const int* __restrict__ off, const int* __restrict__ ids, int n, int total) {
+  const int L = xcd_logical(blockIdx.x, total);
+  const int i = find_group(off, n, L);
+  const RunDesc& d = runs[ids[i]];
+  const int local = L - off[i];
+  const int j = local / d.n_wt;
+  eval_lfw_body<NT, MW>(j, local - j * d.n_wt, d.genomes[st->cur], d.nd, d.xb, d.yb, d.b,
+                        d.partial, d.n_pt);
+}
+
 // ------------------------------------------------------------- dispatch --
 
 namespace {
@@ -444,6 +468,34 @@ hipError_t launch_lfw3(const float* genomes, const NetDesc& nd, int pop, const f
   return hipGetLastError();
 }
 }  // namespace
+
+namespace {
+template <int NT, int MW>
+hipError_t launch_runs_lfw3(const RunDesc* runs, const BatchState* st, const Group& g,
+                            hipStream_t s) {
+  hipLaunchKernelGGL((runs_eval_lfw_kernel<NT, MW>), dim3((unsigned)g.blocks), dim3(256), 0, s,
+                     runs, st, g.off, g.ids, g.n, g.blocks);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_runs_lfw(int nt, int mw, const RunDesc* runs, const BatchState* st,
+                           const Group& g, hipStream_t s) {
+  if (mw != 1 && mw != 2) return hipErrorInvalidValue;
+  switch (nt) {
+#define LEEA_RLFW_CASE(N)                                                  \
+  case N:                                                                  \
+    return mw == 2 ? launch_runs_lfw3<N, 2>(runs, st, g, s)                \
+                   : launch_runs_lfw3<N, 1>(runs, st, g, s);
+    LEEA_RLFW_CASE(1) LEEA_RLFW_CASE(2) LEEA_RLFW_CASE(3) LEEA_RLFW_CASE(4) LEEA_RLFW_CASE(5)
+    LEEA_RLFW_CASE(6) LEEA_RLFW_CASE(7) LEEA_RLFW_CASE(8) LEEA_RLFW_CASE(9) LEEA_RLFW_CASE(10)
+    LEEA_RLFW_CASE(11) LEEA_RLFW_CASE(12) LEEA_RLFW_CASE(13) LEEA_RLFW_CASE(14)
+    LEEA_RLFW_CASE(15) LEEA_RLFW_CASE(16)
+#undef LEEA_RLFW_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_evaluate_lfw(const float* genomes, const NetDesc& nd, int pop, const float* x,
                                const int32_t* y, int b, int mw, float2* partial, hipStream_t s) {

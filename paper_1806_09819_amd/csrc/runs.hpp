@@ -72,6 +72,10 @@ struct Group {
   size_t lds;      // dynamic LDS of the launch (max over its runs)
 };
 
+// Float32 large-batch runs on the global -> LDS kernel (every run of the
+// group taken by eval_lfw_supported; nt column tiles, mw row tiles per wave).
+hipError_t launch_runs_lfw(int nt, int mw, const RunDesc* runs, const BatchState* st,
+                           const Group& g, hipStream_t s);
 hipError_t launch_runs_draw(const RunDesc* runs, const BatchState* st, const Group& g,
                             const float* x_train, const int32_t* y_train, int64_t n_train,
                             int step, hipStream_t s);
@@ -81,7 +85,8 @@ hipError_t launch_runs_vary(const RunDesc* runs, const BatchState* st, const Gro
                             hipStream_t s);
 hipError_t launch_runs_quantize(const RunDesc* runs, const Group& g, hipStream_t s);
 // one evaluation class: every run of the group shares (kind, NT, MW, dt) and
-// rt, whether the large-batch kernels run its tail from registers
+// rt, whether the large-batch kernels run its tail from registers (1), and
+// for float32 also stage by global -> LDS copies (2)
 hipError_t launch_runs_eval(int kind, int nt, int mw, int dt, int rt, const RunDesc* runs,
                             const BatchState* st, const Group& g, hipStream_t s);
 hipError_t launch_runs_eval_lp(int nt, int mw, int dt, int rt, const RunDesc* runs,

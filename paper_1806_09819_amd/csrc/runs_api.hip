@@ -39,6 +39,14 @@ struct EvalClass {
   std::vector<int> runs;
 };
 
+// The large-batch kernels' tail and staging for one run: 0 the LDS-tile
+// epilogue, 1 the register tail, 2 the register tail on the float32 kernel
+// with global -> LDS staging (bitwise equal to 1 with register staging).
+int eval_tail_kind(int kind, int dt, const NetDesc& nd, int b, int mw, const float* xb) {
+  if ((kind != 1 && kind != 2) || !large_reg_tail(nd)) return 0;
+  return kind == 1 && dt == 0 && eval_lfw_supported(nd, b, mw, xb) ? 2 : 1;
+}
+
 }  // namespace
 
 struct leea_runs {
@@ -213,7 +221,7 @@ leea_status build_groups(leea_runs* m) {
     const RunDesc& d = m->desc[r];
     const int nt = (d.nd.w[1] + 15) / 16;
     const int mw = d.ekind == 0 ? 1 : d.emw;
-    const int rt = (d.ekind == 1 || d.ekind == 2) && large_reg_tail(d.nd) ? 1 : 0;
+    const int rt = eval_tail_kind(d.ekind, d.dt, d.nd, d.b, mw, d.xb);
     cls[std::make_tuple(d.ekind, nt, mw, d.dt, rt)].push_back(r);
   }
   m->classes.clear();
@@ -563,7 +571,7 @@ leea_status leea_runs_autotune(leea_runs* m, const float* x_train, const int32_t
         const int nt = (h.nd.w[1] + 15) / 16;
         for (int k = 0; k < 7 && !st; ++k) {
           if (k == 2) hipEventRecord(e0, m->stream);
-          const int rt = (sh.kind == 1 || sh.kind == 2) && large_reg_tail(h.nd) ? 1 : 0;
+          const int rt = eval_tail_kind(sh.kind, d.dt, h.nd, d.b, sh.kind == 0 ? 1 : sh.mw, d.xb);
           st = rdev(m, launch_runs_eval(sh.kind, nt, sh.kind == 0 ? 1 : sh.mw, d.dt, rt,
                                         m->d_desc, m->d_state, g, m->stream),
                     "evaluate");
