@@ -291,12 +291,98 @@ def test_plan_float32_inherited_fitness():
 
 # ------------------------------------------------------------- crossover ---
 
-def test_uniform_mask_layout_is_a_bijection():
-    c = 3 * 8192 + 1000
-    i = np.arange(c)
-    G, t, q, e = i >> 13, (i >> 8) & 31, (i >> 2) & 63, i & 3
-    key = ((G * 64 + q) * 4 + (t >> 3)) * 32 + 4 * (t & 7) + e
-    assert np.unique(key).size == c
+def _mask_with_words(monkeypatch, words_of_block, c, gen=5, slot=0):
+    """oracle.leea.uniform_mask with its generator replaced: block B's four
+    words are words_of_block(B).  The mask function is exercised as written;
+    only the random source is substituted."""
+    def fake_draw(seed, purpose, g, s, block, run=0):
+        assert purpose == philox.XO and g == gen and s == slot
+        block = np.atleast_1d(np.asarray(block, dtype=np.int64))
+        return np.stack([words_of_block(int(b)) for b in block]).astype(np.uint32)
+    monkeypatch.setattr(L.philox, "draw", fake_draw)
+    return L.uniform_mask(123, gen, slot, c)
+
+
+def _bit_words(k):
+    w = [0, 0, 0, 0]
+    w[k >> 5] = 1 << (k & 31)
+    return w
+
+
+def test_uniform_mask_uses_every_generator_bit_once(monkeypatch):
+    """Section 3.2: every gene of a uniform crossover is its own fair coin.
+    With a counter-based generator that holds iff no two genes read the
+    same bit of the same block.  The gene -> (block, bit) map is recovered
+    from the function itself: 128 calls light one bit position in every
+    block (each gene must light up in exactly one of them), 9 calls light
+    whole blocks by the bits of block + 1 (the gene's block).  The map must
+    be injective and use all 128 bits of every block of a full group."""
+    c = 2 * 8192 + 1000 + 3          # two full groups and a ragged third
+    n_blocks = 3 * 64
+    hits = np.zeros(c, dtype=np.int64)
+    bit_of = np.full(c, -1, dtype=np.int64)
+    for k in range(128):
+        m = _mask_with_words(monkeypatch, lambda b, k=k: _bit_words(k), c)
+        hits += m
+        bit_of[m] = k
+    assert np.all(hits == 1), "a gene reads no bit or more than one"
+    block_of = np.zeros(c, dtype=np.int64)
+    full = [0xFFFFFFFF] * 4
+    for r in range(9):
+        m = _mask_with_words(monkeypatch,
+                             lambda b, r=r: full if ((b + 1) >> r) & 1 else [0, 0, 0, 0], c)
+        block_of |= m.astype(np.int64) << r
+    block_of -= 1
+    assert np.all((block_of >= 0) & (block_of < n_blocks))
+    key = block_of * 128 + bit_of
+    assert np.unique(key).size == c, "two genes share a generator bit"
+    full_groups = key[:2 * 8192]
+    assert np.array_equal(np.sort(full_groups), np.arange(2 * 64 * 128)), \
+        "the blocks of a full 8192-gene group are not used bit for bit"
+    # the real generator through the recovered map (Philox itself is pinned
+    # by its published known-answer vectors)
+    monkeypatch.undo()
+    seed, gen, slot, run = 0x1234ABCD5678, 9, 17, 3
+    mask = L.uniform_mask(seed, gen, slot, c, run)
+    genes = np.array([0, 1, 2, 3, 4, 255, 256, 257, 1023, 4099, 8191, 8192, 12345, c - 1])
+    w = philox.philox4x32_10(block_of[genes], slot, gen, (run << 8) | philox.XO,
+                             seed & 0xFFFFFFFF, seed >> 32)
+    word = np.stack(w, axis=-1)[np.arange(genes.size), bit_of[genes] >> 5]
+    expect = (word >> (bit_of[genes] & 31).astype(np.uint32)) & 1
+    assert np.array_equal(mask[genes], expect.astype(bool))
+
+
+def test_uniform_mask_known_answer():
+    """A few genes worked out by hand from raw Philox words under the gene
+    layout the device uses (gene i = 8192 G + 256 t + 4 q + e reads bit
+    4 (t mod 8) + e of word t div 8 of block 64 G + q)."""
+    seed, gen, slot = 42, 3, 5
+    mask = L.uniform_mask(seed, gen, slot, 12000)
+    cases = {  # gene: (block, word, bit)
+        0: (0, 0, 0), 3: (0, 0, 3), 4: (1, 0, 0), 252: (63, 0, 0), 256: (0, 0, 4),
+        2047: (63, 0, 31), 2048: (0, 1, 0), 8191: (63, 3, 31), 8192: (64, 0, 0),
+        8192 + 256 * 9 + 4 * 2 + 1: (66, 1, 5)}
+    for i, (blk, wd, bit) in cases.items():
+        w = philox.philox4x32_10(blk, slot, gen, philox.XO, seed, 0)[wd]
+        assert bool((int(w) >> bit) & 1) == bool(mask[i]), i
+
+
+def test_uniform_mask_neighbouring_coins_independent():
+    """Fair, pairwise independent coins: neighbouring genes (distance 1, 2,
+    3, 4, 256) agree half the time (binomial z-test), and the 16 patterns of
+    four consecutive genes are uniform (chi-square)."""
+    c = 3 * 8192 * 4
+    masks = np.concatenate([L.uniform_mask(7, 11, s, c) for s in range(4)])
+    n = masks.size
+    assert abs(masks.sum() - n / 2) < 5 * math.sqrt(n / 4)
+    for d in (1, 2, 3, 4, 256):
+        agree = np.count_nonzero(masks[:-d] == masks[d:])
+        m = n - d
+        assert abs(agree - m / 2) < 5 * math.sqrt(m / 4), d
+    q = masks[: n - n % 4].reshape(-1, 4).astype(np.int64)
+    pat = q[:, 0] + 2 * q[:, 1] + 4 * q[:, 2] + 8 * q[:, 3]
+    cnt = np.bincount(pat, minlength=16)
+    assert stats.chisquare(cnt).pvalue > 1e-4
 
 
 def test_uniform_crossover_provenance_and_mask():
