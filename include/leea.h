@@ -90,9 +90,10 @@ enum { LEEA_SIGMA_CONSTANT = 0, LEEA_SIGMA_DECAY = 1, LEEA_SIGMA_SELF_ADAPTIVE =
  *       network a NaN fitness; such a W_1 gives its network a NaN fitness. */
 enum { LEEA_DT_F32 = 0, LEEA_DT_BF16 = 1, LEEA_DT_FP8 = 2 };
 
-/* Hyperparameters of one EA run.  Counts are integers: the caller rounds
- * the paper's fractions p_E*lambda, p_C*lambda, p_M*lambda and rho*lambda
- * (Algorithm 1); n_elite + n_cross + n_mut must equal pop. */
+/* Hyperparameters of one EA run.  Counts are integers: the paper's
+ * fractions p_E*lambda, p_C*lambda, p_M*lambda and rho*lambda (Algorithm 1)
+ * are rounded by leea_config_from_fractions (or by the caller);
+ * n_elite + n_cross + n_mut must equal pop. */
 typedef struct {
   int32_t n_layers;                       /* L >= 1 weight layers */
   int32_t widths[LEEA_MAX_LAYERS + 1];    /* widths[0] = input dim (multiple of 4),
@@ -120,6 +121,22 @@ typedef struct {
                                              with max_batch > 16 adds a bfloat16 copy of
                                              every W_1 to the workspace) */
 } leea_config;
+
+/* Host helper: fill the integer fields of cfg that Algorithm 1 writes as
+ * fractions of lambda (section 3.1), from cfg->pop, cfg->n_layers and
+ * cfg->widths, which the caller sets first:
+ *   n_elite = floor(p_elite*pop + 1/2), n_cross = floor(p_cross*pop + 1/2),
+ *   n_mut = pop - n_elite - n_cross (the three always sum to pop),
+ *   n_trunc = floor(rho*pop + 1/2) clamped to [1, pop] (truncation, rho*lambda);
+ * mut_threshold = floor(p_gene * 2^32) (a gene mutates iff its 32-bit draw is
+ * below it; p_gene = 1 mutates every gene, the paper's operator); and each
+ * layer's Glorot-uniform bound glorot_a[l] = sqrt(6 / (n_l + n_{l+1})) in
+ * double, rounded once to float (section 4.1); glorot_a past the last layer
+ * is zeroed.  All arithmetic is double precision on the host.  Fractions
+ * outside [0, 1] or p_elite + p_cross + p_mut further than 1e-9 from 1 give
+ * LEEA_EINVAL and leave cfg unchanged.  Touches no device. */
+leea_status leea_config_from_fractions(leea_config* cfg, double p_elite, double p_cross,
+                                       double p_mut, double rho, double p_gene);
 
 /* Genes per network (c) and the padded per-individual stride in floats. */
 leea_status leea_param_count(const leea_config* cfg, int64_t* genes, int64_t* stride);

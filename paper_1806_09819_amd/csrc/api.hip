@@ -17,7 +17,9 @@ namespace {
 
 enum State { kNeedEval = 0, kEvaluated = 1, kSelected = 2 };
 
-thread_local std::string g_err;
+// Message of the last failure of a call without a ctx: a fixed buffer, so
+// that reporting an error never allocates.
+thread_local char g_err[512];
 
 constexpr uint32_t kStateMagic = 0x4C454541u;  // checkpoint tag
 constexpr uint32_t kStateVersion = 2u;
@@ -80,23 +82,25 @@ struct leea_ctx {
 namespace {
 
 leea_status fail(leea_ctx* c, leea_status st, const char* fmt, const char* extra = nullptr) {
-  char buf[512];
-  snprintf(buf, sizeof buf, fmt, extra ? extra : "");
-  if (c)
+  if (c) {
+    char buf[512];
+    snprintf(buf, sizeof buf, fmt, extra ? extra : "");
     c->err = buf;
-  else
-    g_err = buf;
+  } else {
+    snprintf(g_err, sizeof g_err, fmt, extra ? extra : "");
+  }
   return st;
 }
 
 leea_status dev(leea_ctx* c, hipError_t e, const char* what) {
   if (e == hipSuccess) return LEEA_OK;
-  char buf[512];
-  snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
-  if (c)
+  if (c) {
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
     c->err = buf;
-  else
-    g_err = buf;
+  } else {
+    snprintf(g_err, sizeof g_err, "%s: %s", what, hipGetErrorString(e));
+  }
   return LEEA_EDEVICE;
 }
 
@@ -324,6 +328,41 @@ leea_status leea_param_count(const leea_config* cfg, int64_t* genes, int64_t* st
   if (st) return st;
   if (genes) *genes = nd.genes;
   if (stride) *stride = nd.stride;
+  return LEEA_OK;
+}
+
+leea_status leea_config_from_fractions(leea_config* cfg, double p_elite, double p_cross,
+                                       double p_mut, double rho, double p_gene) {
+  if (!cfg) return fail(nullptr, LEEA_EINVAL, "config is NULL");
+  const int L = cfg->n_layers;
+  if (L < 1 || L > LEEA_MAX_LAYERS) return fail(nullptr, LEEA_EINVAL, "n_layers must be 1..8");
+  if (cfg->pop < 1) return fail(nullptr, LEEA_EINVAL, "pop must be positive");
+  if (!(p_elite >= 0.0 && p_cross >= 0.0 && p_mut >= 0.0 && rho >= 0.0 && rho <= 1.0))
+    return fail(nullptr, LEEA_EINVAL, "fractions must be in [0, 1]");
+  if (fabs(p_elite + p_cross + p_mut - 1.0) > 1e-9)
+    return fail(nullptr, LEEA_EINVAL, "p_elite + p_cross + p_mut must equal 1");
+  if (!(p_gene >= 0.0 && p_gene <= 1.0)) return fail(nullptr, LEEA_EINVAL, "p_gene must be in [0, 1]");
+  const double pop = (double)cfg->pop;
+  const int64_t n_e = (int64_t)floor(p_elite * pop + 0.5);
+  const int64_t n_c = (int64_t)floor(p_cross * pop + 0.5);
+  const int64_t n_m = cfg->pop - n_e - n_c;
+  if (n_e < 0 || n_c < 0 || n_m < 0)
+    return fail(nullptr, LEEA_EINVAL, "counts do not fit the population");
+  int64_t n_r = (int64_t)floor(rho * pop + 0.5);
+  n_r = n_r < 1 ? 1 : (n_r > cfg->pop ? cfg->pop : n_r);
+  cfg->n_elite = (int32_t)n_e;
+  cfg->n_cross = (int32_t)n_c;
+  cfg->n_mut = (int32_t)n_m;
+  cfg->n_trunc = (int32_t)n_r;
+  // p * 2^32 is exact in double (a power-of-two scaling), so the floor is too
+  const double t = floor(p_gene * 4294967296.0);
+  cfg->mut_threshold = t >= 4294967296.0 ? (1ull << 32) : (uint64_t)t;
+  // widths are checked by every call that takes cfg; a bound whose fan sum
+  // is not positive is left at zero
+  for (int l = 0; l < LEEA_MAX_LAYERS; ++l) {
+    const double fan = l < L ? (double)cfg->widths[l] + (double)cfg->widths[l + 1] : 0.0;
+    cfg->glorot_a[l] = fan > 0.0 ? (float)sqrt(6.0 / fan) : 0.0f;
+  }
   return LEEA_OK;
 }
 
@@ -744,7 +783,7 @@ leea_status leea_load(leea_ctx* c, const void* host_buf, size_t bytes) {
   return LEEA_OK;
 }
 
-const char* leea_last_error(const leea_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
+const char* leea_last_error(const leea_ctx* c) { return c ? c->err.c_str() : g_err; }
 
 void leea_destroy(leea_ctx* c) { delete c; }
 
@@ -992,3 +1031,4 @@ leea_status leea_surrogate_views(leea_ctx* c, float** candidates, int32_t** plan
 }
 
 }  // extern "C"
+

@@ -7,9 +7,7 @@ module does not fall back to anything if it is missing.
 """
 
 import ctypes
-import math
 import os
-from fractions import Fraction
 
 import numpy as np
 import torch
@@ -81,6 +79,8 @@ def library():
     CP = ctypes.POINTER(Config)
     sig = {
         "leea_param_count": [CP, ctypes.POINTER(I64), ctypes.POINTER(I64)],
+        "leea_config_from_fractions": [CP, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double],
         "leea_workspace_bytes": [CP, ctypes.POINTER(ctypes.c_size_t)],
         "leea_init_population": [CP, P, ctypes.c_size_t, P, ctypes.POINTER(P)],
         "leea_draw_batch": [P, U32, P, P, I64, I32, P, P],
@@ -156,51 +156,49 @@ def _check(st, ctx=None):
 
 # ------------------------------------------------------------ host helpers --
 
+def _fractions_config(pop, widths, p_elite, p_cross, p_mut, rho, p_gene):
+    """A Config whose counts, mutation threshold and Glorot bounds come from
+    the library's leea_config_from_fractions (section 3.1 rounding)."""
+    widths = tuple(int(w) for w in widths)
+    L = len(widths) - 1
+    if not 1 <= L <= MAX_LAYERS:
+        raise ValueError("1..8 weight layers")
+    c = Config()
+    c.n_layers = L
+    for i, w in enumerate(widths):
+        c.widths[i] = w
+    c.pop = pop
+    st = library().leea_config_from_fractions(ctypes.byref(c), p_elite, p_cross, p_mut, rho,
+                                              p_gene)
+    if st != OK:
+        raise ValueError(library().leea_last_error(None).decode())
+    return c
+
+
 def counts(pop, p_elite, p_cross, p_mut, rho):
-    """Integer offspring counts from the paper's fractions (Algorithm 1):
-    round half up; mutants take the remainder; n_rho clamped to [1, pop]."""
-    if abs(p_elite + p_cross + p_mut - 1.0) > 1e-9:
-        raise ValueError("p_E + p_C + p_M must equal 1")
-    n_e = int(math.floor(p_elite * pop + 0.5))
-    n_c = int(math.floor(p_cross * pop + 0.5))
-    n_m = pop - n_e - n_c
-    if min(n_e, n_c, n_m) < 0:
-        raise ValueError("counts do not fit the population")
-    n_r = min(max(int(math.floor(rho * pop + 0.5)), 1), pop)
-    return n_e, n_c, n_m, n_r
+    """(n_elite, n_cross, n_mut, n_trunc) as the library rounds them."""
+    c = _fractions_config(pop, (4, 2), p_elite, p_cross, p_mut, rho, 1.0)
+    return c.n_elite, c.n_cross, c.n_mut, c.n_trunc
 
 
 def threshold(p_gene):
-    """32-bit mutation threshold floor(p * 2^32) (2^32 = every gene)."""
-    if not 0.0 <= p_gene <= 1.0:
-        raise ValueError("p_gene must be in [0, 1]")
-    return min(1 << 32, int(math.floor(Fraction(p_gene) * (1 << 32))))
+    """The library's 32-bit mutation threshold for a per-gene probability."""
+    return _fractions_config(1, (4, 2), 0.0, 0.0, 1.0, 1.0, p_gene).mut_threshold
 
 
 def make_config(widths, pop, p_elite=0.05, p_cross=0.50, p_mut=0.45, rho=0.5,
                 selection="truncation", tournament_k=2, crossover="uniform", sigma=0.001,
                 p_gene=1.0, alpha=1.0, seed=0, run=0, max_batch=512, sigma_mode="constant",
                 sigma_decay_k=1.0, tau=0.0, pool=0, eval_dtype="f32", **_ignored):
-    """leea_config from the paper's hyperparameters (fractions)."""
-    widths = tuple(int(w) for w in widths)
-    L = len(widths) - 1
-    if not 1 <= L <= MAX_LAYERS:
-        raise ValueError("1..8 weight layers")
-    n_e, n_c, n_m, n_r = counts(pop, p_elite, p_cross, p_mut, rho)
-    c = Config()
-    c.n_layers = L
-    for i, w in enumerate(widths):
-        c.widths[i] = w
-    c.pop, c.n_elite, c.n_cross, c.n_mut, c.n_trunc = pop, n_e, n_c, n_m, n_r
+    """leea_config from the paper's hyperparameters (fractions); the integer
+    counts, the mutation threshold and the Glorot bounds are filled in by the
+    library (leea_config_from_fractions)."""
+    c = _fractions_config(pop, widths, p_elite, p_cross, p_mut, rho, p_gene)
     c.selection = SEL[selection]
     c.tournament_k = tournament_k
     c.crossover = XO[crossover]
     c.sigma = sigma
     c.alpha = alpha
-    c.mut_threshold = threshold(p_gene)
-    for l in range(L):
-        # Glorot-uniform limit sqrt(6 / (fan_in + fan_out)), float64 -> float32
-        c.glorot_a[l] = float(np.float32(math.sqrt(6.0 / (widths[l] + widths[l + 1]))))
     c.seed = seed
     c.run = run
     c.max_batch = max_batch

@@ -59,12 +59,38 @@ def test_param_count_and_workspace(lib):
     assert n.value >= 2 * 1000 * 91904 * 4
 
 
-def test_host_counts_match_the_paper_settings():
+def test_host_counts_match_the_paper_settings(lib):
+    """leea_config_from_fractions (the library's section 3.1 rounding) against
+    the oracle's counts, mutation threshold and Glorot bounds."""
     for args in ((16, 0.05, 0.5, 0.45, 0.25), (1000, 0.05, 0.5, 0.45, 0.5),
                  (2000, 0.05, 0.75, 0.2, 0.5), (7, 0.1, 0.3, 0.6, 0.9)):
         assert B.counts(*args) == O.counts(*args)
-    for p in (0.0, 0.1, 0.5, 1.0, 0.3333):
+    for pop in range(1, 4097, 13):
+        for fr in ((0.05, 0.50, 0.45), (0.05, 0.75, 0.20), (0.1, 0.3, 0.6)):
+            for rho in (0.01, 0.25, 0.5, 1.0):
+                assert B.counts(pop, *fr, rho) == O.counts(pop, *fr, rho)
+    for p in (0.0, 0.1, 0.5, 1.0, 0.3333, 1 - 2 ** -40, 2 ** -33):
         assert B.threshold(p) == O.mutation_threshold(p)
+    for widths in ((784, 32, 10), (784, 112, 32, 10), (196, 256, 128, 64, 10)):
+        cfg = B.make_config(widths, 100)
+        for l in range(len(widths) - 1):
+            assert cfg.glorot_a[l] == O.glorot_bound(widths[l], widths[l + 1])
+        assert all(cfg.glorot_a[l] == 0.0 for l in range(len(widths) - 1, B.MAX_LAYERS))
+
+
+def test_config_from_fractions_rejects_bad_fractions(lib):
+    cfg = B.Config()
+    cfg.n_layers = 2
+    cfg.widths[0], cfg.widths[1], cfg.widths[2] = 784, 32, 10
+    cfg.pop = 16
+    before = bytes(cfg)
+    for args in ((0.5, 0.5, 0.5, 0.5, 1.0), (0.05, 0.5, 0.45, 1.5, 1.0),
+                 (0.05, 0.5, 0.45, 0.5, 1.5), (-0.1, 0.6, 0.5, 0.5, 1.0)):
+        assert lib.leea_config_from_fractions(ctypes.byref(cfg), *args) == B.EINVAL
+        assert lib.leea_last_error(None)
+    assert bytes(cfg) == before
+    cfg.pop = 0
+    assert lib.leea_config_from_fractions(ctypes.byref(cfg), 0.05, 0.5, 0.45, 0.5, 1.0) == B.EINVAL
 
 
 @pytest.mark.parametrize("field,value", [

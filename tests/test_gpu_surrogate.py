@@ -9,7 +9,8 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import FIT_ATOL, FIT_RTOL, F32, genomes_np, make_run, say, to_dev, to_np
+from gpu_helpers import (FIT_ATOL, FIT_RTOL, F32, check_fitness, genomes_np, make_run,
+                         oracle_eval, say, to_dev, to_np)
 from oracle import leea as O
 from oracle import surrogate as S
 from oracle.precision import round_bf16
@@ -108,6 +109,103 @@ def test_surrogate_teacher_forced_arithmetic_tournament():
                   crossover="arithmetic", selection="tournament", alpha=0.5, seed=5)
     used = _teacher_forced(params, gens=3, k=2, steps=2, lr=0.02, warmup=0, tau_min=0.0)
     assert len(used) == 3
+
+
+def test_surrogate_teacher_forced_configured_size():
+    """The surrogate's own configuration: 784-32-10, P = 1000, b = 64, k = 4,
+    so M = 4 * 950 = 3800 candidates of 25,450 genes, a 4096-key screen and
+    the projection split the launch takes at that size.  Two generations,
+    teacher-forced with the device's population, fitness and MLP parameters
+    (generation 1 keeps plain LEEA's mix, generation 2 screens): candidate
+    plan, screen (chosen set and order) and the gathered population
+    bit-exact in full; candidate genomes bit-exact on sampled candidates;
+    features on those, predictions on all 3800 within float32 bounds;
+    fitness of sampled networks within the fitness tolerance; Kendall tau
+    and the training step as in the small tests."""
+    params = dict(presets.SMALL, pop=1000, batch=64)
+    k, steps, lr, warmup, tau_min = 4, 2, 0.01, 1, -1.0
+    b = params["batch"]
+    run, ocfg = make_run(params, max_batch=b)
+    run.attach_surrogate(oversample=k, steps=steps, lr=lr, warmup=warmup, tau_min=tau_min)
+    widths = tuple(params["widths"])
+    g_genes = O.param_count(widths)
+    x, y = datagen.teacher_data(4000)
+    xd, yd = to_dev(x), to_dev(y)
+    R = S.projection_signs(g_genes, ocfg.seed, ocfg.run)
+    n_e, n_c, n_m, _ = O.counts(ocfg.pop, ocfg.p_elite, ocfg.p_cross, ocfg.p_mut, ocfg.rho)
+    N, M, kc = ocfg.pop - n_e, k * (ocfg.pop - n_e), k * n_c
+    assert (M, kc) == (3800, 2000)
+    thr = O.mutation_threshold(ocfg.p_gene)
+    rng = np.random.Generator(np.random.PCG64(11))
+    xb, yb = run.draw_batch(0, xd, yd, b)
+    f_adj, _, _ = run.evaluate(xb, yb)
+    for g in (1, 2):
+        say("configured-size surrogate generation", g)
+        f_prev = to_np(f_adj).copy()
+        pop_prev = genomes_np(run)
+        prm0 = to_np(run.surrogate_views()["params"]).copy()
+        xb, yb = run.draw_batch(g, xd, yd, b)
+        f_adj, f_raw, acc, stats = run.surrogate_step(xb, yb)
+        v = run.surrogate_views()
+        st = to_np(stats)
+        assert int(st[0]) == (0 if g == 1 else 1), (g, st)
+        order = O.rank(f_prev)
+        ops, p1, p2, _ = S.candidate_plan(order, f_prev, ocfg, g, k)
+        plan = to_np(v["plan"])
+        assert np.array_equal(plan[:, 0], ops) and np.array_equal(plan[:, 1], p1), g
+        assert np.array_equal(plan[:, 2], p2), g
+        cand = to_np(v["candidates"])[:, :g_genes]
+        sample = np.unique(np.concatenate([
+            [0, 1, kc - 1, kc, kc + 1, M - 2, M - 1],
+            rng.choice(M, 25, replace=False)]))
+        kids = np.stack([O._child(pop_prev, ops, p1, p2, ocfg, g, F32(ocfg.sigma), thr, int(c),
+                                  g_genes, slot=ocfg.pop + int(c)) for c in sample])
+        assert np.array_equal(cand[sample].view(np.uint32), kids.view(np.uint32)), g
+        X = S.features(kids, pop_prev[p1[sample]], f_prev[p1[sample]], f_prev[p2[sample]], R)
+        Xd_all = to_np(v["features"])[:, :S.INPUTS].astype(np.float64)
+        Xd = Xd_all[sample]
+        mag = (np.abs(round_bf16(kids).astype(np.float64)).sum(axis=1)
+               * float(S.scale(g_genes)))[:, None]
+        nchunks = (g_genes + 31) // 32
+        bound = (nchunks + 40) * U * mag + 2 * U * np.abs(X[:, :256]) + 1e-30
+        assert np.all(np.abs(Xd[:, :256] - X[:, :256]) <= bound), g
+        assert np.array_equal(Xd[:, 256:258], X[:, 256:258]), g
+        assert np.allclose(Xd[:, 258], X[:, 258], rtol=1e-5, atol=1e-9), g
+        prm = {"W1": prm0[:64 * 259].reshape(64, 259), "b1": prm0[64 * 259:64 * 260],
+               "w2": prm0[64 * 260:64 * 261], "b2": prm0[64 * 261]}
+        pred_o, _ = S.mlp_forward(prm, Xd_all)
+        pred = to_np(v["pred"]).astype(np.float64)
+        scl = np.abs(Xd_all) @ np.abs(prm["W1"].astype(np.float64)).T
+        pbound = 600 * U * (np.maximum(scl, 1e-30) @ np.abs(prm["w2"].astype(np.float64))) + 1e-6
+        assert np.all(np.abs(pred - pred_o) <= pbound), g
+        keep = S.screen(to_np(v["pred"]), N, bool(st[0]), k, n_c, n_m)
+        chosen = to_np(v["chosen"])
+        assert np.array_equal(chosen, keep), g
+        if g == 2:
+            assert not np.array_equal(keep, S.screen(None, N, False, k, n_c, n_m))
+        new = genomes_np(run)
+        assert np.array_equal(new[:n_e].view(np.uint32), pop_prev[order[:n_e]].view(np.uint32)), g
+        assert np.array_equal(new[n_e:].view(np.uint32), cand[chosen].view(np.uint32)), g
+        for i, c in enumerate(sample):
+            hit = np.nonzero(chosen == c)[0]
+            if hit.size:
+                assert np.array_equal(new[n_e + hit[0]].view(np.uint32), kids[i].view(np.uint32))
+        idx = O.batch_indices(ocfg.seed, g, b, x.shape[0], ocfg.run)
+        rows = np.unique(np.concatenate([[0, n_e - 1, n_e, ocfg.pop - 1],
+                                         rng.choice(ocfg.pop, 28, replace=False)]))
+        fo, acc_o, amb = oracle_eval(new[rows], widths, x[idx], y[idx])
+        check_fitness(to_np(f_raw)[rows], to_np(acc)[rows], fo, acc_o, amb, b,
+                      "configured surrogate gen%d" % g)
+        yk = to_np(f_raw)[n_e:].astype(np.float64)
+        cp = to_np(v["chosen_pred"]).astype(np.float64)
+        assert abs(S.kendall_tau_a(cp, yk) - float(st[1])) < 1e-6, g
+        p_o = prm
+        for _ in range(steps):
+            p_o = S.mlp_gradient_step(p_o, Xd_all[keep], yk, lr)
+        prm1 = to_np(v["params"]).astype(np.float64)
+        ref = np.concatenate([p_o["W1"].ravel(), p_o["b1"], p_o["w2"], [p_o["b2"]]])
+        assert np.allclose(prm1, ref, rtol=2e-4, atol=2e-6), (g, np.max(np.abs(prm1 - ref)))
+    run.close()
 
 
 def test_surrogate_report_small_config_at_scale():
