@@ -181,6 +181,30 @@ leea_status leea_evaluate(leea_ctx* ctx, const float* x, const int32_t* y, int32
 leea_status leea_score(leea_ctx* ctx, const float* x, const int32_t* y, int32_t n,
                        float* f_raw, float* acc);
 
+/* For callers that cannot allocate device memory or bring a workspace
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): leea_score without a ctx.  Fitness and accuracy (as
+ * leea_score computes them, bit for bit) of the cfg->pop networks in genomes
+ * (device, [pop][stride] floats in the layout above, 16-byte aligned; stride
+ * must be the one leea_param_count gives; padding genes are not read) on n
+ * examples x [n][widths[0]] (device, 16-byte aligned) and y [n] (device),
+ * into f_raw and acc (device [pop], either may be NULL), enqueued on
+ * hip_stream, which must belong to the current device.  Float32 first layer
+ * only (cfg->eval_dtype = LEEA_DT_F32).
+ * The per-network partial sums live in a static device array of
+ * LEEA_NOALLOC_SCRATCH_BYTES per device (131072 float pairs), held by every
+ * device the library runs on until the process ends: pop * ceil(n / 64)
+ * must not exceed 131072 (pop * 1 for n <= 16), else LEEA_EINVAL.  The call
+ * allocates nothing (the array's device address is looked up once per
+ * device, on the first call with that device current).  Every call on a
+ * device shares that device's array, so calls that overlap on one device
+ * (different streams or host threads) race; calls ordered on one stream do
+ * not.  Errors: leea_last_error(NULL). */
+#define LEEA_NOALLOC_SCRATCH_BYTES (1 << 20)
+leea_status leea_score_noalloc(const leea_config* cfg, const float* genomes, int64_t stride,
+                               const float* x, const int32_t* y, int32_t n, float* f_raw,
+                               float* acc, void* hip_stream);
+
 /* Sort by adjusted fitness (descending; ties by slot, -0 == +0, NaN last)
  * and plan the next generation (Algorithm 1, sort / elites / parent pairs /
  * mutation parents): slot j < n_elite copies rank j; the next n_cross slots

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -1032,3 +1033,78 @@ leea_status leea_surrogate_views(leea_ctx* c, float** candidates, int32_t** plan
 
 }  // extern "C"
 
+// ------------------------------------------- scoring without allocation --
+// leea_score_noalloc keeps the per-network partial sums of the evaluation in
+// this array instead of a workspace.  Each device holds its own copy; host
+// code reaches it only through the address hipGetSymbolAddress returns for
+// that device (the array's name is not a device address on the host side).
+
+namespace {
+
+constexpr size_t kScratchPartials = LEEA_NOALLOC_SCRATCH_BYTES / sizeof(float2);
+constexpr int kScratchDevices = 64;
+
+std::mutex g_scratch_mu;
+float2* g_scratch_ptr[kScratchDevices];  // per device, filled on first use
+
+}  // namespace
+
+static __device__ __align__(256) float2 scratch[kScratchPartials];
+
+namespace {
+
+// Device address of the current device's scratch array (looked up once per
+// device, with that device current).
+leea_status current_scratch(float2** out) {
+  int d = -1;
+  hipError_t e = hipGetDevice(&d);
+  if (e != hipSuccess) return dev(nullptr, e, "hipGetDevice");
+  if (d < 0 || d >= kScratchDevices) return fail(nullptr, LEEA_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[d]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return dev(nullptr, e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(nullptr, LEEA_EDEVICE, "scratch array has no device address");
+    g_scratch_ptr[d] = (float2*)p;
+  }
+  *out = g_scratch_ptr[d];
+  return LEEA_OK;
+}
+
+}  // namespace
+
+extern "C" leea_status leea_score_noalloc(const leea_config* cfg, const float* genomes,
+                                          int64_t stride, const float* x, const int32_t* y,
+                                          int32_t n, float* f_raw, float* acc,
+                                          void* hip_stream) {
+  NetDesc nd;
+  leea_status st = validate(cfg, &nd);
+  if (st) return st;
+  if (cfg->eval_dtype != LEEA_DT_F32)
+    return fail(nullptr, LEEA_EINVAL, "leea_score_noalloc evaluates a float32 first layer only");
+  if (!genomes || !aligned16(genomes))
+    return fail(nullptr, LEEA_EINVAL, "genomes must be a 16-byte aligned device pointer");
+  if (stride != nd.stride) return fail(nullptr, LEEA_EINVAL, "stride does not match the widths");
+  if (!x || !y) return fail(nullptr, LEEA_EINVAL, "x and y must be device pointers");
+  if (!aligned16(x)) return fail(nullptr, LEEA_EINVAL, "x must be 16-byte aligned");
+  if (n < 1 || n > LEEA_MAX_BATCH) return fail(nullptr, LEEA_EINVAL, "n must be in 1..65536");
+  const int n_mt = eval_mtiles(nd, n);
+  if ((size_t)cfg->pop * (size_t)n_mt > kScratchPartials)
+    return fail(nullptr, LEEA_EINVAL,
+                "pop * ceil(n / 64) exceeds the scratch of leea_score_noalloc (131072 partials)");
+  float2* part = nullptr;
+  st = current_scratch(&part);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  // every partial the finish reads is written by this call's evaluation
+  // first, so nothing needs clearing
+  const FinArgs fin{nullptr, nullptr, nullptr, nullptr, nullptr, f_raw, acc, 1.0f, 0, 1};
+  bool finalized = false;
+  st = dev(nullptr, launch_evaluate(genomes, nd, cfg->pop, x, y, n, part, s, &fin, &finalized),
+           "evaluate launch");
+  if (st || finalized) return st;
+  return dev(nullptr, launch_finalize(part, cfg->pop, n_mt, n, nullptr, 0, 1.0f, nullptr, nullptr,
+                                      nullptr, nullptr, f_raw, acc, s),
+             "finalize launch");
+}

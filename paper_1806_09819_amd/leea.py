@@ -104,6 +104,7 @@ def library():
         "leea_rng_philox": [P, U64, P, I64, P],
         "leea_rng_ln32": [P, P, I64, P],
         "leea_rng_normal_pairs": [P, P, I64, P],
+        "leea_score_noalloc": [CP, P, I64, P, P, I32, P, P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -405,6 +406,20 @@ class Leea:
     def load(self, buf):
         buf = np.ascontiguousarray(buf, dtype=np.uint8)
         _check(library().leea_load(self._ctx, buf.ctypes.data, buf.size), self._ctx)
+
+
+def score_noalloc(cfg, genomes, stride, x, y, f_raw=None, acc=None):
+    """leea_score_noalloc: fitness and accuracy of the population in genomes
+    ([pop, stride] float32 device tensor) on (x, y) without a ctx; partial
+    sums in the library's static device scratch (no allocation there)."""
+    pop = cfg.pop
+    if f_raw is None:
+        f_raw = torch.empty(pop, dtype=torch.float32, device=genomes.device)
+    if acc is None:
+        acc = torch.empty(pop, dtype=torch.float32, device=genomes.device)
+    _check(library().leea_score_noalloc(ctypes.byref(cfg), _ptr(genomes), stride, _ptr(x),
+                                        _ptr(y), x.shape[0], _ptr(f_raw), _ptr(acc), _stream()))
+    return f_raw, acc
 
 
 # ------------------------------------------------------ generator checks --
