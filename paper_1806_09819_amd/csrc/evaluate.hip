@@ -192,20 +192,34 @@ __global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void eval_small_kernel(const f
 }
 
 // ------------------------------------------------------- b <= 4, FP32 --
-// Layer 1 on the vector ALUs with W_1 streamed row by row: a wave takes rows
-// n = wave, wave + 4, ... and reads each in 1 KiB contiguous instructions
-// (lane l: elements 256 kb + 4 l .. + 3), against the batch held in
-// registers (MB rows padded to a power of two, up to 8; launched for b <= 4).  At
-// tiny batches the matrix cores multiply mostly padding and need the 16-row
-// fragment walk of W_1.  The rows are loaded non-temporally (each is read
-// once, by one wave): 74 -> 68 us at b = 1.  Measured per evaluation at
-// P = 1000, 784-112-32-10: 68 / 79 / 84 us at b = 1 / 4 / 8 against
-// 79 / 82 / 82 us for the small-batch kernel, so it takes b <= 4 only.
-// Each row's MB lane-partial sums are reduced over the wave by a
+// Layer 1 on the vector ALUs with W_1 streamed row by row.  The K range is
+// split in two halves (k < ka and k >= ka, ka = 4 floor(n0 / 8)); waves 0 and
+// 1 take the two halves of rows [0, R), waves 2 and 3 those of rows [R, n1)
+// (R = ceil(n1 / 2)), so every wave walks one contiguous block of W_1 (its
+// half-rows, 1 KiB contiguous per load instruction: lane l reads elements
+// 256 kb + 4 l .. + 3 of the half) with a ring of 4 half-rows in flight,
+// against the batch held in registers (MB rows padded to a power of two, up
+// to 4; the half-K split halves those registers).  Measured in the
+// generation loop at P = 1000, 784-112-32-10: 65 / 66 / 67 us at b = 1 / 2 / 4
+// against 72 / 101 / 87 us for whole rows taken by one wave with rows
+// interleaved across waves.  At tiny batches the matrix cores multiply mostly
+// padding and need the 16-row fragment walk of W_1, which streams slower.
+// Each half-row's MB lane-partial sums are reduced over the wave by a
 // reduce-scatter butterfly (halving the values at xor 32, 16, ... then
-// summing the last one), a fixed order.  Layer-1 activations go to the LDS
-// tile of the small-batch kernel, whose tail and fitness follow.
-constexpr int kStreamBlocks = 4;  // 256-float blocks per row: n0 <= 1024
+// summing the last one), a fixed order whose tree does not depend on MB; the
+// two half sums of a row meet in LDS (half 0 + half 1, then the bias), so
+// grouped runs that size the registers for 4 rows reproduce single runs bit
+// for bit.  Layer-1 activations go to the LDS tile of the small-batch
+// kernel, whose tail and fitness follow.  Rows are loaded non-temporally
+// (each is read once, by one wave).
+constexpr int kStreamBlocks = 2;  // 256-float blocks per half-row: n0 <= 1024
+
+// K split of the row-streaming kernel: floats of the first half.
+__host__ __device__ inline int stream_ka(int n0) { return 4 * (n0 / 8); }
+
+// Floats of LDS the row-streaming kernel uses past the tail layout: the two
+// half-row partial tiles [2][16][ld1].
+__host__ __device__ inline int stream_part_floats(const EvalLds& lo) { return 2 * 16 * lo.ld1; }
 
 template <int MB>
 __device__ __forceinline__ void eval_stream_body(int j, const float* __restrict__ genomes,
@@ -216,6 +230,7 @@ __device__ __forceinline__ void eval_stream_body(int j, const float* __restrict_
                                                  const FinArgs& fin) {
   extern __shared__ float lds[];
   constexpr int KB = kStreamBlocks;
+  constexpr int RF = 4;  // half-rows in flight per wave
   constexpr int LOG2MB = MB == 1 ? 0 : MB == 2 ? 1 : MB == 4 ? 2 : 3;
   static_assert((1 << LOG2MB) == MB, "MB is 1, 2, 4 or 8");
   const int tid = threadIdx.x;
@@ -226,10 +241,14 @@ __device__ __forceinline__ void eval_stream_body(int j, const float* __restrict_
   const float* __restrict__ b1 = genome + nd.boff[0];
   const int n0 = nd.w[0];
   const int n1 = nd.w[1];
-  const int kb_used = (n0 + 255) >> 8;
+  const int half = wave & 1;
+  const int ka = stream_ka(n0);
+  const int kbase = half ? ka : 0;
+  const int klen = half ? n0 - ka : ka;
   const bool hidden = nd.L > 1;
   const int ld1 = lo.ld1;
   float* h1 = lds + lo.h1;
+  float* part = lds + lo.total;  // [half][16][ld1]
   // the 16-row activation tile starts as zeros (padding rows and columns)
   for (int i = tid; i < 16 * ld1; i += 256) h1[i] = 0.0f;
 
@@ -239,44 +258,31 @@ __device__ __forceinline__ void eval_stream_body(int j, const float* __restrict_
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
       const int k = 256 * kb + 4 * lane;
-      xr[m][kb] = (m < b && k < n0) ? *reinterpret_cast<const float4*>(x + (int64_t)m * n0 + k)
-                                    : zero4();
+      xr[m][kb] = (m < b && k < klen)
+                      ? *reinterpret_cast<const float4*>(x + (int64_t)m * n0 + kbase + k)
+                      : zero4();
     }
-  // For MB = 2 the row loads are branch-free (blocks past n0, or past the
-  // used ones, re-read the row's first 16 bytes and are zeroed) and so is
-  // the main loop below (measured at b = 2: 81 -> 71 us; the same form is
-  // slower at b = 1, 66 -> 70 us, where its extra registers cost a
-  // workgroup per CU, and no faster at b = 4).
-  constexpr bool kBranchFree = MB == 2;
-  auto loadrow = [&](int n, float4 (&w)[KB], float& bias) {
-    const float* wr = W1 + (int64_t)n * n0;
+  const int rows_per = (n1 + 1) >> 1;
+  const int r0 = (wave >> 1) * rows_per;
+  const int R = r0 < n1 ? (n1 - r0 < rows_per ? n1 - r0 : rows_per) : 0;
+  auto loadrow = [&](int r, float4 (&w)[KB]) {
+    const float* wr = W1 + (int64_t)(r0 + r) * n0 + kbase;
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
       const int k = 256 * kb + 4 * lane;
-      if constexpr (kBranchFree) {
-        const bool in = kb < kb_used && k < n0;
-        const float4 v = load_once(wr + (in ? k : 0));
-        w[kb] = in ? v : zero4();
-      } else {
-        w[kb] = zero4();
-        if (kb < kb_used) {  // uniform
-          const float4 v = load_once(wr + (k < n0 ? k : 0));
-          if (k < n0) w[kb] = v;
-        }
+      w[kb] = zero4();
+      if (256 * kb < klen) {  // uniform
+        const float4 v = load_once(wr + (k < klen ? k : 0));
+        if (k < klen) w[kb] = v;
       }
     }
-    bias = b1[n];
   };
   __syncthreads();  // the zeroed tile before any row is written
 
-  // RF rows of this wave in flight: a ring of row buffers, the load of row
-  // r + RF issued as soon as row r has been multiplied
-  constexpr int RF = MB == 8 ? 3 : 4;
+  // ring of RF half-rows: the load of half-row r + RF is issued as soon as
+  // half-row r has been multiplied
   float4 w[RF][KB];
-  float bias[RF];
-  const int R = wave < n1 ? (n1 - wave + 3) >> 2 : 0;  // rows wave, wave + 4, ...
   auto row = [&](int r, int q, bool next) {
-    const int n = wave + 4 * r;
     float v[MB];
 #pragma unroll
     for (int m = 0; m < MB; ++m) v[m] = 0.0f;
@@ -289,19 +295,18 @@ __device__ __forceinline__ void eval_stream_body(int j, const float* __restrict_
         v[m] = fmaf(w[q][kb].z, xr[m][kb].z, v[m]);
         v[m] = fmaf(w[q][kb].w, xr[m][kb].w, v[m]);
       }
-    const float bq = bias[q];
-    if (next) loadrow(n + 4 * RF, w[q], bias[q]);
+    if (next) loadrow(r + RF, w[q]);
     // reduce-scatter: after the level with offset 32 >> lvl, a lane with
     // that bit set holds the upper half of the remaining values
 #pragma unroll
     for (int lvl = 0; lvl < LOG2MB; ++lvl) {
       const int off = 32 >> lvl;
-      const int half = MB >> (lvl + 1);
+      const int hv = MB >> (lvl + 1);
       const bool hi = (lane & off) != 0;
 #pragma unroll
-      for (int i = 0; i < half; ++i) {
-        const float mine = hi ? v[i + half] : v[i];
-        const float send = hi ? v[i] : v[i + half];
+      for (int i = 0; i < hv; ++i) {
+        const float mine = hi ? v[i + hv] : v[i];
+        const float send = hi ? v[i] : v[i + hv];
         v[i] = mine + __shfl_xor(send, off);
       }
     }
@@ -311,27 +316,24 @@ __device__ __forceinline__ void eval_stream_body(int j, const float* __restrict_
 #pragma unroll
     for (int lvl = 0; lvl < LOG2MB; ++lvl)
       if (lane & (32 >> lvl)) m += MB >> (lvl + 1);
-    if ((lane & (64 / MB - 1)) == 0 && m < b) {
-      float o = v[0] + bq;
-      if (hidden) o = relu_keep_nan(o);
-      h1[m * ld1 + n] = o;
-    }
+    if ((lane & (64 / MB - 1)) == 0 && m < b) part[(half * 16 + m) * ld1 + r0 + r] = v[0];
   };
 #pragma unroll
   for (int q = 0; q < RF; ++q)
-    if (q < R) loadrow(wave + 4 * q, w[q], bias[q]);
-  int r0 = 0;
-  if constexpr (kBranchFree) {
-    // whole groups whose next rows all exist, without a branch
-    for (; r0 + 2 * RF <= R; r0 += RF) {
-#pragma unroll
-      for (int q = 0; q < RF; ++q) row(r0 + q, q, true);
-    }
-  }
-  for (; r0 < R; r0 += RF) {
+    if (q < R) loadrow(q, w[q]);
+  for (int rb = 0; rb < R; rb += RF) {
 #pragma unroll
     for (int q = 0; q < RF; ++q)
-      if (r0 + q < R) row(r0 + q, q, r0 + q + RF < R);  // uniform
+      if (rb + q < R) row(rb + q, q, rb + q + RF < R);  // uniform
+  }
+  __syncthreads();
+  for (int idx = tid; idx < b * n1; idx += 256) {
+    const int m = idx / n1;
+    const int n = idx - m * n1;
+    float o = part[m * ld1 + n] + part[(16 + m) * ld1 + n];
+    o += b1[n];
+    if (hidden) o = relu_keep_nan(o);
+    h1[m * ld1 + n] = o;
   }
   __syncthreads();
   const float2 r = tail_and_fitness<1>(lds, lo, nd, genome, 0, 1, b, 0, y, tail_vec != 0,
@@ -606,9 +608,15 @@ static hipError_t launch_large(const float* genomes, const NetDesc& nd, int pop,
 
 // Row-streaming kernel for b <= 4: n0 a multiple of 4 and at most 1024.
 static constexpr int kStreamMaxRows = 4;
+static size_t stream_lds_bytes(const NetDesc& nd) {
+  const EvalLds lo = tail_layout(nd, 16);
+  return (size_t)(lo.total + stream_part_floats(lo)) * 4;
+}
+
 static bool stream_ok(const NetDesc& nd, int b) {
-  return b >= 1 && b <= kStreamMaxRows && nd.w[0] % 4 == 0 && nd.w[0] <= 256 * kStreamBlocks &&
-         small_lds_bytes(nd, nullptr) <= kMaxLds;
+  const int n0 = nd.w[0];
+  return b >= 1 && b <= kStreamMaxRows && n0 % 4 == 0 && n0 >= 8 &&
+         n0 - stream_ka(n0) <= 256 * kStreamBlocks && stream_lds_bytes(nd) <= kMaxLds;
 }
 
 static int stream_rows(int b) { return b <= 1 ? 1 : b <= 2 ? 2 : 4; }
@@ -618,8 +626,8 @@ static hipError_t launch_stream_mb(const float* genomes, const NetDesc& nd, int 
                                    const float* x, const int32_t* y, int b, float2* partial,
                                    hipStream_t s, const FinArgs& fin) {
   const int tv = tail_vectorizable(nd) ? 1 : 0;
-  const EvalLds lo = tail_layout(nd, 16);  // the activation tile and the tail buffers only
-  const size_t bytes = (size_t)lo.total * 4;
+  const EvalLds lo = tail_layout(nd, 16);  // the activation tile and the tail buffers
+  const size_t bytes = stream_lds_bytes(nd);      // + the half-row partial tiles
   hipError_t e = allow_lds(eval_stream_kernel<MB>, bytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((eval_stream_kernel<MB>), dim3((unsigned)pop), dim3(256), bytes, s, genomes,
@@ -745,7 +753,7 @@ bool eval_shape_f32(const NetDesc& nd, int b, int kind, int mw, EvalShape* out) 
     sh.n_pt = 1;
     sh.pass_rows = 16;
     sh.lo = tail_layout(nd, 16);
-    sh.lds = (size_t)sh.lo.total * 4;
+    sh.lds = stream_lds_bytes(nd);
   } else if (kind == 0) {
     if (b > 16) return false;
     sh.kind = 0;
