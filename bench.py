@@ -46,6 +46,9 @@ def workload(batch, eval_dtype="f32"):
 
 OPERAND_BYTES = {"f32": 4, "bf16": 2, "fp8": 1}
 
+# surrogate settings of the comparison run (leea_surrogate_config fields)
+SURROGATE = dict(oversample=4, steps=8, lr=0.01, warmup=2, tau_min=0.1)
+
 
 def algorithmic(params, genes, b):
     """Per-launch algorithmic FLOPs and HBM bytes of the evaluation kernel:
@@ -336,44 +339,265 @@ def multi_run_bench(x_train, y_train, steps=20, warmup=3, n=64):
     return out
 
 
-def cpu_baseline(params, b, min_seconds=12.0, max_gens=8):
-    """The oracle (numpy: float64 forward and fitness, float32 genetic
-    operators) running whole generations of the same workload -- rank, plan,
-    vary and evaluate every slot -- until at least min_seconds have passed
-    (at most max_gens generations)."""
-    from oracle import leea as O
-    from paper_1806_09819_amd import datagen
+def host_info():
+    """CPU model and the BLAS threads numpy runs with (threadpoolctl)."""
     import threadpoolctl
-
-    cfg = O.Config(**{k: v for k, v in params.items() if k in O.Config.__dataclass_fields__})
-    widths = tuple(params["widths"])
-    c = O.param_count(widths)
-    rng = np.random.Generator(np.random.PCG64(0))
-    pop = (rng.standard_normal((cfg.pop, c), dtype=np.float32) * np.float32(0.05))
-    f = rng.standard_normal(cfg.pop).astype(np.float32)
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     info = threadpoolctl.threadpool_info()
-    blas_threads = max([i.get("num_threads", 1) for i in info] or [1])
-    gens = 0
+    blas = max([i.get("num_threads", 1) for i in info] or [1])
+    return model, int(blas), len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(params, b, sample_pop=100, reps=3):
+    """The oracle (numpy: float64 forward and fitness, float32 genetic
+    operators) on a bounded sample of the same workloads.  Paper scale: a
+    population of `sample_pop` networks of the 784-112-32-10 workload with the
+    paper's fractions, initialised by the oracle's own Glorot-uniform init;
+    `evaluate` timed at b = 1, 8, 64, 512 and whole generations (rank, plan,
+    vary, evaluate) at batch b, with the vary step timed on its own.  Small
+    workload: all 10 generations of the 784-32-10 population of 16.  Throughput
+    is network-sample evaluations per second (networks * batch / time)."""
+    from oracle import leea as O
+    from paper_1806_09819_amd import datagen, presets
+
+    model, blas, host = host_info()
+    out = dict(unit="network-sample evals/s", cores=blas, kind="oracle", cpu_model=model,
+               host_cpus=host)
+    # paper scale, sampled population
+    cfg = O.Config(**{k: v for k, v in dict(params, pop=sample_pop).items()
+                      if k in O.Config.__dataclass_fields__})
+    widths = tuple(params["widths"])
     t0 = time.perf_counter()
-    while gens < max_gens:
-        g = gens + 1
-        x, y = datagen.prototype_data(b, seed=0, sample_seed=5 + g)
+    pop = O.init_population(cfg)
+    t_init = time.perf_counter() - t0
+    x_all, y_all = datagen.prototype_data(512 * (reps + 1), seed=0, sample_seed=5)
+    evals = {}
+    for bb in (1, 8, 64, 512):
+        ts = []
+        for r in range(reps):
+            xb, yb = x_all[r * 512:r * 512 + bb], y_all[r * 512:r * 512 + bb]
+            t = time.perf_counter()
+            O.evaluate(pop, widths, xb, yb)
+            ts.append(time.perf_counter() - t)
+        evals[bb] = float(np.median(ts))
+    f = O.evaluate(pop, widths, x_all[:b], y_all[:b])[0].astype(np.float32)
+    t_step, t_vary = [], []
+    for g in range(1, reps + 1):
+        xb, yb = x_all[g * 512:g * 512 + b], y_all[g * 512:g * 512 + b]
+        t = time.perf_counter()
         order = O.rank(f)
         ops, p1, p2, fi = O.plan(order, f, cfg, g)
+        tv = time.perf_counter()
         pop = O.vary(pop, ops, p1, p2, cfg, g)
-        f_raw, _ = O.evaluate(pop, widths, x, y)
+        t_vary.append(time.perf_counter() - tv)
+        f_raw, _ = O.evaluate(pop, widths, xb, yb)
         f = O.inherit(f_raw, fi, cfg.alpha).astype(np.float32)
-        gens += 1
-        if time.perf_counter() - t0 >= min_seconds:
-            break
-    t1 = time.perf_counter()
-    return dict(value=gens * cfg.pop * b / (t1 - t0), unit="network-sample evals/s",
-                cores=int(blas_threads), kind="oracle",
-                sample="%d whole generation(s) of the same workload (pop %d, batch %d, "
-                       "91,866-parameter nets): rank, plan, vary and evaluate every slot, "
-                       "%.1f s on the host; value = generations*pop*batch/s"
-                       % (gens, cfg.pop, b, t1 - t0),
-                host_cpus=len(os.sched_getaffinity(0)))
+        t_step.append(time.perf_counter() - t)
+    step = float(np.median(t_step))
+    out["value"] = sample_pop * b / step
+    out["paper_scale"] = dict(
+        networks=sample_pop, batch_for_step=b, init_s=t_init,
+        evaluate_evals_per_s={str(k): sample_pop * k / v for k, v in evals.items()},
+        step_s=step, step_gens_per_s_at_pop_1000=1.0 / (step * 1000 / sample_pop),
+        vary_s=float(np.median(t_vary)),
+        vary_children_per_s=sample_pop / float(np.median(t_vary)))
+    # small workload, every generation
+    sp = dict(presets.SMALL)
+    scfg = O.Config(**{k: v for k, v in sp.items() if k in O.Config.__dataclass_fields__})
+    sw = tuple(sp["widths"])
+    xs, ys = datagen.teacher_data(4000)
+    t = time.perf_counter()
+    spop = O.init_population(scfg)
+    idx = O.batch_indices(scfg.seed, 0, sp["batch"], xs.shape[0])
+    t_eval_small = []
+    te = time.perf_counter()
+    sf = O.evaluate(spop, sw, xs[idx], ys[idx])[0].astype(np.float32)
+    t_eval_small.append(time.perf_counter() - te)
+    for g in range(1, sp["generations"] + 1):
+        idx = O.batch_indices(scfg.seed, g, sp["batch"], xs.shape[0])
+        order = O.rank(sf)
+        ops, p1, p2, fi = O.plan(order, sf, scfg, g)
+        spop = O.vary(spop, ops, p1, p2, scfg, g)
+        te = time.perf_counter()
+        f_raw, _ = O.evaluate(spop, sw, xs[idx], ys[idx])
+        t_eval_small.append(time.perf_counter() - te)
+        sf = O.inherit(f_raw, fi, scfg.alpha).astype(np.float32)
+    t_small = time.perf_counter() - t
+    out["small_workload"] = dict(
+        generations=sp["generations"], seconds=t_small, gens_per_s=sp["generations"] / t_small,
+        evaluate_evals_per_s=sp["pop"] * sp["batch"] / float(np.median(t_eval_small)))
+    out["sample"] = ("paper-scale workload on a %d-network sample (oracle Glorot init, paper "
+                     "fractions): evaluate at b = 1/8/64/512 (median of %d) and %d whole "
+                     "generations at batch %d (rank, plan, vary, evaluate; value = networks * "
+                     "batch / step time); small workload: all %d generations of its population "
+                     "of 16" % (sample_pop, reps, reps, b, sp["generations"]))
+    return out
+
+
+def accuracy_runs(x_train, y_train, x_val, y_val, gens=1000, every=50, batch=512):
+    """The metric's second half: the paper-scale workload (784-112-32-10,
+    P = 1000, batch 512) run for `gens` generations with a float32, bfloat16
+    and FP8 first layer from the same seed.  Generations are timed alone
+    (validation scoring every `every` generations sits outside the timed
+    segments).  Reported per arithmetic: generations/s, the validation
+    accuracy (5000 held-out samples) of the rank-0 network and the
+    population's best after the last generation, and the generations and
+    seconds each needs to reach the float32 run's final rank-0 accuracy."""
+    import torch
+    from paper_1806_09819_amd import leea as B
+
+    out = {}
+    nv = x_val.shape[0]
+    for dt in ("f32", "bf16", "fp8"):
+        params = workload(batch, dt)
+        run = B.Leea(B.make_config(**dict(params, max_batch=max(batch, nv))))
+        xb = torch.empty((batch, params["widths"][0]), dtype=torch.float32, device="cuda")
+        yb = torch.empty((batch,), dtype=torch.int32, device="cuda")
+        run.draw_batch(0, x_train, y_train, batch, xb, yb)
+        run.evaluate(xb, yb)
+        traj, t_gen = [], 0.0
+        for g0 in range(1, gens + 1, every):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for g in range(g0, min(g0 + every, gens + 1)):
+                run.draw_batch(g, x_train, y_train, batch, xb, yb)
+                run.step(xb, yb, outputs=False)
+            torch.cuda.synchronize()
+            t_gen += time.perf_counter() - t
+            _, acc = run.score(x_val, y_val)
+            _, f_adj = run.population()
+            best = int(torch.argmax(torch.nan_to_num(f_adj, nan=-np.inf)).item())
+            a = acc.cpu().numpy()
+            traj.append((min(g0 + every - 1, gens), t_gen, float(a[best]), float(a.max())))
+        run.close()
+        out[dt] = dict(gens_per_s=gens / t_gen, val_acc_rank0=traj[-1][2],
+                       val_acc_best=traj[-1][3],
+                       trajectory=[[g, round(t, 4), round(a0, 4), round(ab, 4)]
+                                   for g, t, a0, ab in traj],
+                       _raw=[(g, t, a0) for g, t, a0, _ in traj])
+    target = out["f32"]["val_acc_rank0"]
+    for dt, r in out.items():
+        hit = [(g, t) for g, t, a0 in r.pop("_raw") if a0 >= target]
+        r["gens_to_f32_final_acc"] = hit[0][0] if hit else None
+        r["seconds_to_f32_final_acc"] = hit[0][1] if hit else None
+    out["matched_accuracy_target"] = target
+    out["workload"] = ("784-112-32-10, P = 1000, batch %d, %d generations, paper defaults, "
+                       "prototype data (45k train, 5k validation)" % (batch, gens))
+    return out
+
+
+def surrogate_vs_plain(gens=400, data_kind="teacher", k=4, batch=64, seed_run=None):
+    """The surrogate's workload (784-32-10 with the small workload's operators,
+    P = 1000, batch 64, 4x over-generated offspring) run with plain LEEA and
+    with the pre-screening surrogate from the same seed: generations/s, the
+    rank-0 network's validation accuracy, and the surrogate's screening
+    (generations screened, mean Kendall tau over the last quarter)."""
+    import torch
+    from paper_1806_09819_amd import datagen, presets
+    from paper_1806_09819_amd import leea as B
+
+    data = datagen.splits(data_kind, sizes=(45000, 5000, 0))
+    xt, yt = torch.from_numpy(data["x_train"]).cuda(), torch.from_numpy(data["y_train"]).cuda()
+    xv, yv = torch.from_numpy(data["x_val"]).cuda(), torch.from_numpy(data["y_val"]).cuda()
+    params = dict(presets.SMALL, pop=1000, batch=batch)
+    res = {}
+    for mode in ("plain", "surrogate"):
+        run = B.Leea(B.make_config(**dict(params, max_batch=xv.shape[0])))
+        if mode == "surrogate":
+            run.attach_surrogate(**SURROGATE)
+        xb = torch.empty((batch, 784), dtype=torch.float32, device="cuda")
+        yb = torch.empty((batch,), dtype=torch.int32, device="cuda")
+        run.draw_batch(0, xt, yt, batch, xb, yb)
+        run.evaluate(xb, yb)
+        stats = []
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for g in range(1, gens + 1):
+            run.draw_batch(g, xt, yt, batch, xb, yb)
+            if mode == "surrogate":
+                stats.append(run.surrogate_step(xb, yb)[3])
+            else:
+                run.step(xb, yb, outputs=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        _, acc = run.score(xv, yv)
+        _, f_adj = run.population()
+        best = int(torch.argmax(torch.nan_to_num(f_adj, nan=-np.inf)).item())
+        r = dict(gens_per_s=gens / dt, val_acc_rank0=float(acc[best].item()),
+                 val_acc_best=float(acc.max().item()))
+        if stats:
+            st = torch.stack(stats).cpu().numpy()
+            q = max(1, gens // 4)
+            r.update(screened_generations=int(st[:, 0].sum()),
+                     tau_last_quarter=float(st[-q:, 1].mean()),
+                     rmse_last_quarter=float(st[-q:, 2].mean()))
+        res[mode] = r
+        run.close()
+    res["workload"] = ("784-32-10, P = 1000, batch %d, sigma 0.01, p_gene 0.1, truncation top "
+                       "25 %%, %s data, %d generations; surrogate: %d x offspring, %s"
+                       % (batch, data_kind, gens, k, SURROGATE))
+    return res
+
+
+def small_workload(steps=2000, warmup=50):
+    """The small workload (784-32-10, P = 16, batch 32, its operators), which
+    is launch-latency bound: microseconds per generation through leea_step
+    (draw + step, eager launches) and through a one-run group replayed from a
+    captured HIP graph (leea_runs)."""
+    import torch
+    from paper_1806_09819_amd import datagen, presets
+    from paper_1806_09819_amd import leea as B
+
+    p = dict(presets.SMALL)
+    b = p["batch"]
+    x, y = datagen.teacher_data(45000)
+    xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    run = B.Leea(B.make_config(**dict(p, max_batch=b)))
+    lib = B.library()
+    xb = torch.empty((b, 784), dtype=torch.float32, device="cuda")
+    yb = torch.empty((b,), dtype=torch.int32, device="cuda")
+    run.draw_batch(0, xt, yt, b, xb, yb)
+    run.evaluate(xb, yb)
+    P = B._ptr
+
+    def gen(g):
+        st = lib.leea_draw_batch(run._ctx, g, P(xt), P(yt), xt.shape[0], b, P(xb), P(yb))
+        st = st or lib.leea_step(run._ctx, P(xb), P(yb), b, None, None, None)
+        if st:
+            raise B.LeeaError(st, lib.leea_last_error(run._ctx).decode())
+
+    for g in range(1, warmup + 1):
+        gen(g)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for g in range(warmup + 1, warmup + 1 + steps):
+        gen(g)
+    torch.cuda.synchronize()
+    eager = (time.perf_counter() - t) / steps
+    run.close()
+    runs = B.Runs([B.make_config(**dict(p, max_batch=b))])
+    runs.generation(xt, yt)
+    for _ in range(warmup):
+        runs.generation(xt, yt)
+    runs.sync()
+    t = time.perf_counter()
+    for _ in range(steps):
+        runs.generation(xt, yt)
+    runs.sync()
+    graph = (time.perf_counter() - t) / steps
+    runs.close()
+    return dict(workload="784-32-10, P = 16, batch 32, sigma 0.01, p_gene 0.1, truncation "
+                         "top 25 %, teacher data",
+                eager_us_per_gen=eager * 1e6, eager_gens_per_s=1.0 / eager,
+                graph_us_per_gen=graph * 1e6, graph_gens_per_s=1.0 / graph,
+                evals_per_s_graph=p["pop"] * b / graph)
 
 
 def main():
@@ -387,6 +611,10 @@ def main():
     ap.add_argument("--sweep-steps", type=int, default=50)
     ap.add_argument("--no-multi-run", action="store_true",
                     help="skip the 64 uneven runs measurement")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the f32 / bf16 / fp8 accuracy runs and the surrogate comparison")
+    ap.add_argument("--accuracy-gens", type=int, default=1000)
+    ap.add_argument("--no-small", action="store_true", help="skip the small workload")
     ap.add_argument("--eval-dtype", default="f32", choices=("f32", "bf16", "fp8"),
                     help="arithmetic of the first layer (bf16 / fp8: reduced-precision variants)")
     ap.add_argument("--fused", action="store_true",
@@ -415,9 +643,11 @@ def main():
     from paper_1806_09819_amd import datagen
 
     torch.cuda.init()
-    data = datagen.splits("prototypes", sizes=(45000, 0, 0))
+    data = datagen.splits("prototypes", sizes=(45000, 5000, 0))
     x_train = torch.from_numpy(data["x_train"]).cuda()
     y_train = torch.from_numpy(data["y_train"]).cuda()
+    x_val = torch.from_numpy(data["x_val"]).cuda()
+    y_val = torch.from_numpy(data["y_val"]).cuda()
 
     params = workload(args.batch, args.eval_dtype)
     log("bench: timed run, batch", args.batch)
@@ -469,6 +699,15 @@ def main():
     if not args.no_multi_run:
         log("bench: 64 uneven runs")
         line["multi_run"] = multi_run_bench(x_train, y_train)
+    if not args.no_small:
+        log("bench: small workload")
+        line["small_workload"] = small_workload()
+    if not args.no_accuracy:
+        log("bench: accuracy runs (f32 / bf16 / fp8)")
+        line["accuracy"] = accuracy_runs(x_train, y_train, x_val, y_val, gens=args.accuracy_gens)
+        log("bench: surrogate vs plain")
+        line["surrogate"] = {kind: surrogate_vs_plain(data_kind=kind)
+                             for kind in ("teacher", "prototypes")}
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(params, b)

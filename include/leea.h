@@ -295,14 +295,18 @@ void leea_destroy(leea_ctx* ctx);
  * streams, section 3.2 operators); each is described by 256 +-1 random
  * projections of its bfloat16-rounded genome (times 1/sqrt(genes)), its
  * parents' adjusted fitness and its distance to parent 1 (times
- * 1/sqrt(genes)); a 259-64-1 MLP predicts its fitness and the best
- * pop - n_elite predictions fill the other slots.  The new population is
- * evaluated as usual (Eq. 1), which judges the MLP (Kendall tau-a and RMSE
- * of its predictions for the kept candidates) and trains it (`steps`
- * full-batch gradient steps on the squared error against the raw
- * fitness).  Until the MLP has trained for `warmup` generations and the
- * previous generation's tau reached tau_min, the first n_cross crossover
- * and n_mut mutation candidates are kept instead (plain LEEA's mix). */
+ * 1/sqrt(genes)); every feature is standardised over the generation's
+ * candidates (minus its mean, divided by its standard deviation, 0 where it
+ * does not vary); a 259-64-1 MLP predicts each candidate's standardised
+ * fitness and the best pop - n_elite predictions fill the other slots.  The
+ * new population is evaluated as usual (Eq. 1), which judges the MLP
+ * (Kendall tau-a of its predictions for the kept candidates against their
+ * fitness, RMSE against the training targets) and trains it (`steps`
+ * full-batch gradient steps on the squared error against the kept
+ * candidates' raw fitness standardised over them).  Until the MLP has
+ * trained for `warmup` generations and the previous generation's tau reached
+ * tau_min, the first n_cross crossover and n_mut mutation candidates are
+ * kept instead (plain LEEA's mix). */
 typedef struct {
   int32_t oversample;  /* k, 1..64; k * (pop - n_elite) <= 8192 */
   int32_t steps;       /* gradient steps per generation, 0..1000 */
@@ -329,11 +333,12 @@ leea_status leea_surrogate_step(leea_ctx* ctx, const float* x, const int32_t* y,
 
 /* Borrowed device views of the last surrogate step (any may be NULL):
  * candidates [n][stride], their plan [n][4] {op, parent 1, parent 2, 0},
- * features [n][260] (259 used), predictions [n], kept candidate indices
- * [pop - n_elite] and their predictions, MLP parameters (W1 [64][259], b1
- * [64], w2 [64], b2); *n_candidates = n. */
+ * features [n][260] (259 used), the MLP's standardised inputs [n][260],
+ * predictions [n], kept candidate indices [pop - n_elite] and their
+ * predictions, MLP parameters (W1 [64][259], b1 [64], w2 [64], b2);
+ * *n_candidates = n. */
 leea_status leea_surrogate_views(leea_ctx* ctx, float** candidates, int32_t** plan,
-                                 float** features, float** pred, int32_t** chosen,
+                                 float** features, float** inputs, float** pred, int32_t** chosen,
                                  float** chosen_pred, float** params, int32_t* n_candidates);
 
 /* ---- Many independent runs driven together -----------------------------

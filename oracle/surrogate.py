@@ -13,12 +13,20 @@ cheap predictions instead of evaluations:
   (256 rows of +-1 signs, the genome rounded to bfloat16, times 1/sqrt(g)
   for g genes), its parents' adjusted fitness, and its distance to parent 1
   (Euclidean, times 1/sqrt(g));
-* a two-layer MLP (259 -> 64 ReLU -> 1) predicts each candidate's fitness;
-  the P - n_E best predictions (descending, ties by candidate index, NaN
-  last) fill the non-elite slots in that order;
+* the MLP sees every feature standardised over the generation's candidates
+  (minus its mean over them, divided by its standard deviation; a feature
+  that does not vary is 0): the projections of children of similar parents
+  differ from each other far less than from zero, and the parents' fitness
+  drifts from generation to generation, so raw values would leave the MLP
+  chasing a moving offset;
+* a two-layer MLP (259 -> 64 ReLU -> 1) predicts each candidate's
+  standardised fitness; the P - n_E best predictions (descending, ties by
+  candidate index, NaN last) fill the non-elite slots in that order;
 * the new population is evaluated as usual (its fitness judges the
   surrogate), and the MLP takes full-batch gradient steps on the mean
-  squared error between its predictions and those fitness values;
+  squared error between its predictions and those fitness values
+  standardised over the kept candidates (a ranking is all the screen uses,
+  and it does not change under that affine map);
 * until the MLP has trained for `warmup` generations and its Kendall tau
   (tau-a) between predicted and evaluated fitness in the previous
   generation reaches tau_min, the pre-screening is off and the first n_C
@@ -74,6 +82,31 @@ def features(children, parents1, f_p1, f_p2, R):
     nu = np.sqrt(np.sum(d * d, axis=1)) * s
     return np.concatenate([proj, np.asarray(f_p1, dtype=np.float64)[:, None],
                            np.asarray(f_p2, dtype=np.float64)[:, None], nu[:, None]], axis=1)
+
+
+def standardize(X):
+    """Each column minus its mean over the rows, divided by its standard
+    deviation (over the rows, no Bessel correction); a column whose standard
+    deviation is 0 becomes 0 (float64)."""
+    X = np.asarray(X, dtype=np.float64)
+    mu = X.mean(axis=0)
+    sd = np.sqrt(((X - mu) ** 2).mean(axis=0))
+    safe = np.where(sd > 0, sd, 1.0)
+    return np.where(sd > 0, (X - mu) / safe, 0.0)
+
+
+def standardize_targets(y):
+    """Training targets: the finite entries minus their mean, divided by their
+    standard deviation (1 if it is 0); non-finite entries stay as they are
+    (the gradient step leaves them out)."""
+    y = np.asarray(y, dtype=np.float64)
+    ok = np.isfinite(y)
+    if not ok.any():
+        return y.copy()
+    mu = y[ok].mean()
+    sd = math.sqrt(((y[ok] - mu) ** 2).mean())
+    sd = sd if sd > 0 else 1.0
+    return np.where(ok, (y - mu) / sd, y)
 
 
 def init_mlp(seed, run=0):

@@ -67,6 +67,8 @@ struct leea_ctx {
   float* snu;
   float* spart;
   float* sfeat;
+  float* szfeat;   // standardised features (the MLP's inputs)
+  float* sytgt;    // standardised fitness of the kept candidates (training targets)
   float* spred;
   int32_t* schosen;
   float* schosen_pred;
@@ -192,12 +194,12 @@ struct Carve {
 int padded_k(int n0) { return (n0 + 31) & ~31; }
 int round128(int v) { return (v + 127) & ~127; }
 
-// bfloat16 W_1 copy: kept when batches above 16 rows can reach the
-// large-batch bfloat16 kernel that reads it (W_1 below 2^24 genes, and the
-// shapes that kernel takes)
+// bfloat16 W_1 copy, read by the bfloat16 evaluation kernels at every batch
+// size (small batches: half the bytes of the float32 W_1 they would stream
+// otherwise); kept when W_1 has fewer than 2^24 genes (the variation kernel
+// finds a gene's row with a float reciprocal)
 bool uses_shadow(const leea_config* cfg, const NetDesc& nd) {
-  return cfg->eval_dtype == LEEA_DT_BF16 && cfg->max_batch > 16 &&
-         (int64_t)nd.w[0] * nd.w[1] < (1 << 24) && eval_lpw_supported(nd, cfg->max_batch);
+  return cfg->eval_dtype == LEEA_DT_BF16 && (int64_t)nd.w[0] * nd.w[1] < (1 << 24);
 }
 int64_t shadow_net(const NetDesc& nd) {
   return (int64_t)padded_k(nd.w[0]) * ((nd.w[1] + 15) & ~15);
@@ -242,6 +244,17 @@ leea_status check_batch(leea_ctx* c, const float* x, const int32_t* y, int32_t b
   return LEEA_OK;
 }
 
+// The bfloat16 copy of W_1, rebuilt first if the population changed other
+// than through the variation kernel.
+leea_status shadow_ready(leea_ctx* c) {
+  if (!c->wsh.p || c->wsh_ok) return LEEA_OK;
+  leea_status st = dev(c, launch_shadow_w1(c->genomes[c->cur], c->nd, c->cfg.pop, c->wsh,
+                                           c->stream),
+                       "W1 copy launch");
+  if (!st) c->wsh_ok = 1;
+  return st;
+}
+
 // Reduced-precision first layer: batch amax (FP8), the quantised batch, then
 // the small-batch kernel on quantised values (b <= 16) or the bf16 / FP8
 // matrix-core kernel.  Returns the number of partial row tiles.
@@ -256,14 +269,9 @@ leea_status run_eval_lp(leea_ctx* c, const float* x, const int32_t* y, int32_t b
   }
   const bool small = b <= 16;
   if (!small && c->wsh.p && eval_lpw_supported(c->nd, b)) {
-    // large batch from the bfloat16 W_1 copy (rebuilt if the population
-    // changed other than through crossover_mutate)
-    if (!c->wsh_ok) {
-      st = dev(c, launch_shadow_w1(c->genomes[c->cur], c->nd, c->cfg.pop, c->wsh, c->stream),
-               "W1 copy launch");
-      if (st) return st;
-      c->wsh_ok = 1;
-    }
+    // large batch from the bfloat16 W_1 copy
+    st = shadow_ready(c);
+    if (st) return st;
     const int bpad = round128(b);
     st = dev(c, launch_quantize_x_chunks(x, b, n0, c->kp, bpad, (uint16_t*)c->xq, c->stream),
              "quantize launch");
@@ -297,11 +305,18 @@ leea_status run_eval(leea_ctx* c, const float* x, const int32_t* y, int32_t b, b
   int n_mt = 1;
   leea_status st;
   const int use_inh = update && c->has_inh && c->cfg.alpha != 1.0f;
+  // batches of up to 16 rows: the evaluation kernel finishes each network
+  // itself (no finalize launch)
+  const FinArgs fin{c->f_inh, update ? c->f_adj : nullptr, update ? c->f_raw : nullptr,
+                    update ? c->acc : nullptr, f_adj, f_raw, acc, c->cfg.alpha, use_inh, 1};
+  if (c->dt == LEEA_DT_BF16 && b <= 16) {
+    st = shadow_ready(c);
+    if (st) return st;
+    return dev(c, launch_evaluate_small_bf16(c->genomes[c->cur], c->nd, c->cfg.pop, c->wsh, x, y,
+                                             b, c->partial, c->stream, fin),
+               "evaluate launch");
+  }
   if (c->dt == LEEA_DT_F32) {
-    // batches of up to 16 rows: the evaluation kernel finishes each network
-    // itself (no finalize launch)
-    const FinArgs fin{c->f_inh, update ? c->f_adj : nullptr, update ? c->f_raw : nullptr,
-                      update ? c->acc : nullptr, f_adj, f_raw, acc, c->cfg.alpha, use_inh, 1};
     bool finalized = false;
     st = dev(c, launch_evaluate(c->genomes[c->cur], c->nd, c->cfg.pop, x, y, b, c->partial,
                                 c->stream, &fin, &finalized),
@@ -864,7 +879,7 @@ leea_status sur_carve(const leea_config* cfg, const leea_surrogate_config* sc, c
   c.prm = align256((size_t)kSurParams * 4);
   c.pre = align256((size_t)c.N * kSurHid * 4);
   c.st = 256;
-  c.total = c.cand + c.cplan + 2 * c.m4 + c.nu + c.part + c.feat + 3 * c.n4 + c.bits + 2 * c.prm +
+  c.total = c.cand + c.cplan + 2 * c.m4 + c.nu + c.part + 2 * c.feat + 4 * c.n4 + c.bits + 2 * c.prm +
             c.pre + 2 * c.st;
   *o = c;
   return LEEA_OK;
@@ -919,6 +934,10 @@ leea_status leea_surrogate_attach(leea_ctx* c, const leea_surrogate_config* sc, 
   p += v.part;
   c->sfeat = (float*)p;
   p += v.feat;
+  c->szfeat = (float*)p;
+  p += v.feat;
+  c->sytgt = (float*)p;
+  p += v.n4;
   c->schosen = (int32_t*)p;
   p += v.n4;
   c->schosen_pred = (float*)p;
@@ -980,8 +999,9 @@ leea_status leea_surrogate_step(leea_ctx* c, const float* x, const int32_t* y, i
     st = dev(c, launch_features(c->spart, c->ssplits, c->sM, c->snu, c->sngroups, c->scplan,
                                 c->f_adj, scale, c->sfeat, s),
              "features");
+  if (!st) st = dev(c, launch_standardize(c->sfeat, c->sM, c->szfeat, s), "standardise");
   if (!st)
-    st = dev(c, launch_mlp_forward(c->sprm, c->sfeat, nullptr, c->sM, nullptr, c->spred, s),
+    st = dev(c, launch_mlp_forward(c->sprm, c->szfeat, nullptr, c->sM, nullptr, c->spred, s),
              "prediction");
   if (!st)
     st = dev(c, launch_screen(c->spred, c->sM, c->sN, c->snc, c->skc, c->sstate, c->schosen,
@@ -1002,11 +1022,13 @@ leea_status leea_surrogate_step(leea_ctx* c, const float* x, const int32_t* y, i
   if (st) return st;
   c->state = kEvaluated;
   const float* yk = c->f_raw + g.n_elite;
-  st = dev(c, launch_surrogate_judge(c->schosen_pred, yk, c->sN, c->sc.warmup, c->sc.tau_min,
-                                     c->sstate, c->sstats, s),
-           "surrogate judge");
+  st = dev(c, launch_targets(yk, c->sN, c->sytgt, s), "training targets");
+  if (!st)
+    st = dev(c, launch_surrogate_judge(c->schosen_pred, yk, c->sytgt, c->sN, c->sc.warmup,
+                                       c->sc.tau_min, c->sstate, c->sstats, s),
+             "surrogate judge");
   for (int k = 0; k < c->sc.steps && !st; ++k)
-    st = dev(c, launch_mlp_train_step(c->sprm, c->sfeat, c->schosen, c->sN, yk, c->spre,
+    st = dev(c, launch_mlp_train_step(c->sprm, c->szfeat, c->schosen, c->sN, c->sytgt, c->spre,
                                       c->spred_t, c->sgrad, c->sc.lr, s),
              "surrogate training");
   if (!st && stats)
@@ -1016,13 +1038,14 @@ leea_status leea_surrogate_step(leea_ctx* c, const float* x, const int32_t* y, i
 }
 
 leea_status leea_surrogate_views(leea_ctx* c, float** candidates, int32_t** plan,
-                                 float** features, float** pred, int32_t** chosen,
+                                 float** features, float** inputs, float** pred, int32_t** chosen,
                                  float** chosen_pred, float** params, int32_t* n_candidates) {
   if (!c) return fail(nullptr, LEEA_EINVAL, "ctx is NULL");
   if (!c->sur) return fail(c, LEEA_ESTATE, "no surrogate attached");
   if (candidates) *candidates = c->scand;
   if (plan) *plan = (int32_t*)c->scplan;
   if (features) *features = c->sfeat;
+  if (inputs) *inputs = c->szfeat;
   if (pred) *pred = c->spred;
   if (chosen) *chosen = c->schosen;
   if (chosen_pred) *chosen_pred = c->schosen_pred;

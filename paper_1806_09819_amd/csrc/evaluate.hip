@@ -78,6 +78,54 @@ __device__ __forceinline__ void finalize_in_kernel(int j, float2 p, int b, const
 }
 
 // ---------------------------------------------------------------- small b --
+// End of the small-batch kernels (one workgroup per network, 4 waves that
+// split K, acc[t] = this wave's K-partial of rows 4 kq + i, neurons
+// 16 t + mn): the 4 K-partial tiles -> LDS [wave][16][ld1], summed in a fixed
+// order into tile 0, which becomes the layer-1 activations (times fac when
+// SCALED, bias, ReLU, zero padding columns); then the tail layers, the
+// fitness and, with fin.on, the network's finish.
+template <int NT, bool SCALED>
+__device__ __forceinline__ void small_epilogue(const floatx4 (&acc)[NT], float fac, int j,
+                                               const float* __restrict__ genome,
+                                               const NetDesc& nd, const int32_t* __restrict__ y,
+                                               int b, float2* __restrict__ partial,
+                                               const EvalLds& lo, int tail_vec,
+                                               const FinArgs& fin) {
+  extern __shared__ float lds[];
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int mn = lane & 15;
+  const int kq = lane >> 4;
+  const int n1 = nd.w[1];
+  const int ld1 = lo.ld1;
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) lds[(wave * 16 + 4 * kq + i) * ld1 + t * 16 + mn] = acc[t][i];
+  __syncthreads();
+  const float* __restrict__ b1 = genome + nd.boff[0];
+  const bool hidden = nd.L > 1;
+  for (int idx = tid; idx < 16 * NT * 16; idx += 256) {
+    const int m = idx / (NT * 16);
+    const int n = idx - m * (NT * 16);
+    float v = 0.0f;
+    if (n < n1) {
+      v = lds[m * ld1 + n] + lds[(16 + m) * ld1 + n];
+      v += lds[(32 + m) * ld1 + n];
+      v += lds[(48 + m) * ld1 + n];
+      if (SCALED) v = v * fac;
+      v += b1[n];
+      if (hidden) v = relu_keep_nan(v);
+    }
+    lds[m * ld1 + n] = v;
+  }
+  __syncthreads();
+  const float2 r = tail_and_fitness<1>(lds, lo, nd, genome, 0, 1, b, 0, y, tail_vec != 0,
+                                       partial + j);
+  if (fin.on && tid == 0) finalize_in_kernel(j, r, b, fin);
+}
+
 // DT selects the first layer's arithmetic (0 float32; 1 bfloat16, 2 FP8
 // E4M3: x holds the batch already quantised, the weight fragments are
 // quantised in registers; products of such values are exact in float32, so
@@ -146,36 +194,8 @@ __device__ __forceinline__ void eval_small_body(int j, const float* __restrict__
     }
   }
 
-  // the 4 K-partial tiles -> LDS [wave][16][ld1], summed in a fixed order
-  // into tile 0, which becomes the layer-1 activations (bias, ReLU, zero
-  // padding columns)
-  const int ld1 = lo.ld1;
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) lds[(wave * 16 + 4 * kq + i) * ld1 + t * 16 + mn] = acc[t][i];
-  __syncthreads();
-  const float* __restrict__ b1 = genome + nd.boff[0];
-  const bool hidden = nd.L > 1;
   const float fac = DT == 2 ? fp8_factor(*x_amax, w_amax[j]) : 1.0f;
-  for (int idx = tid; idx < 16 * NT * 16; idx += 256) {
-    const int m = idx / (NT * 16);
-    const int n = idx - m * (NT * 16);
-    float v = 0.0f;
-    if (n < n1) {
-      v = lds[m * ld1 + n] + lds[(16 + m) * ld1 + n];
-      v += lds[(32 + m) * ld1 + n];
-      v += lds[(48 + m) * ld1 + n];
-      if (DT == 2) v = v * fac;
-      v += b1[n];
-      if (hidden) v = relu_keep_nan(v);
-    }
-    lds[m * ld1 + n] = v;
-  }
-  __syncthreads();
-  const float2 r = tail_and_fitness<1>(lds, lo, nd, genome, 0, 1, b, 0, y, tail_vec != 0,
-                                       partial + j);
-  if (fin.on && tid == 0) finalize_in_kernel(j, r, b, fin);
+  small_epilogue<NT, DT == 2>(acc, fac, j, genome, nd, y, b, partial, lo, tail_vec, fin);
 }
 
 template <int NT, int DT>
@@ -189,6 +209,106 @@ __global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void eval_small_kernel(const f
                                                          FinArgs fin) {
   eval_small_body<NT, DT>(blockIdx.x, genomes, nd, x, y, b, partial, lo, tail_vec, w_amax,
                           x_amax, fin);
+}
+
+// ------------------------------------------------------- b <= 16, BF16 --
+// The small-batch scheme with a bfloat16 first layer on the bfloat16 matrix
+// cores: v_mfma_f32_16x16x32_bf16, lane l = (mn, kq) supplying batch row mn
+// and W_1 row 16 t + mn at k = 32 s + 8 kq .. + 7 (16 bytes each), waves
+// splitting the 32-wide K steps s = wave, wave + 4, ...  FROM_COPY: W_1 comes
+// from its bfloat16 copy (W1Shadow: rows padded to 16, K to 32, zeros), half
+// the bytes of the float32 genome; otherwise it is read as float32 and
+// rounded on the way (the grouped runs, which keep no copy).  The batch is
+// read as float32 and rounded in registers.  Both forms round the same
+// values the same way (nearest even) and issue the same products in the same
+// order, so they are bitwise equal.
+__device__ __forceinline__ uint4 pack_bf16x8(const float4& a, const float4& c) {
+  return make_uint4(pack_bf16x2(a.x, a.y), pack_bf16x2(a.z, a.w), pack_bf16x2(c.x, c.y),
+                    pack_bf16x2(c.z, c.w));
+}
+
+__device__ __forceinline__ floatx4 mfma_bf16x32(const uint4& a, const uint4& b, const floatx4& c) {
+  typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+template <int NT, bool FROM_COPY>
+__device__ __forceinline__ void eval_small_bf16_body(int j, const float* __restrict__ genomes,
+                                                     const NetDesc& nd, const W1Shadow& wsh,
+                                                     const float* __restrict__ x,
+                                                     const int32_t* __restrict__ y, int b,
+                                                     float2* __restrict__ partial,
+                                                     const EvalLds& lo, int tail_vec,
+                                                     const FinArgs& fin) {
+  const int tid = threadIdx.x;
+  const float* __restrict__ genome = genomes + (int64_t)j * nd.stride;
+  const int n0 = nd.w[0];
+  const int n1 = nd.w[1];
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int mn = lane & 15;
+  const int kq = lane >> 4;
+  const bool xv = mn < b;
+  const float* __restrict__ xrow = x + (int64_t)(xv ? mn : 0) * n0;
+  const uint16_t* __restrict__ crow[NT];
+  const float* __restrict__ frow[NT];
+  bool rvalid[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int r = t * 16 + mn;
+    rvalid[t] = r < n1;
+    crow[t] = FROM_COPY ? wsh.p + (int64_t)j * wsh.net + (int64_t)r * wsh.kp : nullptr;
+    frow[t] = genome + nd.woff[0] + (int64_t)(rvalid[t] ? r : 0) * n0;
+  }
+  floatx4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  auto ld8 = [&](const float* row, int k, bool ok) {
+    const float4 a = (ok && k < n0) ? *reinterpret_cast<const float4*>(row + k) : zero4();
+    const float4 c = (ok && k + 4 < n0) ? *reinterpret_cast<const float4*>(row + k + 4) : zero4();
+    return pack_bf16x8(a, c);
+  };
+  const int nss = (n0 + 31) >> 5;
+  uint4 xa, wb[NT];
+  auto load = [&](int s, uint4& xo, uint4* wo) {
+    const int k = 32 * s + 8 * kq;
+    xo = ld8(xrow, k, xv);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if constexpr (FROM_COPY)
+        wo[t] = *reinterpret_cast<const uint4*>(crow[t] + k);
+      else
+        wo[t] = ld8(frow[t], k, rvalid[t]);
+    }
+  };
+  int s = wave;
+  if (s < nss) load(s, xa, wb);
+  for (; s < nss; s += 4) {
+    uint4 xn, wn[NT];
+    if (s + 4 < nss) load(s + 4, xn, wn);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = mfma_bf16x32(xa, wb[t], acc[t]);
+    if (s + 4 < nss) {
+      xa = xn;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) wb[t] = wn[t];
+    }
+  }
+  small_epilogue<NT, false>(acc, 1.0f, j, genome, nd, y, b, partial, lo, tail_vec, fin);
+}
+
+template <int NT>
+__global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void eval_small_bf16_kernel(
+    const float* __restrict__ genomes, NetDesc nd, W1Shadow wsh, const float* __restrict__ x,
+    const int32_t* __restrict__ y, int b, float2* __restrict__ partial, EvalLds lo, int tail_vec,
+    FinArgs fin) {
+  if (wsh.p)
+    eval_small_bf16_body<NT, true>(blockIdx.x, genomes, nd, wsh, x, y, b, partial, lo, tail_vec,
+                                   fin);
+  else
+    eval_small_bf16_body<NT, false>(blockIdx.x, genomes, nd, wsh, x, y, b, partial, lo, tail_vec,
+                                    fin);
 }
 
 // ------------------------------------------------------- b <= 4, FP32 --
@@ -592,6 +712,20 @@ static hipError_t launch_small(const float* genomes, const NetDesc& nd, int pop,
   return hipGetLastError();
 }
 
+template <int NT>
+static hipError_t launch_small_bf16(const float* genomes, const NetDesc& nd, int pop,
+                                    const W1Shadow& wsh, const float* x, const int32_t* y, int b,
+                                    float2* partial, hipStream_t s, const FinArgs& fin) {
+  const int tv = tail_vectorizable(nd) ? 1 : 0;
+  EvalLds lo;
+  const size_t bytes = small_lds_bytes(nd, &lo);
+  hipError_t e = allow_lds(eval_small_bf16_kernel<NT>, bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((eval_small_bf16_kernel<NT>), dim3((unsigned)pop), dim3(256), bytes, s,
+                     genomes, nd, wsh, x, y, b, partial, lo, tv, fin);
+  return hipGetLastError();
+}
+
 template <int NT, int MW, bool RT>
 static hipError_t launch_large(const float* genomes, const NetDesc& nd, int pop, const float* x,
                                const int32_t* y, int b, float2* partial, int n_pt, int tv,
@@ -720,6 +854,13 @@ hipError_t launch_evaluate_small_lp(int dt, const float* genomes, const NetDesc&
                  hipErrorInvalidValue)
 }
 
+hipError_t launch_evaluate_small_bf16(const float* genomes, const NetDesc& nd, int pop,
+                                      const W1Shadow& wsh, const float* x, const int32_t* y,
+                                      int b, float2* partial, hipStream_t s, const FinArgs& fin) {
+  LEEA_NT_SWITCH((launch_small_bf16<N>(genomes, nd, pop, wsh, x, y, b, partial, s, fin)),
+                 hipErrorInvalidValue)
+}
+
 #undef LEEA_NT_SWITCH
 
 // ------------------------------------------------------------- shapes --
@@ -789,9 +930,12 @@ __global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void runs_eval_small_kernel(
     const int* __restrict__ off, const int* __restrict__ ids, int n) {
   const int i = find_group(off, n, blockIdx.x);
   const RunDesc& d = runs[ids[i]];
-  const float* x = DT ? reinterpret_cast<const float*>(d.xq) : d.xb;
-  eval_small_body<NT, DT>(blockIdx.x - off[i], d.genomes[st->cur], d.nd, x, d.yb, d.b, d.partial,
-                          d.lo, d.tail_vec, nullptr, nullptr, FinArgs{});
+  if constexpr (DT == 1)  // bfloat16 matrix cores, W_1 rounded on the way (no copy)
+    eval_small_bf16_body<NT, false>(blockIdx.x - off[i], d.genomes[st->cur], d.nd, W1Shadow{},
+                                    d.xb, d.yb, d.b, d.partial, d.lo, d.tail_vec, FinArgs{});
+  else
+    eval_small_body<NT, DT>(blockIdx.x - off[i], d.genomes[st->cur], d.nd, d.xb, d.yb, d.b,
+                            d.partial, d.lo, d.tail_vec, nullptr, nullptr, FinArgs{});
 }
 
 // Row-streaming evaluation of the float32 runs with b <= 4: the batch

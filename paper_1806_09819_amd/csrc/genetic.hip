@@ -124,10 +124,11 @@ __device__ __forceinline__ void vary_body(int j, int gx, const float* __restrict
         n += 1;
         k -= wsh.n0;
       }
-      uint2 v;
-      v.x = pack_bf16x2(o.x, o.y);
-      v.y = pack_bf16x2(o.z, o.w);
-      *reinterpret_cast<uint2*>(sh + (int64_t)n * wsh.kp + k) = v;
+      typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+      const u32x2 v = {pack_bf16x2(o.x, o.y), pack_bf16x2(o.z, o.w)};
+      // non-temporal like the children themselves: the evaluation reads the
+      // copy once, after this whole kernel
+      __builtin_nontemporal_store(v, reinterpret_cast<u32x2*>(sh + (int64_t)n * wsh.kp + k));
     }
     if (kAmax && f < w1f) {
       uint32_t a = mag_bits(o.x), b = mag_bits(o.y), c = mag_bits(o.z), d = mag_bits(o.w);

@@ -112,6 +112,12 @@ hipError_t launch_evaluate_small_lp(int dt, const float* genomes, const NetDesc&
                                     const float* xq, const int32_t* y, int b, float2* partial,
                                     const uint32_t* w_amax, const uint32_t* x_amax,
                                     hipStream_t s);
+// bfloat16 first layer for b <= 16 on the bfloat16 matrix cores, from the
+// W_1 copy (wsh.p != nullptr) or rounding the float32 genome on the way; x is
+// the float32 batch; finishes each network itself when fin.on.
+hipError_t launch_evaluate_small_bf16(const float* genomes, const NetDesc& nd, int pop,
+                                      const W1Shadow& wsh, const float* x, const int32_t* y,
+                                      int b, float2* partial, hipStream_t s, const FinArgs& fin);
 bool eval_lp_supported(const NetDesc& nd, int b, int dt);
 int eval_lp_ptiles(const NetDesc& nd, int b, int dt);
 hipError_t launch_evaluate_lp(int dt, const float* genomes, const NetDesc& nd, int pop,
@@ -169,8 +175,11 @@ hipError_t launch_gather(const float* cur, const float* cand, float* nxt, int64_
 hipError_t launch_mlp_train_step(float* prm, const float* feat, const int32_t* idx, int N,
                                  const float* y, float* pre, float* pred, float* grad, float lr,
                                  hipStream_t s);
-hipError_t launch_surrogate_judge(const float* pred, const float* y, int N, int warmup,
-                                  float tau_min, int32_t* state, float* stats, hipStream_t s);
+hipError_t launch_standardize(const float* feat, int M, float* z, hipStream_t s);
+hipError_t launch_targets(const float* y, int N, float* out, hipStream_t s);
+hipError_t launch_surrogate_judge(const float* pred, const float* y, const float* yt, int N,
+                                  int warmup, float tau_min, int32_t* state, float* stats,
+                                  hipStream_t s);
 
 // rng.hip (generator entry points)
 hipError_t launch_rng_philox(const uint32_t* ctr, uint64_t key, uint32_t* out, int64_t n,

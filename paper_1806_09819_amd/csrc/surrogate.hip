@@ -4,16 +4,19 @@
 // candidate children (slot P + c of the generation's streams), describes
 // every candidate by a fixed random +-1 projection of its bfloat16-rounded
 // genome (256 values), its parents' adjusted fitness and its distance to
-// parent 1, predicts its fitness with a 259-64-1 MLP, keeps the P - n_E best
+// parent 1, standardises every feature over the generation's candidates,
+// predicts its fitness with a 259-64-1 MLP, keeps the P - n_E best
 // predictions, evaluates the new population as usual and trains the MLP on
-// that evaluation (full-batch gradient steps on the squared error).  Until
+// that evaluation standardised over the kept candidates (full-batch gradient
+// steps on the squared error).  Until
 // the MLP has trained for `warmup` generations and its Kendall tau on the
 // previous generation reaches tau_min, plain LEEA's mix of candidates is
 // kept instead.
 //
 // Kernels: sign bits of the projection (once), candidate plan, the
 // projection as a split-K bfloat16 matrix-core product whose signs are
-// expanded from bits on the fly, feature assembly, prediction, screening
+// expanded from bits on the fly, feature assembly and standardisation,
+// prediction, screening
 // (bitonic sort in LDS), gather of the new population, training (forward,
 // gradient, update) and the tau / fallback decision.  Every sum has a fixed
 // order.
@@ -255,6 +258,107 @@ hipError_t launch_features(const float* part, int splits, int M, const float* nu
   return hipGetLastError();
 }
 
+// Fixed-order sum of one value per thread over a 256-thread workgroup
+// (halving tree in LDS); every thread gets the total.
+__device__ __forceinline__ float block_sum256(float v, float* red) {
+#pragma clang fp contract(off)
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (t < off) red[t] = red[t] + red[t + off];
+    __syncthreads();
+  }
+  const float r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// MLP inputs: feature d of every candidate minus its mean over the M
+// candidates, divided by its standard deviation over them (no Bessel
+// correction); 0 where that deviation is 0.  Workgroup = feature d (d = 259,
+// the padding column, writes zeros); thread t sums candidates t, t + 256, ...
+// in order, then the halving tree.
+__global__ __launch_bounds__(256) void standardize_kernel(const float* __restrict__ feat, int M,
+                                                          float* __restrict__ z) {
+#pragma clang fp contract(off)
+  __shared__ float red[256];
+  const int d = blockIdx.x;
+  const int t = threadIdx.x;
+  if (d >= kIn) {
+    for (int c = t; c < M; c += 256) z[(int64_t)c * kFeatLd + d] = 0.0f;
+    return;
+  }
+  float s = 0.0f;
+  for (int c = t; c < M; c += 256) s += feat[(int64_t)c * kFeatLd + d];
+  const float mean = block_sum256(s, red) / (float)M;
+  float q = 0.0f;
+  for (int c = t; c < M; c += 256) {
+    const float dx = feat[(int64_t)c * kFeatLd + d] - mean;
+    q += dx * dx;
+  }
+  const float var = block_sum256(q, red) / (float)M;
+  const float sd = __builtin_sqrtf(var);
+  for (int c = t; c < M; c += 256) {
+    const float dx = feat[(int64_t)c * kFeatLd + d] - mean;
+    z[(int64_t)c * kFeatLd + d] = sd > 0.0f ? dx / sd : 0.0f;
+  }
+}
+
+hipError_t launch_standardize(const float* feat, int M, float* z, hipStream_t s) {
+  hipLaunchKernelGGL(standardize_kernel, dim3((unsigned)kFeatLd), dim3(256), 0, s, feat, M, z);
+  return hipGetLastError();
+}
+
+// Training targets: the finite fitness values y[n] minus their mean, divided
+// by their standard deviation (1 if it is 0); other values copied.  One
+// workgroup, the same fixed-order sums.
+__global__ __launch_bounds__(256) void targets_kernel(const float* __restrict__ y, int N,
+                                                      float* __restrict__ out) {
+#pragma clang fp contract(off)
+  __shared__ float red[256];
+  const int t = threadIdx.x;
+  float s = 0.0f, k = 0.0f;
+  for (int n = t; n < N; n += 256) {
+    const float v = y[n];
+    const bool ok = v == v && v != __builtin_inff() && v != -__builtin_inff();
+    if (ok) {
+      s += v;
+      k += 1.0f;
+    }
+  }
+  const float tot = block_sum256(s, red);
+  const float cnt = block_sum256(k, red);
+  const float mean = cnt > 0.0f ? tot / cnt : 0.0f;
+  float q = 0.0f;
+  for (int n = t; n < N; n += 256) {
+    const float v = y[n];
+    const bool ok = v == v && v != __builtin_inff() && v != -__builtin_inff();
+    if (ok) {
+      const float dv = v - mean;
+      q += dv * dv;
+    }
+  }
+  const float var = cnt > 0.0f ? block_sum256(q, red) / cnt : 0.0f;
+  float sd = __builtin_sqrtf(var);
+  sd = sd > 0.0f ? sd : 1.0f;
+  for (int n = t; n < N; n += 256) {
+    const float v = y[n];
+    const bool ok = v == v && v != __builtin_inff() && v != -__builtin_inff();
+    if (ok) {
+      const float dv = v - mean;
+      out[n] = dv / sd;
+    } else {
+      out[n] = v;
+    }
+  }
+}
+
+hipError_t launch_targets(const float* y, int N, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(targets_kernel, dim3(1), dim3(256), 0, s, y, N, out);
+  return hipGetLastError();
+}
+
 // MLP forward of rows idx[n] (or n when idx is NULL): pre[n][u] (optional)
 // and pred[n].  Workgroup = one row, thread u = hidden unit; inputs summed
 // in index order, hidden units summed in order by thread 0.
@@ -376,8 +480,44 @@ hipError_t launch_gather(const float* cur, const float* cand, float* nxt, int64_
 }
 
 // Gradient of mean((pred - y)^2) over the rows with a numeric target
-// y[n] = fitness of slot n_e + n; one thread per parameter, rows summed in
-// order; then (2 / rows) times the sum.
+// y[n] = training target of kept candidate n; one thread per parameter.  The
+// rows are summed in 8 interleaved partial sums (row n into sum n mod 8, each
+// in row order), added in a fixed tree ((s0 + s1) + (s2 + s3)) + ((s4 + s5) +
+// (s6 + s7)), so eight rows' loads are in flight at once; then (2 / rows)
+// times the total.
+__device__ __forceinline__ float grad_term(int i, int n, const float* __restrict__ prm,
+                                           const float* __restrict__ feat,
+                                           const int32_t* __restrict__ idx,
+                                           const float* __restrict__ pre,
+                                           const float* __restrict__ pred,
+                                           const float* __restrict__ y, int* rows) {
+#pragma clang fp contract(off)
+  const int nw1 = kHid * kIn;
+  const float t = y[n];
+  if (!(t == t) || t == __builtin_inff() || t == -__builtin_inff()) return 0.0f;
+  ++*rows;
+  const float* w2 = prm + nw1 + kHid;
+  const float e = pred[n] - t;
+  if (i < nw1) {
+    const int u = i / kIn;
+    const int d = i - u * kIn;
+    const float p = pre[(int64_t)n * kHid + u];
+    const float ew = e * w2[u];
+    return p > 0.0f ? ew * feat[(int64_t)idx[n] * kFeatLd + d] : 0.0f;
+  }
+  if (i < nw1 + kHid) {
+    const int u = i - nw1;
+    const float p = pre[(int64_t)n * kHid + u];
+    return p > 0.0f ? e * w2[u] : 0.0f;
+  }
+  if (i < nw1 + 2 * kHid) {
+    const int u = i - nw1 - kHid;
+    const float p = pre[(int64_t)n * kHid + u];
+    return p > 0.0f ? e * p : 0.0f;
+  }
+  return e;
+}
+
 __global__ __launch_bounds__(256) void mlp_grad_kernel(const float* __restrict__ prm,
                                                        const float* __restrict__ feat,
                                                        const int32_t* __restrict__ idx,
@@ -387,39 +527,21 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(const float* __restrict__
                                                        float* __restrict__ grad) {
 #pragma clang fp contract(off)
   const int i = blockIdx.x * 256 + threadIdx.x;
-  const int nw1 = kHid * kIn;
-  const int total = nw1 + 2 * kHid + 1;
+  const int total = kHid * kIn + 2 * kHid + 1;
   if (i >= total) return;
-  const float* w2 = prm + nw1 + kHid;
-  float s = 0.0f;
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   int rows = 0;
-  for (int n = 0; n < N; ++n) {
-    const float t = y[n];
-    if (!(t == t) || t == __builtin_inff() || t == -__builtin_inff()) continue;
-    ++rows;
-    const float e = pred[n] - t;
-    float term;
-    if (i < nw1) {
-      const int u = i / kIn;
-      const int d = i - u * kIn;
-      const float p = pre[(int64_t)n * kHid + u];
-      const float ew = e * w2[u];
-      term = p > 0.0f ? ew * feat[(int64_t)idx[n] * kFeatLd + d] : 0.0f;
-    } else if (i < nw1 + kHid) {
-      const int u = i - nw1;
-      const float p = pre[(int64_t)n * kHid + u];
-      term = p > 0.0f ? e * w2[u] : 0.0f;
-    } else if (i < nw1 + 2 * kHid) {
-      const int u = i - nw1 - kHid;
-      const float p = pre[(int64_t)n * kHid + u];
-      term = p > 0.0f ? e * p : 0.0f;
-    } else {
-      term = e;
-    }
-    s += term;
+  int n = 0;
+  for (; n + 8 <= N; n += 8) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s[q] += grad_term(i, n + q, prm, feat, idx, pre, pred, y, &rows);
   }
+  for (int q = 0; n + q < N; ++q) s[q] += grad_term(i, n + q, prm, feat, idx, pre, pred, y, &rows);
+  const float a = (s[0] + s[1]) + (s[2] + s[3]);
+  const float b = (s[4] + s[5]) + (s[6] + s[7]);
+  const float tot = a + b;
   const float f = rows > 0 ? 2.0f / (float)rows : 0.0f;
-  grad[i] = s * f;
+  grad[i] = tot * f;
 }
 
 __global__ __launch_bounds__(256) void mlp_update_kernel(float* __restrict__ prm,
@@ -445,12 +567,14 @@ hipError_t launch_mlp_train_step(float* prm, const float* feat, const int32_t* i
 }
 
 // Kendall tau-a of the screening predictions against the evaluated fitness
-// of the kept candidates, root mean squared error, and the next
+// of the kept candidates, root mean squared error against their training
+// targets (the standardised fitness), and the next
 // generation's decision: on when `warmup` generations have trained and
 // tau >= tau_min.  state = {flag, trained generations}; stats = {surrogate
 // used this generation, tau, rmse, trained generations}.
 __global__ __launch_bounds__(1024) void surrogate_judge_kernel(const float* __restrict__ p,
-                                                               const float* __restrict__ y, int N,
+                                                               const float* __restrict__ y,
+                                                               const float* __restrict__ yt, int N,
                                                                int warmup, float tau_min,
                                                                int32_t* __restrict__ state,
                                                                float* __restrict__ stats) {
@@ -472,7 +596,7 @@ __global__ __launch_bounds__(1024) void surrogate_judge_kernel(const float* __re
   float e2 = 0.0f;
   int c = 0;
   for (int i = tid; i < N; i += 1024) {
-    const float d = p[i] - y[i];
+    const float d = p[i] - yt[i];
     if (d == d && d != __builtin_inff() && d != -__builtin_inff()) {
       e2 += d * d;
       ++c;
@@ -504,9 +628,10 @@ __global__ __launch_bounds__(1024) void surrogate_judge_kernel(const float* __re
   }
 }
 
-hipError_t launch_surrogate_judge(const float* pred, const float* y, int N, int warmup,
-                                  float tau_min, int32_t* state, float* stats, hipStream_t s) {
-  hipLaunchKernelGGL(surrogate_judge_kernel, dim3(1), dim3(1024), 0, s, pred, y, N, warmup,
+hipError_t launch_surrogate_judge(const float* pred, const float* y, const float* yt, int N,
+                                  int warmup, float tau_min, int32_t* state, float* stats,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(surrogate_judge_kernel, dim3(1), dim3(1024), 0, s, pred, y, yt, N, warmup,
                      tau_min, state, stats);
   return hipGetLastError();
 }

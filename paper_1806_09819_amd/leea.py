@@ -135,7 +135,7 @@ def library():
         "leea_surrogate_workspace_bytes": [CP, SP, ctypes.POINTER(ctypes.c_size_t)],
         "leea_surrogate_attach": [P, SP, P, ctypes.c_size_t],
         "leea_surrogate_step": [P, P, P, I32, P, P, P, P],
-        "leea_surrogate_views": [P] + [ctypes.POINTER(P)] * 7 + [ctypes.POINTER(I32)],
+        "leea_surrogate_views": [P] + [ctypes.POINTER(P)] * 8 + [ctypes.POINTER(I32)],
     }
     for name, args in sur_sig.items():
         fn = getattr(lib, name)
@@ -372,9 +372,10 @@ class Leea:
 
     def surrogate_views(self):
         """Borrowed views of the last surrogate step: dict of candidates
-        [n, stride], plan [n, 4], features [n, 260], pred [n], chosen
-        [pop - n_elite], chosen_pred, params [16769]."""
-        ptrs = [ctypes.c_void_p() for _ in range(7)]
+        [n, stride], plan [n, 4], features [n, 260], inputs (standardised
+        features) [n, 260], pred [n], chosen [pop - n_elite], chosen_pred,
+        params [16769]."""
+        ptrs = [ctypes.c_void_p() for _ in range(8)]
         n = ctypes.c_int32()
         _check(library().leea_surrogate_views(self._ctx, *[ctypes.byref(q) for q in ptrs],
                                               ctypes.byref(n)), self._ctx)
@@ -391,10 +392,11 @@ class Leea:
             candidates=view(ptrs[0].value, M * self.stride, torch.float32, 4).view(M, self.stride),
             plan=view(ptrs[1].value, M * 4, torch.int32, 4).view(M, 4),
             features=view(ptrs[2].value, M * 260, torch.float32, 4).view(M, 260),
-            pred=view(ptrs[3].value, M, torch.float32, 4),
-            chosen=view(ptrs[4].value, N, torch.int32, 4),
-            chosen_pred=view(ptrs[5].value, N, torch.float32, 4),
-            params=view(ptrs[6].value, 64 * 259 + 2 * 64 + 1, torch.float32, 4))
+            inputs=view(ptrs[3].value, M * 260, torch.float32, 4).view(M, 260),
+            pred=view(ptrs[4].value, M, torch.float32, 4),
+            chosen=view(ptrs[5].value, N, torch.int32, 4),
+            chosen_pred=view(ptrs[6].value, N, torch.float32, 4),
+            params=view(ptrs[7].value, 64 * 259 + 2 * 64 + 1, torch.float32, 4))
 
     def save(self):
         n = ctypes.c_size_t()

@@ -22,6 +22,21 @@ pytestmark = pytest.mark.gpu
 U = 2.0 ** -24
 
 
+def check_inputs(Xd, Zd, label):
+    """The device's standardised MLP inputs against the oracle's
+    standardisation of the device's own features, within the float32 error
+    of the fixed-order sums (depth M / 256 + 8) and of x - mean."""
+    M = Xd.shape[0]
+    Zo = S.standardize(Xd)
+    mu = Xd.mean(axis=0)
+    sd = np.sqrt(((Xd - mu) ** 2).mean(axis=0))
+    depth = M / 256.0 + 16.0
+    ok = sd > 0
+    scale = np.abs(Xd).mean(axis=0) + np.abs(Xd - mu)
+    tol = np.where(ok, 4 * depth * U * (scale / np.where(ok, sd, 1.0) + np.abs(Zo)), 0.0) + 1e-6
+    assert np.all(np.abs(Zd - Zo) <= tol), (label, float(np.max(np.abs(Zd - Zo) - tol)))
+
+
 def _teacher_forced(params, gens, k, steps, lr, warmup, tau_min, seed=0):
     b = params["batch"]
     run, ocfg = make_run(params, max_batch=b)
@@ -66,12 +81,15 @@ def _teacher_forced(params, gens, k, steps, lr, warmup, tau_min, seed=0):
         assert np.all(np.abs(Xd[:, :256] - X[:, :256]) <= bound), g
         assert np.array_equal(Xd[:, 256:258], X[:, 256:258]), g
         assert np.allclose(Xd[:, 258], X[:, 258], rtol=1e-5, atol=1e-9), g
-        # predictions from the device's features and parameters
+        # standardised inputs, then predictions from the device's inputs and
+        # parameters
+        Zd = to_np(v["inputs"])[:, :S.INPUTS].astype(np.float64)
+        check_inputs(Xd, Zd, g)
         prm = {"W1": prm0[:64 * 259].reshape(64, 259), "b1": prm0[64 * 259:64 * 260],
                "w2": prm0[64 * 260:64 * 261], "b2": prm0[64 * 261]}
-        pred_o, _ = S.mlp_forward(prm, Xd)
+        pred_o, _ = S.mlp_forward(prm, Zd)
         pred = to_np(v["pred"]).astype(np.float64)
-        scl = np.abs(Xd) @ np.abs(prm["W1"].astype(np.float64)).T
+        scl = np.abs(Zd) @ np.abs(prm["W1"].astype(np.float64)).T
         pbound = 600 * U * (np.maximum(scl, 1e-30) @ np.abs(prm["w2"].astype(np.float64))) + 1e-6
         assert np.all(np.abs(pred - pred_o) <= pbound), g
         # screening (device float32 predictions) and the new population
@@ -89,7 +107,7 @@ def _teacher_forced(params, gens, k, steps, lr, warmup, tau_min, seed=0):
         assert abs(S.kendall_tau_a(cp, yk) - float(st[1])) < 1e-6, g
         p_o = prm
         for _ in range(steps):
-            p_o = S.mlp_gradient_step(p_o, Xd[keep], yk, lr)
+            p_o = S.mlp_gradient_step(p_o, Zd[keep], S.standardize_targets(yk), lr)
         prm1 = to_np(v["params"]).astype(np.float64)
         ref = np.concatenate([p_o["W1"].ravel(), p_o["b1"], p_o["w2"], [p_o["b2"]]])
         assert np.allclose(prm1, ref, rtol=2e-4, atol=2e-6), (g, np.max(np.abs(prm1 - ref)))
@@ -171,11 +189,13 @@ def test_surrogate_teacher_forced_configured_size():
         assert np.all(np.abs(Xd[:, :256] - X[:, :256]) <= bound), g
         assert np.array_equal(Xd[:, 256:258], X[:, 256:258]), g
         assert np.allclose(Xd[:, 258], X[:, 258], rtol=1e-5, atol=1e-9), g
+        Zd_all = to_np(v["inputs"])[:, :S.INPUTS].astype(np.float64)
+        check_inputs(Xd_all, Zd_all, g)
         prm = {"W1": prm0[:64 * 259].reshape(64, 259), "b1": prm0[64 * 259:64 * 260],
                "w2": prm0[64 * 260:64 * 261], "b2": prm0[64 * 261]}
-        pred_o, _ = S.mlp_forward(prm, Xd_all)
+        pred_o, _ = S.mlp_forward(prm, Zd_all)
         pred = to_np(v["pred"]).astype(np.float64)
-        scl = np.abs(Xd_all) @ np.abs(prm["W1"].astype(np.float64)).T
+        scl = np.abs(Zd_all) @ np.abs(prm["W1"].astype(np.float64)).T
         pbound = 600 * U * (np.maximum(scl, 1e-30) @ np.abs(prm["w2"].astype(np.float64))) + 1e-6
         assert np.all(np.abs(pred - pred_o) <= pbound), g
         keep = S.screen(to_np(v["pred"]), N, bool(st[0]), k, n_c, n_m)
@@ -201,7 +221,7 @@ def test_surrogate_teacher_forced_configured_size():
         assert abs(S.kendall_tau_a(cp, yk) - float(st[1])) < 1e-6, g
         p_o = prm
         for _ in range(steps):
-            p_o = S.mlp_gradient_step(p_o, Xd_all[keep], yk, lr)
+            p_o = S.mlp_gradient_step(p_o, Zd_all[keep], S.standardize_targets(yk), lr)
         prm1 = to_np(v["params"]).astype(np.float64)
         ref = np.concatenate([p_o["W1"].ravel(), p_o["b1"], p_o["w2"], [p_o["b2"]]])
         assert np.allclose(prm1, ref, rtol=2e-4, atol=2e-6), (g, np.max(np.abs(prm1 - ref)))

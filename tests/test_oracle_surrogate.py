@@ -172,3 +172,35 @@ def test_screen_brute_force_and_fallback():
     assert keep.tolist() == ref
     fb = S.screen(pred, 10, False, 4, 6, 4)
     assert fb.tolist() == list(range(6)) + [24, 25, 26, 27]
+
+
+def test_standardize_closed_forms():
+    rng = np.random.Generator(np.random.PCG64(9))
+    X = rng.standard_normal((500, 7)) * np.array([1e-4, 1, 3, 0, 1e3, 2, 5]) + 10.0
+    Z = S.standardize(X)
+    ok = np.array([True, True, True, False, True, True, True])
+    assert np.allclose(Z[:, ok].mean(axis=0), 0.0, atol=1e-9)
+    assert np.allclose(Z[:, ok].std(axis=0), 1.0, rtol=1e-9)
+    assert np.array_equal(Z[:, 3], np.zeros(500))               # a constant column
+    # invariant under a positive affine map of a column, negated under a negative one
+    X2 = X.copy()
+    X2[:, 1] = 7.5 * X[:, 1] - 3.0
+    X2[:, 2] = -0.25 * X[:, 2] + 1.0
+    Z2 = S.standardize(X2)
+    assert np.allclose(Z2[:, 1], Z[:, 1], atol=1e-12)
+    assert np.allclose(Z2[:, 2], -Z[:, 2], atol=1e-12)
+    # a two-valued column: +-1 exactly
+    X3 = np.array([[0.0], [2.0], [0.0], [2.0]])
+    assert np.array_equal(S.standardize(X3)[:, 0], np.array([-1.0, 1.0, -1.0, 1.0]))
+
+
+def test_standardize_targets():
+    y = np.array([-2.0, -1.0, np.nan, 0.0, np.inf, 3.0])
+    t = S.standardize_targets(y)
+    f = np.isfinite(y)
+    assert np.allclose(t[f].mean(), 0.0, atol=1e-12) and np.isclose(t[f].std(), 1.0)
+    assert np.isnan(t[2]) and np.isinf(t[4])
+    assert np.array_equal(S.standardize_targets(np.full(5, -2.3)), np.zeros(5))
+    # ranks are kept: Kendall tau of targets and their standardisation is 1
+    v = np.random.Generator(np.random.PCG64(1)).standard_normal(200)
+    assert S.kendall_tau_a(v, S.standardize_targets(v)) == 1.0
