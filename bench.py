@@ -75,15 +75,16 @@ def layer1_flops(params, b):
 def vary_bytes(params, genes):
     """Algorithmic bytes of one variation launch: every child written once;
     elites and mutants read one parent, crossover children two; with a
-    bfloat16 first layer at batches above 16, also each child's W_1 written
-    once more in bfloat16 (the copy the evaluation reads)."""
+    bfloat16 or FP8 first layer also each child's W_1 written once more at
+    that operand size (the copy the evaluation reads)."""
     from paper_1806_09819_amd import leea as B
     n_e, n_c, n_m, _ = B.counts(params["pop"], params["p_elite"], params["p_cross"],
                                 params["p_mut"], params["rho"])
     nbytes = 4.0 * genes * (2 * n_e + 3 * n_c + 2 * n_m)
-    if params.get("eval_dtype", "f32") == "bf16" and params.get("batch", 0) > 16:
-        w = params["widths"]
-        nbytes += 2.0 * w[0] * w[1] * params["pop"]
+    w = params["widths"]
+    dt = params.get("eval_dtype", "f32")
+    if dt in ("bf16", "fp8"):       # the child's W_1 copy, at its operand size
+        nbytes += OPERAND_BYTES[dt] * w[0] * w[1] * params["pop"]
     return nbytes
 
 
@@ -236,8 +237,9 @@ def roofline_of(params, r, b):
         achieved = nbytes / sec / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK / 1e9, unit="GB/s",
                     frac=achieved / (HBM_PEAK / 1e9))
-    roof["traffic"] = (measured_traffic("paper_b%d" % b)
-                       if params.get("eval_dtype", "f32") == "f32" else None)
+    dt_tag = params.get("eval_dtype", "f32")
+    roof["traffic"] = measured_traffic("paper_b%d" % b if dt_tag == "f32"
+                                       else "paper_%s_b%d" % (dt_tag, b))
     roof["vary_hbm_frac"] = vary_bytes(params, r["stride"]) / (r["phases_ms"]["vary"] * 1e-3) / HBM_PEAK
     roof["kernel"] = "evaluate (fused forward + fitness, one launch per generation)"
     roof["per_launch"] = dict(flops=flops, bytes=nbytes, avg_ms=r["phases_ms"]["evaluate"])

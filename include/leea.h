@@ -84,10 +84,17 @@ enum { LEEA_SIGMA_CONSTANT = 0, LEEA_SIGMA_DECAY = 1, LEEA_SIGMA_SELF_ADAPTIVE =
  *       summed in float32 on the bf16 matrix cores.
  * FP8:  OCP FP8 E4M3 with power-of-two scales: X / 2^e_x and W_1 / 2^e_w
  *       rounded to E4M3 (nearest, ties to even), e the smallest integer with
- *       amax <= 448 * 2^e (amax = largest |value| of the batch, resp. of each
- *       network's W_1), products summed in float32 and multiplied by
- *       2^(e_x + e_w).  A batch holding NaN or an infinity gives every
- *       network a NaN fitness; such a W_1 gives its network a NaN fitness. */
+ *       B <= 448 * 2^e, products summed in float32 and multiplied by
+ *       2^(e_x + e_w).  For the batch B is its largest |value|.  For each
+ *       network's W_1 (one scale per individual) B is its largest |value|
+ *       after initialisation, leea_set_state, leea_load or a surrogate step,
+ *       and for a child of crossover_mutate the bound its parents give
+ *       (elite: the parent's largest |W_1|; crossover: the larger parent's;
+ *       mutant: fl(fl(a * (1 + 2^-20)) + fl(6 * sigma)), a the parent's),
+ *       which is known before the child is written, so that the variation
+ *       kernel writes the child's FP8 copy of W_1 with it.  A batch holding
+ *       NaN or an infinity gives every network a NaN fitness; such a W_1
+ *       gives its network a NaN fitness. */
 enum { LEEA_DT_F32 = 0, LEEA_DT_BF16 = 1, LEEA_DT_FP8 = 2 };
 
 /* Hyperparameters of one EA run.  Counts are integers: the paper's
@@ -118,8 +125,8 @@ typedef struct {
   int32_t input_pool;                     /* 0, or 2: draw_batch max-pools 2x2 from square images
                                              of 4*widths[0] pixels (section 4.1) */
   int32_t eval_dtype;                     /* LEEA_DT_*: arithmetic of the first layer (BF16
-                                             with max_batch > 16 adds a bfloat16 copy of
-                                             every W_1 to the workspace) */
+                                             adds a bfloat16 copy of every W_1 to the
+                                             workspace, FP8 an FP8 copy) */
 } leea_config;
 
 /* Host helper: fill the integer fields of cfg that Algorithm 1 writes as

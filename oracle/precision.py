@@ -17,9 +17,13 @@ stay as in ``leea.forward``:
   with power-of-two scales: W_1 of each network is divided by 2^e_w and X
   by 2^e_x, rounded to E4M3 (nearest, ties to even), and the product is
   multiplied back by 2^(e_w + e_x).  e is the smallest integer with
-  amax <= 448 * 2^e, amax the largest magnitude of the operand (per network
-  for W_1, per batch for X), so no scaled value exceeds 448.  An operand
-  holding NaN or an infinity makes the fitness of the affected networks NaN.
+  B <= 448 * 2^e for a bound B of the operand's largest magnitude, so no
+  scaled value exceeds 448.  For the batch, B is its largest magnitude.  For
+  a network's W_1 it is its largest magnitude after initialisation or a
+  restore, and for a child the bound its parents give (``fp8_child_bounds``),
+  known before the child exists, so that the child's FP8 copy can be written
+  as the child is made.  An operand holding NaN or an infinity (a non-finite
+  bound) makes the fitness of the affected networks NaN.
 
 Scaling by powers of two and products of these short significands are
 exact in float64; beyond the quantisation itself the oracle rounds only in
@@ -120,27 +124,69 @@ def fp8_exponent(amax):
     return e
 
 
-def quantize_fp8(a):
+MUT_BOUND_FACTOR = np.float32(1.0 + 2.0**-20)
+MUT_BOUND_Z = np.float32(6.0)
+
+
+def amax_w1(pop, widths):
+    """Largest |W_1| of every network (float32, exact; NaN if W_1 holds a
+    NaN, inf for an infinity)."""
+    pop = np.asarray(pop, dtype=np.float32)
+    w1 = widths[0] * widths[1]
+    a = np.abs(pop[:, :w1])
+    out = a.max(axis=1)
+    out[np.isnan(a).any(axis=1)] = np.nan
+    return out.astype(np.float32)
+
+
+def fp8_child_bounds(parent_amax, ops, p1, p2, sigma):
+    """Bound of each child's largest |W_1| from its parents (float32, each
+    operation rounded): an elite has its parent's largest magnitude; every
+    gene of a crossover child (uniform: a parent's gene; arithmetic:
+    fl(fl(a + b) * 0.5), which lies between them) is bounded by the larger
+    parent's; a mutant's genes are fl(t + fl(sigma * z)) with |z| <= 5.78 for
+    the float32 Box-Muller sampler (radius sqrt(-2 ln 2^-24) ~= 5.768), so
+    fl(fl(a * (1 + 2^-20)) + fl(6 sigma)) covers them with room for every
+    rounding."""
+    amax = np.asarray(parent_amax, dtype=np.float32)
+    ops = np.asarray(ops)
+    a1 = amax[np.asarray(p1)]
+    a2 = amax[np.asarray(p2)]
+    cross = np.where(np.isnan(a1) | np.isnan(a2), np.float32(np.nan), np.maximum(a1, a2))
+    mut = (a1 * MUT_BOUND_FACTOR) + (MUT_BOUND_Z * np.float32(sigma))
+    out = np.where(ops == L.ELITE, a1, np.where(ops == L.CROSS, cross, mut))
+    return out.astype(np.float32)
+
+
+def quantize_fp8(a, bound=None):
     """(values, e): a (float32) divided by 2^e, rounded to E4M3, as float64
-    values still scaled by 2^-e; e from the operand's largest magnitude.
-    Returns (None, None) if a holds NaN or an infinity."""
+    values still scaled by 2^-e; e from `bound` (default: the operand's
+    largest magnitude).  Returns (None, None) if a holds NaN or an infinity
+    or the bound is not finite."""
     a = np.asarray(a, dtype=np.float64)
     if not np.all(np.isfinite(a)):
         return None, None
-    e = fp8_exponent(np.max(np.abs(a)) if a.size else 0.0)
+    if bound is None:
+        bound = np.max(np.abs(a)) if a.size else 0.0
+    if not math.isfinite(float(bound)):
+        return None, None
+    if a.size and np.max(np.abs(a)) > float(bound):
+        raise ValueError("the bound is below the operand's largest magnitude")
+    e = fp8_exponent(float(bound))
     return round_e4m3(a * 2.0**-e), e
 
 
-def layer1_operands(genome, widths, x, dtype):
+def layer1_operands(genome, widths, x, dtype, w_bound=None):
     """(Xq, Wq, factor) such that the first layer's product is
     factor * Xq Wq^T exactly; Xq / Wq are None when an fp8 operand is not
-    finite (the network's fitness is NaN)."""
+    finite (the network's fitness is NaN).  w_bound: the bound the FP8 scale
+    of W_1 comes from (default: its largest magnitude)."""
     W1 = L.unpack(np.asarray(genome), widths)[0][0]
     if dtype == BF16:
         return (round_bf16(x).astype(np.float64), round_bf16(W1).astype(np.float64), 1.0)
     if dtype == FP8:
         xq, ex = quantize_fp8(x)
-        wq, ew = quantize_fp8(W1)
+        wq, ew = quantize_fp8(W1, w_bound)
         if xq is None or wq is None:
             return None, None, None
         return xq, wq, 2.0**(ex + ew)
@@ -149,10 +195,10 @@ def layer1_operands(genome, widths, x, dtype):
     raise ValueError("unknown dtype %r" % (dtype,))
 
 
-def forward_lowp(genome, widths, x, dtype):
+def forward_lowp(genome, widths, x, dtype, w_bound=None):
     """Logits (float64) of one network with the first layer in `dtype`."""
     layers = L.unpack(np.asarray(genome), widths)
-    xq, wq, factor = layer1_operands(genome, widths, x, dtype)
+    xq, wq, factor = layer1_operands(genome, widths, x, dtype, w_bound)
     n = np.asarray(x).shape[0]
     if xq is None:
         return np.full((n, widths[-1]), np.nan)
@@ -165,14 +211,14 @@ def forward_lowp(genome, widths, x, dtype):
     return h
 
 
-def evaluate_lowp(pop, widths, x, y, dtype):
+def evaluate_lowp(pop, widths, x, y, dtype, w_bounds=None):
     """Raw fitness and accuracy of every network with the first layer in
-    `dtype` (float64 everywhere else)."""
+    `dtype` (float64 everywhere else); w_bounds: per-network FP8 bounds."""
     P = pop.shape[0]
     f = np.empty(P, dtype=np.float64)
     acc = np.empty(P, dtype=np.float64)
     for j in range(P):
-        z = forward_lowp(pop[j], widths, x, dtype)
+        z = forward_lowp(pop[j], widths, x, dtype, None if w_bounds is None else w_bounds[j])
         if np.isnan(z).any():
             f[j], acc[j] = np.nan, np.nan
         else:

@@ -55,7 +55,10 @@ struct leea_ctx {
   uint32_t* w_amax[2];  // FP8: largest |W_1| of each network (ping-pong with the genomes)
   uint32_t* x_amax;     // FP8: largest |x| of the batch being evaluated
   void* xq;             // quantised batch (values [b][n0], packed [b][kp] or chunk-major)
-  W1Shadow wsh;         // bfloat16 copy of every W_1 (large-batch bfloat16 kernel), or none
+  W1Shadow wsh;         // bfloat16 copy of every W_1 (bfloat16 kernels), or none
+  W1Fp8 w8;             // FP8 copy of every W_1 with its scale bounds (FP8 kernels)
+  uint32_t* w_bound;    // FP8: bound of each network's largest |W_1| (scale of its copy)
+  int w8_ok;            // FP8 amax, bounds and copy match the current population
   int wsh_ok;           // the copy matches the current population
   // fitness surrogate (leea_surrogate_attach)
   int sur;
@@ -188,7 +191,7 @@ leea_status validate(const leea_config* cfg, NetDesc* nd) {
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Carve {
-  size_t genomes, scalars, plan, order, partial, xq, wsh, total;
+  size_t genomes, scalars, plan, order, partial, xq, wsh, w8, total;
 };
 
 int padded_k(int n0) { return (n0 + 31) & ~31; }
@@ -205,6 +208,14 @@ int64_t shadow_net(const NetDesc& nd) {
   return (int64_t)padded_k(nd.w[0]) * ((nd.w[1] + 15) & ~15);
 }
 
+// FP8 copy of W_1: kept with an FP8 first layer when W_1 has fewer than 2^24
+// genes; rows padded to 16, K to 64 (one byte per element)
+bool uses_fp8_copy(const leea_config* cfg, const NetDesc& nd) {
+  return cfg->eval_dtype == LEEA_DT_FP8 && (int64_t)nd.w[0] * nd.w[1] < (1 << 24);
+}
+int fp8_kp(int n0) { return (n0 + 63) & ~63; }
+int64_t fp8_net(const NetDesc& nd) { return (int64_t)fp8_kp(nd.w[0]) * ((nd.w[1] + 15) & ~15); }
+
 Carve carve(const leea_config* cfg, const NetDesc& nd) {
   Carve c;
   const size_t P = (size_t)cfg->pop;
@@ -216,6 +227,7 @@ Carve carve(const leea_config* cfg, const NetDesc& nd) {
   c.partial = align256(P * (size_t)n_mt * 8);
   c.xq = 0;
   c.wsh = 0;
+  c.w8 = 0;
   if (cfg->eval_dtype != LEEA_DT_F32) {
     const size_t kp = (size_t)padded_k(nd.w[0]);
     const size_t row = (size_t)nd.w[0] * 4 > kp * 2 ? (size_t)nd.w[0] * 4 : kp * 2;
@@ -224,8 +236,9 @@ Carve carve(const leea_config* cfg, const NetDesc& nd) {
                                                             : chunked;
     c.xq = align256(q) + 256;  // + the batch amax
     if (uses_shadow(cfg, nd)) c.wsh = align256(P * (size_t)shadow_net(nd) * 2);
+    if (uses_fp8_copy(cfg, nd)) c.w8 = align256(P * (size_t)fp8_net(nd));
   }
-  c.total = 2 * c.genomes + 9 * c.scalars + c.plan + c.order + c.partial + c.xq + c.wsh;
+  c.total = 2 * c.genomes + 10 * c.scalars + c.plan + c.order + c.partial + c.xq + c.wsh + c.w8;
   return c;
 }
 
@@ -255,12 +268,33 @@ leea_status shadow_ready(leea_ctx* c) {
   return st;
 }
 
+// FP8: the exact largest |W_1| of every network of the current population,
+// the scale bounds (equal to it) and the FP8 copy, rebuilt when the
+// population changed other than through the variation kernel (which keeps
+// all three in step for the children it makes).
+leea_status fp8_ready(leea_ctx* c) {
+  if (c->dt != LEEA_DT_FP8 || c->w8_ok) return LEEA_OK;
+  leea_status st = dev(c, launch_amax_w1(c->genomes[c->cur], c->nd, c->cfg.pop,
+                                         c->w_amax[c->cur], c->stream),
+                       "amax launch");
+  if (!st)
+    st = dev(c, hipMemcpyAsync(c->w_bound, c->w_amax[c->cur], (size_t)c->cfg.pop * 4,
+                               hipMemcpyDeviceToDevice, c->stream),
+             "bound copy");
+  if (!st && c->w8.p)
+    st = dev(c, launch_fp8_copy(c->genomes[c->cur], c->nd, c->cfg.pop, c->w8, c->stream),
+             "FP8 copy launch");
+  if (!st) c->w8_ok = 1;
+  return st;
+}
+
 // Reduced-precision first layer: batch amax (FP8), the quantised batch, then
 // the small-batch kernel on quantised values (b <= 16) or the bf16 / FP8
 // matrix-core kernel.  Returns the number of partial row tiles.
 leea_status run_eval_lp(leea_ctx* c, const float* x, const int32_t* y, int32_t b, int* n_mt) {
   const int n0 = c->nd.w[0];
-  leea_status st = LEEA_OK;
+  leea_status st = fp8_ready(c);
+  if (st) return st;
   if (c->dt == LEEA_DT_FP8) {
     st = dev(c, launch_fill((float*)c->x_amax, 1, 0.0f, c->stream), "amax clear");
     if (!st)
@@ -282,6 +316,20 @@ leea_status run_eval_lp(leea_ctx* c, const float* x, const int32_t* y, int32_t b
                                       c->stream),
                "evaluate launch");
   }
+  if (!small && c->w8.p && eval_lpw_supported(c->nd, b)) {
+    // large batch from the FP8 copy of W_1 (fp8_ready above rebuilt it if
+    // needed; the batch amax is computed above)
+    const int bpad = round128(b);
+    st = dev(c, launch_quantize_x_chunks8(x, b, n0, c->w8.kp, bpad, c->x_amax,
+                                          (uint8_t*)c->xq, c->stream),
+             "quantize launch");
+    if (st) return st;
+    *n_mt = eval_lpw_ptiles(c->nd, b);
+    return dev(c, launch_evaluate_lpw8(c->genomes[c->cur], c->nd, c->cfg.pop, c->w8,
+                                       (const uint8_t*)c->xq, bpad, c->x_amax, y, b, c->partial,
+                                       c->stream),
+               "evaluate launch");
+  }
   if (!small && !eval_lp_supported(c->nd, b, c->dt))
     return fail(c, LEEA_EINVAL, "reduced-precision evaluation does not fit this batch");
   st = dev(c, launch_quantize_x(c->dt, !small, x, b, n0, c->kp, c->x_amax, c->xq, c->stream),
@@ -291,12 +339,12 @@ leea_status run_eval_lp(leea_ctx* c, const float* x, const int32_t* y, int32_t b
     *n_mt = 1;
     return dev(c, launch_evaluate_small_lp(c->dt, c->genomes[c->cur], c->nd, c->cfg.pop,
                                            (const float*)c->xq, y, b, c->partial,
-                                           c->w_amax[c->cur], c->x_amax, c->stream),
+                                           c->w_bound, c->x_amax, c->stream),
                "evaluate launch");
   }
   *n_mt = eval_lp_ptiles(c->nd, b, c->dt);
   return dev(c, launch_evaluate_lp(c->dt, c->genomes[c->cur], c->nd, c->cfg.pop, c->xq, c->kp,
-                                   c->w_amax[c->cur], c->x_amax, y, b, c->partial, c->stream),
+                                   c->w_bound, c->x_amax, y, b, c->partial, c->stream),
              "evaluate launch");
 }
 
@@ -314,6 +362,16 @@ leea_status run_eval(leea_ctx* c, const float* x, const int32_t* y, int32_t b, b
     if (st) return st;
     return dev(c, launch_evaluate_small_bf16(c->genomes[c->cur], c->nd, c->cfg.pop, c->wsh, x, y,
                                              b, c->partial, c->stream, fin),
+               "evaluate launch");
+  }
+  if (c->dt == LEEA_DT_FP8 && b <= 16 && c->w8.p) {
+    st = fp8_ready(c);
+    if (!st) st = dev(c, launch_fill((float*)c->x_amax, 1, 0.0f, c->stream), "amax clear");
+    if (!st)
+      st = dev(c, launch_amax(x, (int64_t)b * c->nd.w[0], c->x_amax, c->stream), "amax launch");
+    if (st) return st;
+    return dev(c, launch_evaluate_small_fp8(c->genomes[c->cur], c->nd, c->cfg.pop, c->w8, x,
+                                            c->x_amax, y, b, c->partial, c->stream, fin),
                "evaluate launch");
   }
   if (c->dt == LEEA_DT_F32) {
@@ -446,6 +504,18 @@ leea_status leea_init_population(const leea_config* cfg, void* workspace, size_t
   c->wsh.kp = padded_k(nd.w[0]);
   c->wsh.rcp_n0 = 1.0f / (float)nd.w[0];
   c->wsh_ok = 0;
+  p += cv.wsh;
+  c->w_bound = (uint32_t*)p;
+  p += cv.scalars;
+  c->w8.p = cv.w8 ? (uint8_t*)p : nullptr;
+  c->w8.net = fp8_net(nd);
+  c->w8.n0 = nd.w[0];
+  c->w8.nrp = (nd.w[1] + 15) & ~15;
+  c->w8.kp = fp8_kp(nd.w[0]);
+  c->w8.rcp_n0 = 1.0f / (float)nd.w[0];
+  c->w8.amax_par = nullptr;
+  c->w8.bound = c->w_bound;
+  c->w8_ok = 0;
   c->dt = cfg->eval_dtype;
   c->kp = padded_k(nd.w[0]);
   c->n_mt_max = (cfg->max_batch + 63) / 64;
@@ -469,9 +539,10 @@ leea_status leea_init_population(const leea_config* cfg, void* workspace, size_t
            "init launch");
   if (!st && cfg->sigma_mode == LEEA_SIGMA_SELF_ADAPTIVE)
     st = dev(nullptr, launch_fill(c->sig[0], cfg->pop, cfg->sigma, c->stream), "sigma fill");
-  if (!st && c->dt == LEEA_DT_FP8)
-    st = dev(nullptr, launch_amax_w1(c->genomes[0], nd, cfg->pop, c->w_amax[0], c->stream),
-             "amax launch");
+  if (!st && c->dt == LEEA_DT_FP8) {
+    st = fp8_ready(c);
+    if (st) fail(nullptr, st, "%s", c->err.c_str());
+  }
   // the whole copy, padding included (the variation writes only W_1 itself)
   if (!st && c->wsh.p)
     st = dev(nullptr, launch_shadow_w1(c->genomes[0], nd, cfg->pop, c->wsh, c->stream),
@@ -586,13 +657,20 @@ leea_status leea_crossover_mutate(leea_ctx* c) {
   float* sig_next;
   vary_sigma(c, g, &sigma, &sig_cur, &sig_next);
   uint32_t* amax = c->dt == LEEA_DT_FP8 ? c->w_amax[c->cur ^ 1] : nullptr;
-  leea_status st = LEEA_OK;
-  if (amax) st = dev(c, launch_fill((float*)amax, c->cfg.pop, 0.0f, c->stream), "amax clear");
+  leea_status st = fp8_ready(c);  // the parents' largest magnitudes
+  if (!st && amax) st = dev(c, launch_fill((float*)amax, c->cfg.pop, 0.0f, c->stream), "amax clear");
   if (st) return st;
+  W1Fp8 w8 = c->w8;
+  if (c->dt == LEEA_DT_FP8) {
+    w8.amax_par = c->w_amax[c->cur];
+    w8.bound = c->w_bound;
+  } else {
+    w8.bound = nullptr;
+  }
   st = dev(c,
            launch_vary(c->genomes[c->cur], c->genomes[c->cur ^ 1], c->plan, c->nd, c->cfg.pop,
                        c->cfg.crossover, sigma, c->cfg.mut_threshold, key_of(c), g, sig_cur,
-                       sig_next, c->tau, amax, c->wsh, c->stream),
+                       sig_next, c->tau, amax, c->wsh, w8, c->stream),
            "vary launch");
   if (st) return st;
   c->wsh_ok = c->wsh.p ? 1 : 0;  // the variation wrote the children's copies
@@ -707,11 +785,11 @@ leea_status leea_set_state(leea_ctx* c, const float* src, const float* f_adj,
   if (!st && f_inh)
     st = dev(c, hipMemcpyAsync(c->f_inh, f_inh, sbytes, hipMemcpyDeviceToDevice, c->stream),
              "f_inh copy");
-  if (!st && src && c->dt == LEEA_DT_FP8)
-    st = dev(c, launch_amax_w1(c->genomes[c->cur], c->nd, c->cfg.pop, c->w_amax[c->cur],
-                               c->stream), "amax launch");
   if (st) return st;
-  if (src) c->wsh_ok = 0;
+  if (src) {
+    c->wsh_ok = 0;
+    c->w8_ok = 0;
+  }
   c->has_inh = f_inh ? 1 : 0;
   c->state = f_adj ? kEvaluated : kNeedEval;
   return LEEA_OK;
@@ -786,11 +864,9 @@ leea_status leea_load(leea_ctx* c, const void* host_buf, size_t bytes) {
     st = dev(c, hipMemcpy(arr[i], p, sbytes, hipMemcpyHostToDevice), "load");
     p += sbytes;
   }
-  if (!st && c->dt == LEEA_DT_FP8)
-    st = dev(c, launch_amax_w1(c->genomes[c->cur], c->nd, c->cfg.pop, c->w_amax[c->cur],
-                               c->stream), "amax launch");
   if (st) return st;
   c->wsh_ok = 0;
+  c->w8_ok = 0;
   c->gen = h.gen;
   // a checkpoint taken between select and crossover_mutate resumes at select
   c->state = h.state == kSelected ? kEvaluated : (int)h.state;
@@ -1012,11 +1088,9 @@ leea_status leea_surrogate_step(leea_ctx* c, const float* x, const int32_t* y, i
                               g.pop, g.n_elite, c->plan, c->schosen, c->f_adj, c->scf_inh,
                               c->f_inh_next, s),
              "gather");
-  if (!st && c->dt == LEEA_DT_FP8)
-    st = dev(c, launch_amax_w1(c->genomes[c->cur ^ 1], c->nd, g.pop, c->w_amax[c->cur ^ 1], s),
-             "amax launch");
   if (st) return st;
   c->wsh_ok = 0;  // the new population came from the candidates
+  c->w8_ok = 0;
   advance(c);
   st = run_eval(c, x, y, b, true, f_adj, f_raw, acc);
   if (st) return st;

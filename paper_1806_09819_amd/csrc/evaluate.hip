@@ -311,6 +311,79 @@ __global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void eval_small_bf16_kernel(
                                     fin);
 }
 
+// ------------------------------------------------------- b <= 16, FP8 --
+// The small-batch scheme with an FP8 (E4M3) first layer on the FP8 matrix
+// cores, reading W_1 from its FP8 copy (a quarter of the float32 genome's
+// bytes).  Lane l = (mn, kq) loads 16 codes of W_1 row 16 t + mn at
+// k = 64 s + 16 kq .. + 15 (16 bytes) and the same 16 elements of batch row
+// mn (float32, scaled by 2^-e_x and rounded on the way); its first 8 feed one
+// v_mfma_f32_16x16x32_fp8_fp8 and its last 8 a second, so the two products
+// cover the 64-wide step between them (the K order inside a step is a
+// permutation shared by both operands).  Waves split the steps
+// s = wave, wave + 4, ...; the sums are multiplied by 2^(e_x + e_w) (NaN if
+// either operand is not finite) before the bias.
+__device__ __forceinline__ floatx4 mfma_fp8x32(uint32_t a0, uint32_t a1, uint32_t b0, uint32_t b1,
+                                               const floatx4& c) {
+  const unsigned long long a = (unsigned long long)a0 | ((unsigned long long)a1 << 32);
+  const unsigned long long b = (unsigned long long)b0 | ((unsigned long long)b1 << 32);
+  return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8((long)a, (long)b, c, 0, 0, 0);
+}
+
+template <int NT>
+__global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void eval_small_fp8_kernel(
+    const float* __restrict__ genomes, NetDesc nd, W1Fp8 w8, const float* __restrict__ x,
+    const uint32_t* __restrict__ x_amax, const int32_t* __restrict__ y, int b,
+    float2* __restrict__ partial, EvalLds lo, int tail_vec, FinArgs fin) {
+  const int j = blockIdx.x;
+  const int tid = threadIdx.x;
+  const float* __restrict__ genome = genomes + (int64_t)j * nd.stride;
+  const int n0 = nd.w[0];
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int mn = lane & 15;
+  const int kq = lane >> 4;
+  const uint32_t xam = *x_amax;
+  const int neg_ex = xam < kNonFinite ? -fp8_exponent(xam) : 0;
+  const float fac = fp8_factor(xam, w8.bound[j]);
+  const bool xv = mn < b;
+  const float* __restrict__ xrow = x + (int64_t)(xv ? mn : 0) * n0;
+  const uint8_t* __restrict__ crow[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) crow[t] = w8.p + (int64_t)j * w8.net + (int64_t)(t * 16 + mn) * w8.kp;
+  floatx4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  auto xq4 = [&](int k) {  // 4 batch elements k .. k + 3 -> one word of codes
+    const float4 v = (xv && k < n0) ? *reinterpret_cast<const float4*>(xrow + k) : zero4();
+    return pack_fp8x4(ldexpf(v.x, neg_ex), ldexpf(v.y, neg_ex), ldexpf(v.z, neg_ex),
+                      ldexpf(v.w, neg_ex));
+  };
+  const int nss = w8.kp >> 6;
+  uint4 xa, wb[NT];
+  auto load = [&](int s, uint4& xo, uint4* wo) {
+    const int k = 64 * s + 16 * kq;
+    xo = make_uint4(xq4(k), xq4(k + 4), xq4(k + 8), xq4(k + 12));
+#pragma unroll
+    for (int t = 0; t < NT; ++t) wo[t] = *reinterpret_cast<const uint4*>(crow[t] + k);
+  };
+  int s = wave;
+  if (s < nss) load(s, xa, wb);
+  for (; s < nss; s += 4) {
+    uint4 xn, wn[NT];
+    if (s + 4 < nss) load(s + 4, xn, wn);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = mfma_fp8x32(xa.x, xa.y, wb[t].x, wb[t].y, acc[t]);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = mfma_fp8x32(xa.z, xa.w, wb[t].z, wb[t].w, acc[t]);
+    if (s + 4 < nss) {
+      xa = xn;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) wb[t] = wn[t];
+    }
+  }
+  small_epilogue<NT, true>(acc, fac, j, genome, nd, y, b, partial, lo, tail_vec, fin);
+}
+
 // ------------------------------------------------------- b <= 4, FP32 --
 // Layer 1 on the vector ALUs with W_1 streamed row by row.  The K range is
 // split in two halves (k < ka and k >= ka, ka = 4 floor(n0 / 8)); waves 0 and
@@ -726,6 +799,21 @@ static hipError_t launch_small_bf16(const float* genomes, const NetDesc& nd, int
   return hipGetLastError();
 }
 
+template <int NT>
+static hipError_t launch_small_fp8(const float* genomes, const NetDesc& nd, int pop,
+                                   const W1Fp8& w8, const float* x, const uint32_t* x_amax,
+                                   const int32_t* y, int b, float2* partial, hipStream_t s,
+                                   const FinArgs& fin) {
+  const int tv = tail_vectorizable(nd) ? 1 : 0;
+  EvalLds lo;
+  const size_t bytes = small_lds_bytes(nd, &lo);
+  hipError_t e = allow_lds(eval_small_fp8_kernel<NT>, bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((eval_small_fp8_kernel<NT>), dim3((unsigned)pop), dim3(256), bytes, s,
+                     genomes, nd, w8, x, x_amax, y, b, partial, lo, tv, fin);
+  return hipGetLastError();
+}
+
 template <int NT, int MW, bool RT>
 static hipError_t launch_large(const float* genomes, const NetDesc& nd, int pop, const float* x,
                                const int32_t* y, int b, float2* partial, int n_pt, int tv,
@@ -858,6 +946,14 @@ hipError_t launch_evaluate_small_bf16(const float* genomes, const NetDesc& nd, i
                                       const W1Shadow& wsh, const float* x, const int32_t* y,
                                       int b, float2* partial, hipStream_t s, const FinArgs& fin) {
   LEEA_NT_SWITCH((launch_small_bf16<N>(genomes, nd, pop, wsh, x, y, b, partial, s, fin)),
+                 hipErrorInvalidValue)
+}
+
+hipError_t launch_evaluate_small_fp8(const float* genomes, const NetDesc& nd, int pop,
+                                     const W1Fp8& w8, const float* x, const uint32_t* x_amax,
+                                     const int32_t* y, int b, float2* partial, hipStream_t s,
+                                     const FinArgs& fin) {
+  LEEA_NT_SWITCH((launch_small_fp8<N>(genomes, nd, pop, w8, x, x_amax, y, b, partial, s, fin)),
                  hipErrorInvalidValue)
 }
 

@@ -44,6 +44,13 @@ __device__ __forceinline__ floatx4 mfma_bf16(const uint4& a, const uint4& b, con
                                                  __builtin_bit_cast(bf16x8w, b), c, 0, 0, 0);
 }
 
+__device__ __forceinline__ floatx4 mfma_fp8(uint32_t a0, uint32_t a1, uint32_t b0, uint32_t b1,
+                                            const floatx4& c) {
+  const unsigned long long a = (unsigned long long)a0 | ((unsigned long long)a1 << 32);
+  const unsigned long long b = (unsigned long long)b0 | ((unsigned long long)b1 << 32);
+  return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8((long)a, (long)b, c, 0, 0, 0);
+}
+
 // Wait until at most N copies of this wave are in flight and its LDS reads
 // are done, then the workgroup barrier; the compiler moves no memory access
 // across either side.
@@ -75,11 +82,21 @@ constexpr int lpw_lds_bytes(int nt, int mw) {
   return lpw_stage1_bytes(nt, mw) + (lpw_stages(nt, mw) - 1) * lpw_stage_bytes(nt, mw);
 }
 
-template <int NT, int MW>
+// DT = 1: bfloat16 (32-element K chunks, one v_mfma_f32_16x16x32_bf16 per
+// tile pair and chunk).  DT = 2: FP8 E4M3 from the FP8 copy of W_1 and the
+// FP8 chunk-major batch (64-element chunks: the 16 bytes of a lane feed two
+// v_mfma_f32_16x16x32_fp8_fp8, its first and its last 8 codes, a K
+// permutation both operands share); the sums are multiplied by
+// 2^(e_x + e_w) (NaN for a non-finite operand) before the bias.  Either way a
+// staged row piece is 64 bytes, so the blocks, the swizzle and the stage plan
+// are the same.  wp: the copy, wnet bytes per network, wrow bytes per row.
+template <int NT, int MW, int DT>
 __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lpw_kernel(
-    const float* __restrict__ genomes, NetDesc nd, W1Shadow wsh, const uint16_t* __restrict__ xq,
-    int nch, int bpad, const int32_t* __restrict__ y, int b, float2* __restrict__ partial,
-    int n_wt, int n_pt, int pop) {
+    const float* __restrict__ genomes, NetDesc nd, const char* __restrict__ wp, int64_t wnet,
+    int64_t wrow, const char* __restrict__ xq, int nch, int bpad,
+    const uint32_t* __restrict__ x_amax, const uint32_t* __restrict__ w_bound,
+    const int32_t* __restrict__ y, int b, float2* __restrict__ partial, int n_wt, int n_pt,
+    int pop) {
   constexpr int S = lpw_stages(NT, MW);
   constexpr int RB = 64;                // bytes per staged row (32 bfloat16)
   constexpr int MT = 64 * MW;           // rows per workgroup
@@ -114,7 +131,6 @@ __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lpw_kernel(
   // which holds logical slot (lane % 4) ^ ((r >> 1) & 3)
   const int r = lane >> 2;
   const int slot = ((lane & 3) ^ ((r >> 1) & 3)) * 16;
-  const int64_t wrow = (int64_t)wsh.kp * 2;  // bytes per row of the W_1 copy
   const char* src[Q];
   int64_t cstride[Q];
   int dst[Q];
@@ -123,12 +139,11 @@ __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lpw_kernel(
     int i = q * 4 + wave;
     if (i >= NB) i -= 4;
     if (i < NT) {
-      src[q] = reinterpret_cast<const char*>(wsh.p + (int64_t)j * wsh.net) +
-               (16 * i + r) * wrow + slot;
+      src[q] = wp + (int64_t)j * wnet + (16 * i + r) * wrow + slot;
       cstride[q] = RB;
       dst[q] = i * 1024;
     } else {
-      src[q] = reinterpret_cast<const char*>(xq) + (int64_t)(m0 + 16 * (i - NT) + r) * RB + slot;
+      src[q] = xq + (int64_t)(m0 + 16 * (i - NT) + r) * RB + slot;
       cstride[q] = (int64_t)bpad * RB;
       dst[q] = NR * RB + (i - NT) * 1024;
     }
@@ -191,8 +206,14 @@ __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lpw_kernel(
 #pragma unroll
     for (int mi = 0; mi < MW; ++mi)
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
-        acc[mi][t] = mfma_bf16(bq[t], a[mi], acc[mi][t]);  // W_1 X^T
+      for (int t = 0; t < NT; ++t) {
+        if constexpr (DT == 1) {
+          acc[mi][t] = mfma_bf16(bq[t], a[mi], acc[mi][t]);  // W_1 X^T
+        } else {
+          acc[mi][t] = mfma_fp8(bq[t].x, bq[t].y, a[mi].x, a[mi].y, acc[mi][t]);
+          acc[mi][t] = mfma_fp8(bq[t].z, bq[t].w, a[mi].z, a[mi].w, acc[mi][t]);
+        }
+      }
   };
 
   // Stage of chunk ch is ch % S; the loop is unrolled by S so that every
@@ -230,7 +251,8 @@ __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lpw_kernel(
 #pragma unroll
   for (int q = 0; q < TQ; ++q) reinterpret_cast<float4*>(st1)[tid + 256 * q] = tv[q];
   __syncthreads();
-  reg_tail<NT, MW>(acc, 1.0f, reinterpret_cast<const float*>(st1), nd, m0, wave * MW * 16, b,
+  const float fac = DT == 2 ? fp8_factor(*x_amax, w_bound[j]) : 1.0f;
+  reg_tail<NT, MW>(acc, fac, reinterpret_cast<const float*>(st1), nd, m0, wave * MW * 16, b,
                    ylab, reinterpret_cast<float*>(st0), partial + (int64_t)j * n_pt, m0 / 64);
 }
 
@@ -421,25 +443,52 @@ int lpw_mw(const NetDesc& nd, int b) {
   return 0;
 }
 
-template <int NT, int MW>
-hipError_t launch_lpw3(const float* genomes, const NetDesc& nd, int pop, const W1Shadow& wsh,
-                       const uint16_t* xq, int kp, int bpad, const int32_t* y, int b,
-                       float2* partial, hipStream_t s) {
+// The copy operands of one launch: W_1 copy (bytes per network and per row)
+// and the chunk-major batch; FP8 also the scale sources.
+struct LpwArgs {
+  const char* wp;
+  int64_t wnet, wrow;
+  const char* xq;
+  int nch, bpad;
+  const uint32_t* x_amax;
+  const uint32_t* w_bound;
+};
+
+template <int NT, int MW, int DT>
+hipError_t launch_lpw3(const float* genomes, const NetDesc& nd, int pop, const LpwArgs& a,
+                       const int32_t* y, int b, float2* partial, hipStream_t s) {
   const int n_wt = (b + 64 * MW - 1) / (64 * MW);
   const int n_pt = (b + 63) / 64;
-  hipLaunchKernelGGL((eval_lpw_kernel<NT, MW>), dim3((unsigned)(n_wt * pop)), dim3(256), 0, s,
-                     genomes, nd, wsh, xq, kp >> 5, bpad, y, b, partial, n_wt, n_pt, pop);
+  hipLaunchKernelGGL((eval_lpw_kernel<NT, MW, DT>), dim3((unsigned)(n_wt * pop)), dim3(256), 0,
+                     s, genomes, nd, a.wp, a.wnet, a.wrow, a.xq, a.nch, a.bpad, a.x_amax,
+                     a.w_bound, y, b, partial, n_wt, n_pt, pop);
   return hipGetLastError();
 }
 
-template <int NT>
-hipError_t launch_lpw_nt(const float* genomes, const NetDesc& nd, int pop, const W1Shadow& wsh,
-                         const uint16_t* xq, int kp, int bpad, const int32_t* y, int b,
-                         float2* partial, hipStream_t s) {
+template <int NT, int DT>
+hipError_t launch_lpw_nt(const float* genomes, const NetDesc& nd, int pop, const LpwArgs& a,
+                         const int32_t* y, int b, float2* partial, hipStream_t s) {
   const int mw = lpw_mw(nd, b);
-  if (mw == 2) return launch_lpw3<NT, 2>(genomes, nd, pop, wsh, xq, kp, bpad, y, b, partial, s);
-  if (mw == 1) return launch_lpw3<NT, 1>(genomes, nd, pop, wsh, xq, kp, bpad, y, b, partial, s);
+  if (mw == 2) return launch_lpw3<NT, 2, DT>(genomes, nd, pop, a, y, b, partial, s);
+  if (mw == 1) return launch_lpw3<NT, 1, DT>(genomes, nd, pop, a, y, b, partial, s);
   return hipErrorInvalidValue;
+}
+
+template <int DT>
+hipError_t launch_lpw_any(const float* genomes, const NetDesc& nd, int pop, const LpwArgs& a,
+                          const int32_t* y, int b, float2* partial, hipStream_t s) {
+  switch ((nd.w[1] + 15) / 16) {
+#define LEEA_LPW_CASE(N) \
+  case N:                \
+    return launch_lpw_nt<N, DT>(genomes, nd, pop, a, y, b, partial, s);
+    LEEA_LPW_CASE(1) LEEA_LPW_CASE(2) LEEA_LPW_CASE(3) LEEA_LPW_CASE(4) LEEA_LPW_CASE(5)
+    LEEA_LPW_CASE(6) LEEA_LPW_CASE(7) LEEA_LPW_CASE(8) LEEA_LPW_CASE(9) LEEA_LPW_CASE(10)
+    LEEA_LPW_CASE(11) LEEA_LPW_CASE(12) LEEA_LPW_CASE(13) LEEA_LPW_CASE(14) LEEA_LPW_CASE(15)
+    LEEA_LPW_CASE(16)
+#undef LEEA_LPW_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
@@ -521,18 +570,19 @@ hipError_t launch_evaluate_lpw(const float* genomes, const NetDesc& nd, int pop,
                                const W1Shadow& wsh, const uint16_t* xq, int kp, int bpad,
                                const int32_t* y, int b, float2* partial, hipStream_t s) {
   if (!wsh.p || bpad % 128 != 0 || bpad < b) return hipErrorInvalidValue;
-  switch ((nd.w[1] + 15) / 16) {
-#define LEEA_LPW_CASE(N) \
-  case N:                \
-    return launch_lpw_nt<N>(genomes, nd, pop, wsh, xq, kp, bpad, y, b, partial, s);
-    LEEA_LPW_CASE(1) LEEA_LPW_CASE(2) LEEA_LPW_CASE(3) LEEA_LPW_CASE(4) LEEA_LPW_CASE(5)
-    LEEA_LPW_CASE(6) LEEA_LPW_CASE(7) LEEA_LPW_CASE(8) LEEA_LPW_CASE(9) LEEA_LPW_CASE(10)
-    LEEA_LPW_CASE(11) LEEA_LPW_CASE(12) LEEA_LPW_CASE(13) LEEA_LPW_CASE(14) LEEA_LPW_CASE(15)
-    LEEA_LPW_CASE(16)
-#undef LEEA_LPW_CASE
-    default:
-      return hipErrorInvalidValue;
-  }
+  const LpwArgs a{reinterpret_cast<const char*>(wsh.p), wsh.net * 2, (int64_t)wsh.kp * 2,
+                  reinterpret_cast<const char*>(xq), kp >> 5, bpad, nullptr, nullptr};
+  return launch_lpw_any<1>(genomes, nd, pop, a, y, b, partial, s);
+}
+
+hipError_t launch_evaluate_lpw8(const float* genomes, const NetDesc& nd, int pop,
+                                const W1Fp8& w8, const uint8_t* xq, int bpad,
+                                const uint32_t* x_amax, const int32_t* y, int b, float2* partial,
+                                hipStream_t s) {
+  if (!w8.p || bpad % 128 != 0 || bpad < b) return hipErrorInvalidValue;
+  const LpwArgs a{reinterpret_cast<const char*>(w8.p), w8.net, (int64_t)w8.kp,
+                  reinterpret_cast<const char*>(xq), w8.kp >> 6, bpad, x_amax, w8.bound};
+  return launch_lpw_any<2>(genomes, nd, pop, a, y, b, partial, s);
 }
 
 }  // namespace leea

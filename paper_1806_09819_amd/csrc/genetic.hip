@@ -73,7 +73,24 @@ hipError_t launch_init(float* genomes, const NetDesc& nd, const Glorot& ga, int 
 // kShadow: also write the child's W_1 rounded to bfloat16 into its W1Shadow
 // slot (n0 % 4 == 0: a float4 of W_1 is 4 consecutive k of one row, one
 // 8-byte store; a wave's stores are contiguous within each row).
-template <int kXoKind, bool kAmax, bool kNorm = false, bool kShadow = false>
+// kFp8: also write the child's W_1 into its FP8 copy, scaled by 2^-e with e
+// from the child's bound (from its parents' largest magnitudes), which the
+// first workgroup of the child stores.
+__device__ __forceinline__ uint32_t fp8_child_bound(const int4& pl, const uint32_t* amax,
+                                                    float sigma) {
+#pragma clang fp contract(off)
+  const uint32_t a1 = amax[pl.y];
+  if (pl.x == kOpElite) return a1;
+  if (pl.x == kOpCross) {
+    const uint32_t a2 = amax[pl.z];
+    return a1 > a2 ? a1 : a2;  // magnitude bits: NaN above inf above every number
+  }
+  const float t = __uint_as_float(a1) * (1.0f + 0x1p-20f);
+  const float m = 6.0f * sigma;
+  return mag_bits(t + m);
+}
+
+template <int kXoKind, bool kAmax, bool kNorm = false, bool kShadow = false, bool kFp8 = false>
 __device__ __forceinline__ void vary_body(int j, int gx, const float* __restrict__ cur,
                                           float* __restrict__ nxt, const int4* __restrict__ plan,
                                           int64_t stride, int64_t genes, float sigma,
@@ -82,7 +99,8 @@ __device__ __forceinline__ void vary_body(int j, int gx, const float* __restrict
                                           float* __restrict__ sig_next, float tau,
                                           uint32_t* __restrict__ amax, int64_t w1n,
                                           uint32_t slot_off = 0, float* __restrict__ nu = nullptr,
-                                          int ngroups = 0, W1Shadow wsh = W1Shadow{}) {
+                                          int ngroups = 0, W1Shadow wsh = W1Shadow{},
+                                          W1Fp8 w8 = W1Fp8{}) {
 #pragma clang fp contract(off)
   const uint32_t pslot = (uint32_t)j + slot_off;
   const int wave = threadIdx.x >> 6;
@@ -94,6 +112,12 @@ __device__ __forceinline__ void vary_body(int j, int gx, const float* __restrict
   if (sig_cur) {
     sigma = child_sigma(pl, sig_cur, key, gen, pslot, tau);
     if (gx == 0 && threadIdx.x == 0) sig_next[j] = sigma;
+  }
+  int neg_e8 = 0;
+  if (kFp8) {
+    const uint32_t bnd = fp8_child_bound(pl, w8.amax_par, sigma);
+    if (gx == 0 && threadIdx.x == 0) w8.bound[j] = bnd;
+    neg_e8 = bnd < kNonFinite ? -fp8_exponent(bnd) : 0;
   }
   if (G * 2048 >= n4) return;
   const float4* __restrict__ a4 = reinterpret_cast<const float4*>(cur + (int64_t)pl.y * stride);
@@ -112,7 +136,23 @@ __device__ __forceinline__ void vary_body(int j, int gx, const float* __restrict
     }
   };
   uint16_t* __restrict__ sh = kShadow ? wsh.p + (int64_t)j * wsh.net : nullptr;
+  uint8_t* __restrict__ s8 = (kFp8 && w8.p) ? w8.p + (int64_t)j * w8.net : nullptr;
   auto track = [&](int64_t f, const float4& o) {
+    if (kFp8 && s8 && f < w1f) {
+      const int g = (int)(4 * f);
+      int n = (int)((float)g * w8.rcp_n0);  // g < 2^24: off by at most one
+      int k = g - n * w8.n0;
+      if (k < 0) {
+        n -= 1;
+        k += w8.n0;
+      } else if (k >= w8.n0) {
+        n += 1;
+        k -= w8.n0;
+      }
+      const uint32_t q = pack_fp8x4(ldexpf(o.x, neg_e8), ldexpf(o.y, neg_e8),
+                                    ldexpf(o.z, neg_e8), ldexpf(o.w, neg_e8));
+      __builtin_nontemporal_store(q, reinterpret_cast<uint32_t*>(s8 + (int64_t)n * w8.kp + k));
+    }
     if (kShadow && f < w1f) {
       const int g = (int)(4 * f);
       int n = (int)((float)g * wsh.rcp_n0);  // g < 2^24: off by at most one
@@ -223,7 +263,7 @@ __device__ __forceinline__ void vary_body(int j, int gx, const float* __restrict
   }
 }
 
-template <int kXoKind, bool kAmax, bool kShadow>
+template <int kXoKind, bool kAmax, bool kShadow, bool kFp8>
 __global__ __launch_bounds__(256) void vary_kernel(const float* __restrict__ cur,
                                                    float* __restrict__ nxt,
                                                    const int4* __restrict__ plan,
@@ -232,11 +272,11 @@ __global__ __launch_bounds__(256) void vary_kernel(const float* __restrict__ cur
                                                    uint32_t mul, const float* __restrict__ sig_cur,
                                                    float* __restrict__ sig_next, float tau,
                                                    uint32_t* __restrict__ amax, int64_t w1n,
-                                                   W1Shadow wsh) {
+                                                   W1Shadow wsh, W1Fp8 w8) {
   const int j = (int)(((uint64_t)blockIdx.y * mul) % (uint32_t)pop);
-  vary_body<kXoKind, kAmax, false, kShadow>(j, blockIdx.x, cur, nxt, plan, stride, genes, sigma,
-                                            thr, key, gen, sig_cur, sig_next, tau, amax, w1n, 0,
-                                            nullptr, 0, wsh);
+  vary_body<kXoKind, kAmax, false, kShadow, kFp8>(j, blockIdx.x, cur, nxt, plan, stride, genes,
+                                                  sigma, thr, key, gen, sig_cur, sig_next, tau,
+                                                  amax, w1n, 0, nullptr, 0, wsh, w8);
 }
 
 // Candidate children of the fitness surrogate: plan index j, random draws
@@ -275,30 +315,37 @@ uint32_t slot_multiplier(int pop) {
 hipError_t launch_vary(const float* cur, float* nxt, const int4* plan, const NetDesc& nd,
                        int pop, int crossover, float sigma, uint64_t mut_threshold,
                        const Key& key, uint32_t gen, const float* sig_cur, float* sig_next,
-                       float tau, uint32_t* amax, const W1Shadow& wsh, hipStream_t s) {
+                       float tau, uint32_t* amax, const W1Shadow& wsh, const W1Fp8& w8,
+                       hipStream_t s) {
   const int64_t groups = (nd.stride + 8191) / 8192;
   dim3 grid((unsigned)((groups + 3) / 4), (unsigned)pop);
   const uint32_t mul = slot_multiplier(pop);
   const int64_t w1n = (int64_t)nd.w[0] * nd.w[1];
-#define LEEA_VARY(XO, AM, SH)                                                                 \
-  hipLaunchKernelGGL((vary_kernel<XO, AM, SH>), grid, dim3(256), 0, s, cur, nxt, plan,         \
+#define LEEA_VARY(XO, AM, SH, F8)                                                              \
+  hipLaunchKernelGGL((vary_kernel<XO, AM, SH, F8>), grid, dim3(256), 0, s, cur, nxt, plan,     \
                      nd.stride, nd.genes, sigma, mut_threshold, key, gen, pop, mul, sig_cur,     \
-                     sig_next, tau, amax, w1n, wsh)
-  const int kind = amax ? 1 : (wsh.p ? 2 : 0);
+                     sig_next, tau, amax, w1n, wsh, w8)
+  // kind: 0 genomes only; 1 + exact largest |W_1|; 2 + bfloat16 copy; 3 + exact
+  // largest |W_1|, the FP8 scale bounds and (if kept) the FP8 copy
+  const int kind = amax ? (w8.bound ? 3 : 1) : (wsh.p ? 2 : 0);
   if (crossover == 0) {
     if (kind == 1)
-      LEEA_VARY(0, true, false);
+      LEEA_VARY(0, true, false, false);
     else if (kind == 2)
-      LEEA_VARY(0, false, true);
+      LEEA_VARY(0, false, true, false);
+    else if (kind == 3)
+      LEEA_VARY(0, true, false, true);
     else
-      LEEA_VARY(0, false, false);
+      LEEA_VARY(0, false, false, false);
   } else {
     if (kind == 1)
-      LEEA_VARY(1, true, false);
+      LEEA_VARY(1, true, false, false);
     else if (kind == 2)
-      LEEA_VARY(1, false, true);
+      LEEA_VARY(1, false, true, false);
+    else if (kind == 3)
+      LEEA_VARY(1, true, false, true);
     else
-      LEEA_VARY(1, false, false);
+      LEEA_VARY(1, false, false, false);
   }
 #undef LEEA_VARY
   return hipGetLastError();

@@ -49,13 +49,34 @@ struct W1Shadow {
   float rcp_n0;  // 1 / n0 (row of a W_1 gene index below 2^24: one fix-up step)
 };
 
+// FP8 (OCP E4M3) copy of every network's W_1 with its per-network
+// power-of-two scale: element (n, k) of network j is p[j * net + n * kp + k],
+// the E4M3 code of W_1[n][k] * 2^-e_j, rows padded to nrp = n1 rounded up to
+// 16 and K to kp = n0 rounded up to 64 (padding zero).  e_j is the smallest
+// integer with B_j <= 448 * 2^e_j for the bound B_j held as magnitude bits in
+// bound[j]: the network's largest |W_1| after initialisation or a restore;
+// for a child, the bound its parents give (elite: the parent's largest
+// magnitude; crossover: the larger parent's; mutant: fl(fl(a (1 + 2^-20)) +
+// fl(6 sigma))), which the variation kernel knows before it writes the
+// child.  amax_par: the parents' exact largest magnitudes (read by the
+// variation kernel).  p == nullptr: no copy.
+struct W1Fp8 {
+  uint8_t* p;
+  int64_t net;
+  int n0, nrp, kp;
+  float rcp_n0;
+  const uint32_t* amax_par;
+  uint32_t* bound;
+};
+
 // init.hip / vary.hip / batch.hip
 hipError_t launch_init(float* genomes, const NetDesc& nd, const Glorot& ga, int pop,
                        const Key& key, hipStream_t s);
 hipError_t launch_vary(const float* cur, float* nxt, const int4* plan, const NetDesc& nd,
                        int pop, int crossover, float sigma, uint64_t mut_threshold,
                        const Key& key, uint32_t gen, const float* sig_cur, float* sig_next,
-                       float tau, uint32_t* amax, const W1Shadow& wsh, hipStream_t s);
+                       float tau, uint32_t* amax, const W1Shadow& wsh, const W1Fp8& w8,
+                       hipStream_t s);
 hipError_t launch_draw_batch(const float* x_train, const int32_t* y_train, int64_t n_train,
                              int n_in, int side, int b, float* x_out, int32_t* y_out,
                              const Key& key, uint32_t gen, hipStream_t s);
@@ -139,9 +160,29 @@ hipError_t launch_quantize_x_chunks(const float* x, int b, int n0, int kp, int b
                                     uint16_t* xq, hipStream_t s);
 hipError_t launch_shadow_w1(const float* genomes, const NetDesc& nd, int pop,
                             const W1Shadow& wsh, hipStream_t s);
+// The FP8 copy rebuilt from the genomes with the scales of w8.bound.
+hipError_t launch_fp8_copy(const float* genomes, const NetDesc& nd, int pop, const W1Fp8& w8,
+                           hipStream_t s);
+// FP8 first layer for b <= 16 on the FP8 matrix cores from the FP8 copy; the
+// batch x (float32) is scaled by 2^-e_x (e_x from *x_amax) and rounded on the
+// way; finishes each network itself when fin.on.
+hipError_t launch_evaluate_small_fp8(const float* genomes, const NetDesc& nd, int pop,
+                                     const W1Fp8& w8, const float* x, const uint32_t* x_amax,
+                                     const int32_t* y, int b, float2* partial, hipStream_t s,
+                                     const FinArgs& fin);
 hipError_t launch_evaluate_lpw(const float* genomes, const NetDesc& nd, int pop,
                                const W1Shadow& wsh, const uint16_t* xq, int kp, int bpad,
                                const int32_t* y, int b, float2* partial, hipStream_t s);
+// The same pipeline with an FP8 first layer from the FP8 copy (same shapes as
+// eval_lpw_supported): the batch chunk-major in E4M3 codes
+// (xq[((k >> 6) * bpad + m) * 64 + (k & 63)], scaled by 2^-e_x, rows b ..
+// bpad - 1 zero) from launch_quantize_x_chunks8.
+hipError_t launch_quantize_x_chunks8(const float* x, int b, int n0, int kp8, int bpad,
+                                     const uint32_t* x_amax, uint8_t* xq, hipStream_t s);
+hipError_t launch_evaluate_lpw8(const float* genomes, const NetDesc& nd, int pop,
+                                const W1Fp8& w8, const uint8_t* xq, int bpad,
+                                const uint32_t* x_amax, const int32_t* y, int b, float2* partial,
+                                hipStream_t s);
 // The float32 large-batch kernel with LDS staging by global -> LDS copies
 // (bitwise equal to the register-staged one): whether it takes a network,
 // batch size, row tiles per wave (1 or 2) and batch pointer, and the launch

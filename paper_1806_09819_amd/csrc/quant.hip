@@ -174,6 +174,43 @@ hipError_t launch_quantize_x_chunks(const float* x, int b, int n0, int kp, int b
   return hipGetLastError();
 }
 
+// Batch in FP8 E4M3 (scaled by 2^-e_x, e_x from *x_amax), chunk-major for the
+// large-batch kernel that reads the FP8 copy of W_1: slot it (16 elements) =
+// chunk it / (4 bpad), row (it / 4) mod bpad, elements 16 (it mod 4) .. + 15
+// of the 64-element chunk; rows at or past b and k at or past n0 are zero.
+__global__ __launch_bounds__(256) void quantize_chunks8_kernel(const float* __restrict__ x, int b,
+                                                               int n0, int bpad, int64_t items,
+                                                               const uint32_t* __restrict__ x_amax,
+                                                               uint4* __restrict__ out) {
+  const uint32_t am = *x_amax;
+  const int neg_e = am < kNonFinite ? -fp8_exponent(am) : 0;
+  for (int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x; it < items;
+       it += (int64_t)gridDim.x * 256) {
+    const int64_t rs = it >> 2;
+    const int ch = (int)(rs / bpad);
+    const int m = (int)(rs - (int64_t)ch * bpad);
+    const int k = ch * 64 + 16 * (int)(it & 3);
+    float v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+      v[e] = (m < b && k + e < n0) ? ldexpf(x[(int64_t)m * n0 + k + e], neg_e) : 0.0f;
+    uint4 o;
+    o.x = pack_fp8x4(v[0], v[1], v[2], v[3]);
+    o.y = pack_fp8x4(v[4], v[5], v[6], v[7]);
+    o.z = pack_fp8x4(v[8], v[9], v[10], v[11]);
+    o.w = pack_fp8x4(v[12], v[13], v[14], v[15]);
+    out[it] = o;
+  }
+}
+
+hipError_t launch_quantize_x_chunks8(const float* x, int b, int n0, int kp8, int bpad,
+                                     const uint32_t* x_amax, uint8_t* xq, hipStream_t s) {
+  const int64_t items = (int64_t)(kp8 >> 6) * bpad * 4;
+  hipLaunchKernelGGL(quantize_chunks8_kernel, dim3(grid_for(items)), dim3(256), 0, s, x, b, n0,
+                     bpad, items, x_amax, reinterpret_cast<uint4*>(xq));
+  return hipGetLastError();
+}
+
 // The bfloat16 W_1 copy rebuilt from the genomes (after initialisation or a
 // population replaced from outside): slot it of network blockIdx.y = row
 // it / (kp / 8), elements 8 (it mod (kp / 8)) .. + 7.
@@ -204,6 +241,42 @@ hipError_t launch_shadow_w1(const float* genomes, const NetDesc& nd, int pop,
   const int64_t items = wsh.net / 8;
   dim3 grid((unsigned)((items + 255) / 256), (unsigned)pop);
   hipLaunchKernelGGL(shadow_w1_kernel, grid, dim3(256), 0, s, genomes, nd, wsh, items);
+  return hipGetLastError();
+}
+
+// The FP8 copy of W_1 rebuilt from the genomes (after initialisation, a
+// restore or a surrogate step): slot it of network blockIdx.y = row
+// it / (kp / 8), elements 8 (it mod (kp / 8)) .. + 7, each scaled by 2^-e_j
+// (e_j from bound[j]) and rounded to E4M3; padding zero.  A network whose
+// bound is not finite gets zeros (its fitness is NaN through the scale).
+__global__ __launch_bounds__(256) void fp8_copy_kernel(const float* __restrict__ genomes,
+                                                       NetDesc nd, W1Fp8 w8, int64_t items) {
+  const int j = blockIdx.y;
+  const int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (it >= items) return;
+  const float* __restrict__ W1 = genomes + (int64_t)j * nd.stride + nd.woff[0];
+  const int n0 = nd.w[0], n1 = nd.w[1];
+  const uint32_t bnd = w8.bound[j];
+  const bool fin = bnd < kNonFinite;
+  const int neg_e = fin ? -fp8_exponent(bnd) : 0;
+  const int per_row = w8.kp >> 3;
+  const int n = (int)(it / per_row);
+  const int k = (int)(it - (int64_t)n * per_row) * 8;
+  float v[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e)
+    v[e] = (fin && n < n1 && k + e < n0) ? ldexpf(W1[(int64_t)n * n0 + k + e], neg_e) : 0.0f;
+  uint2 o;
+  o.x = pack_fp8x4(v[0], v[1], v[2], v[3]);
+  o.y = pack_fp8x4(v[4], v[5], v[6], v[7]);
+  reinterpret_cast<uint2*>(w8.p + (int64_t)j * w8.net)[it] = o;
+}
+
+hipError_t launch_fp8_copy(const float* genomes, const NetDesc& nd, int pop, const W1Fp8& w8,
+                           hipStream_t s) {
+  const int64_t items = w8.net / 8;
+  dim3 grid((unsigned)((items + 255) / 256), (unsigned)pop);
+  hipLaunchKernelGGL(fp8_copy_kernel, grid, dim3(256), 0, s, genomes, nd, w8, items);
   return hipGetLastError();
 }
 

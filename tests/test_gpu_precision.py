@@ -23,12 +23,12 @@ pytestmark = pytest.mark.gpu
 PAPER = dict(presets.PAPER)
 
 
-def lowp_oracle(rows, widths, x, y, dt):
+def lowp_oracle(rows, widths, x, y, dt, w_bounds=None):
     f = np.empty(len(rows))
     acc = np.empty(len(rows))
     amb = np.zeros(len(rows), dtype=np.int64)
     for i, g in enumerate(rows):
-        z = Q.forward_lowp(g, widths, x, dt)
+        z = Q.forward_lowp(g, widths, x, dt, None if w_bounds is None else w_bounds[i])
         if np.isnan(z).any():
             f[i], acc[i] = np.nan, np.nan
             continue
@@ -38,13 +38,25 @@ def lowp_oracle(rows, widths, x, y, dt):
     return f, acc, amb
 
 
-def check(f_gpu, acc_gpu, f_ref, acc_ref, amb, b, label):
+# The scale-stress network of special_population (W_1 times 3e3): its
+# first-layer sums of |x w| are 85-150 times its fitness, so the float32
+# rounding of those sums alone moves its fitness by ~1e-5 relative (the
+# matrix cores' summation order decides the last bits).  It is held to 2e-3
+# relative, which still fails any error of its FP8 scale (a wrong power of two
+# moves its fitness by more than half its value).
+STRESS_RTOL = 2e-3
+
+
+def check(f_gpu, acc_gpu, f_ref, acc_ref, amb, b, label, stress=()):
     f_gpu = np.asarray(f_gpu, dtype=np.float64)
     nan = np.isnan(f_ref)
     assert np.array_equal(np.isnan(f_gpu), nan), (label, np.isnan(f_gpu), nan)
     ok = ~nan
+    rtol = np.full(f_ref.shape, FIT_RTOL)
+    rtol[list(stress)] = STRESS_RTOL
     err = np.abs(f_gpu[ok] - f_ref[ok])
-    assert np.all(err <= FIT_RTOL * np.abs(f_ref[ok]) + FIT_ATOL), (label, err.max())
+    assert np.all(err <= rtol[ok] * np.abs(f_ref[ok]) + FIT_ATOL), \
+        (label, float(np.max(err / np.abs(f_ref[ok]))))
     dc = np.abs(np.rint(np.asarray(acc_gpu, dtype=np.float64)[ok] * b) - np.rint(acc_ref[ok] * b))
     assert np.all(dc <= amb[ok]), (label, dc.max())
     return float(np.max(err / np.maximum(np.abs(f_ref[ok]), 1e-30))) if ok.any() else 0.0
@@ -87,7 +99,8 @@ def test_lowp_forward_matches_oracle(dt, name, widths, batches):
         y = datagen.labels(b, widths[-1], 200 + b)
         f_raw, acc = run.score(to_dev(x), to_dev(y))
         f_ref, acc_ref, amb = lowp_oracle(pop, widths, x, y, dt)
-        rel = check(to_np(f_raw), to_np(acc), f_ref, acc_ref, amb, b, "%s %s b%d" % (dt, name, b))
+        rel = check(to_np(f_raw), to_np(acc), f_ref, acc_ref, amb, b, "%s %s b%d" % (dt, name, b),
+                    stress=(3,))
         say("  worst relative fitness error", rel)
 
 
@@ -124,9 +137,11 @@ def test_lowp_nan_batch_gives_nan_fitness(dt):
 
 @pytest.mark.parametrize("b", [8, 64])
 def test_fp8_scales_from_the_variation_kernel(b):
-    """Generations in FP8 mode: each child's W_1 scale comes from the
-    variation kernel; the oracle recomputes it from the (bit-exact) child.
-    Teacher-forced with the device's adjusted fitness."""
+    """Generations in FP8 mode: each child's W_1 scale comes from the bound
+    its parents give, which the variation kernel computes (and with which it
+    writes the child's FP8 copy, read at b = 8); the oracle recomputes the
+    bound from the parents' largest magnitudes and the plan.  Teacher-forced
+    with the device's adjusted fitness."""
     x, y = datagen.prototype_data(2000, seed=0)
     params = dict(PAPER, pop=24, batch=b, eval_dtype="fp8", p_gene=0.5, sigma=0.02,
                   crossover="arithmetic")
@@ -136,6 +151,9 @@ def test_fp8_scales_from_the_variation_kernel(b):
     pop_o = O.init_population(ocfg)
     xb, yb = run.draw_batch(0, xd, yd, b)
     f_adj, f_raw, acc = run.evaluate(xb, yb)
+    idx = O.batch_indices(ocfg.seed, 0, b, x.shape[0], ocfg.run)
+    f_ref, acc_ref, amb = lowp_oracle(pop_o, widths, x[idx], y[idx], "fp8")
+    check(to_np(f_raw), to_np(acc), f_ref, acc_ref, amb, b, "fp8 gen 0")
     for g in range(1, 5):
         say("fp8 generation", g, "b", b)
         f_prev = to_np(f_adj).copy()
@@ -144,10 +162,12 @@ def test_fp8_scales_from_the_variation_kernel(b):
         run.crossover_mutate()
         f_adj, f_raw, acc = run.evaluate(xb, yb)
         ops, p1, p2, _ = O.plan(O.rank(f_prev), f_prev, ocfg, g)
+        bounds = Q.fp8_child_bounds(Q.amax_w1(pop_o, widths), ops, p1, p2, ocfg.sigma)
         pop_o = O.vary(pop_o, ops, p1, p2, ocfg, g)
         assert np.array_equal(genomes_np(run).view(np.uint32), pop_o.view(np.uint32))
+        assert np.all(Q.amax_w1(pop_o, widths) <= bounds)
         idx = O.batch_indices(ocfg.seed, g, b, x.shape[0], ocfg.run)
-        f_ref, acc_ref, amb = lowp_oracle(pop_o, widths, x[idx], y[idx], "fp8")
+        f_ref, acc_ref, amb = lowp_oracle(pop_o, widths, x[idx], y[idx], "fp8", bounds)
         check(to_np(f_raw), to_np(acc), f_ref, acc_ref, amb, b, "fp8 gen %d" % g)
 
 
@@ -189,7 +209,7 @@ def test_bf16_copy_written_by_the_variation_kernel():
     xv, yv = x[:257], y[:257]
     f_raw, acc = run.score(to_dev(xv), to_dev(yv))
     f_ref, acc_ref, amb = lowp_oracle(pop, widths, xv, yv, "bf16")
-    check(to_np(f_raw), to_np(acc), f_ref, acc_ref, amb, 257, "bf16 replaced")
+    check(to_np(f_raw), to_np(acc), f_ref, acc_ref, amb, 257, "bf16 replaced", stress=(3,))
 
 
 def test_bf16_copy_after_surrogate_step():
@@ -228,7 +248,9 @@ def test_fp8_scales_after_restore():
     f1 = to_np(f1).astype(np.float64)
     ok = ~np.isnan(f_ref)
     assert np.array_equal(np.isnan(f1), ~ok)
-    assert np.all(np.abs(f1[ok] - f_ref[ok]) <= FIT_RTOL * np.abs(f_ref[ok]) + FIT_ATOL)
+    rtol = np.full(f_ref.shape, FIT_RTOL)
+    rtol[3] = STRESS_RTOL
+    assert np.all(np.abs(f1[ok] - f_ref[ok]) <= rtol[ok] * np.abs(f_ref[ok]) + FIT_ATOL)
     run.load(ck)                                       # load recomputes them as well
     f2, _ = run.score(xd, yd)
     pop0 = genomes_np(run)

@@ -167,3 +167,85 @@ def test_lowp_nan_operands_give_nan_fitness():
     for dt in (Q.BF16, Q.FP8):
         f, _ = Q.evaluate_lowp(pop, widths, x, y, dt)
         assert np.isnan(f[1]) and np.isfinite(f[0]) and np.isfinite(f[2])
+
+
+def test_box_muller_radius_bound():
+    """The largest normal the float32 sampler can return: u1 = 2^-24 (its
+    smallest value) gives the largest radius, sqrt(-2 ln 2^-24) ~= 5.768, and
+    the rotated cosine/sine never exceed 1; the FP8 mutation bound uses 6."""
+    from oracle.normal32 import normal_pair
+    words = np.array([0, 1, 0xFF, 0x3FFFFFFF, 0x40000000, 0x7FFFFFFF, 0x80000000, 0xBFFFFFFF,
+                      0xC0000000, 0xFFFFFFFF, 0x12345678], dtype=np.uint32)
+    zmax = 0.0
+    for b in words:
+        for a in (np.uint32(0), np.uint32(0xFF)):          # both give u1 = 2^-24
+            z0, z1 = normal_pair(a, b)
+            zmax = max(zmax, abs(float(z0)), abs(float(z1)))
+    assert 5.76 < zmax <= 5.78
+    # every other u1 gives a smaller radius
+    rng = np.random.Generator(np.random.PCG64(0))
+    for a, b in rng.integers(0, 2**32, (2000, 2), dtype=np.uint64).astype(np.uint32):
+        z0, z1 = normal_pair(a, b)
+        assert abs(float(z0)) <= zmax and abs(float(z1)) <= zmax
+
+
+@pytest.mark.parametrize("crossover", ["uniform", "arithmetic"])
+def test_fp8_child_bounds_cover_the_children(crossover):
+    """Soundness of the parent-derived FP8 bound: for elites it is the
+    parent's largest |W_1| exactly; for crossover children and mutants (many
+    sigmas and mutation rates, magnitudes from 1e-30 to 1e3) every child's
+    largest |W_1| stays at or below it; where sigma is small against the
+    weights (the paper's regime) the scale exponent it gives is the exact
+    one or one above."""
+    widths = (48, 16, 4)
+    c = L.param_count(widths)
+    rng = np.random.Generator(np.random.PCG64(3))
+    for sigma, p_gene, mag in ((0.001, 1.0, 0.08), (0.05, 0.3, 1e-3), (0.0, 1.0, 1.0),
+                               (1e-12, 1.0, 2.0), (3.0, 1.0, 1e3), (0.01, 0.1, 1e-30)):
+        P = 24
+        pop = (rng.standard_normal((P, c)) * mag).astype(np.float32)
+        pop[5, :widths[0] * widths[1]] = 0.0
+        cfg = L.Config(widths=widths, pop=P, p_elite=0.25, p_cross=0.5, p_mut=0.25, rho=0.5,
+                       crossover=crossover, sigma=sigma, p_gene=p_gene, seed=9)
+        f = rng.standard_normal(P).astype(np.float32)
+        for g in (1, 2, 3):
+            ops, p1, p2, _ = L.plan(L.rank(f), f, cfg, g)
+            kids = L.vary(pop, ops, p1, p2, cfg, g)
+            amax_p = Q.amax_w1(pop, widths)
+            bound = Q.fp8_child_bounds(amax_p, ops, p1, p2, sigma)
+            amax_k = Q.amax_w1(kids, widths)
+            assert np.all(amax_k <= bound), (sigma, p_gene, mag, g)
+            el = ops == L.ELITE
+            assert np.array_equal(bound[el], amax_p[p1[el]])
+            tight = 6 * sigma <= mag / 8
+            for j in range(P):
+                if amax_k[j] == 0.0:
+                    continue
+                e_exact = Q.fp8_exponent(float(amax_k[j]))
+                e_bound = Q.fp8_exponent(float(bound[j]))
+                assert e_bound >= e_exact
+                if tight and ops[j] != L.CROSS:
+                    assert e_bound <= e_exact + 1, (sigma, mag, j)
+            pop = kids
+
+
+def test_fp8_child_bounds_non_finite_parents():
+    amax = np.array([0.5, np.nan, np.inf, 0.25], dtype=np.float32)
+    ops = np.array([L.ELITE, L.CROSS, L.CROSS, L.MUT, L.MUT])
+    p1 = np.array([1, 0, 0, 2, 3])
+    p2 = np.array([1, 1, 2, 2, 3])
+    b = Q.fp8_child_bounds(amax, ops, p1, p2, 0.01)
+    assert np.isnan(b[0]) and np.isnan(b[1]) and np.isinf(b[2]) and np.isinf(b[3])
+    assert b[4] == (np.float32(0.25) * Q.MUT_BOUND_FACTOR) + np.float32(6.0) * np.float32(0.01)
+
+
+def test_quantize_fp8_with_a_bound():
+    a = np.array([0.5, -0.25, 0.125], dtype=np.float32)
+    q0, e0 = Q.quantize_fp8(a)
+    q1, e1 = Q.quantize_fp8(a, bound=0.5)
+    assert e0 == e1 and np.array_equal(q0, q1)
+    q2, e2 = Q.quantize_fp8(a, bound=1.0)            # one binade up
+    assert e2 == e0 + 1 and np.array_equal(q2 * 2.0**e2, q0 * 2.0**e0)
+    assert Q.quantize_fp8(a, bound=np.inf) == (None, None)
+    with pytest.raises(ValueError):
+        Q.quantize_fp8(a, bound=0.4)
