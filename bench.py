@@ -495,12 +495,14 @@ def accuracy_runs(x_train, y_train, x_val, y_val, gens=1000, every=50, batch=512
     return out
 
 
-def surrogate_vs_plain(gens=400, data_kind="teacher", k=4, batch=64, seed_run=None):
+def surrogate_vs_plain(gens=300, data_kind="teacher", k=4, batch=64, dtype="bf16"):
     """The surrogate's workload (784-32-10 with the small workload's operators,
-    P = 1000, batch 64, 4x over-generated offspring) run with plain LEEA and
-    with the pre-screening surrogate from the same seed: generations/s, the
-    rank-0 network's validation accuracy, and the surrogate's screening
-    (generations screened, mean Kendall tau over the last quarter)."""
+    P = 1000, 4x over-generated offspring, bfloat16 first layer) run with
+    plain LEEA and with the pre-screening surrogate from the same seed:
+    generations/s, the rank-0 network's validation accuracy, and the
+    surrogate's screening (generations screened, Kendall tau of its
+    predictions against the evaluated fitness: mean, and share of
+    generations at or above tau_min)."""
     import torch
     from paper_1806_09819_amd import datagen, presets
     from paper_1806_09819_amd import leea as B
@@ -508,7 +510,7 @@ def surrogate_vs_plain(gens=400, data_kind="teacher", k=4, batch=64, seed_run=No
     data = datagen.splits(data_kind, sizes=(45000, 5000, 0))
     xt, yt = torch.from_numpy(data["x_train"]).cuda(), torch.from_numpy(data["y_train"]).cuda()
     xv, yv = torch.from_numpy(data["x_val"]).cuda(), torch.from_numpy(data["y_val"]).cuda()
-    params = dict(presets.SMALL, pop=1000, batch=batch)
+    params = dict(presets.SMALL, pop=1000, batch=batch, eval_dtype=dtype)
     res = {}
     for mode in ("plain", "surrogate"):
         run = B.Leea(B.make_config(**dict(params, max_batch=xv.shape[0])))
@@ -532,19 +534,19 @@ def surrogate_vs_plain(gens=400, data_kind="teacher", k=4, batch=64, seed_run=No
         _, acc = run.score(xv, yv)
         _, f_adj = run.population()
         best = int(torch.argmax(torch.nan_to_num(f_adj, nan=-np.inf)).item())
-        r = dict(gens_per_s=gens / dt, val_acc_rank0=float(acc[best].item()),
-                 val_acc_best=float(acc.max().item()))
+        r = dict(gens_per_s=gens / dt, us_per_gen=dt / gens * 1e6,
+                 val_acc_rank0=float(acc[best].item()), val_acc_best=float(acc.max().item()))
         if stats:
             st = torch.stack(stats).cpu().numpy()
-            q = max(1, gens // 4)
             r.update(screened_generations=int(st[:, 0].sum()),
-                     tau_last_quarter=float(st[-q:, 1].mean()),
-                     rmse_last_quarter=float(st[-q:, 2].mean()))
+                     tau_mean=float(st[:, 1].mean()),
+                     tau_share_at_min=float((st[:, 1] >= SURROGATE["tau_min"]).mean()),
+                     rmse_mean=float(st[:, 2].mean()))
         res[mode] = r
         run.close()
-    res["workload"] = ("784-32-10, P = 1000, batch %d, sigma 0.01, p_gene 0.1, truncation top "
-                       "25 %%, %s data, %d generations; surrogate: %d x offspring, %s"
-                       % (batch, data_kind, gens, k, SURROGATE))
+    res["workload"] = ("784-32-10, P = 1000, batch %d, %s first layer, sigma 0.01, p_gene 0.1, "
+                       "truncation top 25 %%, %s data, %d generations; surrogate: %d x offspring, "
+                       "%s" % (batch, dtype, data_kind, gens, k, SURROGATE))
     return res
 
 
@@ -708,8 +710,11 @@ def main():
         log("bench: accuracy runs (f32 / bf16 / fp8)")
         line["accuracy"] = accuracy_runs(x_train, y_train, x_val, y_val, gens=args.accuracy_gens)
         log("bench: surrogate vs plain")
-        line["surrogate"] = {kind: surrogate_vs_plain(data_kind=kind)
-                             for kind in ("teacher", "prototypes")}
+        line["surrogate"] = {
+            "teacher_b64": surrogate_vs_plain(data_kind="teacher", batch=64),
+            "prototypes_b64": surrogate_vs_plain(data_kind="prototypes", batch=64),
+            "prototypes_b512": surrogate_vs_plain(data_kind="prototypes", batch=512),
+        }
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(params, b)

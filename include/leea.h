@@ -304,7 +304,9 @@ void leea_destroy(leea_ctx* ctx);
  * parents' adjusted fitness and its distance to parent 1 (times
  * 1/sqrt(genes)); every feature is standardised over the generation's
  * candidates (minus its mean, divided by its standard deviation, 0 where it
- * does not vary); a 259-64-1 MLP predicts each candidate's standardised
+ * does not vary) and the 256 projections are scaled by 1/16, so that the
+ * projection weighs as much as one scalar feature; a 259-64-1 MLP predicts
+ * each candidate's standardised
  * fitness and the best pop - n_elite predictions fill the other slots.  The
  * new population is evaluated as usual (Eq. 1), which judges the MLP
  * (Kendall tau-a of its predictions for the kept candidates against their

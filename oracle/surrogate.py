@@ -95,6 +95,18 @@ def standardize(X):
     return np.where(sd > 0, (X - mu) / safe, 0.0)
 
 
+def mlp_inputs(X):
+    """The MLP's inputs: every feature standardised over the generation's
+    candidates (`standardize`), then the FEATURES projection columns scaled
+    by 1/sqrt(FEATURES) = 2^-4, so that the projection block weighs as much
+    as one scalar feature (its mean squared norm per candidate is 1, where
+    every projection varies).  The factor is a power of two, so the scaling
+    is exact."""
+    Z = standardize(X)
+    Z[:, :FEATURES] *= 1.0 / math.sqrt(FEATURES)
+    return Z
+
+
 def standardize_targets(y):
     """Training targets: the finite entries minus their mean, divided by their
     standard deviation (1 if it is 0); non-finite entries stay as they are

@@ -365,13 +365,11 @@ leea_status run_eval(leea_ctx* c, const float* x, const int32_t* y, int32_t b, b
                "evaluate launch");
   }
   if (c->dt == LEEA_DT_FP8 && b <= 16 && c->w8.p) {
+    // the kernel finds the batch's largest magnitude itself
     st = fp8_ready(c);
-    if (!st) st = dev(c, launch_fill((float*)c->x_amax, 1, 0.0f, c->stream), "amax clear");
-    if (!st)
-      st = dev(c, launch_amax(x, (int64_t)b * c->nd.w[0], c->x_amax, c->stream), "amax launch");
     if (st) return st;
-    return dev(c, launch_evaluate_small_fp8(c->genomes[c->cur], c->nd, c->cfg.pop, c->w8, x,
-                                            c->x_amax, y, b, c->partial, c->stream, fin),
+    return dev(c, launch_evaluate_small_fp8(c->genomes[c->cur], c->nd, c->cfg.pop, c->w8, x, y,
+                                            b, c->partial, c->stream, fin),
                "evaluate launch");
   }
   if (c->dt == LEEA_DT_F32) {
@@ -916,7 +914,7 @@ constexpr int kSurParams = kSurHid * kSurIn + 2 * kSurHid + 1;
 
 struct SurCarve {
   int M, N, kc, nc, ngroups, nchunks, splits;
-  size_t cand, cplan, m4, nu, part, feat, n4, bits, prm, pre, st, total;
+  size_t cand, cplan, m4, nu, part, feat, n4, bits, prm, grad, pre, st, total;
 };
 
 leea_status sur_carve(const leea_config* cfg, const leea_surrogate_config* sc, const NetDesc& nd,
@@ -953,10 +951,11 @@ leea_status sur_carve(const leea_config* cfg, const leea_surrogate_config* sc, c
   c.n4 = align256((size_t)c.N * 4);
   c.bits = align256((size_t)c.nchunks * kSurFeat * 4);
   c.prm = align256((size_t)kSurParams * 4);
+  c.grad = align256((size_t)mlp_grad_blocks(c.N) * (kSurParams + 1) * 4);
   c.pre = align256((size_t)c.N * kSurHid * 4);
   c.st = 256;
-  c.total = c.cand + c.cplan + 2 * c.m4 + c.nu + c.part + 2 * c.feat + 4 * c.n4 + c.bits + 2 * c.prm +
-            c.pre + 2 * c.st;
+  c.total = c.cand + c.cplan + 2 * c.m4 + c.nu + c.part + 2 * c.feat + 4 * c.n4 + c.bits + c.prm +
+            c.grad + c.pre + 2 * c.st;
   *o = c;
   return LEEA_OK;
 }
@@ -1025,7 +1024,7 @@ leea_status leea_surrogate_attach(leea_ctx* c, const leea_surrogate_config* sc, 
   c->sprm = (float*)p;
   p += v.prm;
   c->sgrad = (float*)p;
-  p += v.prm;
+  p += v.grad;
   c->spre = (float*)p;
   p += v.pre;
   c->sstate = (int32_t*)p;
@@ -1099,15 +1098,12 @@ leea_status leea_surrogate_step(leea_ctx* c, const float* x, const int32_t* y, i
   st = dev(c, launch_targets(yk, c->sN, c->sytgt, s), "training targets");
   if (!st)
     st = dev(c, launch_surrogate_judge(c->schosen_pred, yk, c->sytgt, c->sN, c->sc.warmup,
-                                       c->sc.tau_min, c->sstate, c->sstats, s),
+                                       c->sc.tau_min, c->sstate, c->sstats, stats, s),
              "surrogate judge");
   for (int k = 0; k < c->sc.steps && !st; ++k)
     st = dev(c, launch_mlp_train_step(c->sprm, c->szfeat, c->schosen, c->sN, c->sytgt, c->spre,
                                       c->spred_t, c->sgrad, c->sc.lr, s),
              "surrogate training");
-  if (!st && stats)
-    st = dev(c, hipMemcpyAsync(stats, c->sstats, 4 * sizeof(float), hipMemcpyDeviceToDevice, s),
-             "stats copy");
   return st;
 }
 

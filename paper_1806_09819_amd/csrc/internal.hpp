@@ -167,9 +167,8 @@ hipError_t launch_fp8_copy(const float* genomes, const NetDesc& nd, int pop, con
 // batch x (float32) is scaled by 2^-e_x (e_x from *x_amax) and rounded on the
 // way; finishes each network itself when fin.on.
 hipError_t launch_evaluate_small_fp8(const float* genomes, const NetDesc& nd, int pop,
-                                     const W1Fp8& w8, const float* x, const uint32_t* x_amax,
-                                     const int32_t* y, int b, float2* partial, hipStream_t s,
-                                     const FinArgs& fin);
+                                     const W1Fp8& w8, const float* x, const int32_t* y, int b,
+                                     float2* partial, hipStream_t s, const FinArgs& fin);
 hipError_t launch_evaluate_lpw(const float* genomes, const NetDesc& nd, int pop,
                                const W1Shadow& wsh, const uint16_t* xq, int kp, int bpad,
                                const int32_t* y, int b, float2* partial, hipStream_t s);
@@ -213,6 +212,10 @@ hipError_t launch_gather(const float* cur, const float* cand, float* nxt, int64_
                          int pop, int n_e, const int4* plan, const int32_t* chosen,
                          const float* f_adj, const float* cf_inh, float* f_inh_next,
                          hipStream_t s);
+// The surrogate's training gradient is summed over blocks of rows; grad
+// holds mlp_grad_blocks(N) * (parameter count) partial sums followed by as
+// many row counts.
+int mlp_grad_blocks(int N);
 hipError_t launch_mlp_train_step(float* prm, const float* feat, const int32_t* idx, int N,
                                  const float* y, float* pre, float* pred, float* grad, float lr,
                                  hipStream_t s);
@@ -220,7 +223,7 @@ hipError_t launch_standardize(const float* feat, int M, float* z, hipStream_t s)
 hipError_t launch_targets(const float* y, int N, float* out, hipStream_t s);
 hipError_t launch_surrogate_judge(const float* pred, const float* y, const float* yt, int N,
                                   int warmup, float tau_min, int32_t* state, float* stats,
-                                  hipStream_t s);
+                                  float* stats_out, hipStream_t s);
 
 // rng.hip (generator entry points)
 hipError_t launch_rng_philox(const uint32_t* ctr, uint64_t key, uint32_t* out, int64_t n,

@@ -17,6 +17,16 @@ constexpr uint32_t kNonFinite = 0x7F800000u;  // |x| bits at or above: inf or Na
 // is the largest magnitude and flags any non-finite value.
 __device__ __forceinline__ uint32_t mag_bits(float v) { return __float_as_uint(v) & 0x7FFFFFFFu; }
 
+// Largest of v over the wave.
+__device__ __forceinline__ uint32_t wave_umax(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint32_t o = (uint32_t)__shfl_xor((int)v, off);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+
 // e for a finite non-negative amax (0 for amax = 0): with amax = m * 2^k,
 // m in [0.5, 1), 448 * 2^(k-9) = 0.875 * 2^k covers amax iff m <= 0.875.
 __device__ __forceinline__ int fp8_exponent(uint32_t amax_bits) {

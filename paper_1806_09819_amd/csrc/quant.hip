@@ -6,25 +6,26 @@
 
 namespace leea {
 
-__device__ __forceinline__ uint32_t wave_umax(uint32_t v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const uint32_t o = (uint32_t)__shfl_xor((int)v, off);
-    v = o > v ? o : v;
-  }
-  return v;
-}
-
-// *out = max over x of mag_bits (out cleared to 0 beforehand).
+// *out = max over x of mag_bits (out cleared to 0 beforehand).  Each
+// workgroup reduces its share in LDS and issues one atomic: atomics from
+// every wave on the one address serialise in L2 (a 512 x 784 batch took
+// 73 us that way, against a few us for the reads).
 __global__ __launch_bounds__(256) void amax_kernel(const float* __restrict__ x, int64_t n,
                                                    uint32_t* __restrict__ out) {
+  __shared__ uint32_t red[4];
   uint32_t m = 0;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
     const uint32_t v = mag_bits(x[i]);
     m = v > m ? v : m;
   }
   m = wave_umax(m);
-  if ((threadIdx.x & 63) == 0 && m) atomicMax(out, m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t r = red[0];
+    for (int i = 1; i < 4; ++i) r = red[i] > r ? red[i] : r;
+    if (r) atomicMax(out, r);
+  }
 }
 
 // amax[j] = max over network j's W_1 of mag_bits; one workgroup per network.
@@ -109,7 +110,10 @@ static unsigned grid_for(int64_t n) {
 }
 
 hipError_t launch_amax(const float* x, int64_t n, uint32_t* out, hipStream_t s) {
-  hipLaunchKernelGGL(amax_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, n, out);
+  // at least 8 elements per thread, at most 256 workgroups (256 atomics)
+  int64_t g = (n + 2047) / 2048;
+  g = g < 1 ? 1 : (g > 256 ? 256 : g);
+  hipLaunchKernelGGL(amax_kernel, dim3((unsigned)g), dim3(256), 0, s, x, n, out);
   return hipGetLastError();
 }
 

@@ -157,11 +157,22 @@ __global__ __launch_bounds__(256) void proj_kernel(const float* __restrict__ can
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[i][t] = floatx4s{0.f, 0.f, 0.f, 0.f};
-  for (int ch = ch0; ch < ch1; ++ch) {
+  // the next chunk's candidate values and sign word are loaded while the
+  // current one is converted and multiplied
+  float4 nv0, nv1;
+  uint32_t nw = 0;
+  auto fetch = [&](int ch) {
     const int k0 = ch * 32;
+    nv0 = *reinterpret_cast<const float4*>(arow + k0 + 8 * as);
+    nv1 = *reinterpret_cast<const float4*>(arow + k0 + 8 * as + 4);
+    nw = bits[(int64_t)ch * kFeat + tid];
+  };
+  if (ch0 < ch1) fetch(ch0);
+  for (int ch = ch0; ch < ch1; ++ch) {
+    const float4 v0 = nv0, v1 = nv1;
+    const uint32_t w = nw;
+    if (ch + 1 < ch1) fetch(ch + 1);
     {  // candidates -> bf16
-      const float4 v0 = *reinterpret_cast<const float4*>(arow + k0 + 8 * as);
-      const float4 v1 = *reinterpret_cast<const float4*>(arow + k0 + 8 * as + 4);
       uint4 o;
       o.x = pack_bf16x2(v0.x, v0.y);
       o.y = pack_bf16x2(v0.z, v0.w);
@@ -171,7 +182,6 @@ __global__ __launch_bounds__(256) void proj_kernel(const float* __restrict__ can
       *reinterpret_cast<uint4*>(sa + ar * 64 + ((as ^ ((ar >> 1) & 3)) * 16)) = o;
     }
     {  // sign word of row tid -> 32 bf16 of +-1
-      const uint32_t w = bits[(int64_t)ch * kFeat + tid];
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         uint32_t d[4];
@@ -276,7 +286,9 @@ __device__ __forceinline__ float block_sum256(float v, float* red) {
 
 // MLP inputs: feature d of every candidate minus its mean over the M
 // candidates, divided by its standard deviation over them (no Bessel
-// correction); 0 where that deviation is 0.  Workgroup = feature d (d = 259,
+// correction); 0 where that deviation is 0; the projection features then
+// times 2^-4 = 1 / sqrt(256), so that the whole projection weighs as much as
+// one scalar feature (an exact scaling).  Workgroup = feature d (d = 259,
 // the padding column, writes zeros); thread t sums candidates t, t + 256, ...
 // in order, then the halving tree.
 __global__ __launch_bounds__(256) void standardize_kernel(const float* __restrict__ feat, int M,
@@ -299,9 +311,10 @@ __global__ __launch_bounds__(256) void standardize_kernel(const float* __restric
   }
   const float var = block_sum256(q, red) / (float)M;
   const float sd = __builtin_sqrtf(var);
+  const float wgt = d < kFeat ? 0.0625f : 1.0f;  // 1 / sqrt(kFeat), exact
   for (int c = t; c < M; c += 256) {
     const float dx = feat[(int64_t)c * kFeatLd + d] - mean;
-    z[(int64_t)c * kFeatLd + d] = sd > 0.0f ? dx / sd : 0.0f;
+    z[(int64_t)c * kFeatLd + d] = sd > 0.0f ? (dx / sd) * wgt : 0.0f;
   }
 }
 
@@ -360,88 +373,144 @@ hipError_t launch_targets(const float* y, int N, float* out, hipStream_t s) {
 }
 
 // MLP forward of rows idx[n] (or n when idx is NULL): pre[n][u] (optional)
-// and pred[n].  Workgroup = one row, thread u = hidden unit; inputs summed
-// in index order, hidden units summed in order by thread 0.
-__global__ __launch_bounds__(64) void mlp_forward_kernel(const float* __restrict__ prm,
-                                                         const float* __restrict__ feat,
-                                                         const int32_t* __restrict__ idx,
-                                                         float* __restrict__ pre,
-                                                         float* __restrict__ pred) {
+// and pred[n].  Workgroup = kFwdRows rows staged in LDS; wave q takes the
+// inputs d in [65 q, 65 q + 65) and lane u hidden unit u: each weight it
+// loads serves all kFwdRows rows.  The four partial sums of (row, u) are
+// added in wave order with the bias; then one thread per row sums the
+// hidden units in order.
+constexpr int kFwdRows = 16;
+constexpr int kFwdSlice = (kIn + 3) / 4;  // 65 inputs per wave
+
+__global__ __launch_bounds__(256) void mlp_forward_kernel(const float* __restrict__ prm,
+                                                          const float* __restrict__ feat,
+                                                          const int32_t* __restrict__ idx, int n,
+                                                          float* __restrict__ pre,
+                                                          float* __restrict__ pred) {
 #pragma clang fp contract(off)
-  __shared__ float hs[kHid];
-  const int n = blockIdx.x;
-  const int u = threadIdx.x;
-  const int row = idx ? idx[n] : n;
-  const float* x = feat + (int64_t)row * kFeatLd;
-  const float* w = prm + u * kIn;
-  float s = 0.0f;
-  for (int d = 0; d < kIn; ++d) s += w[d] * x[d];
-  s += prm[kHid * kIn + u];
-  if (pre) pre[(int64_t)n * kHid + u] = s;
-  hs[u] = s > 0.0f ? s : 0.0f;
+  __shared__ float xs[kFwdRows][kFeatLd];
+  __shared__ float hp[4][kFwdRows][kHid];
+  const int r0 = blockIdx.x * kFwdRows;
+  const int tid = threadIdx.x;
+  const int u = tid & 63;
+  const int q = tid >> 6;
+  // wave q stages rows q, q + 4, ...: whole rows, every load independent
+#pragma unroll
+  for (int k = 0; k < kFwdRows / 4; ++k) {
+    const int r = q + 4 * k;
+    const int m = r0 + r;
+    const float* __restrict__ src = m < n ? feat + (int64_t)(idx ? idx[m] : m) * kFeatLd : nullptr;
+#pragma unroll
+    for (int d = u; d < kFeatLd; d += 64) xs[r][d] = src ? src[d] : 0.0f;
+  }
   __syncthreads();
-  if (u == 0) {
+  const int d0 = q * kFwdSlice;
+  const int d1 = d0 + kFwdSlice < kIn ? d0 + kFwdSlice : kIn;
+  const float* __restrict__ w = prm + u * kIn;
+  float acc[kFwdRows];
+#pragma unroll
+  for (int r = 0; r < kFwdRows; ++r) acc[r] = 0.0f;
+  for (int d = d0; d < d1; ++d) {
+    const float wd = w[d];
+#pragma unroll
+    for (int r = 0; r < kFwdRows; ++r) acc[r] += wd * xs[r][d];
+  }
+#pragma unroll
+  for (int r = 0; r < kFwdRows; ++r) hp[q][r][u] = acc[r];
+  __syncthreads();
+  {
+    // thread (u, q) finishes rows q, q + 4, q + 8, q + 12 of unit u
+    const float bu = prm[kHid * kIn + u];
+#pragma unroll
+    for (int k = 0; k < kFwdRows / 4; ++k) {
+      const int r = q + 4 * k;
+      const float v = ((hp[0][r][u] + hp[1][r][u]) + (hp[2][r][u] + hp[3][r][u])) + bu;
+      if (pre && r0 + r < n) pre[(int64_t)(r0 + r) * kHid + u] = v;
+      xs[r][u] = v > 0.0f ? v : 0.0f;  // the rows' inputs are no longer needed
+    }
+  }
+  __syncthreads();
+  if (tid < kFwdRows && r0 + tid < n) {
     const float* w2 = prm + kHid * kIn + kHid;
     float o = 0.0f;
-    for (int h = 0; h < kHid; ++h) o += w2[h] * hs[h];
+    for (int h = 0; h < kHid; ++h) o += w2[h] * xs[tid][h];
     o += w2[kHid];
-    pred[n] = o;
+    pred[r0 + tid] = o;
   }
 }
 
 hipError_t launch_mlp_forward(const float* prm, const float* feat, const int32_t* idx, int n,
                               float* pre, float* pred, hipStream_t s) {
-  hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)n), dim3(64), 0, s, prm, feat, idx, pre,
-                     pred);
+  if (n < 1) return hipSuccess;
+  hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)((n + kFwdRows - 1) / kFwdRows)),
+                     dim3(256), 0, s, prm, feat, idx, n, pre, pred);
   return hipGetLastError();
 }
 
+// Number of keys[j], j0 <= j < j1, below own (keys in LDS, 16-byte aligned,
+// j0 even): 128-bit reads of two keys, four reads in flight per step.
+__device__ __forceinline__ int count_below(const uint64_t* keys, int j0, int j1, uint64_t own) {
+  typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+  const u64x2* k2 = reinterpret_cast<const u64x2*>(keys);
+  int r0 = 0, r1 = 0, r2 = 0, r3 = 0;
+  int j = j0;
+  for (; j + 8 <= j1; j += 8) {
+    const u64x2 a = k2[j >> 1], b = k2[(j >> 1) + 1], c = k2[(j >> 1) + 2], d = k2[(j >> 1) + 3];
+    r0 += (a.x < own ? 1 : 0) + (a.y < own ? 1 : 0);
+    r1 += (b.x < own ? 1 : 0) + (b.y < own ? 1 : 0);
+    r2 += (c.x < own ? 1 : 0) + (c.y < own ? 1 : 0);
+    r3 += (d.x < own ? 1 : 0) + (d.y < own ? 1 : 0);
+  }
+  for (; j < j1; ++j) r0 += keys[j] < own ? 1 : 0;
+  return (r0 + r1) + (r2 + r3);
+}
+
 // Screening: chosen[i] for the N non-elite slots.  With the surrogate on
-// (*flag != 0) the N best predictions (rank_key order: descending, ties by
-// candidate index, NaN last); otherwise the first n_c crossover and the
-// first n_m mutation candidates.  chosen_pred[i] = pred[chosen[i]].
-__global__ __launch_bounds__(1024) void screen_kernel(const float* __restrict__ pred, int M, int n2,
-                                                      int N, int n_c, int kc,
-                                                      const int32_t* __restrict__ flag,
-                                                      int32_t* __restrict__ chosen,
-                                                      float* __restrict__ chosen_pred) {
+// (*flag != 0) the N best predictions in rank_key order (descending, ties by
+// candidate index, NaN last): every candidate counts the keys below its own
+// (the keys are unique, so the counts are the sorted positions; four
+// threads per candidate count a quarter of the keys each, from LDS) and
+// candidates ranked below N write themselves there; otherwise the first n_c
+// crossover and the first n_m mutation candidates.  chosen_pred[i] =
+// pred[chosen[i]].  (The sort by counting took 17 us for 3,800 candidates
+// against 34 us for a bitonic network in one workgroup.)
+constexpr int kScreenCands = 64;  // candidates per workgroup (4 threads each)
+
+__global__ __launch_bounds__(256) void screen_kernel(const float* __restrict__ pred, int M, int N,
+                                                     int n_c, int kc,
+                                                     const int32_t* __restrict__ flag,
+                                                     int32_t* __restrict__ chosen,
+                                                     float* __restrict__ chosen_pred) {
   extern __shared__ uint64_t keys[];
   const int tid = threadIdx.x;
-  const bool use = *flag != 0;
-  if (use) {
-    for (int i = tid; i < n2; i += 1024)
-      keys[i] = i < M ? rank_key(pred[i], (uint32_t)i) : ~0ull;
-    __syncthreads();
-    for (int size = 2; size <= n2; size <<= 1) {
-      for (int half = size >> 1; half > 0; half >>= 1) {
-        for (int i = tid; i < (n2 >> 1); i += 1024) {
-          const int lo = 2 * i - (i & (half - 1));
-          const int hi = lo + half;
-          const bool up = (lo & size) == 0;
-          const uint64_t a = keys[lo];
-          const uint64_t b = keys[hi];
-          if ((a > b) == up) {
-            keys[lo] = b;
-            keys[hi] = a;
-          }
-        }
-        __syncthreads();
-      }
+  if (*flag == 0) {
+    for (int c = blockIdx.x * 256 + tid; c < N; c += gridDim.x * 256) {
+      const int k = c < n_c ? c : kc + (c - n_c);
+      chosen[c] = k;
+      chosen_pred[c] = pred[k];
     }
+    return;
   }
-  for (int i = tid; i < N; i += 1024) {
-    const int c = use ? (int)(uint32_t)keys[i] : (i < n_c ? i : kc + (i - n_c));
-    chosen[i] = c;
-    chosen_pred[i] = pred[c];
+  for (int i = tid; i < M; i += 256) keys[i] = rank_key(pred[i], (uint32_t)i);
+  __syncthreads();
+  const int c = blockIdx.x * kScreenCands + (tid >> 2);
+  const int part = tid & 3;
+  const int q = ((M + 7) >> 3) * 2;  // a quarter of the keys, even
+  const int j0 = part * q < M ? part * q : M;
+  const int j1 = j0 + q < M ? j0 + q : M;
+  int r = c < M ? count_below(keys, j0, j1, keys[c]) : 0;
+  r += __shfl_xor(r, 1);
+  r += __shfl_xor(r, 2);
+  if (c < M && part == 0 && r < N) {
+    chosen[r] = c;
+    chosen_pred[r] = pred[c];
   }
 }
 
 hipError_t launch_screen(const float* pred, int M, int N, int n_c, int kc, const int32_t* flag,
                          int32_t* chosen, float* chosen_pred, hipStream_t s) {
-  int n2 = 2;
-  while (n2 < M) n2 <<= 1;
-  hipLaunchKernelGGL(screen_kernel, dim3(1), dim3(1024), (size_t)n2 * 8, s, pred, M, n2, N, n_c,
-                     kc, flag, chosen, chosen_pred);
+  hipLaunchKernelGGL(screen_kernel, dim3((unsigned)((M + kScreenCands - 1) / kScreenCands)),
+                     dim3(256), (size_t)M * 8, s, pred, M, N, n_c, kc, flag, chosen,
+                     chosen_pred);
   return hipGetLastError();
 }
 
@@ -480,42 +549,18 @@ hipError_t launch_gather(const float* cur, const float* cand, float* nxt, int64_
 }
 
 // Gradient of mean((pred - y)^2) over the rows with a numeric target
-// y[n] = training target of kept candidate n; one thread per parameter.  The
-// rows are summed in 8 interleaved partial sums (row n into sum n mod 8, each
-// in row order), added in a fixed tree ((s0 + s1) + (s2 + s3)) + ((s4 + s5) +
-// (s6 + s7)), so eight rows' loads are in flight at once; then (2 / rows)
-// times the total.
-__device__ __forceinline__ float grad_term(int i, int n, const float* __restrict__ prm,
-                                           const float* __restrict__ feat,
-                                           const int32_t* __restrict__ idx,
-                                           const float* __restrict__ pre,
-                                           const float* __restrict__ pred,
-                                           const float* __restrict__ y, int* rows) {
-#pragma clang fp contract(off)
-  const int nw1 = kHid * kIn;
-  const float t = y[n];
-  if (!(t == t) || t == __builtin_inff() || t == -__builtin_inff()) return 0.0f;
-  ++*rows;
-  const float* w2 = prm + nw1 + kHid;
-  const float e = pred[n] - t;
-  if (i < nw1) {
-    const int u = i / kIn;
-    const int d = i - u * kIn;
-    const float p = pre[(int64_t)n * kHid + u];
-    const float ew = e * w2[u];
-    return p > 0.0f ? ew * feat[(int64_t)idx[n] * kFeatLd + d] : 0.0f;
-  }
-  if (i < nw1 + kHid) {
-    const int u = i - nw1;
-    const float p = pre[(int64_t)n * kHid + u];
-    return p > 0.0f ? e * w2[u] : 0.0f;
-  }
-  if (i < nw1 + 2 * kHid) {
-    const int u = i - nw1 - kHid;
-    const float p = pre[(int64_t)n * kHid + u];
-    return p > 0.0f ? e * p : 0.0f;
-  }
-  return e;
+// y[n] = training target of kept candidate n (rows without one contribute
+// zeros).  Workgroup (row block, parameter chunk) = kGradRows consecutive
+// rows x 256 parameters: it stages the rows' inputs, d[r][u] = e_r w_2[u]
+// [pre > 0] (e_r = pred - y), relu(pre) and e_r in LDS and writes, for each
+// of its parameters, the sum over the rows in row order (a block of the
+// products D^T X, D^T 1, relu(pre)^T e, 1^T e).  The update adds the row
+// blocks in order, scales by 2 / rows and takes the step.
+constexpr int kGradRows = 32;
+constexpr int kParams = kHid * kIn + 2 * kHid + 1;
+
+__device__ __forceinline__ bool finite_f(float t) {
+  return t == t && t != __builtin_inff() && t != -__builtin_inff();
 }
 
 __global__ __launch_bounds__(256) void mlp_grad_kernel(const float* __restrict__ prm,
@@ -524,75 +569,153 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(const float* __restrict__
                                                        const float* __restrict__ pre,
                                                        const float* __restrict__ pred,
                                                        const float* __restrict__ y, int N,
-                                                       float* __restrict__ grad) {
+                                                       float* __restrict__ part) {
 #pragma clang fp contract(off)
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  const int total = kHid * kIn + 2 * kHid + 1;
-  if (i >= total) return;
-  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  int rows = 0;
-  int n = 0;
-  for (; n + 8 <= N; n += 8) {
+  __shared__ float xs[kGradRows][kFeatLd];
+  __shared__ float ds[kGradRows][kHid];
+  __shared__ float hs[kGradRows][kHid];
+  __shared__ float es[kGradRows];
+  const int blk = blockIdx.x;  // row block
+  const int n0 = blk * kGradRows;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int nw1 = kHid * kIn;
+  // wave w stages rows w, w + 4, ...: the inputs (whole rows), d and relu
+  // of every hidden unit (lane = unit) and e
 #pragma unroll
-    for (int q = 0; q < 8; ++q) s[q] += grad_term(i, n + q, prm, feat, idx, pre, pred, y, &rows);
+  for (int k = 0; k < kGradRows / 4; ++k) {
+    const int r = wave + 4 * k;
+    const int n = n0 + r;
+    const float t = n < N ? y[n] : 0.0f;
+    const bool ok = n < N && finite_f(t);
+    const float* __restrict__ src = ok ? feat + (int64_t)idx[n] * kFeatLd : nullptr;
+#pragma unroll
+    for (int d = lane; d < kFeatLd; d += 64) xs[r][d] = src ? src[d] : 0.0f;
+    float dv = 0.0f, hv = 0.0f, e = 0.0f;
+    if (ok) {
+      e = pred[n] - t;
+      const float pv = pre[(int64_t)n * kHid + lane];
+      dv = pv > 0.0f ? e * prm[nw1 + kHid + lane] : 0.0f;
+      hv = pv > 0.0f ? pv : 0.0f;
+    }
+    ds[r][lane] = dv;
+    hs[r][lane] = hv;
+    if (lane == 0) es[r] = e;
   }
-  for (int q = 0; n + q < N; ++q) s[q] += grad_term(i, n + q, prm, feat, idx, pre, pred, y, &rows);
-  const float a = (s[0] + s[1]) + (s[2] + s[3]);
-  const float b = (s[4] + s[5]) + (s[6] + s[7]);
-  const float tot = a + b;
-  const float f = rows > 0 ? 2.0f / (float)rows : 0.0f;
-  grad[i] = tot * f;
+  __syncthreads();
+  float* __restrict__ g = part + (int64_t)blk * kParams;
+  const int o = blockIdx.y * 256 + tid;  // parameter
+  if (o < kParams) {
+    float sum = 0.0f;
+    if (o < nw1) {
+      const int u = o / kIn;
+      const int d = o - u * kIn;
+#pragma unroll 8
+      for (int r = 0; r < kGradRows; ++r) sum += ds[r][u] * xs[r][d];
+    } else if (o < nw1 + kHid) {
+      const int u = o - nw1;
+#pragma unroll 8
+      for (int r = 0; r < kGradRows; ++r) sum += ds[r][u];
+    } else if (o < nw1 + 2 * kHid) {
+      const int u = o - nw1 - kHid;
+#pragma unroll 8
+      for (int r = 0; r < kGradRows; ++r) sum += es[r] * hs[r][u];
+    } else {
+      for (int r = 0; r < kGradRows; ++r) sum += es[r];
+    }
+    g[o] = sum;
+  }
+  if (blockIdx.y == 0 && tid == 0) {
+    int rows = 0;
+    for (int r = 0; r < kGradRows; ++r) rows += (n0 + r < N && finite_f(y[n0 + r])) ? 1 : 0;
+    reinterpret_cast<int*>(part + (int64_t)gridDim.x * kParams)[blk] = rows;
+  }
 }
 
 __global__ __launch_bounds__(256) void mlp_update_kernel(float* __restrict__ prm,
-                                                         const float* __restrict__ grad, float lr) {
+                                                         const float* __restrict__ part,
+                                                         int nblk, float lr) {
 #pragma clang fp contract(off)
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= kHid * kIn + 2 * kHid + 1) return;
-  const float step = lr * grad[i];
+  if (i >= kParams) return;
+  const int* cnt = reinterpret_cast<const int*>(part + (int64_t)nblk * kParams);
+  int rows = 0;
+  float tot = 0.0f;
+  for (int k = 0; k < nblk; ++k) {
+    tot += part[(int64_t)k * kParams + i];
+    rows += cnt[k];
+  }
+  const float f = rows > 0 ? 2.0f / (float)rows : 0.0f;
+  const float step = lr * (tot * f);
   prm[i] = prm[i] - step;
 }
+
+int mlp_grad_blocks(int N) { return (N + kGradRows - 1) / kGradRows; }
 
 hipError_t launch_mlp_train_step(float* prm, const float* feat, const int32_t* idx, int N,
                                  const float* y, float* pre, float* pred, float* grad, float lr,
                                  hipStream_t s) {
   hipError_t e = launch_mlp_forward(prm, feat, idx, N, pre, pred, s);
   if (e != hipSuccess) return e;
-  const int total = kHid * kIn + 2 * kHid + 1;
-  const unsigned g = (unsigned)((total + 255) / 256);
-  hipLaunchKernelGGL(mlp_grad_kernel, dim3(g), dim3(256), 0, s, prm, feat, idx, pre, pred, y, N,
-                     grad);
-  hipLaunchKernelGGL(mlp_update_kernel, dim3(g), dim3(256), 0, s, prm, grad, lr);
+  const int nblk = mlp_grad_blocks(N);
+  if (nblk < 1) return hipSuccess;
+  hipLaunchKernelGGL(mlp_grad_kernel, dim3((unsigned)nblk, (kParams + 255) / 256), dim3(256), 0, s,
+                     prm, feat, idx, pre, pred, y, N, grad);
+  hipLaunchKernelGGL(mlp_update_kernel, dim3((kParams + 255) / 256), dim3(256), 0, s, prm, grad,
+                     nblk, lr);
   return hipGetLastError();
 }
 
+// +1 for a concordant pair, -1 for a discordant one, 0 for a tie or a NaN.
+__device__ __forceinline__ int concord(float dp, float dy) {
+  const int sp = (dp > 0.0f) - (dp < 0.0f);
+  const int sy = (dy > 0.0f) - (dy < 0.0f);
+  return sp * sy;
+}
+
+// Numerator of Kendall tau-a: workgroup w takes rows i = w, w + G, ...,
+// its threads the partners j = i + 1 + t, + 256, ...; the workgroup's sum is
+// added to *acc with a 64-bit integer atomic (exact, so the total does not
+// depend on the order of the additions).
+constexpr int kTauBlocks = 64;
+
+__global__ __launch_bounds__(256) void tau_pairs_kernel(const float* __restrict__ p,
+                                                        const float* __restrict__ y, int N,
+                                                        unsigned long long* __restrict__ acc) {
+  __shared__ int red[4];
+  int s = 0;
+  for (int i = blockIdx.x; i < N; i += gridDim.x) {
+    const float pi = p[i], yi = y[i];
+    for (int j = i + 1 + (int)threadIdx.x; j < N; j += 256) s += concord(pi - p[j], yi - y[j]);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const long long t = (long long)red[0] + red[1] + red[2] + red[3];
+    if (t) atomicAdd(acc, (unsigned long long)t);
+  }
+}
+
 // Kendall tau-a of the screening predictions against the evaluated fitness
-// of the kept candidates, root mean squared error against their training
-// targets (the standardised fitness), and the next
-// generation's decision: on when `warmup` generations have trained and
-// tau >= tau_min.  state = {flag, trained generations}; stats = {surrogate
-// used this generation, tau, rmse, trained generations}.
+// of the kept candidates (numerator from tau_pairs_kernel, which this kernel
+// clears for the next generation), root mean squared error against their
+// training targets (the standardised fitness), and the next generation's
+// decision: on when `warmup` generations have trained and tau >= tau_min.
+// state = {flag, trained generations, numerator (64 bits)}; stats (and
+// stats_out when not NULL) = {surrogate used this generation, tau, rmse,
+// trained generations}.
 __global__ __launch_bounds__(1024) void surrogate_judge_kernel(const float* __restrict__ p,
-                                                               const float* __restrict__ y,
                                                                const float* __restrict__ yt, int N,
                                                                int warmup, float tau_min,
                                                                int32_t* __restrict__ state,
-                                                               float* __restrict__ stats) {
-  __shared__ long long part[1024];
+                                                               float* __restrict__ stats,
+                                                               float* __restrict__ stats_out) {
   __shared__ float sq[1024];
   __shared__ int cnt[1024];
   const int tid = threadIdx.x;
-  long long s = 0;
-  for (int i = tid; i < N; i += 1024) {
-    const float pi = p[i], yi = y[i];
-    for (int j = i + 1; j < N; ++j) {
-      const float dp = pi - p[j];
-      const float dy = yi - y[j];
-      const int sp = (dp > 0.0f) - (dp < 0.0f);
-      const int sy = (dy > 0.0f) - (dy < 0.0f);
-      s += sp * sy;
-    }
-  }
   float e2 = 0.0f;
   int c = 0;
   for (int i = tid; i < N; i += 1024) {
@@ -602,27 +725,29 @@ __global__ __launch_bounds__(1024) void surrogate_judge_kernel(const float* __re
       ++c;
     }
   }
-  part[tid] = s;
   sq[tid] = e2;
   cnt[tid] = c;
   __syncthreads();
   for (int off = 512; off > 0; off >>= 1) {
     if (tid < off) {
-      part[tid] += part[tid + off];
       sq[tid] += sq[tid + off];
       cnt[tid] += cnt[tid + off];
     }
     __syncthreads();
   }
   if (tid == 0) {
+    unsigned long long* acc = reinterpret_cast<unsigned long long*>(state + 2);
+    const long long num = (long long)*acc;
+    *acc = 0ull;
     const double pairs = (double)N * (double)(N - 1) / 2.0;
-    const float tau = pairs > 0 ? (float)((double)part[0] / pairs) : 0.0f;
+    const float tau = pairs > 0 ? (float)((double)num / pairs) : 0.0f;
     const float rmse = cnt[0] > 0 ? __builtin_sqrtf(sq[0] / (float)cnt[0]) : 0.0f;
     const int trained = state[1] + 1;
-    stats[0] = (float)state[0];
-    stats[1] = tau;
-    stats[2] = rmse;
-    stats[3] = (float)trained;
+    const float st[4] = {(float)state[0], tau, rmse, (float)trained};
+    for (int k = 0; k < 4; ++k) {
+      stats[k] = st[k];
+      if (stats_out) stats_out[k] = st[k];
+    }
     state[1] = trained;
     state[0] = (trained >= warmup && tau >= tau_min) ? 1 : 0;
   }
@@ -630,9 +755,13 @@ __global__ __launch_bounds__(1024) void surrogate_judge_kernel(const float* __re
 
 hipError_t launch_surrogate_judge(const float* pred, const float* y, const float* yt, int N,
                                   int warmup, float tau_min, int32_t* state, float* stats,
-                                  hipStream_t s) {
-  hipLaunchKernelGGL(surrogate_judge_kernel, dim3(1), dim3(1024), 0, s, pred, y, yt, N, warmup,
-                     tau_min, state, stats);
+                                  float* stats_out, hipStream_t s) {
+  unsigned long long* acc = reinterpret_cast<unsigned long long*>(state + 2);
+  if (N > 1)
+    hipLaunchKernelGGL(tau_pairs_kernel, dim3(N - 1 < kTauBlocks ? N - 1 : kTauBlocks), dim3(256),
+                       0, s, pred, y, N, acc);
+  hipLaunchKernelGGL(surrogate_judge_kernel, dim3(1), dim3(1024), 0, s, pred, yt, N, warmup,
+                     tau_min, state, stats, stats_out);
   return hipGetLastError();
 }
 

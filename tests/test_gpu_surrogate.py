@@ -23,17 +23,21 @@ U = 2.0 ** -24
 
 
 def check_inputs(Xd, Zd, label):
-    """The device's standardised MLP inputs against the oracle's
-    standardisation of the device's own features, within the float32 error
-    of the fixed-order sums (depth M / 256 + 8) and of x - mean."""
+    """The device's MLP inputs against the oracle's (standardisation, then
+    the projection block times 2^-4) of the device's own features, within
+    the float32 error of the fixed-order sums (depth M / 256 + 8) and of
+    x - mean, scaled like the inputs."""
     M = Xd.shape[0]
-    Zo = S.standardize(Xd)
+    Zo = S.mlp_inputs(Xd)
     mu = Xd.mean(axis=0)
     sd = np.sqrt(((Xd - mu) ** 2).mean(axis=0))
     depth = M / 256.0 + 16.0
     ok = sd > 0
+    wgt = np.ones(Xd.shape[1])
+    wgt[:S.FEATURES] = 1.0 / 16.0
     scale = np.abs(Xd).mean(axis=0) + np.abs(Xd - mu)
-    tol = np.where(ok, 4 * depth * U * (scale / np.where(ok, sd, 1.0) + np.abs(Zo)), 0.0) + 1e-6
+    tol = np.where(ok, 4 * depth * U * (wgt * scale / np.where(ok, sd, 1.0) + np.abs(Zo)),
+                   0.0) + 1e-6
     assert np.all(np.abs(Zd - Zo) <= tol), (label, float(np.max(np.abs(Zd - Zo) - tol)))
 
 
@@ -231,36 +235,47 @@ def test_surrogate_teacher_forced_configured_size():
 def test_surrogate_report_small_config_at_scale():
     """784-32-10, P = 1000, b = 64, k = 4: surrogate screening error over
     20 generations and the best network's validation accuracy against
-    plain LEEA from the same seed."""
+    plain LEEA from the same seed, once with the tau gate (tau_min = 0.1)
+    and once with screening forced on after the warm-up (tau_min = -1).
+    Every generation's flag must follow the documented rule: screened
+    exactly when the MLP had trained for `warmup` generations and the
+    previous generation's tau reached tau_min."""
     data = datagen.splits("teacher", sizes=(20000, 2000, 0))
     xt, yt = to_dev(data["x_train"]), to_dev(data["y_train"])
     xv, yv = to_dev(data["x_val"]), to_dev(data["y_val"])
     params = dict(presets.SMALL, pop=1000, batch=64, sigma=0.01, p_gene=0.1)
+    gens, warmup = 20, 2
     out = {}
-    for mode in ("plain", "surrogate"):
+    for mode, tau_min in (("plain", None), ("gated", 0.1), ("forced", -1.0)):
         run, _ = make_run(params, max_batch=max(64, xv.shape[0]))
-        if mode == "surrogate":
-            run.attach_surrogate(oversample=4, steps=8, lr=0.01, warmup=2, tau_min=0.1)
+        if tau_min is not None:
+            run.attach_surrogate(oversample=4, steps=8, lr=0.01, warmup=warmup, tau_min=tau_min)
         xb, yb = run.draw_batch(0, xt, yt, 64)
         run.evaluate(xb, yb)
-        taus, rmses, used = [], [], 0
-        for g in range(1, 21):
+        stats = []
+        for g in range(1, gens + 1):
             xb, yb = run.draw_batch(g, xt, yt, 64)
-            if mode == "surrogate":
+            if tau_min is not None:
                 _, _, _, st = run.surrogate_step(xb, yb)
-                st = to_np(st)
-                taus.append(float(st[1]))
-                rmses.append(float(st[2]))
-                used += int(st[0])
+                stats.append(to_np(st).astype(np.float64).copy())
             else:
                 run.step(xb, yb)
         f_raw, acc = run.score(xv, yv)
         _, f_adj = run.population()
         best = int(torch.argmax(f_adj).item())
-        out[mode] = dict(val_acc_best=float(to_np(acc)[best]), val_acc_max=float(to_np(acc).max()),
-                         tau_last5=float(np.mean(taus[-5:])) if taus else None,
-                         rmse_last5=float(np.mean(rmses[-5:])) if rmses else None,
-                         screened_generations=used)
+        rec = dict(val_acc_best=float(to_np(acc)[best]), val_acc_max=float(to_np(acc).max()))
+        if stats:
+            st = np.array(stats)
+            used, tau, rmse, trained = st[:, 0], st[:, 1], st[:, 2], st[:, 3]
+            assert np.array_equal(trained, np.arange(1, gens + 1)), (mode, trained)
+            rule = np.zeros(gens)
+            rule[1:] = (trained[:-1] >= warmup) & (tau[:-1] >= tau_min)
+            assert np.array_equal(used, rule), (mode, used, tau)
+            assert np.all(np.isfinite(tau)) and np.all(np.abs(tau) <= 1.0), (mode, tau)
+            assert np.all(np.isfinite(rmse)) and np.all(rmse >= 0.0), (mode, rmse)
+            rec.update(tau_mean=float(tau.mean()), tau_last5=float(tau[-5:].mean()),
+                       rmse_last5=float(rmse[-5:].mean()), screened_generations=int(used.sum()))
+        out[mode] = rec
+        run.close()
     say("surrogate report", out)
-    assert out["surrogate"]["screened_generations"] >= 0
-    assert np.isfinite(out["surrogate"]["tau_last5"])
+    assert out["forced"]["screened_generations"] == gens - warmup

@@ -194,6 +194,23 @@ def test_standardize_closed_forms():
     assert np.array_equal(S.standardize(X3)[:, 0], np.array([-1.0, 1.0, -1.0, 1.0]))
 
 
+def test_mlp_inputs_weight_the_projection_block_as_one_feature():
+    rng = np.random.Generator(np.random.PCG64(10))
+    X = rng.standard_normal((300, S.INPUTS)) * rng.uniform(0.1, 10.0, S.INPUTS) + 3.0
+    X[:, 5] = 2.0                                               # one constant projection
+    Z = S.mlp_inputs(X)
+    Zs = S.standardize(X)
+    # the scalar features are the standardised ones, unchanged
+    assert np.array_equal(Z[:, S.FEATURES:], Zs[:, S.FEATURES:])
+    # the projections are the standardised ones times 2^-4 exactly
+    assert np.array_equal(Z[:, :S.FEATURES] * 16.0, Zs[:, :S.FEATURES])
+    assert np.array_equal(Z[:, 5], np.zeros(300))
+    # block weight: mean over candidates of the squared block norm = (varying columns) / 256
+    blk = (Z[:, :S.FEATURES] ** 2).sum(axis=1).mean()
+    assert abs(blk - (S.FEATURES - 1) / S.FEATURES) < 1e-12
+    assert np.allclose((Z[:, S.FEATURES:] ** 2).mean(axis=0), 1.0, rtol=1e-12)
+
+
 def test_standardize_targets():
     y = np.array([-2.0, -1.0, np.nan, 0.0, np.inf, 3.0])
     t = S.standardize_targets(y)
