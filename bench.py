@@ -623,6 +623,9 @@ def main():
                     help="arithmetic of the first layer (bf16 / fp8: reduced-precision variants)")
     ap.add_argument("--fused", action="store_true",
                     help="time the fused variation + evaluation call at batch <= 16")
+    ap.add_argument("--surrogate-only", type=int, default=0, metavar="GENS",
+                    help="only time GENS surrogate generations at the surrogate's workload "
+                         "(prototypes, batch 64, FP32 first layer; for kernel traces) and exit")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 5 times (scales the "
                          "FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
@@ -636,6 +639,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": n * 4, "copies": 5}), flush=True)
+        return
+    if args.surrogate_only:
+        r = surrogate_vs_plain(gens=args.surrogate_only, data_kind="prototypes", batch=64,
+                               dtype="f32")
+        print(json.dumps(r), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the LEEA hot path here runs on a single MI355X "

@@ -296,9 +296,7 @@ leea_status run_eval_lp(leea_ctx* c, const float* x, const int32_t* y, int32_t b
   leea_status st = fp8_ready(c);
   if (st) return st;
   if (c->dt == LEEA_DT_FP8) {
-    st = dev(c, launch_fill((float*)c->x_amax, 1, 0.0f, c->stream), "amax clear");
-    if (!st)
-      st = dev(c, launch_amax(x, (int64_t)b * n0, c->x_amax, c->stream), "amax launch");
+    st = dev(c, launch_amax(x, (int64_t)b * n0, c->x_amax, c->stream), "amax launch");
     if (st) return st;
   }
   const bool small = b <= 16;
@@ -365,11 +363,12 @@ leea_status run_eval(leea_ctx* c, const float* x, const int32_t* y, int32_t b, b
                "evaluate launch");
   }
   if (c->dt == LEEA_DT_FP8 && b <= 16 && c->w8.p) {
-    // the kernel finds the batch's largest magnitude itself
     st = fp8_ready(c);
+    if (!st)
+      st = dev(c, launch_amax(x, (int64_t)b * c->nd.w[0], c->x_amax, c->stream), "amax launch");
     if (st) return st;
-    return dev(c, launch_evaluate_small_fp8(c->genomes[c->cur], c->nd, c->cfg.pop, c->w8, x, y,
-                                            b, c->partial, c->stream, fin),
+    return dev(c, launch_evaluate_small_fp8(c->genomes[c->cur], c->nd, c->cfg.pop, c->w8, x,
+                                            c->x_amax, y, b, c->partial, c->stream, fin),
                "evaluate launch");
   }
   if (c->dt == LEEA_DT_F32) {

@@ -321,9 +321,7 @@ __global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void eval_small_bf16_kernel(
 // cover the 64-wide step between them (the K order inside a step is a
 // permutation shared by both operands).  Waves split the steps
 // s = wave, wave + 4, ...; the sums are multiplied by 2^(e_x + e_w) (NaN if
-// either operand is not finite) before the bias.  Every workgroup finds the
-// batch's largest magnitude itself (at most 16 rows, read from L2 while its
-// first weight step is in flight), which saves two launches per evaluation.
+// either operand is not finite) before the bias.
 __device__ __forceinline__ floatx4 mfma_fp8x32(uint32_t a0, uint32_t a1, uint32_t b0, uint32_t b1,
                                                const floatx4& c) {
   const unsigned long long a = (unsigned long long)a0 | ((unsigned long long)a1 << 32);
@@ -334,9 +332,8 @@ __device__ __forceinline__ floatx4 mfma_fp8x32(uint32_t a0, uint32_t a1, uint32_
 template <int NT>
 __global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void eval_small_fp8_kernel(
     const float* __restrict__ genomes, NetDesc nd, W1Fp8 w8, const float* __restrict__ x,
-    const int32_t* __restrict__ y, int b, float2* __restrict__ partial, EvalLds lo,
-    int tail_vec, FinArgs fin) {
-  __shared__ uint32_t xred[4];
+    const uint32_t* __restrict__ x_amax, const int32_t* __restrict__ y, int b,
+    float2* __restrict__ partial, EvalLds lo, int tail_vec, FinArgs fin) {
   const int j = blockIdx.x;
   const int tid = threadIdx.x;
   const float* __restrict__ genome = genomes + (int64_t)j * nd.stride;
@@ -345,6 +342,9 @@ __global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void eval_small_fp8_kernel(
   const int lane = tid & 63;
   const int mn = lane & 15;
   const int kq = lane >> 4;
+  const uint32_t xam = *x_amax;
+  const int neg_ex = xam < kNonFinite ? -fp8_exponent(xam) : 0;
+  const float fac = fp8_factor(xam, w8.bound[j]);
   const bool xv = mn < b;
   const float* __restrict__ xrow = x + (int64_t)(xv ? mn : 0) * n0;
   const uint8_t* __restrict__ crow[NT];
@@ -353,7 +353,6 @@ __global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void eval_small_fp8_kernel(
   floatx4 acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-  int neg_ex = 0;  // -e_x, set once the batch's largest magnitude is known
   auto xq4 = [&](int k) {  // 4 batch elements k .. k + 3 -> one word of codes
     const float4 v = (xv && k < n0) ? *reinterpret_cast<const float4*>(xrow + k) : zero4();
     return pack_fp8x4(ldexpf(v.x, neg_ex), ldexpf(v.y, neg_ex), ldexpf(v.z, neg_ex),
@@ -361,44 +360,14 @@ __global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void eval_small_fp8_kernel(
   };
   const int nss = w8.kp >> 6;
   uint4 xa, wb[NT];
-  auto loadw = [&](int s, uint4* wo) {
+  auto load = [&](int s, uint4& xo, uint4* wo) {
     const int k = 64 * s + 16 * kq;
+    xo = make_uint4(xq4(k), xq4(k + 4), xq4(k + 8), xq4(k + 12));
 #pragma unroll
     for (int t = 0; t < NT; ++t) wo[t] = *reinterpret_cast<const uint4*>(crow[t] + k);
   };
-  auto loadx = [&](int s) {
-    const int k = 64 * s + 16 * kq;
-    return make_uint4(xq4(k), xq4(k + 4), xq4(k + 8), xq4(k + 12));
-  };
-  auto load = [&](int s, uint4& xo, uint4* wo) {
-    loadw(s, wo);
-    xo = loadx(s);
-  };
   int s = wave;
-  if (s < nss) loadw(s, wb);
-  {
-    // the batch's largest magnitude (n0 % 4 == 0: whole float4s)
-    const float4* __restrict__ x4 = reinterpret_cast<const float4*>(x);
-    const int n4 = (b * n0) >> 2;
-    uint32_t m = 0;
-    for (int i = tid; i < n4; i += 256) {
-      const float4 v = x4[i];
-      uint32_t p = mag_bits(v.x), q = mag_bits(v.y), r = mag_bits(v.z), u = mag_bits(v.w);
-      p = p > q ? p : q;
-      r = r > u ? r : u;
-      p = p > r ? p : r;
-      m = p > m ? p : m;
-    }
-    m = wave_umax(m);
-    if (lane == 0) xred[wave] = m;
-    __syncthreads();
-  }
-  uint32_t xam = xred[0];
-#pragma unroll
-  for (int w = 1; w < 4; ++w) xam = xred[w] > xam ? xred[w] : xam;
-  neg_ex = xam < kNonFinite ? -fp8_exponent(xam) : 0;
-  const float fac = fp8_factor(xam, w8.bound[j]);
-  if (s < nss) xa = loadx(s);
+  if (s < nss) load(s, xa, wb);
   for (; s < nss; s += 4) {
     uint4 xn, wn[NT];
     if (s + 4 < nss) load(s + 4, xn, wn);
@@ -832,15 +801,16 @@ static hipError_t launch_small_bf16(const float* genomes, const NetDesc& nd, int
 
 template <int NT>
 static hipError_t launch_small_fp8(const float* genomes, const NetDesc& nd, int pop,
-                                   const W1Fp8& w8, const float* x, const int32_t* y, int b,
-                                   float2* partial, hipStream_t s, const FinArgs& fin) {
+                                   const W1Fp8& w8, const float* x, const uint32_t* x_amax,
+                                   const int32_t* y, int b, float2* partial, hipStream_t s,
+                                   const FinArgs& fin) {
   const int tv = tail_vectorizable(nd) ? 1 : 0;
   EvalLds lo;
   const size_t bytes = small_lds_bytes(nd, &lo);
   hipError_t e = allow_lds(eval_small_fp8_kernel<NT>, bytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((eval_small_fp8_kernel<NT>), dim3((unsigned)pop), dim3(256), bytes, s,
-                     genomes, nd, w8, x, y, b, partial, lo, tv, fin);
+                     genomes, nd, w8, x, x_amax, y, b, partial, lo, tv, fin);
   return hipGetLastError();
 }
 
@@ -980,9 +950,10 @@ hipError_t launch_evaluate_small_bf16(const float* genomes, const NetDesc& nd, i
 }
 
 hipError_t launch_evaluate_small_fp8(const float* genomes, const NetDesc& nd, int pop,
-                                     const W1Fp8& w8, const float* x, const int32_t* y, int b,
-                                     float2* partial, hipStream_t s, const FinArgs& fin) {
-  LEEA_NT_SWITCH((launch_small_fp8<N>(genomes, nd, pop, w8, x, y, b, partial, s, fin)),
+                                     const W1Fp8& w8, const float* x, const uint32_t* x_amax,
+                                     const int32_t* y, int b, float2* partial, hipStream_t s,
+                                     const FinArgs& fin) {
+  LEEA_NT_SWITCH((launch_small_fp8<N>(genomes, nd, pop, w8, x, x_amax, y, b, partial, s, fin)),
                  hipErrorInvalidValue)
 }
 

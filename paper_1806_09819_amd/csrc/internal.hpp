@@ -145,6 +145,7 @@ hipError_t launch_evaluate_lp(int dt, const float* genomes, const NetDesc& nd, i
                               const void* xq, int kp, const uint32_t* w_amax,
                               const uint32_t* x_amax, const int32_t* y, int b, float2* partial,
                               hipStream_t s);
+// *out = the largest magnitude bits over x[0..n) (written, not accumulated).
 hipError_t launch_amax(const float* x, int64_t n, uint32_t* out, hipStream_t s);
 hipError_t launch_amax_w1(const float* genomes, const NetDesc& nd, int pop, uint32_t* amax,
                           hipStream_t s);
@@ -167,8 +168,9 @@ hipError_t launch_fp8_copy(const float* genomes, const NetDesc& nd, int pop, con
 // batch x (float32) is scaled by 2^-e_x (e_x from *x_amax) and rounded on the
 // way; finishes each network itself when fin.on.
 hipError_t launch_evaluate_small_fp8(const float* genomes, const NetDesc& nd, int pop,
-                                     const W1Fp8& w8, const float* x, const int32_t* y, int b,
-                                     float2* partial, hipStream_t s, const FinArgs& fin);
+                                     const W1Fp8& w8, const float* x, const uint32_t* x_amax,
+                                     const int32_t* y, int b, float2* partial, hipStream_t s,
+                                     const FinArgs& fin);
 hipError_t launch_evaluate_lpw(const float* genomes, const NetDesc& nd, int pop,
                                const W1Shadow& wsh, const uint16_t* xq, int kp, int bpad,
                                const int32_t* y, int b, float2* partial, hipStream_t s);

@@ -28,6 +28,26 @@ __global__ __launch_bounds__(256) void amax_kernel(const float* __restrict__ x, 
   }
 }
 
+// The same for small batches in one workgroup, which writes *out itself
+// (no clearing launch before it).
+__global__ __launch_bounds__(1024) void amax_one_kernel(const float* __restrict__ x, int64_t n,
+                                                        uint32_t* __restrict__ out) {
+  __shared__ uint32_t red[16];
+  uint32_t m = 0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    const uint32_t v = mag_bits(x[i]);
+    m = v > m ? v : m;
+  }
+  m = wave_umax(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t r = red[0];
+    for (int i = 1; i < 16; ++i) r = red[i] > r ? red[i] : r;
+    *out = r;
+  }
+}
+
 // amax[j] = max over network j's W_1 of mag_bits; one workgroup per network.
 __global__ __launch_bounds__(256) void amax_w1_kernel(const float* __restrict__ genomes,
                                                       NetDesc nd, uint32_t* __restrict__ amax) {
@@ -110,6 +130,12 @@ static unsigned grid_for(int64_t n) {
 }
 
 hipError_t launch_amax(const float* x, int64_t n, uint32_t* out, hipStream_t s) {
+  if (n <= 65536) {  // up to 64 elements per thread in one workgroup
+    hipLaunchKernelGGL(amax_one_kernel, dim3(1), dim3(1024), 0, s, x, n, out);
+    return hipGetLastError();
+  }
+  hipError_t e = launch_fill(reinterpret_cast<float*>(out), 1, 0.0f, s);
+  if (e != hipSuccess) return e;
   // at least 8 elements per thread, at most 256 workgroups (256 atomics)
   int64_t g = (n + 2047) / 2048;
   g = g < 1 ? 1 : (g > 256 ? 256 : g);
