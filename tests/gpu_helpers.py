@@ -11,7 +11,18 @@ from paper_1806_09819_amd import leea as B
 F32 = np.float32
 DEV = "cuda"
 FIT_RTOL = 1e-5      # fitness tolerance relative to the float64 oracle
-FIT_ATOL = 1e-6      # absolute floor for fitness values near zero
+FIT_ATOL = 1e-6      # absolute floor, only for fitness values below FIT_ABS_BELOW
+FIT_ABS_BELOW = 0.1  # |f| below which float32 log-softmax loses log(1 + t) terms outright
+
+
+def fit_tol(f_ref, rtol=FIT_RTOL):
+    """Allowed |f_gpu - f_ref|: rtol |f_ref|, plus FIT_ATOL where |f_ref| <
+    FIT_ABS_BELOW (a network that fits its batch almost perfectly: its
+    per-sample log-likelihoods are -log(1 + t) with t below float32's
+    resolution, which the float32 softmax rounds to 0; relative error cannot
+    bound that)."""
+    a = np.abs(np.asarray(f_ref, dtype=np.float64))
+    return rtol * a + np.where(a < FIT_ABS_BELOW, FIT_ATOL, 0.0)
 
 
 def say(*a):
@@ -78,7 +89,7 @@ def check_fitness(f_gpu, acc_gpu, f_ref, acc_ref, amb, b, label=""):
     assert np.array_equal(np.isnan(f_gpu), nan_ref), label
     ok = ~nan_ref
     err = np.abs(f_gpu[ok] - f_ref[ok])
-    tol = FIT_RTOL * np.abs(f_ref[ok]) + FIT_ATOL
+    tol = fit_tol(f_ref[ok])
     assert np.all(err <= tol), (label, float(np.max(err / np.maximum(np.abs(f_ref[ok]), 1e-30))))
     dc = np.abs(np.rint(np.asarray(acc_gpu, dtype=np.float64) * b) - np.rint(acc_ref * b))
     assert np.all(dc[ok] <= amb[ok]), (label, dc.max())

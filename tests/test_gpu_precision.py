@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import (F32, FIT_ATOL, FIT_RTOL, genomes_np, make_run, oracle_cfg, say, to_dev,
+from gpu_helpers import (F32, FIT_RTOL, fit_tol, genomes_np, make_run, oracle_cfg, say, to_dev,
                          to_np)
 from oracle import leea as O
 from oracle import precision as Q
@@ -55,7 +55,7 @@ def check(f_gpu, acc_gpu, f_ref, acc_ref, amb, b, label, stress=()):
     rtol = np.full(f_ref.shape, FIT_RTOL)
     rtol[list(stress)] = STRESS_RTOL
     err = np.abs(f_gpu[ok] - f_ref[ok])
-    assert np.all(err <= rtol[ok] * np.abs(f_ref[ok]) + FIT_ATOL), \
+    assert np.all(err <= fit_tol(f_ref[ok], rtol[ok])), \
         (label, float(np.max(err / np.abs(f_ref[ok]))))
     dc = np.abs(np.rint(np.asarray(acc_gpu, dtype=np.float64)[ok] * b) - np.rint(acc_ref[ok] * b))
     assert np.all(dc <= amb[ok]), (label, dc.max())
@@ -250,12 +250,12 @@ def test_fp8_scales_after_restore():
     assert np.array_equal(np.isnan(f1), ~ok)
     rtol = np.full(f_ref.shape, FIT_RTOL)
     rtol[3] = STRESS_RTOL
-    assert np.all(np.abs(f1[ok] - f_ref[ok]) <= rtol[ok] * np.abs(f_ref[ok]) + FIT_ATOL)
+    assert np.all(np.abs(f1[ok] - f_ref[ok]) <= fit_tol(f_ref[ok], rtol[ok]))
     run.load(ck)                                       # load recomputes them as well
     f2, _ = run.score(xd, yd)
     pop0 = genomes_np(run)
     f_ref0, _, _ = lowp_oracle(pop0, widths, x, y, "fp8")
-    assert np.all(np.abs(to_np(f2) - f_ref0) <= FIT_RTOL * np.abs(f_ref0) + FIT_ATOL)
+    assert np.all(np.abs(to_np(f2) - f_ref0) <= fit_tol(f_ref0))
 
 
 @pytest.mark.parametrize("dt", ["bf16", "fp8"])

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import (F32, check_fitness, genomes_np, make_run, oracle_eval, say, to_dev,
+from gpu_helpers import (F32, check_fitness, fit_tol, genomes_np, make_run, oracle_eval, say, to_dev,
                          to_np)
 from oracle import leea as O
 from paper_1806_09819_amd import datagen
@@ -72,7 +72,7 @@ def test_teacher_forced_generations(data, name, over):
         check_fitness(to_np(f_raw), to_np(acc), f_o, acc_o, amb, b, "gen%d" % g)
         fa_o = O.inherit(f_o, fi.astype(np.float64), ocfg.alpha)
         fa = to_np(f_adj).astype(np.float64)
-        assert np.all(np.abs(fa - fa_o) <= 1e-5 * np.abs(fa_o) + 1e-6)
+        assert np.all(np.abs(fa - fa_o) <= fit_tol(fa_o))
 
 
 def _run_steps(run, xd, yd, b, g0, n):

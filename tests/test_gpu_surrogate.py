@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import (FIT_ATOL, FIT_RTOL, F32, check_fitness, genomes_np, make_run,
+from gpu_helpers import (F32, check_fitness, fit_tol, genomes_np, make_run,
                          oracle_eval, say, to_dev, to_np)
 from oracle import leea as O
 from oracle import surrogate as S
@@ -104,7 +104,7 @@ def _teacher_forced(params, gens, k, steps, lr, warmup, tau_min, seed=0):
         idx = O.batch_indices(ocfg.seed, g, b, x.shape[0], ocfg.run)
         fo, _ = O.evaluate(new_o, widths, x[idx], y[idx])
         fr = to_np(f_raw).astype(np.float64)
-        assert np.all(np.abs(fr - fo) <= FIT_RTOL * np.abs(fo) + FIT_ATOL), g
+        assert np.all(np.abs(fr - fo) <= fit_tol(fo)), g
         # judge and training
         yk = to_np(f_raw)[n_e:].astype(np.float64)
         cp = to_np(v["chosen_pred"]).astype(np.float64)
