@@ -443,55 +443,70 @@ def cpu_baseline(params, b, sample_pop=100, reps=3):
     return out
 
 
-def accuracy_runs(x_train, y_train, x_val, y_val, gens=1000, every=50, batch=512):
+def accuracy_runs(x_train, y_train, x_val, y_val, gens=1000, every=50, batch=512,
+                  seeds=(1, 2, 3)):
     """The metric's second half: the paper-scale workload (784-112-32-10,
-    P = 1000, batch 512) run for `gens` generations with a float32, bfloat16
-    and FP8 first layer from the same seed.  Generations are timed alone
-    (validation scoring every `every` generations sits outside the timed
-    segments).  Reported per arithmetic: generations/s, the validation
-    accuracy (5000 held-out samples) of the rank-0 network and the
-    population's best after the last generation, and the generations and
-    seconds each needs to reach the float32 run's final rank-0 accuracy."""
+    P = 1000, batch 512) run for `gens` generations in float32, bfloat16 and
+    FP8, each from the same seeds (one run per seed and arithmetic: the
+    trajectory of one run depends on every rounding, so single runs differ by
+    a few points of accuracy).  Generations are timed alone (validation
+    scoring every `every` generations sits outside the timed segments).
+    Reported per arithmetic: generations/s, the validation accuracy (5000
+    held-out samples) of the rank-0 network after the last generation (mean
+    over the seeds and per seed), the mean trajectory, its largest distance
+    from the float32 one, and the generations and seconds the seed-mean
+    accuracy needs to come within one point of the float32 runs' final
+    seed-mean accuracy."""
     import torch
     from paper_1806_09819_amd import leea as B
 
     out = {}
     nv = x_val.shape[0]
     for dt in ("f32", "bf16", "fp8"):
-        params = workload(batch, dt)
-        run = B.Leea(B.make_config(**dict(params, max_batch=max(batch, nv))))
-        xb = torch.empty((batch, params["widths"][0]), dtype=torch.float32, device="cuda")
-        yb = torch.empty((batch,), dtype=torch.int32, device="cuda")
-        run.draw_batch(0, x_train, y_train, batch, xb, yb)
-        run.evaluate(xb, yb)
-        traj, t_gen = [], 0.0
-        for g0 in range(1, gens + 1, every):
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            for g in range(g0, min(g0 + every, gens + 1)):
-                run.draw_batch(g, x_train, y_train, batch, xb, yb)
-                run.step(xb, yb, outputs=False)
-            torch.cuda.synchronize()
-            t_gen += time.perf_counter() - t
-            _, acc = run.score(x_val, y_val)
-            _, f_adj = run.population()
-            best = int(torch.argmax(torch.nan_to_num(f_adj, nan=-np.inf)).item())
-            a = acc.cpu().numpy()
-            traj.append((min(g0 + every - 1, gens), t_gen, float(a[best]), float(a.max())))
-        run.close()
-        out[dt] = dict(gens_per_s=gens / t_gen, val_acc_rank0=traj[-1][2],
-                       val_acc_best=traj[-1][3],
-                       trajectory=[[g, round(t, 4), round(a0, 4), round(ab, 4)]
-                                   for g, t, a0, ab in traj],
-                       _raw=[(g, t, a0) for g, t, a0, _ in traj])
-    target = out["f32"]["val_acc_rank0"]
+        per_seed, t_total, trajs = [], 0.0, []
+        for seed in seeds:
+            params = dict(workload(batch, dt), seed=seed)
+            run = B.Leea(B.make_config(**dict(params, max_batch=max(batch, nv))))
+            xb = torch.empty((batch, params["widths"][0]), dtype=torch.float32, device="cuda")
+            yb = torch.empty((batch,), dtype=torch.int32, device="cuda")
+            run.draw_batch(0, x_train, y_train, batch, xb, yb)
+            run.evaluate(xb, yb)
+            traj, t_gen = [], 0.0
+            for g0 in range(1, gens + 1, every):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                for g in range(g0, min(g0 + every, gens + 1)):
+                    run.draw_batch(g, x_train, y_train, batch, xb, yb)
+                    run.step(xb, yb, outputs=False)
+                torch.cuda.synchronize()
+                t_gen += time.perf_counter() - t
+                _, acc = run.score(x_val, y_val)
+                _, f_adj = run.population()
+                best = int(torch.argmax(torch.nan_to_num(f_adj, nan=-np.inf)).item())
+                traj.append((min(g0 + every - 1, gens), t_gen, float(acc[best].item())))
+            run.close()
+            t_total += t_gen
+            per_seed.append(traj[-1][2])
+            trajs.append(traj)
+        gens_per_s = gens * len(seeds) / t_total
+        mean_traj = [(trajs[0][i][0], float(np.mean([tr[i][2] for tr in trajs])))
+                     for i in range(len(trajs[0]))]
+        out[dt] = dict(gens_per_s=gens_per_s, val_acc_rank0=float(np.mean(per_seed)),
+                       val_acc_rank0_per_seed=per_seed,
+                       trajectory=[[g, round(a, 4)] for g, a in mean_traj])
+    # "same accuracy": within one point of the float32 runs' final seed-mean
+    # accuracy (the seed means themselves spread by about that much)
+    target = out["f32"]["val_acc_rank0"] - 0.01
+    f32_traj = dict((g, a) for g, a in out["f32"]["trajectory"])
     for dt, r in out.items():
-        hit = [(g, t) for g, t, a0 in r.pop("_raw") if a0 >= target]
-        r["gens_to_f32_final_acc"] = hit[0][0] if hit else None
-        r["seconds_to_f32_final_acc"] = hit[0][1] if hit else None
+        hit = [g for g, a in r["trajectory"] if a >= target]
+        r["gens_to_f32_final_acc"] = hit[0] if hit else None
+        r["seconds_to_f32_final_acc"] = hit[0] / r["gens_per_s"] if hit else None
+        r["max_abs_diff_vs_f32"] = round(max(abs(a - f32_traj[g]) for g, a in r["trajectory"]), 4)
     out["matched_accuracy_target"] = target
     out["workload"] = ("784-112-32-10, P = 1000, batch %d, %d generations, paper defaults, "
-                       "prototype data (45k train, 5k validation)" % (batch, gens))
+                       "prototype data (45k train, 5k validation), seeds %s"
+                       % (batch, gens, list(seeds)))
     return out
 
 

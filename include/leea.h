@@ -76,25 +76,27 @@ enum { LEEA_OP_ELITE = 0, LEEA_OP_CROSSOVER = 1, LEEA_OP_MUTATION = 2 };
  * self-adaptive, where every individual carries a sigma gene (see
  * leea_crossover_mutate). */
 enum { LEEA_SIGMA_CONSTANT = 0, LEEA_SIGMA_DECAY = 1, LEEA_SIGMA_SELF_ADAPTIVE = 2 };
-/* Arithmetic of the first layer, the shared-batch product X W_1^T of the
- * whole population (section 3.3); every other layer, the fitness (Eq. 1)
- * and the genomes stay float32.
+/* Arithmetic of the forward pass (section 3.3): the weights of every layer
+ * and the network's input, the batch, in the given format; the products
+ * are summed in float32; biases, hidden activations, the fitness (Eq. 1)
+ * and the genomes stay float32.  (Hidden activations are not rounded: they
+ * are float32 sums whose last bits depend on the summation order.)
  * F32:  float32 operands (the paper's arithmetic).
- * BF16: X and W_1 rounded to bfloat16 (nearest, ties to even), products
- *       summed in float32 on the bf16 matrix cores.
- * FP8:  OCP FP8 E4M3 with power-of-two scales: X / 2^e_x and W_1 / 2^e_w
- *       rounded to E4M3 (nearest, ties to even), e the smallest integer with
- *       B <= 448 * 2^e, products summed in float32 and multiplied by
- *       2^(e_x + e_w).  For the batch B is its largest |value|.  For each
- *       network's W_1 (one scale per individual) B is its largest |value|
- *       after initialisation, leea_set_state, leea_load or a surrogate step,
- *       and for a child of crossover_mutate the bound its parents give
- *       (elite: the parent's largest |W_1|; crossover: the larger parent's;
- *       mutant: fl(fl(a * (1 + 2^-20)) + fl(6 * sigma)), a the parent's),
- *       which is known before the child is written, so that the variation
- *       kernel writes the child's FP8 copy of W_1 with it.  A batch holding
- *       NaN or an infinity gives every network a NaN fitness; such a W_1
- *       gives its network a NaN fitness. */
+ * BF16: X and every W_l rounded to bfloat16 (nearest, ties to even); the
+ *       first layer on the bf16 matrix cores.
+ * FP8:  OCP FP8 E4M3 with power-of-two scales, one per network and layer:
+ *       X / 2^e_x and W_l / 2^e_l rounded to E4M3 (nearest, ties to even), e
+ *       the smallest integer with B <= 448 * 2^e, each layer's sums
+ *       multiplied by 2^(e_x + e_1) (first layer) or 2^e_l.  For the batch
+ *       and for W_2 .. W_L, B is the largest |value|.  For each network's W_1
+ *       B is its largest |value| after initialisation, leea_set_state,
+ *       leea_load or a surrogate step, and for a child of crossover_mutate
+ *       the bound its parents give (elite: the parent's largest |W_1|;
+ *       crossover: the larger parent's; mutant: fl(fl(a * (1 + 2^-20)) +
+ *       fl(6 * sigma)), a the parent's), which is known before the child is
+ *       written, so that the variation kernel writes the child's FP8 copy of
+ *       W_1 with it.  A batch holding NaN or an infinity gives every network a
+ *       NaN fitness; such a weight gives its network a NaN fitness. */
 enum { LEEA_DT_F32 = 0, LEEA_DT_BF16 = 1, LEEA_DT_FP8 = 2 };
 
 /* Hyperparameters of one EA run.  Counts are integers: the paper's
@@ -124,7 +126,7 @@ typedef struct {
   float tau;                              /* self-adaptation rate in [0, 10]; 0 = 1/sqrt(genes) */
   int32_t input_pool;                     /* 0, or 2: draw_batch max-pools 2x2 from square images
                                              of 4*widths[0] pixels (section 4.1) */
-  int32_t eval_dtype;                     /* LEEA_DT_*: arithmetic of the first layer (BF16
+  int32_t eval_dtype;                     /* LEEA_DT_*: arithmetic of the weights (BF16
                                              adds a bfloat16 copy of every W_1 to the
                                              workspace, FP8 an FP8 copy) */
 } leea_config;

@@ -1,29 +1,35 @@
 """Reduced-precision evaluation of the population (oracle side; test
 infrastructure only).
 
-The paper evaluates in float32.  The reduced-precision variants change only
-the first layer, the product of the shared batch with every network's
-first weight matrix (section 3.3), which holds most of the weights and
-FLOPs; the per-network rest of the forward pass and the fitness (Eq. 1)
-stay as in ``leea.forward``:
+The paper evaluates in float32.  The reduced-precision variants round the
+weights of every layer and the network's input, the batch; the products
+accumulate in float32 and the biases, the hidden activations and the
+fitness (Eq. 1) stay float32 (float64 here):
 
-* ``bf16``: the batch X and the weights W_1 are rounded to bfloat16
-  (8 significant bits, float32's exponent range; round to nearest, ties to
-  even).  Products of two such values are exact in float32, so the layer is
-  a sum of exact products: the device accumulates it in float32, the
-  oracle in float64.
+* ``bf16``: the batch X and every weight matrix W_l are rounded to
+  bfloat16 (8 significant bits, float32's exponent range; round to
+  nearest, ties to even).  In the first layer both operands are bfloat16,
+  so its products are exact in float32 and the layer is a sum of exact
+  products: the device accumulates it in float32, the oracle in float64.
 * ``fp8``: OCP FP8 E4M3 (1 sign, 4 exponent bits with bias 7, 3 mantissa
   bits; largest finite value 448, no infinities, subnormals down to 2^-9)
-  with power-of-two scales: W_1 of each network is divided by 2^e_w and X
-  by 2^e_x, rounded to E4M3 (nearest, ties to even), and the product is
-  multiplied back by 2^(e_w + e_x).  e is the smallest integer with
+  with power-of-two scales, one per network and layer: W_l of each network
+  is divided by 2^e_l and X by 2^e_x, rounded to E4M3 (nearest, ties to
+  even), and each layer's sums are multiplied back by 2^(e_l + e_x) (the
+  first layer) or 2^e_l (later layers).  e is the smallest integer with
   B <= 448 * 2^e for a bound B of the operand's largest magnitude, so no
-  scaled value exceeds 448.  For the batch, B is its largest magnitude.  For
-  a network's W_1 it is its largest magnitude after initialisation or a
-  restore, and for a child the bound its parents give (``fp8_child_bounds``),
-  known before the child exists, so that the child's FP8 copy can be written
-  as the child is made.  An operand holding NaN or an infinity (a non-finite
-  bound) makes the fitness of the affected networks NaN.
+  scaled value exceeds 448.  For the batch and for W_2 .. W_L, B is the
+  largest magnitude.  For a network's W_1 it is its largest magnitude after
+  initialisation or a restore, and for a child the bound its parents give
+  (``fp8_child_bounds``), known before the child exists, so that the
+  child's FP8 copy can be written as the child is made.  An operand holding
+  NaN or an infinity (a non-finite bound) makes the fitness of the affected
+  networks NaN.
+
+The hidden activations are not rounded: they are float32 sums whose
+summation order differs between any two implementations, and rounding them
+to 8 or 3 significant bits would turn that last-bit difference into a
+whole rounding step wherever a sum lies near a rounding midpoint.
 
 Scaling by powers of two and products of these short significands are
 exact in float64; beyond the quantisation itself the oracle rounds only in
@@ -195,8 +201,24 @@ def layer1_operands(genome, widths, x, dtype, w_bound=None):
     raise ValueError("unknown dtype %r" % (dtype,))
 
 
+def tail_operand(W, dtype):
+    """(Wq, factor) of a weight matrix past the first layer: the layer's
+    product with activations h is factor * h Wq^T exactly as in float64;
+    Wq is None when an fp8 weight is not finite."""
+    W = np.asarray(W, dtype=np.float32)
+    if dtype == BF16:
+        return round_bf16(W).astype(np.float64), 1.0
+    if dtype == FP8:
+        wq, e = quantize_fp8(W)
+        return (None, None) if wq is None else (wq, 2.0**e)
+    if dtype == F32:
+        return W.astype(np.float64), 1.0
+    raise ValueError("unknown dtype %r" % (dtype,))
+
+
 def forward_lowp(genome, widths, x, dtype, w_bound=None):
-    """Logits (float64) of one network with the first layer in `dtype`."""
+    """Logits (float64) of one network with every layer's weights (and the
+    batch) in `dtype`."""
     layers = L.unpack(np.asarray(genome), widths)
     xq, wq, factor = layer1_operands(genome, widths, x, dtype, w_bound)
     n = np.asarray(x).shape[0]
@@ -205,15 +227,19 @@ def forward_lowp(genome, widths, x, dtype, w_bound=None):
     h = factor * (xq @ wq.T) + layers[0][1].astype(np.float64)
     for l, (W, b) in enumerate(layers):
         if l > 0:
-            h = h @ W.astype(np.float64).T + b.astype(np.float64)
+            Wq, fac_l = tail_operand(W, dtype)
+            if Wq is None:
+                return np.full((n, widths[-1]), np.nan)
+            h = fac_l * (h @ Wq.T) + b.astype(np.float64)
         if l < len(layers) - 1:
             h = np.maximum(h, 0.0)
     return h
 
 
 def evaluate_lowp(pop, widths, x, y, dtype, w_bounds=None):
-    """Raw fitness and accuracy of every network with the first layer in
-    `dtype` (float64 everywhere else); w_bounds: per-network FP8 bounds."""
+    """Raw fitness and accuracy of every network with its weights and the
+    batch in `dtype` (float64 everywhere else); w_bounds: per-network FP8
+    bounds of W_1."""
     P = pop.shape[0]
     f = np.empty(P, dtype=np.float64)
     acc = np.empty(P, dtype=np.float64)

@@ -58,6 +58,7 @@ struct leea_ctx {
   W1Shadow wsh;         // bfloat16 copy of every W_1 (bfloat16 kernels), or none
   W1Fp8 w8;             // FP8 copy of every W_1 with its scale bounds (FP8 kernels)
   uint32_t* w_bound;    // FP8: bound of each network's largest |W_1| (scale of its copy)
+  uint32_t* tail_amax;  // FP8: largest |W_l| (l >= 2) of each network, [pop][kTailScales]
   int w8_ok;            // FP8 amax, bounds and copy match the current population
   int wsh_ok;           // the copy matches the current population
   // fitness surrogate (leea_surrogate_attach)
@@ -191,7 +192,7 @@ leea_status validate(const leea_config* cfg, NetDesc* nd) {
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Carve {
-  size_t genomes, scalars, plan, order, partial, xq, wsh, w8, total;
+  size_t genomes, scalars, plan, order, partial, xq, wsh, w8, tail, total;
 };
 
 int padded_k(int n0) { return (n0 + 31) & ~31; }
@@ -228,6 +229,7 @@ Carve carve(const leea_config* cfg, const NetDesc& nd) {
   c.xq = 0;
   c.wsh = 0;
   c.w8 = 0;
+  c.tail = 0;
   if (cfg->eval_dtype != LEEA_DT_F32) {
     const size_t kp = (size_t)padded_k(nd.w[0]);
     const size_t row = (size_t)nd.w[0] * 4 > kp * 2 ? (size_t)nd.w[0] * 4 : kp * 2;
@@ -237,8 +239,10 @@ Carve carve(const leea_config* cfg, const NetDesc& nd) {
     c.xq = align256(q) + 256;  // + the batch amax
     if (uses_shadow(cfg, nd)) c.wsh = align256(P * (size_t)shadow_net(nd) * 2);
     if (uses_fp8_copy(cfg, nd)) c.w8 = align256(P * (size_t)fp8_net(nd));
+    if (cfg->eval_dtype == LEEA_DT_FP8) c.tail = align256(P * (size_t)kTailScales * 4);
   }
-  c.total = 2 * c.genomes + 10 * c.scalars + c.plan + c.order + c.partial + c.xq + c.wsh + c.w8;
+  c.total = 2 * c.genomes + 10 * c.scalars + c.plan + c.order + c.partial + c.xq + c.wsh + c.w8 +
+            c.tail;
   return c;
 }
 
@@ -288,7 +292,7 @@ leea_status fp8_ready(leea_ctx* c) {
   return st;
 }
 
-// Reduced-precision first layer: batch amax (FP8), the quantised batch, then
+// Reduced-precision forward pass: FP8 scales, the quantised batch, then
 // the small-batch kernel on quantised values (b <= 16) or the bf16 / FP8
 // matrix-core kernel.  Returns the number of partial row tiles.
 leea_status run_eval_lp(leea_ctx* c, const float* x, const int32_t* y, int32_t b, int* n_mt) {
@@ -296,7 +300,10 @@ leea_status run_eval_lp(leea_ctx* c, const float* x, const int32_t* y, int32_t b
   leea_status st = fp8_ready(c);
   if (st) return st;
   if (c->dt == LEEA_DT_FP8) {
-    st = dev(c, launch_amax(x, (int64_t)b * n0, c->x_amax, c->stream), "amax launch");
+    // the batch amax and the later layers' largest magnitudes in one launch
+    st = dev(c, launch_fp8_scales(x, (int64_t)b * n0, c->x_amax, c->genomes[c->cur], c->nd,
+                                  c->cfg.pop, c->tail_amax, c->stream),
+             "FP8 scales launch");
     if (st) return st;
   }
   const bool small = b <= 16;
@@ -365,7 +372,9 @@ leea_status run_eval(leea_ctx* c, const float* x, const int32_t* y, int32_t b, b
   if (c->dt == LEEA_DT_FP8 && b <= 16 && c->w8.p) {
     st = fp8_ready(c);
     if (!st)
-      st = dev(c, launch_amax(x, (int64_t)b * c->nd.w[0], c->x_amax, c->stream), "amax launch");
+      st = dev(c, launch_fp8_scales(x, (int64_t)b * c->nd.w[0], c->x_amax, c->genomes[c->cur],
+                                    c->nd, c->cfg.pop, c->tail_amax, c->stream),
+               "FP8 scales launch");
     if (st) return st;
     return dev(c, launch_evaluate_small_fp8(c->genomes[c->cur], c->nd, c->cfg.pop, c->w8, x,
                                             c->x_amax, y, b, c->partial, c->stream, fin),
@@ -513,6 +522,10 @@ leea_status leea_init_population(const leea_config* cfg, void* workspace, size_t
   c->w8.amax_par = nullptr;
   c->w8.bound = c->w_bound;
   c->w8_ok = 0;
+  p += cv.w8;
+  c->tail_amax = cv.tail ? (uint32_t*)p : nullptr;
+  c->w8.tail = c->tail_amax;
+  p += cv.tail;
   c->dt = cfg->eval_dtype;
   c->kp = padded_k(nd.w[0]);
   c->n_mt_max = (cfg->max_batch + 63) / 64;

@@ -4,6 +4,7 @@
 #pragma once
 
 #include "internal.hpp"
+#include "lowp.hpp"
 
 namespace leea {
 
@@ -73,10 +74,13 @@ __device__ __forceinline__ float4 load_once(const float* p) {
 // tile once and runs G row tiles at a time on independent accumulators, so
 // the matrix-core chains overlap (G = 1 for register-tight kernels); every
 // output tile accumulates its K range in the same order (s = 0, 1, ... and
-// e = 0..3 inside a super-step) whatever G is.
-template <int G>
+// e = 0..3 inside a super-step) whatever G is.  DT != 0: the weights are
+// quantised as they are loaded and, for DT = 2, the sums multiplied by wfac
+// before the bias (tail_and_fitness).
+template <int G, int DT = 0>
 static __device__ void mfma_layer(const float* in, int ldi, int n_in, float* out, int ldo, int n_out,
-                           const float* W, const float* bias, bool relu, int mtiles) {
+                           const float* W, const float* bias, bool relu, int mtiles,
+                           int neg_e = 0, float wfac = 1.0f) {
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int mn = lane & 15;
@@ -107,7 +111,13 @@ static __device__ void mfma_layer(const float* in, int ldi, int n_in, float* out
       if (s < kss) {
         const int k = 16 * s + 4 * kq;
         const bool kv = k < n_in;
-        const float4 v = *reinterpret_cast<const float4*>(wr + (kv ? k : 0));
+        float4 v = *reinterpret_cast<const float4*>(wr + (kv ? k : 0));
+        if constexpr (DT != 0) {
+          v.x = quantize<DT>(v.x, neg_e);
+          v.y = quantize<DT>(v.y, neg_e);
+          v.z = quantize<DT>(v.z, neg_e);
+          v.w = quantize<DT>(v.w, neg_e);
+        }
         if (nv && kv) bf[s] = v;
       }
     }
@@ -145,7 +155,9 @@ static __device__ void mfma_layer(const float* in, int ldi, int n_in, float* out
           const int m = mt + g * mstep;
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            float v = acc[g][i] + bb;
+            float v = acc[g][i];
+            if constexpr (DT == 2) v = v * wfac;
+            v = v + bb;
             if (relu) v = relu_keep_nan(v);
             out[(m * 16 + 4 * kq + i) * ldo + n] = nv ? v : 0.0f;
           }
@@ -158,10 +170,10 @@ static __device__ void mfma_layer(const float* in, int ldi, int n_in, float* out
 // mfma_layer with as many row tiles per group as this wave has (up to GMAX):
 // a wave with fewer row tiles than the group size would multiply copies of
 // its last tile for nothing.  The result does not depend on the group size.
-template <int GMAX>
+template <int GMAX, int DT = 0>
 static __device__ void mfma_layer_fit(const float* in, int ldi, int n_in, float* out, int ldo,
                                       int n_out, const float* W, const float* bias, bool relu,
-                                      int mtiles) {
+                                      int mtiles, int neg_e = 0, float wfac = 1.0f) {
   const int wave = threadIdx.x >> 6;
   const int ntiles = (n_out + 15) >> 4;
   int mt0 = 0, mstep = 1;
@@ -172,22 +184,24 @@ static __device__ void mfma_layer_fit(const float* in, int ldi, int n_in, float*
   const int r = mt0 < mtiles ? (mtiles - mt0 + mstep - 1) / mstep : 0;
   if constexpr (GMAX >= 4) {
     if (r >= 3) {
-      mfma_layer<4>(in, ldi, n_in, out, ldo, n_out, W, bias, relu, mtiles);
+      mfma_layer<4, DT>(in, ldi, n_in, out, ldo, n_out, W, bias, relu, mtiles, neg_e, wfac);
       return;
     }
   }
   if constexpr (GMAX >= 2) {
     if (r == 2) {
-      mfma_layer<2>(in, ldi, n_in, out, ldo, n_out, W, bias, relu, mtiles);
+      mfma_layer<2, DT>(in, ldi, n_in, out, ldo, n_out, W, bias, relu, mtiles, neg_e, wfac);
       return;
     }
   }
-  mfma_layer<1>(in, ldi, n_in, out, ldo, n_out, W, bias, relu, mtiles);
+  mfma_layer<1, DT>(in, ldi, n_in, out, ldo, n_out, W, bias, relu, mtiles, neg_e, wfac);
 }
 
 // The same layer on VALU, for hidden widths that are not multiples of 4.
+template <int DT = 0>
 static __device__ void scalar_layer(const float* in, int ldi, int n_in, float* out, int ldo, int n_out,
-                             const float* W, const float* bias, bool relu, int rows) {
+                             const float* W, const float* bias, bool relu, int rows,
+                             int neg_e = 0, float wfac = 1.0f) {
   const int n16 = (n_out + 15) & ~15;
   for (int idx = threadIdx.x; idx < rows * n16; idx += blockDim.x) {
     const int m = idx / n16;
@@ -196,7 +210,8 @@ static __device__ void scalar_layer(const float* in, int ldi, int n_in, float* o
     if (n < n_out) {
       const float* a = in + m * ldi;
       const float* w = W + (int64_t)n * n_in;
-      for (int k = 0; k < n_in; ++k) v += a[k] * w[k];
+      for (int k = 0; k < n_in; ++k) v += a[k] * quantize<DT>(w[k], neg_e);
+      if constexpr (DT == 2) v = v * wfac;
       v += bias[n];
       if (relu) v = relu_keep_nan(v);
     }
@@ -213,12 +228,17 @@ static __device__ void scalar_layer(const float* in, int ldi, int n_in, float* o
 // global memory with toff = 0, or a copy of the genome's tail in LDS).
 // G: row tiles per matrix-core group in the hidden layers (see mfma_layer).
 // y == nullptr: the label of row threadIdx.x is ylab (rows <= blockDim.x),
-// loaded by the caller ahead of time.
-template <int G>
+// loaded by the caller ahead of time.  DT: arithmetic of the weights of
+// layers 2..L (0 float32; 1 rounded to bfloat16; 2 E4M3 with a power-of-two
+// scale per layer from its largest magnitude, whose factor multiplies the
+// layer's sums before the bias: ts.amax[l] when given, else reduced here);
+// the activations stay float32.  Every thread of the workgroup calls it.
+template <int G, int DT = 0>
 static __device__ float2 tail_and_fitness(float* lds, const EvalLds& lo, const NetDesc& nd,
                                  const float* tw, int64_t toff, int mtiles, int rows,
                                  int m0, const int32_t* __restrict__ y, bool tail_vec,
-                                 float2* __restrict__ out, int ylab = 0) {
+                                 float2* __restrict__ out, int ylab = 0,
+                                 const TailScales& ts = TailScales{{}, 0}) {
   const float* in = lds + lo.h1;
   int ldi = lo.ld1;
   float* dst = lds + lo.ta;
@@ -226,10 +246,16 @@ static __device__ float2 tail_and_fitness(float* lds, const EvalLds& lo, const N
     const float* W = tw + (nd.woff[l] - toff);
     const float* bias = tw + (nd.boff[l] - toff);
     const bool relu = l < nd.L - 1;
+    int neg_e = 0;
+    float wfac = 1.0f;
+    if constexpr (DT == 2)
+      tail_fp8_scale(ts.given ? ts.amax[l] : block_amax(W, nd.w[l] * nd.w[l + 1]), neg_e, wfac);
     if (tail_vec)
-      mfma_layer_fit<G>(in, ldi, nd.w[l], dst, lo.ldt, nd.w[l + 1], W, bias, relu, mtiles);
+      mfma_layer_fit<G, DT>(in, ldi, nd.w[l], dst, lo.ldt, nd.w[l + 1], W, bias, relu, mtiles,
+                            neg_e, wfac);
     else
-      scalar_layer(in, ldi, nd.w[l], dst, lo.ldt, nd.w[l + 1], W, bias, relu, 16 * mtiles);
+      scalar_layer<DT>(in, ldi, nd.w[l], dst, lo.ldt, nd.w[l + 1], W, bias, relu, 16 * mtiles,
+                       neg_e, wfac);
     __syncthreads();
     in = dst;
     ldi = lo.ldt;

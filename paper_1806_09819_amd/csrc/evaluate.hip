@@ -82,15 +82,17 @@ __device__ __forceinline__ void finalize_in_kernel(int j, float2 p, int b, const
 // split K, acc[t] = this wave's K-partial of rows 4 kq + i, neurons
 // 16 t + mn): the 4 K-partial tiles -> LDS [wave][16][ld1], summed in a fixed
 // order into tile 0, which becomes the layer-1 activations (times fac when
-// SCALED, bias, ReLU, zero padding columns); then the tail layers, the
-// fitness and, with fin.on, the network's finish.
-template <int NT, bool SCALED>
+// SCALED, bias, ReLU, zero padding columns); then the tail layers (weights
+// in the arithmetic DT, see tail_and_fitness), the fitness and, with fin.on,
+// the network's finish.
+template <int NT, bool SCALED, int DT = 0>
 __device__ __forceinline__ void small_epilogue(const floatx4 (&acc)[NT], float fac, int j,
                                                const float* __restrict__ genome,
                                                const NetDesc& nd, const int32_t* __restrict__ y,
                                                int b, float2* __restrict__ partial,
                                                const EvalLds& lo, int tail_vec,
-                                               const FinArgs& fin) {
+                                               const FinArgs& fin,
+                                               const TailScales& ts = TailScales{{}, 0}) {
   extern __shared__ float lds[];
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
@@ -121,8 +123,8 @@ __device__ __forceinline__ void small_epilogue(const floatx4 (&acc)[NT], float f
     lds[m * ld1 + n] = v;
   }
   __syncthreads();
-  const float2 r = tail_and_fitness<1>(lds, lo, nd, genome, 0, 1, b, 0, y, tail_vec != 0,
-                                       partial + j);
+  const float2 r = tail_and_fitness<1, DT>(lds, lo, nd, genome, 0, 1, b, 0, y, tail_vec != 0,
+                                           partial + j, 0, ts);
   if (fin.on && tid == 0) finalize_in_kernel(j, r, b, fin);
 }
 
@@ -195,7 +197,7 @@ __device__ __forceinline__ void eval_small_body(int j, const float* __restrict__
   }
 
   const float fac = DT == 2 ? fp8_factor(*x_amax, w_amax[j]) : 1.0f;
-  small_epilogue<NT, DT == 2>(acc, fac, j, genome, nd, y, b, partial, lo, tail_vec, fin);
+  small_epilogue<NT, DT == 2, DT>(acc, fac, j, genome, nd, y, b, partial, lo, tail_vec, fin);
 }
 
 template <int NT, int DT>
@@ -295,7 +297,7 @@ __device__ __forceinline__ void eval_small_bf16_body(int j, const float* __restr
       for (int t = 0; t < NT; ++t) wb[t] = wn[t];
     }
   }
-  small_epilogue<NT, false>(acc, 1.0f, j, genome, nd, y, b, partial, lo, tail_vec, fin);
+  small_epilogue<NT, false, 1>(acc, 1.0f, j, genome, nd, y, b, partial, lo, tail_vec, fin);
 }
 
 template <int NT>
@@ -381,7 +383,12 @@ __global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void eval_small_fp8_kernel(
       for (int t = 0; t < NT; ++t) wb[t] = wn[t];
     }
   }
-  small_epilogue<NT, true>(acc, fac, j, genome, nd, y, b, partial, lo, tail_vec, fin);
+  // the later layers' scales are read here, not at the start: kept through
+  // the main loop they cost scalar registers the loop needs (measured 43 vs
+  // 39 us at b = 8)
+  const TailScales ts =
+      load_tail_scales(w8.tail ? w8.tail + (int64_t)j * kTailScales : nullptr, nd.L);
+  small_epilogue<NT, true, 2>(acc, fac, j, genome, nd, y, b, partial, lo, tail_vec, fin, ts);
 }
 
 // ------------------------------------------------------- b <= 4, FP32 --

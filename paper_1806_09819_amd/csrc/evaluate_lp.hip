@@ -227,10 +227,11 @@ __device__ __forceinline__ void eval_lp_body(int j, int wt, const float* __restr
     }
     float* red = lds + reg_tail_copy_floats(nd);
     __syncthreads();
-    reg_tail<NT, MW>(acc, fac, lds, nd, m0, wave * MW * 16, b, ylab, red,
-                     partial + (int64_t)j * n_pt, m0 / 64);
+    reg_tail<NT, MW, DT>(acc, fac, lds, nd, m0, wave * MW * 16, b, ylab, red,
+                         partial + (int64_t)j * n_pt, m0 / 64);
   } else {
-    lds_epilogue<NT, MW>(lds, acc, fac, j, wt, genome, nd, y, b, partial, lo, n_pt, tail_vec);
+    lds_epilogue<NT, MW, DT>(lds, acc, fac, j, wt, genome, nd, y, b, partial, lo, n_pt,
+                             tail_vec);
   }
 }
 

@@ -95,8 +95,8 @@ __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lpw_kernel(
     const float* __restrict__ genomes, NetDesc nd, const char* __restrict__ wp, int64_t wnet,
     int64_t wrow, const char* __restrict__ xq, int nch, int bpad,
     const uint32_t* __restrict__ x_amax, const uint32_t* __restrict__ w_bound,
-    const int32_t* __restrict__ y, int b, float2* __restrict__ partial, int n_wt, int n_pt,
-    int pop) {
+    const uint32_t* __restrict__ tail, const int32_t* __restrict__ y, int b,
+    float2* __restrict__ partial, int n_wt, int n_pt, int pop) {
   constexpr int S = lpw_stages(NT, MW);
   constexpr int RB = 64;                // bytes per staged row (32 bfloat16)
   constexpr int MT = 64 * MW;           // rows per workgroup
@@ -169,6 +169,8 @@ __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lpw_kernel(
     const int r = m0 + wave * MW * 16 + mi * 16 + mn;
     ylab[mi] = r < b ? y[r] : 0;
   }
+  const TailScales ts =
+      load_tail_scales(DT == 2 && tail ? tail + (int64_t)j * kTailScales : nullptr, nd.L);
   const int tn = (int)reg_tail_genes(nd);
   constexpr int TQ = kTailGenesCap / 16 / 256;  // float4 per thread
   float4 tv[TQ];
@@ -252,8 +254,9 @@ __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void eval_lpw_kernel(
   for (int q = 0; q < TQ; ++q) reinterpret_cast<float4*>(st1)[tid + 256 * q] = tv[q];
   __syncthreads();
   const float fac = DT == 2 ? fp8_factor(*x_amax, w_bound[j]) : 1.0f;
-  reg_tail<NT, MW>(acc, fac, reinterpret_cast<const float*>(st1), nd, m0, wave * MW * 16, b,
-                   ylab, reinterpret_cast<float*>(st0), partial + (int64_t)j * n_pt, m0 / 64);
+  reg_tail<NT, MW, DT>(acc, fac, reinterpret_cast<const float*>(st1), nd, m0, wave * MW * 16, b,
+                       ylab, reinterpret_cast<float*>(st0), partial + (int64_t)j * n_pt, m0 / 64,
+                       ts);
 }
 
 // ------------------------------------------------ float32 first layer --
@@ -452,6 +455,7 @@ struct LpwArgs {
   int nch, bpad;
   const uint32_t* x_amax;
   const uint32_t* w_bound;
+  const uint32_t* tail;  // FP8: later layers' largest magnitudes, [pop][kTailScales]
 };
 
 template <int NT, int MW, int DT>
@@ -461,7 +465,7 @@ hipError_t launch_lpw3(const float* genomes, const NetDesc& nd, int pop, const L
   const int n_pt = (b + 63) / 64;
   hipLaunchKernelGGL((eval_lpw_kernel<NT, MW, DT>), dim3((unsigned)(n_wt * pop)), dim3(256), 0,
                      s, genomes, nd, a.wp, a.wnet, a.wrow, a.xq, a.nch, a.bpad, a.x_amax,
-                     a.w_bound, y, b, partial, n_wt, n_pt, pop);
+                     a.w_bound, a.tail, y, b, partial, n_wt, n_pt, pop);
   return hipGetLastError();
 }
 
@@ -571,7 +575,7 @@ hipError_t launch_evaluate_lpw(const float* genomes, const NetDesc& nd, int pop,
                                const int32_t* y, int b, float2* partial, hipStream_t s) {
   if (!wsh.p || bpad % 128 != 0 || bpad < b) return hipErrorInvalidValue;
   const LpwArgs a{reinterpret_cast<const char*>(wsh.p), wsh.net * 2, (int64_t)wsh.kp * 2,
-                  reinterpret_cast<const char*>(xq), kp >> 5, bpad, nullptr, nullptr};
+                  reinterpret_cast<const char*>(xq), kp >> 5, bpad, nullptr, nullptr, nullptr};
   return launch_lpw_any<1>(genomes, nd, pop, a, y, b, partial, s);
 }
 
@@ -581,7 +585,8 @@ hipError_t launch_evaluate_lpw8(const float* genomes, const NetDesc& nd, int pop
                                 hipStream_t s) {
   if (!w8.p || bpad % 128 != 0 || bpad < b) return hipErrorInvalidValue;
   const LpwArgs a{reinterpret_cast<const char*>(w8.p), w8.net, (int64_t)w8.kp,
-                  reinterpret_cast<const char*>(xq), w8.kp >> 6, bpad, x_amax, w8.bound};
+                  reinterpret_cast<const char*>(xq), w8.kp >> 6, bpad, x_amax, w8.bound,
+                  w8.tail};
   return launch_lpw_any<2>(genomes, nd, pop, a, y, b, partial, s);
 }
 

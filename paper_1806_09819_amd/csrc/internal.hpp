@@ -67,6 +67,7 @@ struct W1Fp8 {
   float rcp_n0;
   const uint32_t* amax_par;
   uint32_t* bound;
+  const uint32_t* tail;  // largest |W_l| of the later layers, [pop][kTailScales] (evaluation)
 };
 
 // init.hip / vary.hip / batch.hip
@@ -145,8 +146,12 @@ hipError_t launch_evaluate_lp(int dt, const float* genomes, const NetDesc& nd, i
                               const void* xq, int kp, const uint32_t* w_amax,
                               const uint32_t* x_amax, const int32_t* y, int b, float2* partial,
                               hipStream_t s);
-// *out = the largest magnitude bits over x[0..n) (written, not accumulated).
-hipError_t launch_amax(const float* x, int64_t n, uint32_t* out, hipStream_t s);
+// The FP8 scales of one evaluation in one launch: *x_amax over the batch
+// x[0..n) and tail[j * kTailScales + l] = the largest magnitude bits of
+// network j's W_l for every later layer l = 1 .. L - 1 (0-based).
+constexpr int kTailScales = kMaxLayers;
+hipError_t launch_fp8_scales(const float* x, int64_t n, uint32_t* x_amax, const float* genomes,
+                             const NetDesc& nd, int pop, uint32_t* tail, hipStream_t s);
 hipError_t launch_amax_w1(const float* genomes, const NetDesc& nd, int pop, uint32_t* amax,
                           hipStream_t s);
 hipError_t launch_quantize_x(int dt, bool packed, const float* x, int b, int n0, int kp,

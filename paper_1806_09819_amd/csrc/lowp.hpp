@@ -73,13 +73,62 @@ __device__ __forceinline__ float round_fp8(float v) {
   return __builtin_amdgcn_cvt_f32_fp8(p, 0);
 }
 
-// Quantised value of a first-layer operand element in the given mode:
+// Quantised value of a weight or input element in the given mode:
 // BF16 -> nearest bfloat16; FP8 -> nearest E4M3 of v * 2^-e (still scaled).
 template <int DT>
 __device__ __forceinline__ float quantize(float v, int neg_e) {
   if constexpr (DT == 1) return round_bf16(v);
   else if constexpr (DT == 2) return round_fp8(ldexpf(v, neg_e));
   else return v;
+}
+
+// Largest magnitude bits of n floats at W (global memory or LDS) over the
+// workgroup; every thread of the workgroup (a multiple of 64 threads, at most
+// 1024) calls it, with the same arguments.
+__device__ __forceinline__ uint32_t block_amax(const float* W, int n) {
+  __shared__ uint32_t red[16];
+  uint32_t m = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const uint32_t v = mag_bits(W[i]);
+    m = v > m ? v : m;
+  }
+  m = wave_umax(m);
+  __syncthreads();  // red is free (an earlier call's readers are done)
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  uint32_t r = red[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = red[w] > r ? red[w] : r;
+  return r;
+}
+
+// Largest magnitude bits of a network's later layers (entry l for W_l,
+// l >= 1), read once at the start of an evaluation kernel so that the tail
+// does not wait on them; given = 0: the tail reduces each layer itself.
+struct TailScales {
+  uint32_t amax[kMaxLayers];
+  int given;
+};
+
+__device__ __forceinline__ TailScales load_tail_scales(const uint32_t* p, int L) {
+  TailScales t;
+  t.given = p != nullptr;
+#pragma unroll
+  for (int l = 0; l < kMaxLayers; ++l) t.amax[l] = (p && l >= 1 && l < L) ? p[l] : 0u;
+  return t;
+}
+
+// Scale of a later layer's FP8 weights from their largest magnitude bits:
+// neg_e = -e for quantize<2>, fac = 2^e multiplies the layer's sums; a
+// non-finite weight gives fac = NaN (the network's fitness becomes NaN).
+__device__ __forceinline__ void tail_fp8_scale(uint32_t amax, int& neg_e, float& fac) {
+  if (amax >= kNonFinite) {
+    neg_e = 0;
+    fac = __builtin_nanf("");
+  } else {
+    const int e = fp8_exponent(amax);
+    neg_e = -e;
+    fac = ldexpf(1.0f, e);
+  }
 }
 
 }  // namespace leea

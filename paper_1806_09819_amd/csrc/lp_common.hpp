@@ -16,8 +16,8 @@ namespace leea {
 // unless it is the output layer) into the tile, then the tail layers and the
 // fitness of the pass run; each pass writes partial[j * n_pt + m0 / 64 + p].
 // The tail layers read their weights from tw + (offset - toff) (the genome:
-// toff = 0).
-template <int NT, int MW>
+// toff = 0); DT: arithmetic of their weights (tail_and_fitness).
+template <int NT, int MW, int DT = 0>
 __device__ __forceinline__ void lds_epilogue(float* lds, const floatx4 (&acc)[MW][NT], float fac,
                                              int j, int wt, const float* __restrict__ genome,
                                              const NetDesc& nd, const int32_t* __restrict__ y,
@@ -64,8 +64,8 @@ __device__ __forceinline__ void lds_epilogue(float* lds, const floatx4 (&acc)[MW
       }
     }
     __syncthreads();
-    tail_and_fitness<4>(lds, lo, nd, genome, 0, PR / 16, prow, m0 + pr0, y, tail_vec != 0,
-                        partial + (int64_t)j * n_pt + m0 / 64 + p);
+    tail_and_fitness<4, DT>(lds, lo, nd, genome, 0, PR / 16, prow, m0 + pr0, y, tail_vec != 0,
+                            partial + (int64_t)j * n_pt + m0 / 64 + p);
     __syncthreads();
   }
 }

@@ -6,17 +6,79 @@
 
 namespace leea {
 
-// *out = max over x of mag_bits (out cleared to 0 beforehand).  Each
-// workgroup reduces its share in LDS and issues one atomic: atomics from
-// every wave on the one address serialise in L2 (a 512 x 784 batch took
-// 73 us that way, against a few us for the reads).
-__global__ __launch_bounds__(256) void amax_kernel(const float* __restrict__ x, int64_t n,
-                                                   uint32_t* __restrict__ out) {
+// FP8 scales of one evaluation: workgroups [0, pop) find the largest
+// magnitude of each later layer's weights of network blockIdx.x; the others
+// reduce the batch (one workgroup: it writes *x_amax; several: one atomic
+// each into a word cleared before the launch).
+__global__ __launch_bounds__(256) void fp8_scales_kernel(const float* __restrict__ x, int64_t n,
+                                                         uint32_t* __restrict__ x_amax, int xg,
+                                                         const float* __restrict__ genomes,
+                                                         NetDesc nd, int pop,
+                                                         uint32_t* __restrict__ tail) {
   __shared__ uint32_t red[4];
+  __shared__ uint32_t lred[4][kTailScales];
+  const int j = blockIdx.x;
+  if (j < pop) {
+    const float* g = genomes + (int64_t)j * nd.stride;
+    const int L = nd.L;
+    uint32_t m[kTailScales];
+#pragma unroll
+    for (int l = 0; l < kTailScales; ++l) m[l] = 0u;
+    // each later layer's weights on their own (a few thousand values), four
+    // independent loads in flight per thread
+    for (int l = 1; l < L; ++l) {
+      const float* w = g + nd.woff[l];
+      const int n = nd.w[l] * nd.w[l + 1];
+      uint32_t ml = 0;
+      for (int i0 = threadIdx.x; i0 < n; i0 += 4 * 256) {
+        float v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = i0 + 256 * k < n ? w[i0 + 256 * k] : 0.0f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t a = mag_bits(v[k]);
+          ml = a > ml ? a : ml;
+        }
+      }
+#pragma unroll
+      for (int q = 1; q < kTailScales; ++q)
+        if (q == l) m[q] = ml;
+    }
+#pragma unroll
+    for (int l = 1; l < kTailScales; ++l) {
+      const uint32_t w = wave_umax(m[l]);
+      if ((threadIdx.x & 63) == 0) lred[threadIdx.x >> 6][l] = w;
+    }
+    __syncthreads();
+    const int l = threadIdx.x;
+    if (l >= 1 && l < L) {
+      uint32_t r = lred[0][l];
+      for (int w = 1; w < 4; ++w) r = lred[w][l] > r ? lred[w][l] : r;
+      tail[(int64_t)j * kTailScales + l] = r;
+    }
+    return;
+  }
+  const int g = j - pop;
   uint32_t m = 0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    const uint32_t v = mag_bits(x[i]);
-    m = v > m ? v : m;
+  // the batch is 16-byte aligned with n a multiple of 4: 16-byte loads, four
+  // in flight per thread
+  const float4* x4 = reinterpret_cast<const float4*>(x);
+  const int64_t n4 = n >> 2;
+  const int64_t step = (int64_t)xg * 256;
+  for (int64_t i0 = (int64_t)g * 256 + threadIdx.x; i0 < n4; i0 += 4 * step) {
+    float4 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      v[k] = i0 + step * k < n4 ? x4[i0 + step * k] : float4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      uint32_t a = mag_bits(v[k].x), c = mag_bits(v[k].y), d = mag_bits(v[k].z),
+               e = mag_bits(v[k].w);
+      a = a > c ? a : c;
+      d = d > e ? d : e;
+      a = a > d ? a : d;
+      m = a > m ? a : m;
+    }
   }
   m = wave_umax(m);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
@@ -24,28 +86,26 @@ __global__ __launch_bounds__(256) void amax_kernel(const float* __restrict__ x, 
   if (threadIdx.x == 0) {
     uint32_t r = red[0];
     for (int i = 1; i < 4; ++i) r = red[i] > r ? red[i] : r;
-    if (r) atomicMax(out, r);
+    if (xg == 1)
+      *x_amax = r;
+    else if (r)
+      atomicMax(x_amax, r);
   }
 }
 
-// The same for small batches in one workgroup, which writes *out itself
-// (no clearing launch before it).
-__global__ __launch_bounds__(1024) void amax_one_kernel(const float* __restrict__ x, int64_t n,
-                                                        uint32_t* __restrict__ out) {
-  __shared__ uint32_t red[16];
-  uint32_t m = 0;
-  for (int64_t i = threadIdx.x; i < n; i += 1024) {
-    const uint32_t v = mag_bits(x[i]);
-    m = v > m ? v : m;
+hipError_t launch_fp8_scales(const float* x, int64_t n, uint32_t* x_amax, const float* genomes,
+                             const NetDesc& nd, int pop, uint32_t* tail, hipStream_t s) {
+  // the batch: one workgroup up to 16 K values, else at most 256 (one
+  // atomic each, after clearing the word)
+  int64_t xg = (n + 2047) / 2048;
+  xg = n <= 16384 ? 1 : (xg > 256 ? 256 : xg);
+  if (xg > 1) {
+    const hipError_t e = launch_fill(reinterpret_cast<float*>(x_amax), 1, 0.0f, s);
+    if (e != hipSuccess) return e;
   }
-  m = wave_umax(m);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t r = red[0];
-    for (int i = 1; i < 16; ++i) r = red[i] > r ? red[i] : r;
-    *out = r;
-  }
+  hipLaunchKernelGGL(fp8_scales_kernel, dim3((unsigned)(pop + xg)), dim3(256), 0, s, x, n, x_amax,
+                     (int)xg, genomes, nd, pop, tail);
+  return hipGetLastError();
 }
 
 // amax[j] = max over network j's W_1 of mag_bits; one workgroup per network.
@@ -127,20 +187,6 @@ static unsigned grid_for(int64_t n) {
   int64_t g = (n + 255) / 256;
   if (g > 4096) g = 4096;
   return (unsigned)(g < 1 ? 1 : g);
-}
-
-hipError_t launch_amax(const float* x, int64_t n, uint32_t* out, hipStream_t s) {
-  if (n <= 65536) {  // up to 64 elements per thread in one workgroup
-    hipLaunchKernelGGL(amax_one_kernel, dim3(1), dim3(1024), 0, s, x, n, out);
-    return hipGetLastError();
-  }
-  hipError_t e = launch_fill(reinterpret_cast<float*>(out), 1, 0.0f, s);
-  if (e != hipSuccess) return e;
-  // at least 8 elements per thread, at most 256 workgroups (256 atomics)
-  int64_t g = (n + 2047) / 2048;
-  g = g < 1 ? 1 : (g > 256 ? 256 : g);
-  hipLaunchKernelGGL(amax_kernel, dim3((unsigned)g), dim3(256), 0, s, x, n, out);
-  return hipGetLastError();
 }
 
 hipError_t launch_amax_w1(const float* genomes, const NetDesc& nd, int pop, uint32_t* amax,

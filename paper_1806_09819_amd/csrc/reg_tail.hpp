@@ -69,11 +69,13 @@ __device__ __forceinline__ void copy_tail_genes(const float* __restrict__ genome
 // loads its TO weight fragments first and then runs its 4 TO MW products
 // across all the accumulators, so consecutive products never wait on each
 // other; each accumulator still sums its K-steps in order (t, then i).
-template <int MW, int TI, int TO, int TIN>
+// DT != 0: weights quantised as they are loaded (quantize<DT>, scale
+// exponent neg_e); DT = 2: the sums times wfac before the bias.
+template <int MW, int TI, int TO, int TIN, int DT>
 __device__ __forceinline__ void reg_layer_t(const floatx4 (&in)[MW][TIN],
                                             floatx4 (&out)[MW][kRegTailMax], const float* W,
                                             const float* bias, const float* z4, int n_in,
-                                            int n_out, bool relu) {
+                                            int n_out, bool relu, int neg_e, float wfac) {
   static_assert(TI <= TIN && TO <= kRegTailMax, "tile counts");
   const int lane = threadIdx.x & 63;
   const int mn = lane & 15;
@@ -93,8 +95,15 @@ __device__ __forceinline__ void reg_layer_t(const floatx4 (&in)[MW][TIN],
     const int k = 16 * t + 4 * kq;
     float4 w[TO];
 #pragma unroll
-    for (int o = 0; o < TO; ++o)
+    for (int o = 0; o < TO; ++o) {
       w[o] = *reinterpret_cast<const float4*>(k < n_in ? wr[o] + k : z4);
+      if constexpr (DT != 0) {
+        w[o].x = quantize<DT>(w[o].x, neg_e);
+        w[o].y = quantize<DT>(w[o].y, neg_e);
+        w[o].z = quantize<DT>(w[o].z, neg_e);
+        w[o].w = quantize<DT>(w[o].w, neg_e);
+      }
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -113,31 +122,39 @@ __device__ __forceinline__ void reg_layer_t(const floatx4 (&in)[MW][TIN],
     for (int mi = 0; mi < MW; ++mi)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        float v = out[mi][o][i] + (i == 0 ? bv.x : i == 1 ? bv.y : i == 2 ? bv.z : bv.w);
+        float v = out[mi][o][i];
+        if constexpr (DT == 2) v = v * wfac;
+        v = v + (i == 0 ? bv.x : i == 1 ? bv.y : i == 2 ? bv.z : bv.w);
         if (relu) v = relu_keep_nan(v);
         out[mi][o][i] = c + i < n_out ? v : 0.0f;
       }
   }
 }
 
-// reg_layer_t with TO = the column tiles of n_out (1 .. kRegTailMax).
-template <int MW, int TI, int TIN>
+// reg_layer_t with TO = the column tiles of n_out (1 .. kRegTailMax); for
+// DT = 2 the layer's FP8 scale comes from its weights' largest magnitude,
+// *tam when given, else reduced here by the workgroup (every thread of the
+// workgroup calls this).
+template <int MW, int TI, int TIN, int DT>
 __device__ __forceinline__ void reg_layer(const floatx4 (&in)[MW][TIN],
                                           floatx4 (&out)[MW][kRegTailMax], const float* W,
                                           const float* bias, const float* z4, int n_in, int n_out,
-                                          bool relu) {
+                                          bool relu, const uint32_t* tam) {
+  int neg_e = 0;
+  float wfac = 1.0f;
+  if constexpr (DT == 2) tail_fp8_scale(tam ? *tam : block_amax(W, n_in * n_out), neg_e, wfac);
   switch ((n_out + 15) >> 4) {
     case 1:
-      reg_layer_t<MW, TI, 1, TIN>(in, out, W, bias, z4, n_in, n_out, relu);
+      reg_layer_t<MW, TI, 1, TIN, DT>(in, out, W, bias, z4, n_in, n_out, relu, neg_e, wfac);
       break;
     case 2:
-      reg_layer_t<MW, TI, 2, TIN>(in, out, W, bias, z4, n_in, n_out, relu);
+      reg_layer_t<MW, TI, 2, TIN, DT>(in, out, W, bias, z4, n_in, n_out, relu, neg_e, wfac);
       break;
     case 3:
-      reg_layer_t<MW, TI, 3, TIN>(in, out, W, bias, z4, n_in, n_out, relu);
+      reg_layer_t<MW, TI, 3, TIN, DT>(in, out, W, bias, z4, n_in, n_out, relu, neg_e, wfac);
       break;
     default:
-      reg_layer_t<MW, TI, 4, TIN>(in, out, W, bias, z4, n_in, n_out, relu);
+      reg_layer_t<MW, TI, 4, TIN, DT>(in, out, W, bias, z4, n_in, n_out, relu, neg_e, wfac);
       break;
   }
 }
@@ -214,12 +231,15 @@ __device__ __forceinline__ void reg_fitness(const floatx4 (&z)[MW][TC], int tc_u
 // 2 * 4 * MW floats; rows of this wave: r0 + 16 mi + mn (r0 relative to the
 // workgroup's first row m0); labels ylab[mi] of those rows (any value for
 // rows at or past b).  partial: the network's partials, one per 64-row group,
-// g0 = index of the workgroup's first group.
-template <int NT, int MW>
+// g0 = index of the workgroup's first group.  DT: arithmetic of the weights
+// of layers 2..L (as in tail_and_fitness); ts: their largest magnitudes, if
+// given.
+template <int NT, int MW, int DT = 0>
 __device__ __forceinline__ void reg_tail(floatx4 (&z)[MW][NT], float fac, const float* tl,
                                          const NetDesc& nd, int m0, int r0, int b,
                                          const int (&ylab)[MW], float* red,
-                                         float2* __restrict__ partial, int g0) {
+                                         float2* __restrict__ partial, int g0,
+                                         const TailScales& ts = TailScales{{}, 0}) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int mn = lane & 15;
@@ -258,8 +278,8 @@ __device__ __forceinline__ void reg_tail(floatx4 (&z)[MW][NT], float fac, const 
   } else {
     const float* z4 = tl + reg_tail_copy_floats(nd) - 4;
     floatx4 h2[MW][kRegTailMax];
-    reg_layer<MW, NT, NT>(z, h2, tl + (nd.woff[1] - base), tl + (nd.boff[1] - base), z4, n1,
-                          nd.w[2], nd.L > 2);
+    reg_layer<MW, NT, NT, DT>(z, h2, tl + (nd.woff[1] - base), tl + (nd.boff[1] - base), z4, n1,
+                              nd.w[2], nd.L > 2, ts.given ? &ts.amax[1] : nullptr);
     const int t2 = (nd.w[2] + 15) >> 4;
     if (nd.L == 2) {
       reg_fitness<MW, kRegTailMax>(h2, t2, nd.w[2], ylab, ll, cor);
@@ -269,16 +289,20 @@ __device__ __forceinline__ void reg_tail(floatx4 (&z)[MW][NT], float fac, const 
       const float* b3 = tl + (nd.boff[2] - base);
       switch (t2) {
         case 1:
-          reg_layer<MW, 1, kRegTailMax>(h2, h3, W3, b3, z4, nd.w[2], nd.w[3], false);
+          reg_layer<MW, 1, kRegTailMax, DT>(h2, h3, W3, b3, z4, nd.w[2], nd.w[3], false,
+                                             ts.given ? &ts.amax[2] : nullptr);
           break;
         case 2:
-          reg_layer<MW, 2, kRegTailMax>(h2, h3, W3, b3, z4, nd.w[2], nd.w[3], false);
+          reg_layer<MW, 2, kRegTailMax, DT>(h2, h3, W3, b3, z4, nd.w[2], nd.w[3], false,
+                                             ts.given ? &ts.amax[2] : nullptr);
           break;
         case 3:
-          reg_layer<MW, 3, kRegTailMax>(h2, h3, W3, b3, z4, nd.w[2], nd.w[3], false);
+          reg_layer<MW, 3, kRegTailMax, DT>(h2, h3, W3, b3, z4, nd.w[2], nd.w[3], false,
+                                             ts.given ? &ts.amax[2] : nullptr);
           break;
         default:
-          reg_layer<MW, 4, kRegTailMax>(h2, h3, W3, b3, z4, nd.w[2], nd.w[3], false);
+          reg_layer<MW, 4, kRegTailMax, DT>(h2, h3, W3, b3, z4, nd.w[2], nd.w[3], false,
+                                             ts.given ? &ts.amax[2] : nullptr);
           break;
       }
       reg_fitness<MW, kRegTailMax>(h3, (nd.w[3] + 15) >> 4, nd.w[3], ylab, ll, cor);

@@ -1,12 +1,13 @@
-"""GPU parity of the reduced-precision first layer (bfloat16 and OCP FP8
-E4M3 with power-of-two scales) against the oracle's reduced-precision
-forward pass: the device multiplies exactly the quantised operands the
-oracle defines and sums in float32, so fitness must agree within the
-float32 tolerance.  Covers the small-batch kernel (b <= 16, quantised
-values on the FP32 matrix cores) and the bf16 / FP8 matrix-core kernel
-(b > 16), ragged shapes, special networks (zero, tiny, huge and NaN
-weights), a NaN batch, the FP8 scales that the variation kernel derives
-for each child, and state restores."""
+"""GPU parity of the reduced-precision forward pass (weights of every layer
+and the batch in bfloat16 or OCP FP8 E4M3 with power-of-two scales, one per
+network and layer) against the oracle's reduced-precision forward pass: the
+device multiplies exactly the quantised operands the oracle defines and sums
+in float32, so fitness must agree within the float32 tolerance.  Covers the
+small-batch kernels (b <= 16) and the bf16 / FP8 matrix-core kernels
+(b > 16), the register tail and the LDS-tile tail of the later layers,
+ragged shapes, special networks (zero, tiny, huge and NaN weights), a NaN
+batch, the FP8 scales that the variation kernel derives for each child, and
+state restores."""
 import numpy as np
 import pytest
 import torch
@@ -64,7 +65,9 @@ def check(f_gpu, acc_gpu, f_ref, acc_ref, amb, b, label, stress=()):
 
 def special_population(run, widths, seed):
     """Random genomes with a few special networks: all-zero first layer,
-    tiny and huge first-layer weights, and (slot 4) a NaN weight."""
+    tiny and huge first-layer weights, (slot 4) a NaN weight, and for the
+    later layers (their own FP8 scales): huge (slot 5) and tiny (slot 7)
+    weights and (slot 6) a NaN weight."""
     rng = np.random.Generator(np.random.PCG64(seed))
     c = O.param_count(widths)
     pop = (rng.standard_normal((run.pop, c)) * 0.05).astype(F32)
@@ -73,6 +76,10 @@ def special_population(run, widths, seed):
     pop[2, :w1] *= F32(1e-30)
     pop[3, :w1] *= F32(3e3)
     pop[4, 7] = np.nan
+    tail = w1 + widths[1]                      # first gene of W_2
+    pop[5, tail:] *= F32(1e4)
+    pop[6, tail + 1] = np.nan
+    pop[7, tail:] *= F32(1e-25)
     full = np.zeros((run.pop, run.stride), dtype=F32)
     full[:, :c] = pop
     run.set_state(to_dev(full))

@@ -1,4 +1,4 @@
-"""Pins for the reduced-precision oracle (first layer in bfloat16 or OCP
+"""Pins for the reduced-precision oracle (weights and batch in bfloat16 or OCP
 FP8 E4M3 with power-of-two scales): the roundings against torch's own
 casts and against brute force over the formats' value grids, the scale
 rule in closed form, and the forward pass against the float64 forward on
@@ -157,6 +157,65 @@ def test_forward_lowp_error_within_quantisation_bound():
         assert np.any(got != exact), dt
 
 
+def test_tail_weights_rounded_hand_example():
+    """A later layer's weight 1 + 2^-9 with an exact first layer: the float32
+    logit is 1 + 2^-9; bfloat16 (spacing 2^-7 at 1) rounds the weight to 1;
+    FP8 scales it by 2^-(-8) to 256.5, which E4M3 (spacing 32 there) rounds to
+    256, i.e. 1 after the scale."""
+    widths = (2, 1, 1)
+    g = np.zeros(L.param_count(widths), dtype=F32)
+    (W1, b1), (W2, b2) = L.unpack(g, widths)
+    W1[0, 0] = 1.0
+    W2[0, 0] = 1.0 + 2.0**-9
+    g = np.concatenate([W1.ravel(), b1, W2.ravel(), b2]).astype(F32)
+    x = np.array([[1.0, 0.0]], dtype=F32)
+    assert Q.forward_lowp(g, widths, x, Q.F32)[0, 0] == 1.0 + 2.0**-9
+    assert Q.forward_lowp(g, widths, x, Q.BF16)[0, 0] == 1.0
+    assert Q.fp8_exponent(1.0 + 2.0**-9) == -8
+    assert Q.forward_lowp(g, widths, x, Q.FP8)[0, 0] == 1.0
+
+
+@pytest.mark.parametrize("dt", [Q.BF16, Q.FP8])
+def test_tail_layer_scale_is_per_layer(dt):
+    """Multiplying the last layer's weights by 2^k (bias zero) multiplies the
+    logits by exactly 2^k: the last layer's FP8 scale follows its own largest
+    magnitude (a scale taken from another layer would overflow E4M3 at
+    2^20 or lose bits at 2^-20), and bfloat16 rounding commutes with powers
+    of two."""
+    rng = np.random.Generator(np.random.PCG64(11))
+    widths = (16, 8, 5)
+    g = (rng.standard_normal(L.param_count(widths)) * 0.3).astype(F32)
+    (W1, b1), (W2, b2) = L.unpack(g, widths)
+    b2[:] = 0.0
+    x = rng.random((7, 16)).astype(F32)
+    base = np.concatenate([W1.ravel(), b1, W2.ravel(), b2]).astype(F32)
+    ref = Q.forward_lowp(base, widths, x, dt)
+    for k in (20, -20, 3):
+        gk = np.concatenate([W1.ravel(), b1, (W2 * F32(2.0**k)).ravel(), b2]).astype(F32)
+        assert np.array_equal(Q.forward_lowp(gk, widths, x, dt), ref * 2.0**k), (dt, k)
+    # and the rounding of the later layer is there: it differs from float32
+    assert not np.array_equal(ref, Q.forward_lowp(base, widths, x, Q.F32))
+
+
+def test_tail_product_error_within_quantisation_bound():
+    """A later layer's product against the exact one: each weight carries a
+    relative error <= 2^-8 (bfloat16) or 2^-4 (E4M3 normals) plus, for FP8,
+    an absolute 2^-10 * 2^e for subnormals."""
+    rng = np.random.Generator(np.random.PCG64(12))
+    W = (rng.standard_normal((10, 32)) * 0.2).astype(F32)
+    h = np.abs(rng.standard_normal((20, 32)))
+    exact = h @ W.astype(np.float64).T
+    mag = h @ np.abs(W.astype(np.float64)).T
+    for dt, u in ((Q.BF16, 2.0**-8), (Q.FP8, 2.0**-4)):
+        wq, fac = Q.tail_operand(W, dt)
+        got = fac * (h @ wq.T)
+        bound = mag * u
+        if dt == Q.FP8:
+            bound += h.sum(1)[:, None] * 2.0**-10 * fac
+        assert np.all(np.abs(got - exact) <= bound * 1.0001 + 1e-15), dt
+        assert np.any(got != exact), dt
+
+
 def test_lowp_nan_operands_give_nan_fitness():
     rng = np.random.Generator(np.random.PCG64(9))
     widths = (8, 4, 3)
@@ -167,6 +226,11 @@ def test_lowp_nan_operands_give_nan_fitness():
     for dt in (Q.BF16, Q.FP8):
         f, _ = Q.evaluate_lowp(pop, widths, x, y, dt)
         assert np.isnan(f[1]) and np.isfinite(f[0]) and np.isfinite(f[2])
+    # a non-finite weight in a later layer: NaN fitness under FP8 (its scale)
+    w2 = widths[0] * widths[1] + widths[1]
+    pop[2, w2 + 1] = np.inf
+    f, _ = Q.evaluate_lowp(pop, widths, x, y, Q.FP8)
+    assert np.isnan(f[2]) and np.isfinite(f[0])
 
 
 def test_box_muller_radius_bound():
