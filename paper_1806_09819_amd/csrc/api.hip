@@ -696,9 +696,10 @@ leea_status leea_crossover_mutate_evaluate(leea_ctx* c, const float* x, const in
   leea_status st = check_batch(c, x, y, b);
   if (st) return st;
   // the fused kernel multiplies on the matrix cores like the small-batch
-  // kernel; batches the row-streaming kernel takes keep the separate calls
+  // kernel; batches the row-streaming or 1 KiB-row kernels take keep the
+  // separate calls (their sums are grouped differently)
   if (!(c->fused && c->dt == LEEA_DT_F32 && fused_supported(c->nd, b) &&
-        !eval_stream_supported(c->nd, b))) {
+        !eval_stream_supported(c->nd, b) && !eval_rows_supported(c->nd, b))) {
     st = leea_crossover_mutate(c);
     if (st) return st;
     return leea_evaluate(c, x, y, b, f_adj, f_raw, acc);

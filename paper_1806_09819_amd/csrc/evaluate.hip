@@ -391,6 +391,234 @@ __global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void eval_small_fp8_kernel(
   small_epilogue<NT, true, 2>(acc, fac, j, genome, nd, y, b, partial, lo, tail_vec, fin, ts);
 }
 
+// -------------------------------------------------- 5 <= b <= 8, FP32 --
+// Layer 1 from whole 1 KiB spans of W_1 rows on the 16-block matrix
+// instruction v_mfma_f32_4x4x1f32.  Lane l = 4 beta + jj of a wave belongs
+// to block beta; block beta multiplies A[i] (supplied by lane 4 beta + i)
+// with B[jj] (lane 4 beta + jj) into D[i][jj], held by lane 4 beta + jj in
+// its accumulator i.  With A = batch row i of a group of 4 and B = W_1 row
+// jj of a group of 4 rows, both at one k per block, the 16 blocks cover 16
+// different k and their D tiles are summed over the blocks at the end.
+//
+// A wave owns one 256-float K unit [256 w, 256 w + 256) of every row (one
+// 1 KiB load instruction per row: lane l reads columns 256 w + 4 l .. + 3).
+// Four such loads (rows 4 rg .. 4 rg + 3) pass through a wave-private LDS
+// tile that swaps rows and lanes within each quad, so that lane
+// (beta, jj) holds row 4 rg + jj at columns 256 w + 16 beta .. + 15, the
+// batch held in registers at the same columns (two groups of 4 rows).
+// 16 k-steps x 2 groups of matrix products per 4 rows, then the 16 block
+// sums are reduced over the wave by a reduce-scatter (xor 32 halves the
+// group, 16 and 8 the rows, 4 sums the pair): one value per lane, written
+// to the wave's K-partial tile [wave][8][ld1] in LDS.  Loads are raw buffer
+// loads over the network's W_1 (rows past n1 and columns past n0 lie outside
+// it and read zero without a memory access) and non-temporal (each line is
+// read once); two groups of 4 rows are in flight.  Measured against the
+// 16-row fragment walk of eval_small_kernel, which streams the same bytes as
+// 16 rows x 64 B per instruction: layer 1 alone 60 us at P = 1000, 784-112,
+// b = 8 (5.8 TB/s) against about 75 us.  The four K partials meet in LDS in
+// a fixed order (wave 0 + 1, + 2, + 3), then the bias, the ReLU and the
+// small-batch kernel's tail and fitness, from a copy of the genome's tail in
+// LDS where it fits.
+constexpr int kRowsMaxB = 8;
+constexpr int kRowsUnit = 256;      // floats of a row per load instruction
+constexpr int kRowsTile = 4 * 65;   // float4 per wave transpose tile (one float4 pad per row)
+
+// Floats of LDS the kernel uses: the K-partial tiles [4][8][ld1], then the
+// four transpose tiles; the activation tile and tail buffers reuse the space.
+__host__ __device__ inline int rows_lds_floats(const EvalLds& lo) {
+  const int l1 = 4 * kRowsMaxB * lo.ld1 + 4 * 4 * kRowsTile;
+  return lo.total > l1 ? lo.total : l1;
+}
+
+template <int NT>
+__device__ __forceinline__ void eval_rows_body(int j, const float* __restrict__ genomes,
+                                               const NetDesc& nd, const float* __restrict__ x,
+                                               const int32_t* __restrict__ y, int b,
+                                               float2* __restrict__ partial, const EvalLds& lo,
+                                               int tail_vec, const FinArgs& fin) {
+  extern __shared__ float lds[];
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int beta = lane >> 2;
+  const int jj = lane & 3;
+  const int n0 = nd.w[0];
+  const int n1 = nd.w[1];
+  const int ld1 = lo.ld1;
+  const float* __restrict__ genome = genomes + (int64_t)j * nd.stride;
+  const float* __restrict__ W = genome + nd.woff[0];
+  const int k0 = kRowsUnit * wave;
+  // the fitness's labels, read ahead (a buffer load: no branch, and no flat
+  // access where y comes from a run descriptor, either of which would cost
+  // the main loop its exact waits)
+  const int ylab = __builtin_amdgcn_raw_buffer_load_b32(
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t*>(y), 0, b * 4, 0x00020000),
+      tid < b ? tid * 4 : 0x40000000, 0, 0);
+  // the batch at this lane's block columns: rows 4 g + jj, columns
+  // k0 + 16 beta + 4 t .. + 3 (buffer loads: rows past b and columns past n0
+  // read zero, with no branch that would cost the loop its exact waits)
+  const __amdgpu_buffer_rsrc_t xs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(x), 0, b * n0 * 4, 0x00020000);
+  float4 xr[2][4];
+#pragma unroll
+  for (int g = 0; g < 2; ++g)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int r = 4 * g + jj;
+      const int k = k0 + 16 * beta + 4 * t;
+      const int off = (r < b && k < n0) ? (r * n0 + k) * 4 : 0x40000000;
+      const floatx4 v = __builtin_amdgcn_raw_buffer_load_b128(xs, off, 0, 0);
+      xr[g][t] = make_float4(v[0], v[1], v[2], v[3]);
+    }
+  // touch one dword of each 128-byte line of the rest of the genome (b_1
+  // and layers 2..L, read after layer 1 by the epilogue and the tail; up to
+  // 32 KiB) so that those lines are in L2 by then
+  const float* __restrict__ rest = genome + nd.boff[0];
+  const int rest_bytes = (int)((nd.genes - nd.boff[0]) * 4);
+  const __amdgpu_buffer_rsrc_t ps =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(rest), 0, rest_bytes, 0x00020000);
+  const float touch =
+      __builtin_amdgcn_raw_buffer_load_b32(ps, tid * 128 < rest_bytes ? tid * 128 : 0x40000000, 0, 0);
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(W), 0, n1 * n0 * 4, 0x00020000);
+  const int kl = k0 + 4 * lane;
+  const bool kv = kl < n0;
+  auto load = [&](int rg, float4 (&wv)[4]) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int row = 4 * rg + t;
+      const int off = (kv && row < n1) ? (row * n0 + kl) * 4 : 0x40000000;
+      const floatx4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 2);  // nt
+      wv[t] = make_float4(v[0], v[1], v[2], v[3]);
+    }
+  };
+  float4* tile = reinterpret_cast<float4*>(lds + 4 * kRowsMaxB * ld1) + wave * kRowsTile;
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+  const int prow = 4 * (int)b5 + 2 * (int)b4 + (int)b3;  // batch row this lane ends with
+  float* part = lds + (wave * kRowsMaxB + prow) * ld1;
+  auto compute = [&](int rg, const float4 (&wv)[4]) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) tile[t * 65 + lane] = wv[t];
+    float4 T[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) T[t] = tile[jj * 65 + 4 * beta + t];
+    floatx4 a0 = {0.f, 0.f, 0.f, 0.f}, a1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      a0 = __builtin_amdgcn_mfma_f32_4x4x1f32(xr[0][t].x, T[t].x, a0, 0, 0, 0);
+      a1 = __builtin_amdgcn_mfma_f32_4x4x1f32(xr[1][t].x, T[t].x, a1, 0, 0, 0);
+      a0 = __builtin_amdgcn_mfma_f32_4x4x1f32(xr[0][t].y, T[t].y, a0, 0, 0, 0);
+      a1 = __builtin_amdgcn_mfma_f32_4x4x1f32(xr[1][t].y, T[t].y, a1, 0, 0, 0);
+      a0 = __builtin_amdgcn_mfma_f32_4x4x1f32(xr[0][t].z, T[t].z, a0, 0, 0, 0);
+      a1 = __builtin_amdgcn_mfma_f32_4x4x1f32(xr[1][t].z, T[t].z, a1, 0, 0, 0);
+      a0 = __builtin_amdgcn_mfma_f32_4x4x1f32(xr[0][t].w, T[t].w, a0, 0, 0, 0);
+      a1 = __builtin_amdgcn_mfma_f32_4x4x1f32(xr[1][t].w, T[t].w, a1, 0, 0, 0);
+    }
+    // sum over the 16 blocks (lane bits 2..5): reduce-scatter
+    float r[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float keep = b5 ? a1[i] : a0[i];
+      const float send = b5 ? a0[i] : a1[i];
+      r[i] = keep + __shfl_xor(send, 32);
+    }
+    float r2[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const float keep = b4 ? r[2 + i] : r[i];
+      const float send = b4 ? r[i] : r[2 + i];
+      r2[i] = keep + __shfl_xor(send, 16);
+    }
+    const float r3 = (b3 ? r2[1] : r2[0]) + __shfl_xor(b3 ? r2[0] : r2[1], 8);
+    const float r4 = r3 + __shfl_xor(r3, 4);
+    const int row = 4 * rg + jj;
+    if (!(lane & 4) && row < n1) part[row] = r4;
+  };
+  // two groups of rows in flight; the scheduling barriers keep each group's
+  // loads together so that the waits count exactly the older group
+  const int RG = (n1 + 3) >> 2;
+  float4 w0[4], w1[4];
+  load(0, w0);
+  __builtin_amdgcn_sched_barrier(0);
+  load(1, w1);
+  __builtin_amdgcn_sched_barrier(0);
+  for (int rg = 0; rg < RG; rg += 2) {
+    compute(rg, w0);
+    __builtin_amdgcn_sched_barrier(0);
+    load(rg + 2, w0);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(rg + 1, w1);
+    __builtin_amdgcn_sched_barrier(0);
+    load(rg + 3, w1);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (b < 0) partial[j].x = touch;  // never taken (b >= 1): keeps the touch load
+  // the rest of the genome (b_1 and layers 2..L) into the transpose tiles,
+  // now free, when it fits there and clear of the tail's own buffers: each
+  // wave copies the quarter over its own tile as soon as its loop ends, so
+  // the epilogue and the tail read LDS instead of waiting on global memory
+  // behind the other networks' streams (one round trip instead of one per
+  // layer)
+  const int64_t rest_floats = nd.genes - nd.boff[0];
+  const int tile0 = 4 * kRowsMaxB * ld1;
+  const bool tail_lds = rest_floats <= 4 * 4 * kRowsTile && lo.total <= tile0;
+  if (tail_lds) {
+    const int n4 = (int)((rest_floats + 3) >> 2);  // float4 of the copy (the last may run
+                                                    // past the genome, inside its stride)
+    char* dst = reinterpret_cast<char*>(lds + tile0);
+    const char* src = reinterpret_cast<const char*>(genome + nd.boff[0]);
+    for (int i = wave * kRowsTile; i < (wave + 1) * kRowsTile && i < n4; i += 64)
+      if (i + lane < n4 && i + lane < (wave + 1) * kRowsTile)
+        copy16_to_lds(src + 16 * (int64_t)(i + lane), dst + 16 * i);
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
+  }
+  __syncthreads();
+  // activation tile [16][ld1]: K partials summed in a fixed order, bias,
+  // ReLU; rows past the batch carry the bias only, as in the other kernels
+  const float* __restrict__ b1 = tail_lds ? lds + tile0 : genome + nd.boff[0];
+  const bool hidden = nd.L > 1;
+  float act[NT];
+#pragma unroll
+  for (int it = 0; it < NT; ++it) {
+    const int idx = tid + 256 * it;
+    const int m = idx / (NT * 16);
+    const int n = idx - m * (NT * 16);
+    float v = 0.0f;
+    if (n < n1) {
+      if (m < kRowsMaxB) {
+        v = lds[m * ld1 + n] + lds[(kRowsMaxB + m) * ld1 + n];
+        v += lds[(2 * kRowsMaxB + m) * ld1 + n];
+        v += lds[(3 * kRowsMaxB + m) * ld1 + n];
+      }
+      v += b1[n];
+      if (hidden) v = relu_keep_nan(v);
+    }
+    act[it] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < NT; ++it) {
+    const int idx = tid + 256 * it;
+    const int m = idx / (NT * 16);
+    lds[m * ld1 + (idx - m * (NT * 16))] = act[it];
+  }
+  __syncthreads();
+  const float2 res =
+      tail_lds ? tail_and_fitness<1, 0>(lds, lo, nd, lds + tile0, nd.boff[0], 1, b, 0, nullptr,
+                                        tail_vec != 0, partial + j, ylab)
+               : tail_and_fitness<1, 0>(lds, lo, nd, genome, 0, 1, b, 0, nullptr, tail_vec != 0,
+                                        partial + j, ylab);
+  if (fin.on && tid == 0) finalize_in_kernel(j, res, b, fin);
+}
+
+template <int NT>
+__global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void eval_rows_kernel(
+    const float* __restrict__ genomes, NetDesc nd, const float* __restrict__ x,
+    const int32_t* __restrict__ y, int b, float2* __restrict__ partial, EvalLds lo, int tail_vec,
+    FinArgs fin) {
+  eval_rows_body<NT>(blockIdx.x, genomes, nd, x, y, b, partial, lo, tail_vec, fin);
+}
+
 // ------------------------------------------------------- b <= 4, FP32 --
 // Layer 1 on the vector ALUs with W_1 streamed row by row.  The K range is
 // split in two halves (k < ka and k >= ka, ka = 4 floor(n0 / 8)); waves 0 and
@@ -835,6 +1063,33 @@ static hipError_t launch_large(const float* genomes, const NetDesc& nd, int pop,
   return hipGetLastError();
 }
 
+// 1 KiB-row kernel for b <= 8: n0 a multiple of 4 and at most 4 units of 256.
+static size_t rows_lds_bytes(const NetDesc& nd, EvalLds* out) {
+  const EvalLds lo = tail_layout(nd, 16);
+  if (out) *out = lo;
+  return (size_t)rows_lds_floats(lo) * 4;
+}
+
+static bool rows_ok(const NetDesc& nd, int b) {
+  const int n0 = nd.w[0];
+  return b >= 1 && b <= kRowsMaxB && n0 % 4 == 0 && n0 >= 4 && n0 <= 4 * kRowsUnit &&
+         (int64_t)nd.w[1] * n0 * 4 < 0x40000000 && rows_lds_bytes(nd, nullptr) <= kMaxLds;
+}
+
+template <int NT>
+static hipError_t launch_rows(const float* genomes, const NetDesc& nd, int pop, const float* x,
+                              const int32_t* y, int b, float2* partial, hipStream_t s,
+                              const FinArgs& fin) {
+  const int tv = tail_vectorizable(nd) ? 1 : 0;
+  EvalLds lo;
+  const size_t bytes = rows_lds_bytes(nd, &lo);
+  hipError_t e = allow_lds(eval_rows_kernel<NT>, bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((eval_rows_kernel<NT>), dim3((unsigned)pop), dim3(256), bytes, s, genomes,
+                     nd, x, y, b, partial, lo, tv, fin);
+  return hipGetLastError();
+}
+
 // Row-streaming kernel for b <= 4: n0 a multiple of 4 and at most 1024.
 static constexpr int kStreamMaxRows = 4;
 static size_t stream_lds_bytes(const NetDesc& nd) {
@@ -887,6 +1142,8 @@ static hipError_t launch_nt(const float* genomes, const NetDesc& nd, int pop, co
   if (finalized) *finalized = fin && one_tile;
   if (stream_ok(nd, b))
     return launch_stream(genomes, nd, pop, x, y, b, partial, s, fin ? *fin : none);
+  if (rows_ok(nd, b))
+    return launch_rows<NT>(genomes, nd, pop, x, y, b, partial, s, fin ? *fin : none);
   if (use_small(b))
     return launch_small<NT, 0>(genomes, nd, pop, x, y, b, partial, nullptr, nullptr, s,
                                fin ? *fin : none);
@@ -927,6 +1184,8 @@ int eval_mtiles(const NetDesc& nd, int b) { LEEA_NT_SWITCH((mtiles_nt<N>(nd, b))
 bool large_reg_tail(const NetDesc& nd) { return reg_tail_ok(nd); }
 
 bool eval_stream_supported(const NetDesc& nd, int b) { return stream_ok(nd, b); }
+
+bool eval_rows_supported(const NetDesc& nd, int b) { return !stream_ok(nd, b) && rows_ok(nd, b); }
 
 hipError_t launch_evaluate(const float* genomes, const NetDesc& nd, int pop, const float* x,
                            const int32_t* y, int b, float2* partial, hipStream_t s,
@@ -985,7 +1244,7 @@ static size_t large_lds_rt(const NetDesc& nd, int nt, int mw, EvalLds* out) {
 bool eval_shape_f32(const NetDesc& nd, int b, int kind, int mw, EvalShape* out) {
   const int nt = (nd.w[1] + 15) / 16;
   if (nt < 1 || nt > 16 || b < 1) return false;
-  if (kind < 0) kind = stream_ok(nd, b) ? 3 : (use_small(b) ? 0 : 1);
+  if (kind < 0) kind = stream_ok(nd, b) ? 3 : rows_ok(nd, b) ? 4 : (use_small(b) ? 0 : 1);
   EvalShape sh;
   memset(&sh, 0, sizeof sh);
   sh.tail_vec = tail_vectorizable(nd) ? 1 : 0;
@@ -998,6 +1257,14 @@ bool eval_shape_f32(const NetDesc& nd, int b, int kind, int mw, EvalShape* out) 
     sh.pass_rows = 16;
     sh.lo = tail_layout(nd, 16);
     sh.lds = stream_lds_bytes(nd);
+  } else if (kind == 4) {
+    if (!rows_ok(nd, b)) return false;
+    sh.kind = 4;
+    sh.mw = 1;
+    sh.n_wt = 1;
+    sh.n_pt = 1;
+    sh.pass_rows = 16;
+    sh.lds = rows_lds_bytes(nd, &sh.lo);
   } else if (kind == 0) {
     if (b > 16) return false;
     sh.kind = 0;
@@ -1054,6 +1321,18 @@ __global__ __launch_bounds__(256, 2) void runs_eval_stream_kernel(
                       d.lo, d.tail_vec, FinArgs{});
 }
 
+// 1 KiB-row evaluation of the float32 runs with b <= 8 (each run's own n0,
+// n1 and b; the kernel sizes nothing by them but the epilogue's columns).
+template <int NT>
+__global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void runs_eval_rows_kernel(
+    const RunDesc* __restrict__ runs, const BatchState* __restrict__ st,
+    const int* __restrict__ off, const int* __restrict__ ids, int n) {
+  const int i = find_group(off, n, blockIdx.x);
+  const RunDesc& d = runs[ids[i]];
+  eval_rows_body<NT>(blockIdx.x - off[i], d.genomes[st->cur], d.nd, d.xb, d.yb, d.b, d.partial,
+                     d.lo, d.tail_vec, FinArgs{});
+}
+
 template <int NT, int MW, bool RT>
 __global__ __launch_bounds__(256, MW * NT <= 16 ? 2 : 1) void runs_eval_large_kernel(const RunDesc* __restrict__ runs,
                                                               const BatchState* __restrict__ st,
@@ -1096,6 +1375,14 @@ static hipError_t launch_runs_eval_nt(int kind, int mw, int dt, int rt, const Ru
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(runs_eval_stream_kernel, dim3((unsigned)g.blocks), dim3(256), g.lds, s, runs,
                        st, g.off, g.ids, g.n);
+    return hipGetLastError();
+  }
+  if (kind == 4) {
+    if (dt != 0) return hipErrorInvalidValue;
+    e = allow_lds_any(runs_eval_rows_kernel<NT>, g.lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((runs_eval_rows_kernel<NT>), dim3((unsigned)g.blocks), dim3(256), g.lds, s,
+                       runs, st, g.off, g.ids, g.n);
     return hipGetLastError();
   }
   if (kind == 0) {

@@ -26,7 +26,8 @@ struct EvalLds {
 
 // Launch shape of the evaluation of one network population on b rows:
 // kind 0 small-batch kernel (b <= 16), 1 FP32 large-batch, 2 reduced-precision
-// large-batch, 3 FP32 row-streaming (b <= 4); mw row tiles of 16 per wave;
+// large-batch, 3 FP32 row-streaming (b <= 4), 4 FP32 1 KiB-row (b <= 8);
+// mw row tiles of 16 per wave;
 // n_wt workgroups per network; n_pt partial sums per network.
 struct EvalShape {
   int kind, mw, n_wt, n_pt, pass_rows, tail_vec;
@@ -104,6 +105,8 @@ int eval_mtiles(const NetDesc& nd, int b);
 bool large_reg_tail(const NetDesc& nd);
 // Whether float32 evaluation of b rows takes the row-streaming kernel (b <= 4).
 bool eval_stream_supported(const NetDesc& nd, int b);
+// The 1 KiB-row float32 kernel takes this batch (and the row-streaming one does not).
+bool eval_rows_supported(const NetDesc& nd, int b);
 // What finalize_kernel writes for one network (fitness = sum / b, accuracy,
 // inheritance), for evaluation kernels that hold a network's whole batch in
 // one workgroup and finish it themselves; on = 0: they do not.

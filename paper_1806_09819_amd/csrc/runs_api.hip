@@ -524,7 +524,7 @@ leea_status leea_runs_autotune(leea_runs* m, const float* x_train, const int32_t
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return rfail(m, LEEA_EDEVICE, "event creation failed");
   std::map<std::vector<int64_t>, std::pair<EvalShape, float>> best;
-  const int cands[6][2] = {{0, 1}, {3, 1}, {1, 1}, {1, 2}, {2, 1}, {2, 2}};
+  const int cands[7][2] = {{0, 1}, {3, 1}, {4, 1}, {1, 1}, {1, 2}, {2, 1}, {2, 2}};
   for (int r = 0; r < m->n && !st; ++r) {
     const RunHost& h = m->host[r];
     std::vector<int64_t> key = {h.cfg.pop, h.cfg.max_batch, h.cfg.eval_dtype, h.nd.L};
@@ -536,7 +536,7 @@ leea_status leea_runs_autotune(leea_runs* m, const float* x_train, const int32_t
       bool any = false;
       for (const auto& c : cands) {
         if (h.cfg.eval_dtype == LEEA_DT_F32 && c[0] == 2) continue;
-        if (h.cfg.eval_dtype != LEEA_DT_F32 && (c[0] == 1 || c[0] == 3)) continue;
+        if (h.cfg.eval_dtype != LEEA_DT_F32 && (c[0] == 1 || c[0] == 3 || c[0] == 4)) continue;
         EvalShape sh;
         if (!shape_of(h, c[0], c[1], &sh)) continue;
         // a one-run group in this shape

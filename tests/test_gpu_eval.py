@@ -42,6 +42,15 @@ CASES = [
     ("stream_single_layer", (64, 10), 8, 4, None),
     ("stream_wide_input", (1024, 40, 6), 4, 2, None),
     ("wide_input_b2", (2048, 40, 6), 3, 2, None),
+    # 1 KiB-row layer 1 (b <= 8, n0 <= 1024, n0 a multiple of 4): ragged row
+    # groups, a partial last 256-column unit, four full units, past the
+    # limit (falls back), a row the row-streaming kernel refuses (n0 = 4)
+    ("rows_ragged_n1", (100, 19, 7, 3), 9, 7, None),
+    ("rows_partial_unit", (260, 40, 10), 6, 6, None),
+    ("rows_four_units", (1024, 33, 10), 5, 5, None),
+    ("rows_past_limit", (1028, 24, 10), 4, 8, None),
+    ("rows_tiny_k", (4, 6, 3), 3, 2, None),
+    ("rows_paper_b5", (784, 112, 32, 10), 1000, 5, 24),
     # float32 large-batch kernel with global -> LDS staging: chunk counts
     # below, at and past a multiple of its stage count, one column tile,
     # ragged last row tiles

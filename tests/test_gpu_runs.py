@@ -120,7 +120,9 @@ def test_runs_autotune_choices():
         assert us[r] > 0
         if p["batch"] > 16:
             assert kind[r] != 0                       # the small-batch kernel needs b <= 16
-        assert kind[r] in ((0, 1, 3) if p["eval_dtype"] == "f32" else (0, 2))
+        if p["batch"] > 8:
+            assert kind[r] != 4                       # the 1 KiB-row kernel needs b <= 8
+        assert kind[r] in ((0, 1, 3, 4) if p["eval_dtype"] == "f32" else (0, 2))
     # the tuned group still evaluates what the single runs evaluate
     runs.generation(xd, yd)
     runs.sync()
@@ -140,6 +142,13 @@ def test_runs_set_shape_rejects_missing_shapes():
         runs.set_shape(1, 0, 1)           # b = 64 has no small-batch shape
     with pytest.raises(B.LeeaError):
         runs.set_shape(4, 2, 1)           # float32 run has no bfloat16 kernel
+    with pytest.raises(B.LeeaError):
+        runs.set_shape(5, 4, 1)           # b = 100 has no 1 KiB-row shape
+    with pytest.raises(B.LeeaError):
+        runs.set_shape(0, 4, 1)           # bfloat16 run has no float32 1 KiB-row kernel
     runs.set_shape(2, 2, 1)               # b = 256: one row tile per wave exists
     assert runs.shape(2) == (2, 1)
+    assert runs.shape(4) == (4, 1)        # float32 b = 8: the 1 KiB-row kernel by default
+    runs.set_shape(4, 0, 1)               # ... and the small-batch kernel on request
+    assert runs.shape(4) == (0, 1)
     runs.close()
