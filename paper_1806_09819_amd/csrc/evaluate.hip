@@ -677,32 +677,42 @@ __device__ __forceinline__ void eval_stream_body(int j, const float* __restrict_
   const int ld1 = lo.ld1;
   float* h1 = lds + lo.h1;
   float* part = lds + lo.total;  // [half][16][ld1]
+  // the fitness's labels, read ahead (a buffer load: no branch in front of
+  // the row loop)
+  const int ylab = __builtin_amdgcn_raw_buffer_load_b32(
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t*>(y), 0, b * 4, 0x00020000),
+      tid < b ? tid * 4 : 0x40000000, 0, 0);
   // the 16-row activation tile starts as zeros (padding rows and columns)
   for (int i = tid; i < 16 * ld1; i += 256) h1[i] = 0.0f;
 
+  // all loads of the row loop are raw buffer loads: rows past this wave's
+  // share and columns past its half lie outside the resources (or are sent
+  // there) and read zero without a memory access, so no load sits behind a
+  // branch and the waits of the ring count exactly the older half-rows
+  const __amdgpu_buffer_rsrc_t xs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(x), 0, b * n0 * 4, 0x00020000);
   float4 xr[MB][KB];
 #pragma unroll
   for (int m = 0; m < MB; ++m)
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
       const int k = 256 * kb + 4 * lane;
-      xr[m][kb] = (m < b && k < klen)
-                      ? *reinterpret_cast<const float4*>(x + (int64_t)m * n0 + kbase + k)
-                      : zero4();
+      const int off = (m < b && k < klen) ? (m * n0 + kbase + k) * 4 : 0x40000000;
+      const floatx4 v = __builtin_amdgcn_raw_buffer_load_b128(xs, off, 0, 0);
+      xr[m][kb] = make_float4(v[0], v[1], v[2], v[3]);
     }
   const int rows_per = (n1 + 1) >> 1;
   const int r0 = (wave >> 1) * rows_per;
   const int R = r0 < n1 ? (n1 - r0 < rows_per ? n1 - r0 : rows_per) : 0;
+  const __amdgpu_buffer_rsrc_t ws =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(W1), 0, n1 * n0 * 4, 0x00020000);
   auto loadrow = [&](int r, float4 (&w)[KB]) {
-    const float* wr = W1 + (int64_t)(r0 + r) * n0 + kbase;
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
       const int k = 256 * kb + 4 * lane;
-      w[kb] = zero4();
-      if (256 * kb < klen) {  // uniform
-        const float4 v = load_once(wr + (k < klen ? k : 0));
-        if (k < klen) w[kb] = v;
-      }
+      const int off = (r < R && k < klen) ? ((r0 + r) * n0 + kbase + k) * 4 : 0x40000000;
+      const floatx4 v = __builtin_amdgcn_raw_buffer_load_b128(ws, off, 0, 2);  // nt
+      w[kb] = make_float4(v[0], v[1], v[2], v[3]);
     }
   };
   __syncthreads();  // the zeroed tile before any row is written
@@ -710,7 +720,7 @@ __device__ __forceinline__ void eval_stream_body(int j, const float* __restrict_
   // ring of RF half-rows: the load of half-row r + RF is issued as soon as
   // half-row r has been multiplied
   float4 w[RF][KB];
-  auto row = [&](int r, int q, bool next) {
+  auto row = [&](int r, int q) {
     float v[MB];
 #pragma unroll
     for (int m = 0; m < MB; ++m) v[m] = 0.0f;
@@ -723,7 +733,9 @@ __device__ __forceinline__ void eval_stream_body(int j, const float* __restrict_
         v[m] = fmaf(w[q][kb].z, xr[m][kb].z, v[m]);
         v[m] = fmaf(w[q][kb].w, xr[m][kb].w, v[m]);
       }
-    if (next) loadrow(r + RF, w[q]);
+    __builtin_amdgcn_sched_barrier(0);
+    loadrow(r + RF, w[q]);  // past the share: reads nothing
+    __builtin_amdgcn_sched_barrier(0);
     // reduce-scatter: after the level with offset 32 >> lvl, a lane with
     // that bit set holds the upper half of the remaining values
 #pragma unroll
@@ -744,15 +756,16 @@ __device__ __forceinline__ void eval_stream_body(int j, const float* __restrict_
 #pragma unroll
     for (int lvl = 0; lvl < LOG2MB; ++lvl)
       if (lane & (32 >> lvl)) m += MB >> (lvl + 1);
-    if ((lane & (64 / MB - 1)) == 0 && m < b) part[(half * 16 + m) * ld1 + r0 + r] = v[0];
+    if ((lane & (64 / MB - 1)) == 0 && m < b && r < R) part[(half * 16 + m) * ld1 + r0 + r] = v[0];
   };
 #pragma unroll
-  for (int q = 0; q < RF; ++q)
-    if (q < R) loadrow(q, w[q]);
+  for (int q = 0; q < RF; ++q) {
+    loadrow(q, w[q]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
   for (int rb = 0; rb < R; rb += RF) {
 #pragma unroll
-    for (int q = 0; q < RF; ++q)
-      if (rb + q < R) row(rb + q, q, rb + q + RF < R);  // uniform
+    for (int q = 0; q < RF; ++q) row(rb + q, q);  // rows past R: zeros, not written
   }
   __syncthreads();
   for (int idx = tid; idx < b * n1; idx += 256) {
@@ -764,8 +777,8 @@ __device__ __forceinline__ void eval_stream_body(int j, const float* __restrict_
     h1[m * ld1 + n] = o;
   }
   __syncthreads();
-  const float2 r = tail_and_fitness<1>(lds, lo, nd, genome, 0, 1, b, 0, y, tail_vec != 0,
-                                       partial + j);
+  const float2 r = tail_and_fitness<1>(lds, lo, nd, genome, 0, 1, b, 0, nullptr, tail_vec != 0,
+                                       partial + j, ylab);
   if (fin.on && tid == 0) finalize_in_kernel(j, r, b, fin);
 }
 
