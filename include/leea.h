@@ -398,9 +398,9 @@ leea_status leea_runs_population(leea_runs* m, int32_t r, float** genomes, int64
 
 /* Evaluation shape of run r: kind 0 small-batch kernel (b <= 16), 1 float32
  * large-batch, 2 bfloat16 large-batch, 3 float32 row-streaming (b <= 4, the
- * float32 default there), 4 float32 1 KiB-row kernel (b <= 8, n0 a multiple
- * of 4 and at most 1024; the float32 default for b <= 8 where kind 3 does not
- * apply); mw = row tiles of 16 rows per wave (1 for kinds 0, 3 and 4).
+ * float32 default there), 4 1 KiB-row kernel, float32 or bfloat16 (b <= 8,
+ * n0 a multiple of 4 and at most 1024; the default for b <= 8 where kind 3
+ * does not apply); mw = row tiles of 16 rows per wave (1 for kinds 0, 3, 4).
  * set_shape fails with LEEA_EINVAL for a shape that does not exist there.
  * A different shape may change the last bits of the fitness (the per-row
  * sums are grouped differently). */

@@ -430,13 +430,25 @@ __host__ __device__ inline int rows_lds_floats(const EvalLds& lo) {
   return lo.total > l1 ? lo.total : l1;
 }
 
-template <int NT>
+// DT 0: float32.  DT 1: bfloat16 products (exact in float32) on
+// v_mfma_f32_4x4x4_16b_bf16, K = 4 per block, W_1 from its bfloat16 copy
+// (FROM_COPY, 1 KiB = 512 elements per row load) or read as float32 and
+// rounded in registers (grouped runs, which keep no copy; the same values in
+// the same places, so the two forms are bitwise equal), the batch rounded in
+// registers, later layers' weights rounded as the tail loads them.
+// A unit is 1 KiB of a row in the copy's element size (256 floats, 512
+// bfloat16); units (at most 4) are rounded up to 1, 2 or 4 and the four
+// waves take (unit, row phase): wave w owns unit w mod UP and every
+// (4 / UP)-th group of rows, so each (unit, row) partial is one wave's.
+template <int NT, int DT, bool FROM_COPY>
 __device__ __forceinline__ void eval_rows_body(int j, const float* __restrict__ genomes,
-                                               const NetDesc& nd, const float* __restrict__ x,
+                                               const NetDesc& nd, const W1Shadow& wsh,
+                                               const float* __restrict__ x,
                                                const int32_t* __restrict__ y, int b,
                                                float2* __restrict__ partial, const EvalLds& lo,
                                                int tail_vec, const FinArgs& fin) {
   extern __shared__ float lds[];
+  constexpr int KU = DT == 1 ? 2 * kRowsUnit : kRowsUnit;
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const int lane = tid & 63;
@@ -447,72 +459,131 @@ __device__ __forceinline__ void eval_rows_body(int j, const float* __restrict__ 
   const int ld1 = lo.ld1;
   const float* __restrict__ genome = genomes + (int64_t)j * nd.stride;
   const float* __restrict__ W = genome + nd.woff[0];
-  const int k0 = kRowsUnit * wave;
+  const int U = (n0 + KU - 1) / KU;
+  const int UP = U <= 1 ? 1 : (U <= 2 ? 2 : 4);
+  const int unit = wave & (UP - 1);
+  const int phase = wave / UP;
+  const int nphase = 4 / UP;
+  const int k0 = KU * unit;
   // the fitness's labels, read ahead (a buffer load: no branch, and no flat
   // access where y comes from a run descriptor, either of which would cost
   // the main loop its exact waits)
   const int ylab = __builtin_amdgcn_raw_buffer_load_b32(
       __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t*>(y), 0, b * 4, 0x00020000),
       tid < b ? tid * 4 : 0x40000000, 0, 0);
-  // the batch at this lane's block columns: rows 4 g + jj, columns
-  // k0 + 16 beta + 4 t .. + 3 (buffer loads: rows past b and columns past n0
-  // read zero, with no branch that would cost the loop its exact waits)
+  // the batch at this lane's block columns, rows 4 g + jj (buffer loads:
+  // rows past b and columns past n0 read zero): float32 columns
+  // k0 + 16 beta + 4 t .. + 3, or bfloat16 columns k0 + 32 beta + 8 t .. + 7
   const __amdgpu_buffer_rsrc_t xs =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(x), 0, b * n0 * 4, 0x00020000);
-  float4 xr[2][4];
+  auto xload = [&](int r, int k) {
+    const int off = (r < b && k < n0) ? (r * n0 + k) * 4 : 0x40000000;
+    const floatx4 v = __builtin_amdgcn_raw_buffer_load_b128(xs, off, 0, 0);
+    return make_float4(v[0], v[1], v[2], v[3]);
+  };
+  uint4 xr[2][4];
 #pragma unroll
   for (int g = 0; g < 2; ++g)
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int r = 4 * g + jj;
-      const int k = k0 + 16 * beta + 4 * t;
-      const int off = (r < b && k < n0) ? (r * n0 + k) * 4 : 0x40000000;
-      const floatx4 v = __builtin_amdgcn_raw_buffer_load_b128(xs, off, 0, 0);
-      xr[g][t] = make_float4(v[0], v[1], v[2], v[3]);
+      if constexpr (DT == 1) {
+        const int k = k0 + 32 * beta + 8 * t;
+        xr[g][t] = pack_bf16x8(xload(r, k), xload(r, k + 4));
+      } else {
+        const float4 v = xload(r, k0 + 16 * beta + 4 * t);
+        xr[g][t] = make_uint4(__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z),
+                              __float_as_uint(v.w));
+      }
     }
   // touch one dword of each 128-byte line of the rest of the genome (b_1
   // and layers 2..L, read after layer 1 by the epilogue and the tail; up to
   // 32 KiB) so that those lines are in L2 by then
   const float* __restrict__ rest = genome + nd.boff[0];
   const int rest_bytes = (int)((nd.genes - nd.boff[0]) * 4);
-  const __amdgpu_buffer_rsrc_t ps =
-      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(rest), 0, rest_bytes, 0x00020000);
-  const float touch =
-      __builtin_amdgcn_raw_buffer_load_b32(ps, tid * 128 < rest_bytes ? tid * 128 : 0x40000000, 0, 0);
+  const float touch = __builtin_amdgcn_raw_buffer_load_b32(
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(rest), 0, rest_bytes, 0x00020000),
+      tid * 128 < rest_bytes ? tid * 128 : 0x40000000, 0, 0);
+  // W_1 row loads, 16 bytes per lane: rows past n1 and columns past the row
+  // lie outside the resource and read zero without a memory access.  The
+  // float32 form of DT 1 loads 32 bytes (two float4) and rounds them when
+  // the row group is used.
+  constexpr int LW = (DT == 1 && !FROM_COPY) ? 2 : 1;
   const __amdgpu_buffer_rsrc_t rs =
-      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(W), 0, n1 * n0 * 4, 0x00020000);
-  const int kl = k0 + 4 * lane;
-  const bool kv = kl < n0;
-  auto load = [&](int rg, float4 (&wv)[4]) {
+      (DT == 1 && FROM_COPY)
+          ? __builtin_amdgcn_make_buffer_rsrc(wsh.p + (int64_t)j * wsh.net, 0,
+                                              (int)(wsh.net * 2), 0x00020000)
+          : __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(W), 0, n1 * n0 * 4, 0x00020000);
+  const int kl = k0 + (DT == 1 ? 8 : 4) * lane;
+  auto load = [&](int rg, uint4 (&wv)[4][LW]) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int row = 4 * rg + t;
-      const int off = (kv && row < n1) ? (row * n0 + kl) * 4 : 0x40000000;
-      const floatx4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 2);  // nt
-      wv[t] = make_float4(v[0], v[1], v[2], v[3]);
+#pragma unroll
+      for (int h = 0; h < LW; ++h) {
+        int off;
+        if constexpr (DT == 1 && FROM_COPY)
+          off = (row < n1 && kl < wsh.kp) ? (row * wsh.kp + kl) * 2 : 0x40000000;
+        else
+          off = (row < n1 && kl + 4 * h < n0) ? (row * n0 + kl + 4 * h) * 4 : 0x40000000;
+        const floatx4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 2);  // nt
+        wv[t][h] = make_uint4(__float_as_uint(v[0]), __float_as_uint(v[1]),
+                              __float_as_uint(v[2]), __float_as_uint(v[3]));
+      }
     }
   };
-  float4* tile = reinterpret_cast<float4*>(lds + 4 * kRowsMaxB * ld1) + wave * kRowsTile;
+  uint4* tile = reinterpret_cast<uint4*>(lds + 4 * kRowsMaxB * ld1) + wave * kRowsTile;
   const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
   const int prow = 4 * (int)b5 + 2 * (int)b4 + (int)b3;  // batch row this lane ends with
-  float* part = lds + (wave * kRowsMaxB + prow) * ld1;
-  auto compute = [&](int rg, const float4 (&wv)[4]) {
+  float* part = lds + (unit * kRowsMaxB + prow) * ld1;
+  auto compute = [&](int rg, const uint4 (&wv)[4][LW]) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) tile[t * 65 + lane] = wv[t];
-    float4 T[4];
+    for (int t = 0; t < 4; ++t) {
+      if constexpr (LW == 2)
+        tile[t * 65 + lane] = pack_bf16x8(
+            make_float4(__uint_as_float(wv[t][0].x), __uint_as_float(wv[t][0].y),
+                        __uint_as_float(wv[t][0].z), __uint_as_float(wv[t][0].w)),
+            make_float4(__uint_as_float(wv[t][1].x), __uint_as_float(wv[t][1].y),
+                        __uint_as_float(wv[t][1].z), __uint_as_float(wv[t][1].w)));
+      else
+        tile[t * 65 + lane] = wv[t][0];
+    }
+    uint4 T[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) T[t] = tile[jj * 65 + 4 * beta + t];
     floatx4 a0 = {0.f, 0.f, 0.f, 0.f}, a1 = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (DT == 1) {
+      typedef short shortx4 __attribute__((ext_vector_type(4)));
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      a0 = __builtin_amdgcn_mfma_f32_4x4x1f32(xr[0][t].x, T[t].x, a0, 0, 0, 0);
-      a1 = __builtin_amdgcn_mfma_f32_4x4x1f32(xr[1][t].x, T[t].x, a1, 0, 0, 0);
-      a0 = __builtin_amdgcn_mfma_f32_4x4x1f32(xr[0][t].y, T[t].y, a0, 0, 0, 0);
-      a1 = __builtin_amdgcn_mfma_f32_4x4x1f32(xr[1][t].y, T[t].y, a1, 0, 0, 0);
-      a0 = __builtin_amdgcn_mfma_f32_4x4x1f32(xr[0][t].z, T[t].z, a0, 0, 0, 0);
-      a1 = __builtin_amdgcn_mfma_f32_4x4x1f32(xr[1][t].z, T[t].z, a1, 0, 0, 0);
-      a0 = __builtin_amdgcn_mfma_f32_4x4x1f32(xr[0][t].w, T[t].w, a0, 0, 0, 0);
-      a1 = __builtin_amdgcn_mfma_f32_4x4x1f32(xr[1][t].w, T[t].w, a1, 0, 0, 0);
+      for (int t = 0; t < 4; ++t) {
+        const uint2 wl = make_uint2(T[t].x, T[t].y), wh = make_uint2(T[t].z, T[t].w);
+        a0 = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(
+            __builtin_bit_cast(shortx4, make_uint2(xr[0][t].x, xr[0][t].y)),
+            __builtin_bit_cast(shortx4, wl), a0, 0, 0, 0);
+        a1 = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(
+            __builtin_bit_cast(shortx4, make_uint2(xr[1][t].x, xr[1][t].y)),
+            __builtin_bit_cast(shortx4, wl), a1, 0, 0, 0);
+        a0 = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(
+            __builtin_bit_cast(shortx4, make_uint2(xr[0][t].z, xr[0][t].w)),
+            __builtin_bit_cast(shortx4, wh), a0, 0, 0, 0);
+        a1 = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(
+            __builtin_bit_cast(shortx4, make_uint2(xr[1][t].z, xr[1][t].w)),
+            __builtin_bit_cast(shortx4, wh), a1, 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const uint32_t w4[4] = {T[t].x, T[t].y, T[t].z, T[t].w};
+        const uint32_t x0[4] = {xr[0][t].x, xr[0][t].y, xr[0][t].z, xr[0][t].w};
+        const uint32_t x1[4] = {xr[1][t].x, xr[1][t].y, xr[1][t].z, xr[1][t].w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          a0 = __builtin_amdgcn_mfma_f32_4x4x1f32(__uint_as_float(x0[e]), __uint_as_float(w4[e]),
+                                                  a0, 0, 0, 0);
+          a1 = __builtin_amdgcn_mfma_f32_4x4x1f32(__uint_as_float(x1[e]), __uint_as_float(w4[e]),
+                                                  a1, 0, 0, 0);
+        }
+      }
     }
     // sum over the 16 blocks (lane bits 2..5): reduce-scatter
     float r[4];
@@ -534,22 +605,23 @@ __device__ __forceinline__ void eval_rows_body(int j, const float* __restrict__ 
     const int row = 4 * rg + jj;
     if (!(lane & 4) && row < n1) part[row] = r4;
   };
-  // two groups of rows in flight; the scheduling barriers keep each group's
-  // loads together so that the waits count exactly the older group
+  // this wave's row groups phase, phase + nphase, ...; two in flight (the
+  // scheduling barriers keep each group's loads together so that the waits
+  // count exactly the older group)
   const int RG = (n1 + 3) >> 2;
-  float4 w0[4], w1[4];
-  load(0, w0);
+  uint4 w0[4][LW], w1[4][LW];
+  load(phase, w0);
   __builtin_amdgcn_sched_barrier(0);
-  load(1, w1);
+  load(phase + nphase, w1);
   __builtin_amdgcn_sched_barrier(0);
-  for (int rg = 0; rg < RG; rg += 2) {
+  for (int rg = phase; rg < RG; rg += 2 * nphase) {
     compute(rg, w0);
     __builtin_amdgcn_sched_barrier(0);
-    load(rg + 2, w0);
+    load(rg + 2 * nphase, w0);
     __builtin_amdgcn_sched_barrier(0);
-    compute(rg + 1, w1);
+    compute(rg + nphase, w1);
     __builtin_amdgcn_sched_barrier(0);
-    load(rg + 3, w1);
+    load(rg + 3 * nphase, w1);
     __builtin_amdgcn_sched_barrier(0);
   }
   if (b < 0) partial[j].x = touch;  // never taken (b >= 1): keeps the touch load
@@ -566,16 +638,17 @@ __device__ __forceinline__ void eval_rows_body(int j, const float* __restrict__ 
     const int n4 = (int)((rest_floats + 3) >> 2);  // float4 of the copy (the last may run
                                                     // past the genome, inside its stride)
     char* dst = reinterpret_cast<char*>(lds + tile0);
-    const char* src = reinterpret_cast<const char*>(genome + nd.boff[0]);
+    const char* src = reinterpret_cast<const char*>(rest);
     for (int i = wave * kRowsTile; i < (wave + 1) * kRowsTile && i < n4; i += 64)
       if (i + lane < n4 && i + lane < (wave + 1) * kRowsTile)
         copy16_to_lds(src + 16 * (int64_t)(i + lane), dst + 16 * i);
     __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
   }
   __syncthreads();
-  // activation tile [16][ld1]: K partials summed in a fixed order, bias,
-  // ReLU; rows past the batch carry the bias only, as in the other kernels
-  const float* __restrict__ b1 = tail_lds ? lds + tile0 : genome + nd.boff[0];
+  // activation tile [16][ld1]: the unit partials summed in a fixed order,
+  // bias, ReLU; rows past the batch carry the bias only, as in the other
+  // kernels
+  const float* __restrict__ b1 = tail_lds ? lds + tile0 : rest;
   const bool hidden = nd.L > 1;
   float act[NT];
 #pragma unroll
@@ -586,9 +659,12 @@ __device__ __forceinline__ void eval_rows_body(int j, const float* __restrict__ 
     float v = 0.0f;
     if (n < n1) {
       if (m < kRowsMaxB) {
-        v = lds[m * ld1 + n] + lds[(kRowsMaxB + m) * ld1 + n];
-        v += lds[(2 * kRowsMaxB + m) * ld1 + n];
-        v += lds[(3 * kRowsMaxB + m) * ld1 + n];
+        v = lds[m * ld1 + n];
+        if (UP > 1) v += lds[(kRowsMaxB + m) * ld1 + n];
+        if (UP > 2) {
+          v += lds[(2 * kRowsMaxB + m) * ld1 + n];
+          v += lds[(3 * kRowsMaxB + m) * ld1 + n];
+        }
       }
       v += b1[n];
       if (hidden) v = relu_keep_nan(v);
@@ -604,10 +680,10 @@ __device__ __forceinline__ void eval_rows_body(int j, const float* __restrict__ 
   }
   __syncthreads();
   const float2 res =
-      tail_lds ? tail_and_fitness<1, 0>(lds, lo, nd, lds + tile0, nd.boff[0], 1, b, 0, nullptr,
-                                        tail_vec != 0, partial + j, ylab)
-               : tail_and_fitness<1, 0>(lds, lo, nd, genome, 0, 1, b, 0, nullptr, tail_vec != 0,
-                                        partial + j, ylab);
+      tail_lds ? tail_and_fitness<1, DT>(lds, lo, nd, lds + tile0, nd.boff[0], 1, b, 0, nullptr,
+                                         tail_vec != 0, partial + j, ylab)
+               : tail_and_fitness<1, DT>(lds, lo, nd, genome, 0, 1, b, 0, nullptr, tail_vec != 0,
+                                         partial + j, ylab);
   if (fin.on && tid == 0) finalize_in_kernel(j, res, b, fin);
 }
 
@@ -616,7 +692,17 @@ __global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void eval_rows_kernel(
     const float* __restrict__ genomes, NetDesc nd, const float* __restrict__ x,
     const int32_t* __restrict__ y, int b, float2* __restrict__ partial, EvalLds lo, int tail_vec,
     FinArgs fin) {
-  eval_rows_body<NT>(blockIdx.x, genomes, nd, x, y, b, partial, lo, tail_vec, fin);
+  eval_rows_body<NT, 0, false>(blockIdx.x, genomes, nd, W1Shadow{}, x, y, b, partial, lo,
+                               tail_vec, fin);
+}
+
+// bfloat16 first layer from the copy (single runs)
+template <int NT>
+__global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void eval_rows_bf16_kernel(
+    const float* __restrict__ genomes, NetDesc nd, W1Shadow wsh, const float* __restrict__ x,
+    const int32_t* __restrict__ y, int b, float2* __restrict__ partial, EvalLds lo, int tail_vec,
+    FinArgs fin) {
+  eval_rows_body<NT, 1, true>(blockIdx.x, genomes, nd, wsh, x, y, b, partial, lo, tail_vec, fin);
 }
 
 // ------------------------------------------------------- b <= 4, FP32 --
@@ -1103,6 +1189,20 @@ static hipError_t launch_rows(const float* genomes, const NetDesc& nd, int pop, 
   return hipGetLastError();
 }
 
+template <int NT>
+static hipError_t launch_rows_bf16(const float* genomes, const NetDesc& nd, int pop,
+                                   const W1Shadow& wsh, const float* x, const int32_t* y, int b,
+                                   float2* partial, hipStream_t s, const FinArgs& fin) {
+  const int tv = tail_vectorizable(nd) ? 1 : 0;
+  EvalLds lo;
+  const size_t bytes = rows_lds_bytes(nd, &lo);
+  hipError_t e = allow_lds(eval_rows_bf16_kernel<NT>, bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((eval_rows_bf16_kernel<NT>), dim3((unsigned)pop), dim3(256), bytes, s,
+                     genomes, nd, wsh, x, y, b, partial, lo, tv, fin);
+  return hipGetLastError();
+}
+
 // Row-streaming kernel for b <= 4: n0 a multiple of 4 and at most 1024.
 static constexpr int kStreamMaxRows = 4;
 static size_t stream_lds_bytes(const NetDesc& nd) {
@@ -1224,6 +1324,9 @@ hipError_t launch_evaluate_small_lp(int dt, const float* genomes, const NetDesc&
 hipError_t launch_evaluate_small_bf16(const float* genomes, const NetDesc& nd, int pop,
                                       const W1Shadow& wsh, const float* x, const int32_t* y,
                                       int b, float2* partial, hipStream_t s, const FinArgs& fin) {
+  if (wsh.p && rows_ok(nd, b))
+    LEEA_NT_SWITCH((launch_rows_bf16<N>(genomes, nd, pop, wsh, x, y, b, partial, s, fin)),
+                   hipErrorInvalidValue)
   LEEA_NT_SWITCH((launch_small_bf16<N>(genomes, nd, pop, wsh, x, y, b, partial, s, fin)),
                  hipErrorInvalidValue)
 }
@@ -1342,8 +1445,20 @@ __global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void runs_eval_rows_kernel(
     const int* __restrict__ off, const int* __restrict__ ids, int n) {
   const int i = find_group(off, n, blockIdx.x);
   const RunDesc& d = runs[ids[i]];
-  eval_rows_body<NT>(blockIdx.x - off[i], d.genomes[st->cur], d.nd, d.xb, d.yb, d.b, d.partial,
-                     d.lo, d.tail_vec, FinArgs{});
+  eval_rows_body<NT, 0, false>(blockIdx.x - off[i], d.genomes[st->cur], d.nd, W1Shadow{}, d.xb,
+                               d.yb, d.b, d.partial, d.lo, d.tail_vec, FinArgs{});
+}
+
+// bfloat16 runs: W_1 read as float32 and rounded in registers (no copy),
+// bitwise what a single run gets from its copy
+template <int NT>
+__global__ __launch_bounds__(256, 2) void runs_eval_rows_bf16_kernel(
+    const RunDesc* __restrict__ runs, const BatchState* __restrict__ st,
+    const int* __restrict__ off, const int* __restrict__ ids, int n) {
+  const int i = find_group(off, n, blockIdx.x);
+  const RunDesc& d = runs[ids[i]];
+  eval_rows_body<NT, 1, false>(blockIdx.x - off[i], d.genomes[st->cur], d.nd, W1Shadow{}, d.xb,
+                               d.yb, d.b, d.partial, d.lo, d.tail_vec, FinArgs{});
 }
 
 template <int NT, int MW, bool RT>
@@ -1391,11 +1506,19 @@ static hipError_t launch_runs_eval_nt(int kind, int mw, int dt, int rt, const Ru
     return hipGetLastError();
   }
   if (kind == 4) {
-    if (dt != 0) return hipErrorInvalidValue;
-    e = allow_lds_any(runs_eval_rows_kernel<NT>, g.lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((runs_eval_rows_kernel<NT>), dim3((unsigned)g.blocks), dim3(256), g.lds, s,
-                       runs, st, g.off, g.ids, g.n);
+    if (dt == 0) {
+      e = allow_lds_any(runs_eval_rows_kernel<NT>, g.lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((runs_eval_rows_kernel<NT>), dim3((unsigned)g.blocks), dim3(256), g.lds,
+                         s, runs, st, g.off, g.ids, g.n);
+    } else if (dt == 1) {
+      e = allow_lds_any(runs_eval_rows_bf16_kernel<NT>, g.lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((runs_eval_rows_bf16_kernel<NT>), dim3((unsigned)g.blocks), dim3(256),
+                         g.lds, s, runs, st, g.off, g.ids, g.n);
+    } else {
+      return hipErrorInvalidValue;
+    }
     return hipGetLastError();
   }
   if (kind == 0) {

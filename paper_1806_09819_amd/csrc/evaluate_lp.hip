@@ -310,11 +310,16 @@ bool eval_lp_supported(const NetDesc& nd, int b, int dt) {
 bool eval_shape_lp(const NetDesc& nd, int b, int dt, int kind, int mw, EvalShape* out) {
   const int nt = (nd.w[1] + 15) / 16;
   if (nt < 1 || nt > 16 || b < 1 || (dt != 1 && dt != 2)) return false;
-  if (kind < 0) kind = b <= 16 ? 0 : 2;
+  if (kind < 0) {
+    EvalShape rows;
+    kind = (dt == 1 && eval_shape_f32(nd, b, 4, 1, &rows)) ? 4 : (b <= 16 ? 0 : 2);
+  }
   if (kind == 0) {
     if (!eval_shape_f32(nd, b, 0, 1, out)) return false;
     return true;  // small-batch kernel on quantised values
   }
+  if (kind == 4)  // 1 KiB-row kernel, bfloat16 only
+    return dt == 1 && eval_shape_f32(nd, b, 4, 1, out);
   if (kind != 2) return false;
   LpShape sh;
   if (!lp_shape(nd, b, dt, &sh)) return false;

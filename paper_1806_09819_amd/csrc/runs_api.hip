@@ -204,7 +204,7 @@ leea_status build_groups(leea_runs* m) {
     b_fin[r] = (d.pop + 255) / 256;
     sel_lds = std::max(sel_lds, (size_t)d.n2 * 8);
     if (d.dt == LEEA_DT_BF16) {
-      const int64_t items = d.ekind == 0 ? (int64_t)d.b * d.nd.w[0] : (int64_t)d.b * (d.kp >> 3);
+      const int64_t items = (d.ekind == 0 || d.ekind == 4) ? (int64_t)d.b * d.nd.w[0] : (int64_t)d.b * (d.kp >> 3);
       q_ids.push_back(r);
       q_blocks.push_back((int)((items + 255) / 256));
     }
@@ -536,7 +536,8 @@ leea_status leea_runs_autotune(leea_runs* m, const float* x_train, const int32_t
       bool any = false;
       for (const auto& c : cands) {
         if (h.cfg.eval_dtype == LEEA_DT_F32 && c[0] == 2) continue;
-        if (h.cfg.eval_dtype != LEEA_DT_F32 && (c[0] == 1 || c[0] == 3 || c[0] == 4)) continue;
+        if (h.cfg.eval_dtype != LEEA_DT_F32 && (c[0] == 1 || c[0] == 3)) continue;
+        if (h.cfg.eval_dtype == LEEA_DT_FP8 && c[0] == 4) continue;
         EvalShape sh;
         if (!shape_of(h, c[0], c[1], &sh)) continue;
         // a one-run group in this shape
@@ -557,7 +558,7 @@ leea_status leea_runs_autotune(leea_runs* m, const float* x_train, const int32_t
         g.blocks = tab[1];
         g.lds = sh.lds;
         if (d.dt == LEEA_DT_BF16) {
-          const int64_t items = sh.kind == 0 ? (int64_t)d.b * d.nd.w[0] : (int64_t)d.b * (d.kp >> 3);
+          const int64_t items = (sh.kind == 0 || sh.kind == 4) ? (int64_t)d.b * d.nd.w[0] : (int64_t)d.b * (d.kp >> 3);
           Group q = g;
           q.blocks = (int)((items + 255) / 256);
           std::vector<int> qt = {0, q.blocks};

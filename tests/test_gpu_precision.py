@@ -89,8 +89,8 @@ def special_population(run, widths, seed):
 CASES = [
     ("paper", (784, 112, 32, 10), (1, 8, 16, 17, 64, 100, 300)),
     ("ragged", (100, 20, 12, 3), (5, 33, 130)),
-    ("scalar_tail", (28, 7, 3), (9, 70)),
-    ("wide", (196, 256, 128, 64, 10), (12, 64, 200)),
+    ("scalar_tail", (28, 7, 3), (2, 3, 9, 70)),
+    ("wide", (196, 256, 128, 64, 10), (6, 12, 64, 200)),
 ]
 
 

@@ -122,7 +122,7 @@ def test_runs_autotune_choices():
             assert kind[r] != 0                       # the small-batch kernel needs b <= 16
         if p["batch"] > 8:
             assert kind[r] != 4                       # the 1 KiB-row kernel needs b <= 8
-        assert kind[r] in ((0, 1, 3, 4) if p["eval_dtype"] == "f32" else (0, 2))
+        assert kind[r] in ((0, 1, 3, 4) if p["eval_dtype"] == "f32" else (0, 2, 4))
     # the tuned group still evaluates what the single runs evaluate
     runs.generation(xd, yd)
     runs.sync()
@@ -145,7 +145,8 @@ def test_runs_set_shape_rejects_missing_shapes():
     with pytest.raises(B.LeeaError):
         runs.set_shape(5, 4, 1)           # b = 100 has no 1 KiB-row shape
     with pytest.raises(B.LeeaError):
-        runs.set_shape(0, 4, 1)           # bfloat16 run has no float32 1 KiB-row kernel
+        runs.set_shape(1, 4, 1)           # bfloat16 b = 64 has no 1 KiB-row shape
+    assert runs.shape(0) == (4, 1)        # bfloat16 b = 8: the 1 KiB-row kernel by default
     runs.set_shape(2, 2, 1)               # b = 256: one row tile per wave exists
     assert runs.shape(2) == (2, 1)
     assert runs.shape(4) == (4, 1)        # float32 b = 8: the 1 KiB-row kernel by default
