@@ -67,7 +67,7 @@ def algorithmic(params, genes, b):
 
 
 def layer1_flops(params, b):
-    """FLOPs of the first layer alone (the reduced-precision product)."""
+    """FLOPs of the first layer alone (the product on the bfloat16 / FP8 matrix cores)."""
     w = params["widths"]
     return 2.0 * w[0] * w[1] * params["pop"] * b
 
@@ -75,7 +75,7 @@ def layer1_flops(params, b):
 def vary_bytes(params, genes):
     """Algorithmic bytes of one variation launch: every child written once;
     elites and mutants read one parent, crossover children two; with a
-    bfloat16 or FP8 first layer also each child's W_1 written once more at
+    bfloat16 or FP8 weights also each child's W_1 written once more at
     that operand size (the copy the evaluation reads)."""
     from paper_1806_09819_amd import leea as B
     n_e, n_c, n_m, _ = B.counts(params["pop"], params["p_elite"], params["p_cross"],
@@ -249,7 +249,7 @@ def roofline_of(params, r, b):
 def uneven_runs(n=64, seed=0):
     """n uneven run configs: populations log-uniform in [32, 2048], MLP
     784-h-10 with h in {16, 64, 112, 256}, batch in {8, 64, 256}, bfloat16
-    first layer, the paper's other defaults; run index r, seed r."""
+    weights, the paper's other defaults; run index r, seed r."""
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
     for r in range(n):
@@ -512,7 +512,7 @@ def accuracy_runs(x_train, y_train, x_val, y_val, gens=1000, every=50, batch=512
 
 def surrogate_vs_plain(gens=300, data_kind="teacher", k=4, batch=64, dtype="bf16"):
     """The surrogate's workload (784-32-10 with the small workload's operators,
-    P = 1000, 4x over-generated offspring, bfloat16 first layer) run with
+    P = 1000, 4x over-generated offspring, bfloat16 weights and batch) run with
     plain LEEA and with the pre-screening surrogate from the same seed:
     generations/s, the rank-0 network's validation accuracy, and the
     surrogate's screening (generations screened, Kendall tau of its
@@ -559,7 +559,7 @@ def surrogate_vs_plain(gens=300, data_kind="teacher", k=4, batch=64, dtype="bf16
                      rmse_mean=float(st[:, 2].mean()))
         res[mode] = r
         run.close()
-    res["workload"] = ("784-32-10, P = 1000, batch %d, %s first layer, sigma 0.01, p_gene 0.1, "
+    res["workload"] = ("784-32-10, P = 1000, batch %d, %s weights, sigma 0.01, p_gene 0.1, "
                        "truncation top 25 %%, %s data, %d generations; surrogate: %d x offspring, "
                        "%s" % (batch, dtype, data_kind, gens, k, SURROGATE))
     return res
@@ -635,12 +635,13 @@ def main():
     ap.add_argument("--accuracy-gens", type=int, default=1000)
     ap.add_argument("--no-small", action="store_true", help="skip the small workload")
     ap.add_argument("--eval-dtype", default="f32", choices=("f32", "bf16", "fp8"),
-                    help="arithmetic of the first layer (bf16 / fp8: reduced-precision variants)")
+                    help="arithmetic of the weights and the batch (bf16 / fp8: reduced-precision "
+                         "variants; activations and sums stay float32)")
     ap.add_argument("--fused", action="store_true",
                     help="time the fused variation + evaluation call at batch <= 16")
     ap.add_argument("--surrogate-only", type=int, default=0, metavar="GENS",
                     help="only time GENS surrogate generations at the surrogate's workload "
-                         "(prototypes, batch 64, FP32 first layer; for kernel traces) and exit")
+                         "(prototypes, batch 64, FP32; for kernel traces) and exit")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 5 times (scales the "
                          "FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
