@@ -235,9 +235,10 @@ leea_status leea_select(leea_ctx* ctx, int32_t* plan_out, float* f_inh_out,
 leea_status leea_crossover_mutate(leea_ctx* ctx);
 
 /* select -> crossover_mutate -> evaluate, one generation.  With the fused
- * path allowed (leea_set_fused_step), for float32 batches of 5..16 rows (and
- * hidden widths that are multiples of 4, with the genes after layer 1's
- * weights small enough for LDS) the variation and the evaluation run as one
+ * path allowed (leea_set_fused_step), for float32 batches of 5..16 rows that
+ * the 1 KiB-row evaluation kernel does not take (and hidden widths that are
+ * multiples of 4, with the genes after layer 1's weights small enough for
+ * LDS) the variation and the evaluation run as one
  * kernel that builds each child from its parents in registers and evaluates
  * it as it is written (the children are not streamed back from HBM); the
  * results are bitwise identical to the three separate calls. */
@@ -253,7 +254,8 @@ leea_status leea_crossover_mutate_evaluate(leea_ctx* ctx, const float* x, const 
  * leea_step and leea_crossover_mutate_evaluate: one kernel that builds each
  * child from its parents and evaluates it without writing and re-reading it
  * (float32 batches of 5..16 rows, hidden widths multiples of 4; batches of at
- * most 4 always take the separate calls and their row-streaming evaluation).
+ * most 4, and of at most 8 where the 1 KiB-row evaluation kernel applies
+ * (n0 a multiple of 4, at most 1024), always take the separate calls).
  * Results are bit-identical either way; it is off by default because the
  * separate variation and evaluation kernels measured faster. */
 leea_status leea_set_fused_step(leea_ctx* ctx, int32_t enable);

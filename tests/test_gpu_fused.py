@@ -55,6 +55,7 @@ def test_fused_step_bitwise_equals_separate(name, params):
 
 
 def test_fused_teacher_forced_against_oracle():
+    # b = 12: batches of at most 8 take the separate calls (1 KiB-row evaluation)
     x, y = datagen.prototype_data(3000, seed=0)
-    params = dict(PAPER, pop=40, batch=8, generations=3)
+    params = dict(PAPER, pop=40, batch=12, generations=3)
     teacher_forced(params, 3, x, y, label="fused", use_step=True)
