@@ -430,6 +430,88 @@ __host__ __device__ inline int rows_lds_floats(const EvalLds& lo) {
   return lo.total > l1 ? lo.total : l1;
 }
 
+// Layers 2..L and the fitness of the 1 KiB-row kernels: at most 8 batch
+// rows, the weights from the LDS copy of the genome's tail (W_l at
+// tw + woff[l] - toff), one output (row, neuron) per thread at a time as a
+// float32 dot product in k order (weights rounded as loaded for DT 1), then
+// one thread per row for the fitness (as tail_and_fitness) and thread 0 for
+// the row sums, in row order.  A short chain per thread in place of the
+// 16-row matrix tail: at the end of the kernel only the last networks' tails
+// are left, and their latency is what shows.
+template <int DT>
+__device__ float2 rows_tail(float* lds, const EvalLds& lo, const NetDesc& nd, const float* tw,
+                            int64_t toff, int b, int ylab, bool vec, float2* __restrict__ out) {
+  const int tid = threadIdx.x;
+  const float* in = lds + lo.h1;
+  int ldi = lo.ld1;
+  float* dst = lds + lo.ta;
+  for (int l = 1; l < nd.L; ++l) {
+    const int n_in = nd.w[l];
+    const int n_out = nd.w[l + 1];
+    const float* W = tw + (nd.woff[l] - toff);
+    const float* bias = tw + (nd.boff[l] - toff);
+    const bool relu = l < nd.L - 1;
+    for (int idx = tid; idx < kRowsMaxB * n_out; idx += 256) {
+      const int m = idx & (kRowsMaxB - 1);
+      const int n = idx / kRowsMaxB;
+      if (m < b) {
+        const float* a = in + m * ldi;
+        const float* w = W + n * n_in;
+        float v = 0.0f;
+        int k = 0;
+        if (vec) {
+          for (; k + 4 <= n_in; k += 4) {
+            const float4 av = *reinterpret_cast<const float4*>(a + k);
+            const float4 wv = *reinterpret_cast<const float4*>(w + k);
+            v = fmaf(av.x, quantize<DT>(wv.x, 0), v);
+            v = fmaf(av.y, quantize<DT>(wv.y, 0), v);
+            v = fmaf(av.z, quantize<DT>(wv.z, 0), v);
+            v = fmaf(av.w, quantize<DT>(wv.w, 0), v);
+          }
+        }
+        for (; k < n_in; ++k) v = fmaf(a[k], quantize<DT>(w[k], 0), v);
+        v += bias[n];
+        if (relu) v = relu_keep_nan(v);
+        dst[m * lo.ldt + n] = v;
+      }
+    }
+    __syncthreads();
+    in = dst;
+    ldi = lo.ldt;
+    dst = (dst == lds + lo.ta) ? lds + lo.h1 : lds + lo.ta;
+  }
+  const int d = nd.w[nd.L];
+  float* ll = lds + lo.ll;
+  int* cor = reinterpret_cast<int*>(lds + lo.cor);
+  if (tid < b) {
+    const float* z = in + tid * ldi;
+    float mx = z[0];
+    int best = 0;
+    for (int k = 1; k < d; ++k)
+      if (z[k] > mx) {
+        mx = z[k];
+        best = k;
+      }
+    float sx = 0.0f;
+    for (int k = 0; k < d; ++k) sx += expf(z[k] - mx);
+    ll[tid] = (ylab >= 0 && ylab < d) ? (z[ylab] - mx) - logf(sx) : __builtin_nanf("");
+    cor[tid] = (best == ylab) ? 1 : 0;
+  }
+  __syncthreads();
+  float2 r = make_float2(0.0f, 0.0f);
+  if (tid == 0) {
+    float sl = 0.0f;
+    int c = 0;
+    for (int m = 0; m < b; ++m) {
+      sl += ll[m];
+      c += cor[m];
+    }
+    r = make_float2(sl, (float)c);
+    *out = r;
+  }
+  return r;  // thread 0: the partial it wrote
+}
+
 // DT 0: float32.  DT 1: bfloat16 products (exact in float32) on
 // v_mfma_f32_4x4x4_16b_bf16, K = 4 per block, W_1 from its bfloat16 copy
 // (FROM_COPY, 1 KiB = 512 elements per row load) or read as float32 and
@@ -680,8 +762,8 @@ __device__ __forceinline__ void eval_rows_body(int j, const float* __restrict__ 
   }
   __syncthreads();
   const float2 res =
-      tail_lds ? tail_and_fitness<1, DT>(lds, lo, nd, lds + tile0, nd.boff[0], 1, b, 0, nullptr,
-                                         tail_vec != 0, partial + j, ylab)
+      tail_lds ? rows_tail<DT>(lds, lo, nd, lds + tile0, nd.boff[0], b, ylab, tail_vec != 0,
+                               partial + j)
                : tail_and_fitness<1, DT>(lds, lo, nd, genome, 0, 1, b, 0, nullptr, tail_vec != 0,
                                          partial + j, ylab);
   if (fin.on && tid == 0) finalize_in_kernel(j, res, b, fin);
