@@ -433,7 +433,8 @@ __host__ __device__ inline int rows_lds_floats(const EvalLds& lo) {
 // Layers 2..L and the fitness of the 1 KiB-row kernels: at most 8 batch
 // rows, the weights from the LDS copy of the genome's tail (W_l at
 // tw + woff[l] - toff), one output (row, neuron) per thread at a time as a
-// float32 dot product in k order (weights rounded as loaded for DT 1), then
+// float32 dot product (four partial sums by k mod 4, weights rounded as
+// loaded for DT 1), then
 // one thread per row for the fitness (as tail_and_fitness) and thread 0 for
 // the row sums, in row order.  A short chain per thread in place of the
 // 16-row matrix tail: at the end of the kernel only the last networks' tails
@@ -457,19 +458,24 @@ __device__ float2 rows_tail(float* lds, const EvalLds& lo, const NetDesc& nd, co
       if (m < b) {
         const float* a = in + m * ldi;
         const float* w = W + n * n_in;
-        float v = 0.0f;
+        // four partial sums (k mod 4), added pairwise at the end: four
+        // independent chains, and the unrolled loop issues its LDS reads
+        // ahead of the multiplies
+        float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f, v3 = 0.0f;
         int k = 0;
         if (vec) {
+#pragma unroll 4
           for (; k + 4 <= n_in; k += 4) {
             const float4 av = *reinterpret_cast<const float4*>(a + k);
             const float4 wv = *reinterpret_cast<const float4*>(w + k);
-            v = fmaf(av.x, quantize<DT>(wv.x, 0), v);
-            v = fmaf(av.y, quantize<DT>(wv.y, 0), v);
-            v = fmaf(av.z, quantize<DT>(wv.z, 0), v);
-            v = fmaf(av.w, quantize<DT>(wv.w, 0), v);
+            v0 = fmaf(av.x, quantize<DT>(wv.x, 0), v0);
+            v1 = fmaf(av.y, quantize<DT>(wv.y, 0), v1);
+            v2 = fmaf(av.z, quantize<DT>(wv.z, 0), v2);
+            v3 = fmaf(av.w, quantize<DT>(wv.w, 0), v3);
           }
         }
-        for (; k < n_in; ++k) v = fmaf(a[k], quantize<DT>(w[k], 0), v);
+        for (; k < n_in; ++k) v0 = fmaf(a[k], quantize<DT>(w[k], 0), v0);
+        float v = (v0 + v1) + (v2 + v3);
         v += bias[n];
         if (relu) v = relu_keep_nan(v);
         dst[m * lo.ldt + n] = v;
