@@ -733,38 +733,29 @@ __device__ __forceinline__ void eval_rows_body(int j, const float* __restrict__ 
     __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
   }
   __syncthreads();
-  // activation tile [16][ld1]: the unit partials summed in a fixed order,
-  // bias, ReLU; rows past the batch carry the bias only, as in the other
-  // kernels
+  // activation rows [0, 8) of the tile [16][ld1], in place over unit 0's
+  // partials (each element is read and written by the same thread; the
+  // other units' partials, rows 8 and up, are only read): the unit partials
+  // summed in a fixed order, bias, ReLU, zero padding columns.  Rows 8..15
+  // keep what they hold; every row past the batch is left out of the
+  // fitness, and no layer mixes rows.
   const float* __restrict__ b1 = tail_lds ? lds + tile0 : rest;
   const bool hidden = nd.L > 1;
-  float act[NT];
-#pragma unroll
-  for (int it = 0; it < NT; ++it) {
-    const int idx = tid + 256 * it;
+  for (int idx = tid; idx < kRowsMaxB * NT * 16; idx += 256) {
     const int m = idx / (NT * 16);
     const int n = idx - m * (NT * 16);
     float v = 0.0f;
     if (n < n1) {
-      if (m < kRowsMaxB) {
-        v = lds[m * ld1 + n];
-        if (UP > 1) v += lds[(kRowsMaxB + m) * ld1 + n];
-        if (UP > 2) {
-          v += lds[(2 * kRowsMaxB + m) * ld1 + n];
-          v += lds[(3 * kRowsMaxB + m) * ld1 + n];
-        }
+      v = lds[m * ld1 + n];
+      if (UP > 1) v += lds[(kRowsMaxB + m) * ld1 + n];
+      if (UP > 2) {
+        v += lds[(2 * kRowsMaxB + m) * ld1 + n];
+        v += lds[(3 * kRowsMaxB + m) * ld1 + n];
       }
       v += b1[n];
       if (hidden) v = relu_keep_nan(v);
     }
-    act[it] = v;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int it = 0; it < NT; ++it) {
-    const int idx = tid + 256 * it;
-    const int m = idx / (NT * 16);
-    lds[m * ld1 + (idx - m * (NT * 16))] = act[it];
+    lds[m * ld1 + n] = v;
   }
   __syncthreads();
   const float2 res =
