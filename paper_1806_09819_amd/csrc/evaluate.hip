@@ -16,7 +16,12 @@
 // in the e-th one lane (m, kq) contributes k = k0 + 4*kq + e, so the four
 // MFMAs together cover k0 .. k0+15 (one "super-step").
 //
-// Two layer-1 schemes:
+// Layer-1 schemes:
+// * tiny batch (b <= 4, float32): rows of W_1 streamed 1 KiB per load
+//   instruction against the batch held in registers, on the vector ALUs.
+// * batch <= 8 (float32 or bfloat16): rows of W_1 loaded 1 KiB per
+//   instruction, regrouped through a wave-private LDS tile for the
+//   16-block 4x4 matrix products (see the 1 KiB-row kernels below).
 // * small batch (b <= 16, bandwidth-bound): one workgroup per individual;
 //   its 4 waves split the K range, weight fragments stream straight from
 //   HBM into registers (every weight is read exactly once), batch fragments
@@ -391,34 +396,36 @@ __global__ __launch_bounds__(256, NT > 8 ? 3 : 4) void eval_small_fp8_kernel(
   small_epilogue<NT, true, 2>(acc, fac, j, genome, nd, y, b, partial, lo, tail_vec, fin, ts);
 }
 
-// -------------------------------------------------- 5 <= b <= 8, FP32 --
+// ------------------------------------------ b <= 8, FP32 / BF16, 1 KiB rows --
 // Layer 1 from whole 1 KiB spans of W_1 rows on the 16-block matrix
-// instruction v_mfma_f32_4x4x1f32.  Lane l = 4 beta + jj of a wave belongs
-// to block beta; block beta multiplies A[i] (supplied by lane 4 beta + i)
-// with B[jj] (lane 4 beta + jj) into D[i][jj], held by lane 4 beta + jj in
-// its accumulator i.  With A = batch row i of a group of 4 and B = W_1 row
-// jj of a group of 4 rows, both at one k per block, the 16 blocks cover 16
+// instructions v_mfma_f32_4x4x1f32 (float32) and v_mfma_f32_4x4x4_16b_bf16
+// (bfloat16, 4 k per lane).  Lane l = 4 beta + jj of a wave belongs to block
+// beta; block beta multiplies A[i] (supplied by lane 4 beta + i) with B[jj]
+// (lane 4 beta + jj) into D[i][jj], held by lane 4 beta + jj in its
+// accumulator i.  With A = batch row i of a group of 4 and B = W_1 row jj of
+// a group of 4 rows, both at the same k in a block, the 16 blocks cover
 // different k and their D tiles are summed over the blocks at the end.
 //
-// A wave owns one 256-float K unit [256 w, 256 w + 256) of every row (one
-// 1 KiB load instruction per row: lane l reads columns 256 w + 4 l .. + 3).
-// Four such loads (rows 4 rg .. 4 rg + 3) pass through a wave-private LDS
-// tile that swaps rows and lanes within each quad, so that lane
-// (beta, jj) holds row 4 rg + jj at columns 256 w + 16 beta .. + 15, the
-// batch held in registers at the same columns (two groups of 4 rows).
-// 16 k-steps x 2 groups of matrix products per 4 rows, then the 16 block
-// sums are reduced over the wave by a reduce-scatter (xor 32 halves the
-// group, 16 and 8 the rows, 4 sums the pair): one value per lane, written
-// to the wave's K-partial tile [wave][8][ld1] in LDS.  Loads are raw buffer
-// loads over the network's W_1 (rows past n1 and columns past n0 lie outside
-// it and read zero without a memory access) and non-temporal (each line is
-// read once); two groups of 4 rows are in flight.  Measured against the
-// 16-row fragment walk of eval_small_kernel, which streams the same bytes as
-// 16 rows x 64 B per instruction: layer 1 alone 60 us at P = 1000, 784-112,
-// b = 8 (5.8 TB/s) against about 75 us.  The four K partials meet in LDS in
-// a fixed order (wave 0 + 1, + 2, + 3), then the bias, the ReLU and the
-// small-batch kernel's tail and fitness, from a copy of the genome's tail in
-// LDS where it fits.
+// A unit is 1 KiB of a row (256 floats, or 512 bfloat16 of the copy); a
+// wave owns one unit of every row it takes (one load instruction per row:
+// lane l reads the unit's 16 bytes at 16 l).  Four such loads (rows
+// 4 rg .. 4 rg + 3) pass through a wave-private LDS tile that swaps rows and
+// lanes within each quad, so that lane (beta, jj) holds row 4 rg + jj at 16
+// (float32) or 32 (bfloat16) consecutive columns of block beta, and the
+// batch is held in registers at the same columns (two groups of 4 rows).
+// The matrix products of 4 rows are followed by a reduce-scatter of the 16
+// block sums over the wave (xor 32 halves the group, 16 and 8 the rows, 4
+// sums the pair): one value per lane, written to the unit's K-partial tile
+// [unit][8][ld1] in LDS.  Loads are raw buffer loads over the network's W_1
+// or its copy (rows past n1 and columns past the row lie outside and read
+// zero without a memory access) and non-temporal (each line is read once);
+// two groups of 4 rows are in flight.  Measured against the 16-row fragment
+// walk of eval_small_kernel, which streams the same bytes as 16 rows x 64 B
+// per instruction: float32 layer 1 alone 60 us at P = 1000, 784-112, b = 8
+// (5.8 TB/s) against about 75 us.  The unit partials meet in LDS in a fixed
+// order (unit 0 + 1, + 2, + 3), then the bias, the ReLU and a tail for at
+// most 8 rows from a copy of the genome's tail in LDS where it fits (else
+// the small-batch kernel's tail from global memory).
 constexpr int kRowsMaxB = 8;
 constexpr int kRowsUnit = 256;      // floats of a row per load instruction
 constexpr int kRowsTile = 4 * 65;   // float4 per wave transpose tile (one float4 pad per row)
