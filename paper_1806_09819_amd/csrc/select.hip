@@ -4,8 +4,9 @@
 // Each slot's fitness becomes a unique 64-bit key: the high word is an
 // order-reversing map of the float (larger fitness -> smaller key, -0 -> +0,
 // every NaN -> 0xFFFFFFFF), the low word the slot index.  Unique keys make
-// the result independent of the sorting algorithm; an LDS bitonic sort over
-// the next power of two (padding keys all-ones) then gives the order.
+// the result independent of the sorting algorithm; a bitonic sort over the
+// next power of two (padding keys all-ones) then gives the order: in
+// registers with lane shuffles up to 1024 keys, in LDS beyond.
 #include "internal.hpp"
 #include "runs.hpp"
 #include "select_common.hpp"
@@ -20,23 +21,54 @@ __device__ void select_body(uint64_t* keys, const float* __restrict__ f_adj, int
                             float* __restrict__ f_inh_next, int32_t* __restrict__ order_out) {
 #pragma clang fp contract(off)
   const int tid = threadIdx.x;
-  for (int i = tid; i < n2; i += 1024)
-    keys[i] = i < pop ? rank_key(f_adj[i], (uint32_t)i) : ~0ull;
-  __syncthreads();
-  for (int size = 2; size <= n2; size <<= 1) {
-    for (int half = size >> 1; half > 0; half >>= 1) {
-      for (int i = tid; i < (n2 >> 1); i += 1024) {
-        const int lo = 2 * i - (i & (half - 1));
-        const int hi = lo + half;
-        const bool up = (lo & size) == 0;
-        const uint64_t a = keys[lo];
-        const uint64_t b = keys[hi];
-        if ((a > b) == up) {
-          keys[lo] = b;
-          keys[hi] = a;
+  if (n2 <= 1024) {
+    // one key per thread: partners less than 64 apart are in the same wave
+    // and trade keys by lane shuffles; only the 10 exchange steps over 64 or
+    // more (n2 = 1024) go through LDS with barriers.  Element t ends with
+    // the smaller key when it is the lower of its pair in an ascending block
+    // (t & size == 0) or the upper in a descending one.
+    uint64_t a = tid < pop ? rank_key(f_adj[tid], (uint32_t)tid) : ~0ull;
+    for (int size = 2; size <= n2; size <<= 1) {
+      for (int half = size >> 1; half > 0; half >>= 1) {
+        uint64_t b;
+        if (half >= 64) {  // uniform
+          if (tid < n2) keys[tid] = a;
+          __syncthreads();
+          b = tid < n2 ? keys[tid ^ half] : a;
+          __syncthreads();
+        } else {
+          const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)a, half);
+          const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(a >> 32), half);
+          b = ((uint64_t)hi << 32) | lo;
         }
+        const bool asc = (tid & size) == 0;
+        const bool lower = (tid & half) == 0;
+        const uint64_t mn = a < b ? a : b;
+        const uint64_t mx = a < b ? b : a;
+        a = (lower == asc) ? mn : mx;
       }
-      __syncthreads();
+    }
+    if (tid < n2) keys[tid] = a;
+    __syncthreads();
+  } else {
+    for (int i = tid; i < n2; i += 1024)
+      keys[i] = i < pop ? rank_key(f_adj[i], (uint32_t)i) : ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= n2; size <<= 1) {
+      for (int half = size >> 1; half > 0; half >>= 1) {
+        for (int i = tid; i < (n2 >> 1); i += 1024) {
+          const int lo = 2 * i - (i & (half - 1));
+          const int hi = lo + half;
+          const bool up = (lo & size) == 0;
+          const uint64_t a = keys[lo];
+          const uint64_t b = keys[hi];
+          if ((a > b) == up) {
+            keys[lo] = b;
+            keys[hi] = a;
+          }
+        }
+        __syncthreads();
+      }
     }
   }
   for (int r = tid; r < pop; r += 1024) {
