@@ -821,6 +821,16 @@ __host__ __device__ inline int stream_ka(int n0) { return 4 * (n0 / 8); }
 // half-row partial tiles [2][16][ld1].
 __host__ __device__ inline int stream_part_floats(const EvalLds& lo) { return 2 * 16 * lo.ld1; }
 
+// Floats of the copy of the rest of the genome (b_1 and layers 2..L) that
+// the row-streaming kernel keeps in LDS past its partial tiles for the
+// epilogue and the tail, 0 when that rest is larger than 16 KiB (they then
+// read global memory).
+constexpr int64_t kStreamTailMax = 4096;
+__host__ __device__ inline int stream_tail_floats(const NetDesc& nd) {
+  const int64_t r = nd.genes - nd.boff[0];
+  return r <= kStreamTailMax ? (int)((r + 3) & ~(int64_t)3) : 0;
+}
+
 template <int MB>
 __device__ __forceinline__ void eval_stream_body(int j, const float* __restrict__ genomes,
                                                  const NetDesc& nd, const float* __restrict__ x,
@@ -939,18 +949,37 @@ __device__ __forceinline__ void eval_stream_body(int j, const float* __restrict_
 #pragma unroll
     for (int q = 0; q < RF; ++q) row(rb + q, q);  // rows past R: zeros, not written
   }
+  // the rest of the genome into LDS past the partial tiles where it fits,
+  // each wave a quarter once its rows are done, for the epilogue and the
+  // tail of at most 8 rows (rows_tail)
+  const int tail_n = stream_tail_floats(nd);
+  float* tail_copy = part + stream_part_floats(lo);
+  if (tail_n) {
+    const int n4 = tail_n >> 2;
+    const int per = (n4 + 3) >> 2;
+    const char* src = reinterpret_cast<const char*>(b1);
+    char* dst = reinterpret_cast<char*>(tail_copy);
+    for (int i = wave * per; i < (wave + 1) * per && i < n4; i += 64)
+      if (i + lane < n4 && i + lane < (wave + 1) * per)
+        copy16_to_lds(src + 16 * (int64_t)(i + lane), dst + 16 * i);
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
+  }
   __syncthreads();
+  const float* __restrict__ bias1 = tail_n ? tail_copy : b1;
   for (int idx = tid; idx < b * n1; idx += 256) {
     const int m = idx / n1;
     const int n = idx - m * n1;
     float o = part[m * ld1 + n] + part[(16 + m) * ld1 + n];
-    o += b1[n];
+    o += bias1[n];
     if (hidden) o = relu_keep_nan(o);
     h1[m * ld1 + n] = o;
   }
   __syncthreads();
-  const float2 r = tail_and_fitness<1>(lds, lo, nd, genome, 0, 1, b, 0, nullptr, tail_vec != 0,
-                                       partial + j, ylab);
+  const float2 r =
+      tail_n ? rows_tail<0>(lds, lo, nd, tail_copy, nd.boff[0], b, ylab, tail_vec != 0,
+                            partial + j)
+             : tail_and_fitness<1>(lds, lo, nd, genome, 0, 1, b, 0, nullptr, tail_vec != 0,
+                                   partial + j, ylab);
   if (fin.on && tid == 0) finalize_in_kernel(j, r, b, fin);
 }
 
@@ -1293,7 +1322,7 @@ static hipError_t launch_rows_bf16(const float* genomes, const NetDesc& nd, int 
 static constexpr int kStreamMaxRows = 4;
 static size_t stream_lds_bytes(const NetDesc& nd) {
   const EvalLds lo = tail_layout(nd, 16);
-  return (size_t)(lo.total + stream_part_floats(lo)) * 4;
+  return (size_t)(lo.total + stream_part_floats(lo) + stream_tail_floats(nd)) * 4;
 }
 
 static bool stream_ok(const NetDesc& nd, int b) {
