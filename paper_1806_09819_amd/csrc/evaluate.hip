@@ -864,8 +864,12 @@ __device__ __forceinline__ void eval_stream_body(int j, const float* __restrict_
   const int ylab = __builtin_amdgcn_raw_buffer_load_b32(
       __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t*>(y), 0, b * 4, 0x00020000),
       tid < b ? tid * 4 : 0x40000000, 0, 0);
-  // the 16-row activation tile starts as zeros (padding rows and columns)
-  for (int i = tid; i < 16 * ld1; i += 256) h1[i] = 0.0f;
+  // with the global-memory matrix tail (a rest of the genome too large for
+  // the LDS copy) the 16-row activation tile starts as zeros (padding rows
+  // and columns); the tail of at most 8 rows reads only written entries
+  const bool tail_in_lds = stream_tail_floats(nd) != 0;
+  if (!tail_in_lds)
+    for (int i = tid; i < 16 * ld1; i += 256) h1[i] = 0.0f;
 
   // all loads of the row loop are raw buffer loads: rows past this wave's
   // share and columns past its half lie outside the resources (or are sent
@@ -897,7 +901,7 @@ __device__ __forceinline__ void eval_stream_body(int j, const float* __restrict_
       w[kb] = make_float4(v[0], v[1], v[2], v[3]);
     }
   };
-  __syncthreads();  // the zeroed tile before any row is written
+  if (!tail_in_lds) __syncthreads();  // the zeroed tile before any row is written (uniform)
 
   // ring of RF half-rows: the load of half-row r + RF is issued as soon as
   // half-row r has been multiplied
